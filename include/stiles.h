@@ -1,0 +1,234 @@
+/*
+ * stiles.h -- C ABI of the MI355X (gfx950) sparse tile Cholesky library for
+ * symmetric positive-definite block-arrowhead matrices with variable
+ * bandwidth (sTiles, arXiv 2501.02483).
+ *
+ * The paper splits sparse Cholesky into reordering, symbolic factorization
+ * and numerical factorization (Section II, the three-step list).  Here:
+ *   stiles_analyze / stiles_analyze_profile   -- steps 1 and 2, on the host;
+ *   stiles_factorize                          -- step 3, on the GPU;
+ *   stiles_solve, stiles_logdet               -- uses of the factor.
+ * A symbolic object is built once per sparsity pattern and reused for many
+ * numerical factorizations with new values (Section III-A: preprocessing is
+ * paid once when many factorizations share a structure; Appendix A).
+ *
+ * Conventions shared by every entry point:
+ *  - Sizes and indices are int64_t, 0-based.  Matrices are symmetric and
+ *    given by their lower triangle, diagonal included.
+ *  - "arrow" is the number of trailing dense rows/columns of the
+ *    block-arrowhead matrix (Section I); the n = N - arrow leading rows form
+ *    the band part.  The arrow rows always stay last (partial permutation,
+ *    Section III-A).
+ *  - Pointers named d_* are device pointers on the current HIP device; all
+ *    other pointers are host pointers.  The library never allocates device
+ *    memory: the caller owns every device buffer (workspaces, values,
+ *    right-hand sides, outputs) and must keep it alive while work that uses
+ *    it is in flight on the stream.
+ *  - Argument errors are reported synchronously by the return value;
+ *    stiles_last_error_arg() then gives the 1-based position of the
+ *    offending argument.  Device work is asynchronous on the given stream.
+ *  - A numerical failure (a pivot that is not positive, i.e. the matrix is
+ *    not SPD) is detected on the device and reported by stiles_factor_info
+ *    with the LAPACK potrf convention (1-based index, in the permuted order,
+ *    of the first column whose pivot failed).
+ */
+#ifndef STILES_H
+#define STILES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t stiles_status;
+#define STILES_OK 0
+#define STILES_EINVAL (-1)   /* bad argument; see stiles_last_error_arg()          */
+#define STILES_ENOTSUP (-2)  /* valid request the library does not support          */
+#define STILES_ENOMEM (-3)   /* caller-provided workspace too small                 */
+#define STILES_EDEVICE (-4)  /* a HIP call failed                                   */
+#define STILES_ESTATE (-5)   /* object in the wrong state (e.g. factor failed)      */
+
+/* Orderings (Section III-A).  AUTO tries partial RCM on the band part (the
+ * arrow rows are left in place) and keeps it only if it reduces the number
+ * of stored tiles ("if there is no improvement, the method is not used"). */
+#define STILES_ORDER_AUTO 0
+#define STILES_ORDER_NONE 1
+#define STILES_ORDER_PARTIAL_RCM 2
+
+/* Precisions of the numerical factorization. */
+#define STILES_FP64 0     /* every step in FP64                                     */
+#define STILES_MIXED32 1  /* band/arrow tile updates in FP32 on MFMA; POTRF, TRSM,
+                             arrow-corner accumulation, logdet and refinement FP64  */
+
+typedef struct stiles_symbolic stiles_symbolic; /* opaque, host memory, immutable  */
+typedef struct stiles_factor stiles_factor;     /* opaque host handle bound to a
+                                                   caller-owned device workspace   */
+
+typedef struct stiles_opts {
+  int32_t tile;           /* tile size T: 32 or 64 (0 = 64)                          */
+  int32_t ordering;       /* STILES_ORDER_*                                          */
+  int32_t tree_min_ratio; /* arrow-corner tree reduction is used when the number of
+                             accumulations is >= tree_min_ratio x the number of
+                             partial workers (Section IV-A recommends 2); <= 0
+                             disables the tree (sequential accumulation chain)       */
+  int32_t chunk;          /* tile products per accumulation task (0 = default 8)      */
+  double refine_tol;      /* mixed mode: stop when the backward error of every
+                             right-hand side is <= refine_tol (0 = 2^-52 * N^0.5)    */
+  int32_t refine_max_iter;/* mixed mode: at most this many refinement steps (0 = 30) */
+  int32_t reserved[3];
+} stiles_opts;
+
+typedef struct stiles_symbolic_info {
+  int64_t N, n, arrow;    /* order, band part, arrow width                           */
+  int32_t tile;           /* tile size T                                             */
+  int32_t ordering_used;  /* STILES_ORDER_NONE or STILES_ORDER_PARTIAL_RCM           */
+  int64_t tile_rows;      /* band tile rows + arrow tile rows                        */
+  int64_t band_tile_rows;
+  int64_t tiles;          /* stored T x T tiles of the factor                       */
+  int64_t nnz_L;          /* entries of L inside the envelope (band+arrow, lower)    */
+  double flops_alg;       /* sum_j (eta_j + 1)^2, eta_j = sub-diagonal count of col j */
+  double flops_exec;      /* flops the tile kernels execute (padded tiles)           */
+  int64_t factor_tasks;   /* tasks in the factorization DAG                          */
+  int64_t solve_tasks;    /* tasks in the solve DAG                                  */
+  int64_t corner_accumulations; /* tile products summed into the arrow-corner tile(s)
+                                   from band columns (about one per band tile row)   */
+  int32_t tree_used;      /* 1 if the arrow corner is reduced by a tree              */
+  int32_t reserved;
+} stiles_symbolic_info;
+
+typedef struct stiles_solve_report {
+  int32_t iterations;     /* refinement steps taken (0 in FP64 mode)                 */
+  int32_t converged;      /* 1 if the stopping test was met                          */
+  double backward_error;  /* max over right-hand sides of ||b-Ax||/(||A|| ||x||+||b||),
+                             inf-norms; computed in mixed mode only (else -1)        */
+} stiles_solve_report;
+
+/* Fill *opts with the defaults (tile 64, AUTO ordering, tree ratio 2). */
+void stiles_default_opts(stiles_opts* opts);
+
+/* Human-readable name of a status code (static string). */
+const char* stiles_status_string(stiles_status s);
+
+/* 1-based index of the argument rejected by the last call that returned
+ * STILES_EINVAL on this thread (0 if none). */
+int32_t stiles_last_error_arg(void);
+
+/*
+ * Reordering + symbolic factorization from a lower-triangle CSC pattern
+ * (the paper's CTSF reads CSC input, Section III-B).
+ *   N        order of A (N >= 1);  arrow  trailing dense rows (0 <= arrow <= N)
+ *   colptr   N+1 entries, colptr[0] = 0, non-decreasing
+ *   rowind   colptr[N] row indices; in each column strictly increasing, all
+ *            >= the column index (lower triangle) and < N; each column must
+ *            hold its diagonal entry
+ *   opts     may be NULL (defaults)
+ *   out      receives a new symbolic object (free with stiles_symbolic_destroy)
+ * Values passed later to stiles_factorize are in this CSC order.
+ * Errors: EINVAL (argument index in stiles_last_error_arg), ENOTSUP (tile).
+ */
+stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t* colptr, const int64_t* rowind,
+                             const stiles_opts* opts, stiles_symbolic** out);
+
+/*
+ * Same, for a band-plus-arrow envelope given by its profile: band row i
+ * (0 <= i < n_band) has nonzeros in columns first_col[i]..i
+ * (0 <= first_col[i] <= i), the arrow rows are dense.  Values passed to
+ * stiles_factorize are in row-profile order: row 0, row 1, ..., row N-1,
+ * each from its first column to its diagonal (arrow row n_band + r holds
+ * n_band + r + 1 entries).  No reordering is applied (ordering must be AUTO
+ * or NONE): the band is already in envelope order.
+ */
+stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, const int64_t* first_col,
+                                     const stiles_opts* opts, stiles_symbolic** out);
+
+stiles_status stiles_symbolic_query(const stiles_symbolic* sym, stiles_symbolic_info* info);
+
+/* perm[i] = original index of permuted row i (N entries, host). */
+stiles_status stiles_symbolic_perm(const stiles_symbolic* sym, int64_t* perm);
+
+void stiles_symbolic_destroy(stiles_symbolic* sym);
+
+/*
+ * Device workspace bytes for one resident factor of `sym` in the given
+ * precision, able to solve with up to nrhs_max right-hand sides at once.
+ * The workspace holds the tile store of L (CTSF), the inverse diagonal tiles,
+ * the partial sums of the arrow-corner tree, the task tables of the
+ * factorization and solve DAGs and their progress counters.
+ */
+stiles_status stiles_workspace_size(const stiles_symbolic* sym, int32_t precision, int64_t nrhs_max,
+                                    size_t* bytes);
+
+/*
+ * Bind a factor handle to a caller-owned device workspace (>= the size above,
+ * 256-byte aligned) and upload the static task tables into it (asynchronous on
+ * `stream`; the symbolic object must outlive the handle).  One workspace holds
+ * one factor; calls that use the same workspace must be ordered on one stream.
+ */
+stiles_status stiles_workspace_init(const stiles_symbolic* sym, int32_t precision, int64_t nrhs_max,
+                                    void* d_ws, size_t ws_bytes, hipStream_t stream,
+                                    stiles_factor** out);
+
+/*
+ * Numerical factorization PAP^T = L L^T (Algorithm 1, left-looking, over the
+ * nonzero tiles only; arrow-corner accumulations by a reduction tree,
+ * Algorithm 3).  d_values: FP64 values in the order fixed at analysis (CSC or
+ * row profile); read by the first kernel, may be reused once the stream has
+ * passed this call.  Asynchronous; failures surface in stiles_factor_info.
+ */
+stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStream_t stream);
+
+/*
+ * Many independent factorizations in one persistent launch (Appendix A:
+ * concurrent factorizations).  factors[i] must use distinct workspaces and
+ * share one tile size; d_batch_ws (>= stiles_batch_workspace_size bytes) holds
+ * the launch's merged task order.  Each result is bitwise identical to a
+ * single stiles_factorize of the same matrix on the same symbolic object.
+ */
+stiles_status stiles_batch_workspace_size(int32_t count, stiles_factor* const* factors, size_t* bytes);
+stiles_status stiles_factorize_batch(int32_t count, stiles_factor* const* factors,
+                                     const double* const* d_values, void* d_batch_ws,
+                                     size_t batch_ws_bytes, hipStream_t stream);
+
+/* Waits for the stream, then sets *info to 0 (success) or the 1-based
+ * permuted column of the first non-positive pivot. */
+stiles_status stiles_factor_info(stiles_factor* f, hipStream_t stream, int64_t* info);
+
+/*
+ * Solve A X = B in place.  d_B: N x nrhs column-major, leading dimension
+ * ldb >= N, original (unpermuted) ordering.  1 <= nrhs <= nrhs_max of the
+ * workspace.  FP64 mode: one forward and one backward sweep over the tiles.
+ * Mixed mode: the same, followed by FP64 iterative refinement against the
+ * resident original A (synchronizes the stream once per step to test
+ * convergence).  report may be NULL.  If the factorization failed, the
+ * result is NaN (and ESTATE is returned when the failure is already known).
+ */
+stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_B, int64_t ldb, hipStream_t stream,
+                           stiles_solve_report* report);
+
+/* logdet A = 2 sum log L_ii, written to *d_out (one FP64 on the device).
+ * Deterministic fixed-shape reduction.  NaN if the factorization failed. */
+stiles_status stiles_logdet(stiles_factor* f, double* d_out, hipStream_t stream);
+
+/* Copy the factor L out of the tile store into d_L, in row-profile order of
+ * the permuted envelope: row i of P A P^T holds columns f_i..i, f_i being the
+ * first column of row i in P A P^T (for stiles_analyze_profile input this is
+ * exactly the value layout of d_values).  d_L holds nnz_L doubles
+ * (stiles_symbolic_info).  For tests and for callers that want L itself. */
+stiles_status stiles_factor_extract(stiles_factor* f, double* d_L, hipStream_t stream);
+
+/* Upper bound on the workgroups a factorization launch uses (0 = fill the
+ * GPU).  Lets several factorizations on different streams share the GPU. */
+stiles_status stiles_factor_set_max_workgroups(stiles_factor* f, int32_t max_wg);
+
+/* Releases the host handle (the caller frees the workspace). */
+void stiles_factor_release(stiles_factor* f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STILES_H */

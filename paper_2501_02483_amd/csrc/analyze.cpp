@@ -1,0 +1,667 @@
+// analyze.cpp -- host phases 1 and 2 of the three-phase sparse Cholesky
+// (Section II): reordering (partial RCM with the fill check of Section III-A),
+// symbolic factorization at tile granularity (CTSF tiles, Section III-B), and
+// the construction and static scheduling of the task DAGs executed on the GPU
+// (Algorithm 1 task types, Algorithm 2 progress counters, Algorithm 3 trees).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <utility>
+
+#include "symbolic.h"
+
+using namespace stiles;
+
+namespace {
+
+thread_local int32_t g_err_arg = 0;
+
+struct TaskBuilder {
+  std::vector<int32_t> words;             // TASK_WORDS per task (succ/ndeps filled later)
+  std::vector<std::vector<int32_t>> preds;
+  std::vector<float> cost;
+
+  int add(int32_t type_flags, int32_t tile, int32_t a, int32_t b, int32_t c, float cst) {
+    int id = (int)cost.size();
+    int32_t w[TASK_WORDS] = {type_flags, tile, a, b, c, 0, 0, 0};
+    words.insert(words.end(), w, w + TASK_WORDS);
+    preds.emplace_back();
+    cost.push_back(cst);
+    return id;
+  }
+  void dep(int task, int pred) {
+    if (pred >= 0 && pred != task) preds[task].push_back(pred);
+  }
+};
+
+// Static schedule: earliest start in an unbounded-resource model (hop latency
+// on every edge), ties broken by longer remaining path.  Tasks are renumbered
+// in that order, which is topological; workgroups take them in this order.
+void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int32_t>& succ_out,
+              std::vector<float>* est_out, std::vector<int32_t>* pair_words, bool remap_pairs) {
+  (void)pair_words;
+  (void)remap_pairs;
+  const int nt = (int)tb.cost.size();
+  const float hop = 0.8f;
+  for (auto& p : tb.preds) {
+    std::sort(p.begin(), p.end());
+    p.erase(std::unique(p.begin(), p.end()), p.end());
+  }
+  // tasks were created in an order where every predecessor precedes its
+  // successor; verify and compute est forward, bottom level backward.
+  std::vector<float> est(nt, 0.f), bl(nt, 0.f);
+  std::vector<std::vector<int32_t>> succ(nt);
+  for (int t = 0; t < nt; t++) {
+    float e = 0.f;
+    for (int p : tb.preds[t]) {
+      if (p >= t) { fprintf(stderr, "stiles: internal task order error\n"); abort(); }
+      e = std::max(e, est[p] + tb.cost[p] + hop);
+      succ[p].push_back(t);
+    }
+    est[t] = e;
+  }
+  for (int t = nt - 1; t >= 0; t--) {
+    float b = 0.f;
+    for (int s : succ[t]) b = std::max(b, bl[s] + hop);
+    bl[t] = b + tb.cost[t];
+  }
+  std::vector<int32_t> order(nt);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (est[x] != est[y]) return est[x] < est[y];
+    return bl[x] > bl[y];
+  });
+  std::vector<int32_t> newid(nt);
+  for (int i = 0; i < nt; i++) newid[order[i]] = i;
+  tasks_out.assign((size_t)nt * TASK_WORDS, 0);
+  succ_out.clear();
+  if (est_out) est_out->assign(nt, 0.f);
+  for (int i = 0; i < nt; i++) {
+    int t = order[i];
+    int32_t* w = &tasks_out[(size_t)i * TASK_WORDS];
+    std::memcpy(w, &tb.words[(size_t)t * TASK_WORDS], sizeof(int32_t) * TASK_WORDS);
+    w[5] = (int32_t)succ_out.size();
+    std::vector<int32_t> s;
+    for (int x : succ[t]) s.push_back(newid[x]);
+    std::sort(s.begin(), s.end());
+    succ_out.insert(succ_out.end(), s.begin(), s.end());
+    w[6] = (int32_t)succ_out.size();
+    w[7] = (int32_t)tb.preds[t].size();
+    if (est_out) (*est_out)[i] = est[t];
+  }
+  // topological check of the final numbering
+  for (int i = 0; i < nt; i++) {
+    const int32_t* w = &tasks_out[(size_t)i * TASK_WORDS];
+    for (int q = w[5]; q < w[6]; q++)
+      if (succ_out[q] <= i) { fprintf(stderr, "stiles: schedule is not topological\n"); abort(); }
+  }
+}
+
+inline int64_t tile_of_col(const stiles_symbolic& s, int64_t g) {
+  return g < s.n ? g / s.T : s.ntb + (g - s.n) / s.T;
+}
+
+int32_t tile_lookup(const stiles_symbolic& s, int64_t m, int64_t j) {
+  const int32_t* b = s.tcol.data() + s.trow_ptr[m];
+  const int32_t* e = s.tcol.data() + s.trow_ptr[m + 1];
+  const int32_t* p = std::lower_bound(b, e, (int32_t)j);
+  if (p == e || *p != j) return -1;
+  return (int32_t)(p - s.tcol.data());
+}
+
+// Reverse Cuthill-McKee on the band part (rows [0, n)) of a symmetric pattern
+// given as adjacency lists; start nodes are pseudo-peripheral (George-Liu),
+// neighbours visited by increasing degree, ties by lower index.
+std::vector<int64_t> rcm_order(int64_t n, const std::vector<int64_t>& xadj, const std::vector<int64_t>& adj) {
+  std::vector<int64_t> deg(n);
+  for (int64_t v = 0; v < n; v++) deg[v] = xadj[v + 1] - xadj[v];
+  std::vector<char> placed(n, 0);
+  std::vector<int64_t> order;
+  order.reserve(n);
+  std::vector<int64_t> level(n, -1);
+  auto bfs_levels = [&](int64_t root, std::vector<int64_t>& nodes, int64_t& ecc) {
+    nodes.clear();
+    nodes.push_back(root);
+    level[root] = 0;
+    size_t head = 0;
+    ecc = 0;
+    while (head < nodes.size()) {
+      int64_t v = nodes[head++];
+      for (int64_t q = xadj[v]; q < xadj[v + 1]; q++) {
+        int64_t u = adj[q];
+        if (level[u] < 0) { level[u] = level[v] + 1; ecc = std::max(ecc, level[u]); nodes.push_back(u); }
+      }
+    }
+    for (int64_t u : nodes) level[u] = -1;
+  };
+  std::vector<int64_t> comp;
+  for (int64_t s0 = 0; s0 < n; s0++) {
+    if (placed[s0]) continue;
+    // pseudo-peripheral node search
+    int64_t root = s0, ecc = 0;
+    bfs_levels(root, comp, ecc);
+    for (int it = 0; it < 8; it++) {
+      // last level: nodes at distance ecc; pick min degree (lowest index on ties)
+      std::vector<int64_t> lvl_nodes;
+      {
+        std::vector<int64_t> nodes;
+        int64_t e2;
+        // recompute levels to find the last level
+        nodes.push_back(root);
+        level[root] = 0;
+        size_t head = 0;
+        while (head < nodes.size()) {
+          int64_t v = nodes[head++];
+          for (int64_t q = xadj[v]; q < xadj[v + 1]; q++) {
+            int64_t u = adj[q];
+            if (level[u] < 0) { level[u] = level[v] + 1; nodes.push_back(u); }
+          }
+        }
+        for (int64_t u : nodes) if (level[u] == ecc) lvl_nodes.push_back(u);
+        for (int64_t u : nodes) level[u] = -1;
+        (void)e2;
+      }
+      int64_t best = lvl_nodes[0];
+      for (int64_t u : lvl_nodes)
+        if (deg[u] < deg[best] || (deg[u] == deg[best] && u < best)) best = u;
+      int64_t ecc2;
+      std::vector<int64_t> tmp;
+      bfs_levels(best, tmp, ecc2);
+      if (ecc2 > ecc) { root = best; ecc = ecc2; } else break;
+    }
+    // Cuthill-McKee from root
+    size_t start = order.size();
+    order.push_back(root);
+    placed[root] = 1;
+    size_t head = start;
+    std::vector<int64_t> nb;
+    while (head < order.size()) {
+      int64_t v = order[head++];
+      nb.clear();
+      for (int64_t q = xadj[v]; q < xadj[v + 1]; q++)
+        if (!placed[adj[q]]) nb.push_back(adj[q]);
+      std::sort(nb.begin(), nb.end(), [&](int64_t x, int64_t y) {
+        return deg[x] != deg[y] ? deg[x] < deg[y] : x < y;
+      });
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      for (int64_t u : nb) { placed[u] = 1; order.push_back(u); }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+// number of tiles in the tile envelope of a lower profile f over the band part
+// (the arrow tile rows are dense and identical for every band ordering)
+int64_t envelope_tiles(const std::vector<int64_t>& f, int64_t n, int32_t T) {
+  int64_t ntb = (n + T - 1) / T, tot = 0;
+  for (int64_t m = 0; m < ntb; m++) {
+    int64_t F = m;
+    for (int64_t i = m * T; i < std::min<int64_t>(n, (m + 1) * T); i++) F = std::min<int64_t>(F, f[i] / T);
+    tot += m - F + 1;
+  }
+  return tot;
+}
+
+stiles_status check_opts(const stiles_opts* o, int arg) {
+  if (!o) return STILES_OK;
+  if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_err_arg = arg; return STILES_ENOTSUP; }
+  if (o->ordering < STILES_ORDER_AUTO || o->ordering > STILES_ORDER_PARTIAL_RCM) { g_err_arg = arg; return STILES_EINVAL; }
+  if (o->chunk < 0 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
+  return STILES_OK;
+}
+
+void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>& a_cols);
+
+}  // namespace
+
+namespace stiles {
+void set_error_arg(int32_t idx) { g_err_arg = idx; }
+}
+
+extern "C" int32_t stiles_last_error_arg(void) { return g_err_arg; }
+
+extern "C" void stiles_default_opts(stiles_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tile = 64;
+  o->ordering = STILES_ORDER_AUTO;
+  o->tree_min_ratio = 2;
+  o->chunk = 0;
+  o->refine_tol = 0.0;
+  o->refine_max_iter = 0;
+}
+
+static void init_common(stiles_symbolic& s, int64_t N, int64_t a, const stiles_opts* opts) {
+  if (opts) s.opts = *opts; else stiles_default_opts(&s.opts);
+  if (s.opts.tile == 0) s.opts.tile = 64;
+  s.T = s.opts.tile;
+  s.N = N;
+  s.a = a;
+  s.n = N - a;
+  s.ntb = (int32_t)((s.n + s.T - 1) / s.T);
+  s.nta = (int32_t)((s.a + s.T - 1) / s.T);
+  s.ntr = s.ntb + s.nta;
+  s.row_base.resize(s.ntr);
+  s.row_cnt.resize(s.ntr);
+  for (int32_t m = 0; m < s.ntr; m++) {
+    if (m < s.ntb) {
+      s.row_base[m] = (int64_t)m * s.T;
+      s.row_cnt[m] = (int32_t)std::min<int64_t>(s.T, s.n - (int64_t)m * s.T);
+    } else {
+      s.row_base[m] = s.n + (int64_t)(m - s.ntb) * s.T;
+      s.row_cnt[m] = (int32_t)std::min<int64_t>(s.T, s.a - (int64_t)(m - s.ntb) * s.T);
+    }
+  }
+}
+
+extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, const int64_t* first_col,
+                                                const stiles_opts* opts, stiles_symbolic** out) {
+  g_err_arg = 0;
+  if (n_band < 0) { g_err_arg = 1; return STILES_EINVAL; }
+  if (arrow < 0 || n_band + arrow < 1) { g_err_arg = 2; return STILES_EINVAL; }
+  if (n_band > 0 && !first_col) { g_err_arg = 3; return STILES_EINVAL; }
+  for (int64_t i = 0; i < n_band; i++)
+    if (first_col[i] < 0 || first_col[i] > i) { g_err_arg = 3; return STILES_EINVAL; }
+  stiles_status st = check_opts(opts, 4);
+  if (st != STILES_OK) return st;
+  if (opts && opts->ordering == STILES_ORDER_PARTIAL_RCM) { g_err_arg = 4; return STILES_ENOTSUP; }
+  if (!out) { g_err_arg = 5; return STILES_EINVAL; }
+  const int64_t N = n_band + arrow;
+  if ((N + 63) / 16 > INT32_MAX / 4) { g_err_arg = 1; return STILES_ENOTSUP; }
+  stiles_symbolic* s = new stiles_symbolic();
+  init_common(*s, N, arrow, opts);
+  s->profile_input = true;
+  s->ordering_used = STILES_ORDER_NONE;
+  s->perm.resize(N);
+  std::iota(s->perm.begin(), s->perm.end(), 0);
+  s->iperm = s->perm;
+  s->f.resize(N);
+  for (int64_t i = 0; i < n_band; i++) s->f[i] = first_col[i];
+  for (int64_t i = n_band; i < N; i++) s->f[i] = 0;
+  s->in_rp.resize(N + 1);
+  s->in_rp[0] = 0;
+  for (int64_t i = 0; i < N; i++) s->in_rp[i + 1] = s->in_rp[i] + (i - s->f[i] + 1);
+  // tile pattern of A: band tile row m holds tiles F_m..m, arrow rows 0..m
+  std::vector<std::vector<int32_t>> a_cols(s->ntr);  // column lists: rows m >= j
+  for (int32_t m = 0; m < s->ntr; m++) {
+    int64_t F = m;
+    if (m < s->ntb) {
+      for (int64_t i = s->row_base[m]; i < s->row_base[m] + s->row_cnt[m]; i++)
+        F = std::min<int64_t>(F, tile_of_col(*s, s->f[i]));
+    } else {
+      F = 0;
+    }
+    for (int64_t j = F; j <= m; j++) a_cols[j].push_back(m);
+  }
+  finish_symbolic(*s, a_cols);
+  *out = s;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t* colptr, const int64_t* rowind,
+                                        const stiles_opts* opts, stiles_symbolic** out) {
+  g_err_arg = 0;
+  if (N < 1) { g_err_arg = 1; return STILES_EINVAL; }
+  if (arrow < 0 || arrow > N) { g_err_arg = 2; return STILES_EINVAL; }
+  if (!colptr || colptr[0] != 0) { g_err_arg = 3; return STILES_EINVAL; }
+  for (int64_t j = 0; j < N; j++)
+    if (colptr[j + 1] < colptr[j] + 1) { g_err_arg = 3; return STILES_EINVAL; }
+  const int64_t nnz = colptr[N];
+  if (!rowind) { g_err_arg = 4; return STILES_EINVAL; }
+  for (int64_t j = 0; j < N; j++) {
+    if (rowind[colptr[j]] != j) { g_err_arg = 4; return STILES_EINVAL; }  // diagonal first
+    for (int64_t q = colptr[j] + 1; q < colptr[j + 1]; q++)
+      if (rowind[q] <= rowind[q - 1] || rowind[q] >= N) { g_err_arg = 4; return STILES_EINVAL; }
+  }
+  stiles_status st = check_opts(opts, 5);
+  if (st != STILES_OK) return st;
+  if (!out) { g_err_arg = 6; return STILES_EINVAL; }
+  stiles_symbolic* s = new stiles_symbolic();
+  init_common(*s, N, arrow, opts);
+  s->profile_input = false;
+  const int64_t n = s->n;
+  // profile of the identity ordering
+  std::vector<int64_t> f_id(N);
+  for (int64_t i = 0; i < N; i++) f_id[i] = i;
+  for (int64_t j = 0; j < N; j++)
+    for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) f_id[rowind[q]] = std::min(f_id[rowind[q]], j);
+  std::vector<int64_t> perm(N);
+  std::iota(perm.begin(), perm.end(), 0);
+  s->ordering_used = STILES_ORDER_NONE;
+  if (s->opts.ordering != STILES_ORDER_NONE && n > 2) {
+    // symmetric adjacency of the band part (partial permutation: arrow excluded)
+    std::vector<int64_t> deg(n + 1, 0);
+    for (int64_t j = 0; j < n; j++)
+      for (int64_t q = colptr[j] + 1; q < colptr[j + 1]; q++)
+        if (rowind[q] < n) { deg[j]++; deg[rowind[q]]++; }
+    std::vector<int64_t> xadj(n + 1, 0);
+    for (int64_t v = 0; v < n; v++) xadj[v + 1] = xadj[v] + deg[v];
+    std::vector<int64_t> fillp(xadj.begin(), xadj.end() - 1), adj(xadj[n]);
+    for (int64_t j = 0; j < n; j++)
+      for (int64_t q = colptr[j] + 1; q < colptr[j + 1]; q++)
+        if (rowind[q] < n) { adj[fillp[j]++] = rowind[q]; adj[fillp[rowind[q]]++] = j; }
+    std::vector<int64_t> ord = rcm_order(n, xadj, adj);
+    std::vector<int64_t> inv(N);
+    for (int64_t i = 0; i < n; i++) inv[ord[i]] = i;
+    for (int64_t i = n; i < N; i++) inv[i] = i;
+    std::vector<int64_t> f_r(N);
+    for (int64_t i = 0; i < N; i++) f_r[i] = i;
+    for (int64_t j = 0; j < N; j++)
+      for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
+        int64_t p = inv[rowind[q]], c = inv[j];
+        int64_t hi = std::max(p, c), lo = std::min(p, c);
+        f_r[hi] = std::min(f_r[hi], lo);
+      }
+    bool use = s->opts.ordering == STILES_ORDER_PARTIAL_RCM;
+    if (s->opts.ordering == STILES_ORDER_AUTO)
+      use = envelope_tiles(f_r, n, s->T) < envelope_tiles(f_id, n, s->T);   // fill check
+    if (use) {
+      for (int64_t i = 0; i < n; i++) perm[i] = ord[i];
+      s->ordering_used = STILES_ORDER_PARTIAL_RCM;
+    }
+  }
+  s->perm = perm;
+  s->iperm.resize(N);
+  for (int64_t i = 0; i < N; i++) s->iperm[perm[i]] = i;
+  s->f.assign(N, 0);
+  for (int64_t i = 0; i < N; i++) s->f[i] = i;
+  for (int64_t j = 0; j < N; j++)
+    for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
+      int64_t p = s->iperm[rowind[q]], c = s->iperm[j];
+      int64_t hi = std::max(p, c), lo = std::min(p, c);
+      s->f[hi] = std::min(s->f[hi], lo);
+    }
+  // tile pattern of A from the entries actually present
+  std::vector<std::vector<int32_t>> a_cols(s->ntr);
+  for (int32_t m = 0; m < s->ntr; m++) a_cols[m].push_back(m);
+  for (int64_t j = 0; j < N; j++)
+    for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
+      int64_t p = s->iperm[rowind[q]], c = s->iperm[j];
+      int64_t hi = std::max(p, c), lo = std::min(p, c);
+      a_cols[tile_of_col(*s, lo)].push_back((int32_t)tile_of_col(*s, hi));
+    }
+  for (auto& c : a_cols) { std::sort(c.begin(), c.end()); c.erase(std::unique(c.begin(), c.end()), c.end()); }
+  s->in_rp.resize(N + 1);
+  s->in_rp[0] = 0;
+  for (int64_t i = 0; i < N; i++) s->in_rp[i + 1] = s->in_rp[i] + (i - s->f[i] + 1);
+  finish_symbolic(*s, a_cols);
+  // value index -> element offset in the tile store
+  s->map.resize(nnz);
+  const int64_t TT = (int64_t)s->T * s->T;
+  for (int64_t j = 0; j < N; j++)
+    for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
+      int64_t p = s->iperm[rowind[q]], c = s->iperm[j];
+      int64_t hi = std::max(p, c), lo = std::min(p, c);
+      int64_t tm = tile_of_col(*s, hi), tj = tile_of_col(*s, lo);
+      int32_t t = tile_lookup(*s, tm, tj);
+      s->map[q] = (int64_t)t * TT + (lo - s->row_base[tj]) * s->T + (hi - s->row_base[tm]);
+    }
+  *out = s;
+  return STILES_OK;
+}
+
+namespace {
+
+void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>& a_cols) {
+  const int32_t ntr = s.ntr, T = s.T;
+  // ---- tile-level symbolic factorization (elimination tree, column merge)
+  std::vector<std::vector<int32_t>> lcol(ntr);
+  std::vector<std::vector<int32_t>> children(ntr);
+  for (int32_t j = 0; j < ntr; j++) {
+    std::vector<int32_t> c = a_cols[j];
+    for (int32_t ch : children[j]) {
+      for (int32_t r : lcol[ch]) if (r != ch) c.push_back(r);
+    }
+    std::sort(c.begin(), c.end());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
+    // rows >= j only, diagonal present
+    c.erase(std::remove_if(c.begin(), c.end(), [&](int32_t r) { return r < j; }), c.end());
+    if (c.empty() || c[0] != j) c.insert(c.begin(), j);
+    lcol[j] = c;
+    if (c.size() > 1) children[c[1]].push_back(j);
+  }
+  // ---- row lists
+  std::vector<int32_t> rcount(ntr, 0);
+  for (int32_t j = 0; j < ntr; j++) for (int32_t r : lcol[j]) rcount[r]++;
+  s.trow_ptr.assign(ntr + 1, 0);
+  for (int32_t m = 0; m < ntr; m++) s.trow_ptr[m + 1] = s.trow_ptr[m] + rcount[m];
+  s.ntiles = s.trow_ptr[ntr];
+  s.tcol.assign(s.ntiles, 0);
+  s.trow.assign(s.ntiles, 0);
+  {
+    std::vector<int32_t> fillp(s.trow_ptr.begin(), s.trow_ptr.end() - 1);
+    for (int32_t j = 0; j < ntr; j++)
+      for (int32_t r : lcol[j]) { s.tcol[fillp[r]] = j; s.trow[fillp[r]] = r; fillp[r]++; }
+  }
+  // column lists with tile ids (ascending row)
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> ctiles(ntr);
+  for (int32_t m = 0; m < ntr; m++)
+    for (int32_t t = s.trow_ptr[m]; t < s.trow_ptr[m + 1]; t++) ctiles[s.tcol[t]].push_back({m, t});
+
+  // ---- statistics over the element envelope
+  {
+    const int64_t N = s.N;
+    std::vector<int64_t> d(N + 1, 0);
+    s.nnzL = 0;
+    for (int64_t i = 0; i < N; i++) {
+      s.nnzL += i - s.f[i] + 1;
+      d[s.f[i]] += 1;
+      d[i] -= 1;
+    }
+    double F = 0.0;
+    int64_t run = 0;
+    for (int64_t j = 0; j < N; j++) {
+      run += d[j];          // rows i > j with f_i <= j
+      double e = (double)run + 1.0;
+      F += e * e;
+    }
+    s.flops_alg = F;
+  }
+
+  // ---- factorization DAG
+  const int32_t chunk = s.opts.chunk > 0 ? s.opts.chunk : (T == 64 ? 8 : 16);
+  const double t3 = std::pow((double)T / 64.0, 3.0);
+  TaskBuilder tb;
+  std::vector<int32_t> final_task(s.ntiles, -1);
+  std::vector<int32_t> pairs;
+  s.npart = 0;
+  s.tree_used = 0;
+  s.corner_acc = 0;
+  double fexec = 0.0;
+  const double T3 = (double)T * T * T;
+  for (int32_t k = 0; k < ntr; k++) {
+    const int32_t kb = s.trow_ptr[k], ke = s.trow_ptr[k + 1];   // row k tiles (cols ascending, last = k)
+    int32_t potrf_task = -1;
+    for (auto& mt : ctiles[k]) {
+      const int32_t m = mt.first, tgt = mt.second;
+      // pairs (m,j),(k,j), j < k, both present
+      std::vector<std::pair<int32_t, int32_t>> pr;  // (tile m j, tile k j) ascending j
+      std::vector<int32_t> pj;
+      {
+        int32_t p = s.trow_ptr[m], pe = s.trow_ptr[m + 1];
+        int32_t q = kb, qe = ke - 1;   // exclude the diagonal tile (k,k)
+        while (p < pe && q < qe) {
+          int32_t cm = s.tcol[p], ck = s.tcol[q];
+          if (cm >= k) break;
+          if (cm == ck) { pr.push_back({p, q}); pj.push_back(cm); p++; q++; }
+          else if (cm < ck) p++;
+          else q++;
+        }
+      }
+      const bool diag = (m == k);
+      int32_t last = -1;
+      size_t start = 0;
+      const bool corner = (m >= s.ntb && k >= s.ntb);
+      if (corner) {
+        size_t nb = 0;
+        while (nb < pr.size() && pj[nb] < s.ntb) nb++;
+        s.corner_acc = std::max<int64_t>(s.corner_acc, (int64_t)nb);
+        const int64_t G = ((int64_t)nb + chunk - 1) / chunk;
+        if (s.opts.tree_min_ratio > 0 && G >= 2 && (int64_t)nb >= (int64_t)s.opts.tree_min_ratio * G) {
+          s.tree_used = 1;
+          // leaves: PART tasks over contiguous ranges of band columns (Alg. 3)
+          std::vector<std::pair<int32_t, int32_t>> level;   // (slot, producing task)
+          for (int64_t g = 0; g < G; g++) {
+            size_t lo = (size_t)(g * chunk), hi = std::min(nb, (size_t)((g + 1) * chunk));
+            int32_t p0 = (int32_t)(pairs.size() / 2);
+            for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+            int32_t p1 = (int32_t)(pairs.size() / 2);
+            int32_t slot = s.npart++;
+            int t = tb.add(TK_PART, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+            fexec += 2.0 * T3 * (hi - lo);
+            for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+            level.push_back({slot, t});
+          }
+          // binary GEADD tree in index order; the root subtracts into the target
+          while (level.size() > 2) {
+            std::vector<std::pair<int32_t, int32_t>> next;
+            for (size_t q = 0; q + 1 < level.size(); q += 2) {
+              int32_t slot = s.npart++;
+              int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
+              tb.dep(t, level[q].second);
+              tb.dep(t, level[q + 1].second);
+              next.push_back({slot, t});
+            }
+            if (level.size() % 2) next.push_back(level.back());
+            level.swap(next);
+          }
+          int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
+          tb.dep(t, level[0].second);
+          tb.dep(t, level[1].second);
+          last = t;
+          start = nb;
+        }
+      }
+      for (size_t lo = start; lo < pr.size(); lo += chunk) {
+        size_t hi = std::min(pr.size(), lo + chunk);
+        int32_t p0 = (int32_t)(pairs.size() / 2);
+        for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+        int32_t p1 = (int32_t)(pairs.size() / 2);
+        float c = 0.5f + (diag ? 1.35f : 1.8f) * (float)(t3 * (hi - lo));
+        int t = tb.add(TK_UPD | (diag ? TF_DIAG : 0), tgt, p0, p1, 0, c);
+        fexec += (diag ? 1.5 : 2.0) * T3 * (hi - lo);
+        for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+        tb.dep(t, last);
+        last = t;
+      }
+      if (diag) {
+        int t = tb.add(TK_POTRF, tgt, k, 0, 0, T == 64 ? 10.f : 4.f);
+        fexec += 2.0 * T3 / 3.0;
+        tb.dep(t, last);
+        potrf_task = t;
+        final_task[tgt] = t;
+      } else {
+        // the diagonal tile (k,k) comes first in the column list
+        int t = tb.add(TK_TRSM, tgt, k, 0, 0, 0.5f + 1.8f * (float)t3);
+        fexec += 2.0 * T3;
+        tb.dep(t, potrf_task);
+        tb.dep(t, last);
+        final_task[tgt] = t;
+      }
+    }
+  }
+  s.flops_exec = fexec;
+  s.fpairs = pairs;
+  schedule(tb, s.ftask, s.fsucc, &s.fest, nullptr, false);
+
+  // ---- solve DAG (forward then backward sweep over tile rows)
+  TaskBuilder sb;
+  std::vector<int32_t> sp;
+  const int32_t schunk = T == 64 ? 8 : 16;
+  std::vector<int32_t> fdiag(ntr, -1), bdiag(ntr, -1);
+  // forward-read tasks of each Y_j (FUPD chunks that read it) -- the backward
+  // sweep writes into Z only, so no write-after-read edges are needed.
+  for (int32_t m = 0; m < ntr; m++) {
+    int32_t last = -1;
+    const int32_t rb = s.trow_ptr[m], re = s.trow_ptr[m + 1] - 1;
+    for (int32_t lo = rb; lo < re; lo += schunk) {
+      int32_t hi = std::min(re, lo + schunk);
+      int32_t p0 = (int32_t)(sp.size() / 2);
+      for (int32_t t = lo; t < hi; t++) { sp.push_back(t); sp.push_back(s.tcol[t]); }
+      int32_t p1 = (int32_t)(sp.size() / 2);
+      int t = sb.add(TK_FUPD, m, p0, p1, 0, 0.4f + 0.15f * (hi - lo));
+      for (int32_t q = lo; q < hi; q++) sb.dep(t, fdiag[s.tcol[q]]);
+      sb.dep(t, last);
+      last = t;
+    }
+    int t = sb.add(TK_FDIAG, m, 0, 0, 0, 0.6f);
+    sb.dep(t, last);
+    fdiag[m] = t;
+  }
+  for (int32_t m = ntr - 1; m >= 0; m--) {
+    // tiles (i, m), i > m, in descending i (Z_i become final in that order)
+    std::vector<std::pair<int32_t, int32_t>> below;
+    for (auto& it : ctiles[m]) if (it.first > m) below.push_back(it);
+    std::reverse(below.begin(), below.end());
+    int32_t last = -1;
+    bool first = true;
+    for (size_t lo = 0; lo < below.size(); lo += schunk) {
+      size_t hi = std::min(below.size(), lo + schunk);
+      int32_t p0 = (int32_t)(sp.size() / 2);
+      for (size_t q = lo; q < hi; q++) { sp.push_back(below[q].second); sp.push_back(below[q].first); }
+      int32_t p1 = (int32_t)(sp.size() / 2);
+      int t = sb.add(TK_BUPD | (first ? TF_FIRST : 0), m, p0, p1, 0, 0.4f + 0.15f * (hi - lo));
+      for (size_t q = lo; q < hi; q++) sb.dep(t, bdiag[below[q].first]);
+      sb.dep(t, fdiag[m]);
+      sb.dep(t, last);
+      last = t;
+      first = false;
+    }
+    int t = sb.add(TK_BDIAG | (below.empty() ? TF_FIRST : 0), m, 0, 0, 0, 0.6f);
+    sb.dep(t, last);
+    sb.dep(t, fdiag[m]);
+    bdiag[m] = t;
+  }
+  s.spairs = sp;
+  schedule(sb, s.stask, s.ssucc, nullptr, nullptr, false);
+}
+
+}  // namespace
+
+extern "C" stiles_status stiles_symbolic_query(const stiles_symbolic* s, stiles_symbolic_info* info) {
+  g_err_arg = 0;
+  if (!s) { g_err_arg = 1; return STILES_EINVAL; }
+  if (!info) { g_err_arg = 2; return STILES_EINVAL; }
+  std::memset(info, 0, sizeof(*info));
+  info->N = s->N;
+  info->n = s->n;
+  info->arrow = s->a;
+  info->tile = s->T;
+  info->ordering_used = s->ordering_used;
+  info->tile_rows = s->ntr;
+  info->band_tile_rows = s->ntb;
+  info->tiles = s->ntiles;
+  info->nnz_L = s->nnzL;
+  info->flops_alg = s->flops_alg;
+  info->flops_exec = s->flops_exec;
+  info->factor_tasks = (int64_t)(s->ftask.size() / TASK_WORDS);
+  info->solve_tasks = (int64_t)(s->stask.size() / TASK_WORDS);
+  info->corner_accumulations = s->corner_acc;
+  info->tree_used = s->tree_used;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_symbolic_perm(const stiles_symbolic* s, int64_t* perm) {
+  g_err_arg = 0;
+  if (!s) { g_err_arg = 1; return STILES_EINVAL; }
+  if (!perm) { g_err_arg = 2; return STILES_EINVAL; }
+  std::memcpy(perm, s->perm.data(), sizeof(int64_t) * s->N);
+  return STILES_OK;
+}
+
+extern "C" void stiles_symbolic_destroy(stiles_symbolic* s) { delete s; }
+
+extern "C" const char* stiles_status_string(stiles_status st) {
+  switch (st) {
+    case STILES_OK: return "ok";
+    case STILES_EINVAL: return "invalid argument";
+    case STILES_ENOTSUP: return "not supported";
+    case STILES_ENOMEM: return "workspace too small";
+    case STILES_EDEVICE: return "device error";
+    case STILES_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}

@@ -1,0 +1,559 @@
+// capi.cpp -- the C ABI entry points: workspace layout, upload of the static
+// task tables, and the stream-ordered launches of the device kernels.
+// The library never allocates device memory; every buffer is carved out of
+// caller-owned workspaces.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "launch.h"
+#include "symbolic.h"
+
+using namespace stiles;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t ctrl_f, ctrl_s, info, mat_f, mat_s;
+  size_t ftask, fsucc, frem, fpairs;
+  size_t stask, ssucc, srem, spairs;
+  size_t row_base, row_cnt, trow_ptr, trow, tcol, perm;
+  size_t in_rp, fprof, map;
+  size_t tiles, linv, part, shadow, orig;
+  size_t vy, vz, vx, vr, vb, vd;
+  size_t ldpart, stats;
+  size_t ccol_tile, ccol_row, items, item_ptr, rpart;
+  size_t total;
+};
+
+struct Plan {   // host-side refinement tables (mixed mode)
+  std::vector<int32_t> ccol_tile, ccol_row, items, item_ptr;
+};
+
+void make_plan(const stiles_symbolic& s, Plan& p) {
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> below(s.ntr);
+  for (int32_t m = 0; m < s.ntr; m++)
+    for (int32_t t = s.trow_ptr[m]; t < s.trow_ptr[m + 1]; t++)
+      if (s.tcol[t] != m) below[s.tcol[t]].push_back({t, m});
+  std::vector<int32_t> cptr(s.ntr + 1, 0);
+  for (int32_t m = 0; m < s.ntr; m++) cptr[m + 1] = cptr[m] + (int32_t)below[m].size();
+  p.ccol_tile.clear();
+  p.ccol_row.clear();
+  for (int32_t m = 0; m < s.ntr; m++)
+    for (auto& e : below[m]) { p.ccol_tile.push_back(e.first); p.ccol_row.push_back(e.second); }
+  const int32_t CH = 16;
+  p.items.clear();
+  p.item_ptr.assign(s.ntr + 1, 0);
+  for (int32_t m = 0; m < s.ntr; m++) {
+    for (int32_t lo = s.trow_ptr[m]; lo < s.trow_ptr[m + 1]; lo += CH) {
+      int32_t hi = std::min(s.trow_ptr[m + 1], lo + CH);
+      int32_t it[4] = {m, 0, lo, hi};
+      p.items.insert(p.items.end(), it, it + 4);
+    }
+    for (int32_t lo = cptr[m]; lo < cptr[m + 1]; lo += CH) {
+      int32_t hi = std::min(cptr[m + 1], lo + CH);
+      int32_t it[4] = {m, 1, lo, hi};
+      p.items.insert(p.items.end(), it, it + 4);
+    }
+    p.item_ptr[m + 1] = (int32_t)(p.items.size() / 4);
+  }
+}
+
+Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max, const Plan* plan) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = up(o + std::max<size_t>(bytes, 1)); return r; };
+  const size_t TT = (size_t)s.T * s.T;
+  const size_t nft = s.ftask.size() / TASK_WORDS, nst = s.stask.size() / TASK_WORDS;
+  L.ctrl_f = take(sizeof(ExecCtrl));
+  L.ctrl_s = take(sizeof(ExecCtrl));
+  L.info = take(8);
+  L.mat_f = take(sizeof(ExecMat));
+  L.mat_s = take(sizeof(ExecMat));
+  L.ftask = take(s.ftask.size() * 4);
+  L.fsucc = take(s.fsucc.size() * 4);
+  L.frem = take(nft * 4);
+  L.fpairs = take(s.fpairs.size() * 4);
+  L.stask = take(s.stask.size() * 4);
+  L.ssucc = take(s.ssucc.size() * 4);
+  L.srem = take(nst * 4);
+  L.spairs = take(s.spairs.size() * 4);
+  L.row_base = take(s.row_base.size() * 8);
+  L.row_cnt = take(s.row_cnt.size() * 4);
+  L.trow_ptr = take(s.trow_ptr.size() * 4);
+  L.trow = take(s.trow.size() * 4);
+  L.tcol = take(s.tcol.size() * 4);
+  L.perm = take(s.perm.size() * 8);
+  L.in_rp = take(s.in_rp.size() * 8);   // row pointers of the permuted envelope
+  L.fprof = take(s.f.size() * 8);
+  L.map = s.profile_input ? 0 : take(s.map.size() * 8);
+  L.tiles = take(s.ntiles * TT * 8);
+  L.linv = take((size_t)s.ntr * TT * 8);
+  L.part = take((size_t)s.npart * TT * 8);
+  const bool mixed = precision == STILES_MIXED32;
+  L.shadow = mixed ? take(s.ntiles * TT * 4) : 0;
+  L.orig = mixed ? take(s.ntiles * TT * 8) : 0;
+  const size_t vbytes = (size_t)s.ntr * s.T * nrhs_max * 8;
+  L.vy = take(vbytes);
+  L.vz = take(vbytes);
+  L.vx = mixed ? take(vbytes) : 0;
+  L.vr = mixed ? take(vbytes) : 0;
+  L.vb = mixed ? take(vbytes) : 0;
+  L.vd = mixed ? take((size_t)s.ntr * s.T * 8) : 0;   // row sums of |A|
+  L.ldpart = take((size_t)s.ntr * 8);
+  L.stats = take(2 * 16 * 8 + 16);
+  if (mixed && plan) {
+    L.ccol_tile = take(plan->ccol_tile.size() * 4);
+    L.ccol_row = take(plan->ccol_row.size() * 4);
+    L.items = take(plan->items.size() * 4);
+    L.item_ptr = take(plan->item_ptr.size() * 4);
+    L.rpart = take((plan->items.size() / 4) * (size_t)s.T * nrhs_max * 8);
+  }
+  L.total = o;
+  return L;
+}
+
+int device_wg_capacity(int T) {
+  static std::mutex mu;
+  static int cache[2][64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> g(mu);
+  int& c = cache[T == 64 ? 1 : 0][dev];
+  if (c == 0) {
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    // LDS of the executor: 2 T^2 doubles + T doubles (+ ticket)
+    const size_t lds = (2 * (size_t)T * T + T) * 8 + 64;
+    int per_cu = (int)std::min<size_t>(8, (160 * 1024) / lds);
+    if (per_cu < 1) per_cu = 1;
+    c = cus * per_cu;
+  }
+  return c;
+}
+
+}  // namespace
+
+struct stiles_factor {
+  const stiles_symbolic* sym = nullptr;
+  int32_t precision = STILES_FP64;
+  int64_t nrhs_max = 1;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  Layout L{};
+  Plan plan;
+  ExecMat mf{}, ms{};
+  int32_t max_wg = 0;
+  int32_t state = 0;   // 0 unknown, 1 factored ok, 2 failed, -1 not factored
+  double anorm = -1.0; // inf-norm of A (mixed mode), computed lazily
+};
+
+namespace {
+
+template <class T>
+T* at(stiles_factor* f, size_t off) { return reinterpret_cast<T*>(f->ws + off); }
+
+hipError_t upload(stiles_factor* f, size_t off, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  return hipMemcpyAsync(f->ws + off, src, bytes, hipMemcpyHostToDevice, st);
+}
+
+int nwg_for(const stiles_factor* f, int32_t ntasks) {
+  int cap = device_wg_capacity(f->sym->T);
+  if (f->max_wg > 0) cap = std::min(cap, (int)f->max_wg);
+  return std::max(1, std::min(cap, (int)ntasks));
+}
+
+}  // namespace
+
+extern "C" stiles_status stiles_workspace_size(const stiles_symbolic* s, int32_t precision, int64_t nrhs_max,
+                                               size_t* bytes) {
+  set_error_arg(0);
+  if (!s) { set_error_arg(1); return STILES_EINVAL; }
+  if (precision != STILES_FP64 && precision != STILES_MIXED32) { set_error_arg(2); return STILES_EINVAL; }
+  if (nrhs_max < 1) { set_error_arg(3); return STILES_EINVAL; }
+  if (!bytes) { set_error_arg(4); return STILES_EINVAL; }
+  Plan p;
+  if (precision == STILES_MIXED32) make_plan(*s, p);
+  *bytes = make_layout(*s, precision, nrhs_max, precision == STILES_MIXED32 ? &p : nullptr).total;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t precision, int64_t nrhs_max,
+                                               void* d_ws, size_t ws_bytes, hipStream_t st, stiles_factor** out) {
+  set_error_arg(0);
+  if (!s) { set_error_arg(1); return STILES_EINVAL; }
+  if (precision != STILES_FP64 && precision != STILES_MIXED32) { set_error_arg(2); return STILES_EINVAL; }
+  if (nrhs_max < 1) { set_error_arg(3); return STILES_EINVAL; }
+  if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % ALIGN) != 0) { set_error_arg(4); return STILES_EINVAL; }
+  if (!out) { set_error_arg(7); return STILES_EINVAL; }
+  stiles_factor* f = new stiles_factor();
+  f->sym = s;
+  f->precision = precision;
+  f->nrhs_max = nrhs_max;
+  f->ws = static_cast<char*>(d_ws);
+  f->bytes = ws_bytes;
+  const bool mixed = precision == STILES_MIXED32;
+  if (mixed) make_plan(*s, f->plan);
+  f->L = make_layout(*s, precision, nrhs_max, mixed ? &f->plan : nullptr);
+  if (ws_bytes < f->L.total) { delete f; set_error_arg(5); return STILES_ENOMEM; }
+  const Layout& L = f->L;
+  const size_t nft = s->ftask.size() / TASK_WORDS, nst = s->stask.size() / TASK_WORDS;
+  // progress counters start at each task's predecessor count and re-arm
+  // themselves after every launch
+  std::vector<int32_t> frem(nft), srem(nst);
+  for (size_t t = 0; t < nft; t++) frem[t] = s->ftask[t * TASK_WORDS + 7];
+  for (size_t t = 0; t < nst; t++) srem[t] = s->stask[t * TASK_WORDS + 7];
+  ExecCtrl ctrl{};
+  ExecMat& mf = f->mf;
+  mf.tiles = at<double>(f, L.tiles);
+  mf.linv = at<double>(f, L.linv);
+  mf.shadow = mixed ? at<float>(f, L.shadow) : nullptr;
+  mf.part = at<double>(f, L.part);
+  mf.vy = at<double>(f, L.vy);
+  mf.vz = at<double>(f, L.vz);
+  mf.tasks = at<int32_t>(f, L.ftask);
+  mf.succ = at<int32_t>(f, L.fsucc);
+  mf.remaining = at<int32_t>(f, L.frem);
+  mf.pairs = at<int32_t>(f, L.fpairs);
+  mf.info = at<unsigned long long>(f, L.info);
+  mf.row_base = at<int64_t>(f, L.row_base);
+  mf.ntasks = (int32_t)nft;
+  mf.ntr = s->ntr;
+  mf.mixed = mixed ? 1 : 0;
+  ExecMat& ms = f->ms;
+  ms = mf;
+  ms.tasks = at<int32_t>(f, L.stask);
+  ms.succ = at<int32_t>(f, L.ssucc);
+  ms.remaining = at<int32_t>(f, L.srem);
+  ms.pairs = at<int32_t>(f, L.spairs);
+  ms.ntasks = (int32_t)nst;
+  ms.mixed = 0;
+  unsigned long long info0 = ~0ull;
+  hipError_t e = hipSuccess;
+  auto U = [&](size_t off, const void* src, size_t b) { if (e == hipSuccess) e = upload(f, off, src, b, st); };
+  U(L.ctrl_f, &ctrl, sizeof(ctrl));
+  U(L.ctrl_s, &ctrl, sizeof(ctrl));
+  U(L.info, &info0, 8);
+  U(L.mat_f, &mf, sizeof(mf));
+  U(L.mat_s, &ms, sizeof(ms));
+  U(L.ftask, s->ftask.data(), s->ftask.size() * 4);
+  U(L.fsucc, s->fsucc.data(), s->fsucc.size() * 4);
+  U(L.frem, frem.data(), frem.size() * 4);
+  U(L.fpairs, s->fpairs.data(), s->fpairs.size() * 4);
+  U(L.stask, s->stask.data(), s->stask.size() * 4);
+  U(L.ssucc, s->ssucc.data(), s->ssucc.size() * 4);
+  U(L.srem, srem.data(), srem.size() * 4);
+  U(L.spairs, s->spairs.data(), s->spairs.size() * 4);
+  U(L.row_base, s->row_base.data(), s->row_base.size() * 8);
+  U(L.row_cnt, s->row_cnt.data(), s->row_cnt.size() * 4);
+  U(L.trow_ptr, s->trow_ptr.data(), s->trow_ptr.size() * 4);
+  U(L.trow, s->trow.data(), s->trow.size() * 4);
+  U(L.tcol, s->tcol.data(), s->tcol.size() * 4);
+  U(L.perm, s->perm.data(), s->perm.size() * 8);
+  U(L.in_rp, s->in_rp.data(), s->in_rp.size() * 8);
+  U(L.fprof, s->f.data(), s->f.size() * 8);
+  if (!s->profile_input) U(L.map, s->map.data(), s->map.size() * 8);
+  if (mixed) {
+    U(L.ccol_tile, f->plan.ccol_tile.data(), f->plan.ccol_tile.size() * 4);
+    U(L.ccol_row, f->plan.ccol_row.data(), f->plan.ccol_row.size() * 4);
+    U(L.items, f->plan.items.data(), f->plan.items.size() * 4);
+    U(L.item_ptr, f->plan.item_ptr.data(), f->plan.item_ptr.size() * 4);
+  }
+  // the host vectors above must stay alive until the copies are done
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { delete f; return STILES_EDEVICE; }
+  f->state = -1;
+  *out = f;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_factor_set_max_workgroups(stiles_factor* f, int32_t max_wg) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (max_wg < 0) { set_error_arg(2); return STILES_EINVAL; }
+  f->max_wg = max_wg;
+  return STILES_OK;
+}
+
+static stiles_status scatter_values(stiles_factor* f, const double* d_values, hipStream_t st) {
+  const stiles_symbolic& s = *f->sym;
+  const Layout& L = f->L;
+  double* orig = f->precision == STILES_MIXED32 ? at<double>(f, L.orig) : nullptr;
+  hipError_t e;
+  if (s.profile_input)
+    e = launch_scatter_profile(s.T, d_values, at<int64_t>(f, L.in_rp), at<int64_t>(f, L.fprof), at<int32_t>(f, L.trow),
+                               at<int32_t>(f, L.tcol), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
+                               s.ntiles, at<double>(f, L.tiles), orig, at<unsigned long long>(f, L.info), st);
+  else
+    e = launch_scatter_map(s.T, d_values, at<int64_t>(f, L.map), (int64_t)s.map.size(), at<int32_t>(f, L.trow),
+                           at<int32_t>(f, L.tcol), at<int32_t>(f, L.row_cnt), s.ntiles, at<double>(f, L.tiles), orig,
+                           at<unsigned long long>(f, L.info), st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+extern "C" stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStream_t st) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_values && (f->sym->profile_input ? f->sym->in_rp.back() : (int64_t)f->sym->map.size()) > 0) {
+    set_error_arg(2);
+    return STILES_EINVAL;
+  }
+  stiles_status r = scatter_values(f, d_values, st);
+  if (r != STILES_OK) return r;
+  const int32_t nt = f->mf.ntasks;
+  hipError_t e = launch_exec(f->sym->T, at<ExecMat>(f, f->L.mat_f), nullptr, nt, at<ExecCtrl>(f, f->L.ctrl_f), 0,
+                             nwg_for(f, nt), st);
+  if (e != hipSuccess) return STILES_EDEVICE;
+  f->state = 0;
+  f->anorm = -1.0;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_factor_info(stiles_factor* f, hipStream_t st, int64_t* info) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (!info) { set_error_arg(3); return STILES_EINVAL; }
+  if (f->state == -1) return STILES_ESTATE;
+  unsigned long long v = 0;
+  if (hipMemcpyAsync(&v, at<unsigned long long>(f, f->L.info), 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return STILES_EDEVICE;
+  *info = v == ~0ull ? 0 : (int64_t)v;
+  f->state = v == ~0ull ? 1 : 2;
+  return STILES_OK;
+}
+
+static stiles_status solve_sweep(stiles_factor* f, const double* d_src, int64_t ldsrc, int nrhs, hipStream_t st) {
+  // src (original order) -> Y; run the solve DAG; result in Z
+  const stiles_symbolic& s = *f->sym;
+  const Layout& L = f->L;
+  hipError_t e = launch_pack(s.T, d_src, ldsrc, nrhs, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
+                             at<int32_t>(f, L.row_cnt), s.ntr, at<double>(f, L.vy), st);
+  if (e == hipSuccess)
+    e = launch_exec(s.T, at<ExecMat>(f, L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, L.ctrl_s), nrhs,
+                    nwg_for(f, f->ms.ntasks), st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+static stiles_status solve_tiles_from_tiles(stiles_factor* f, const double* d_tile_src, int nrhs, hipStream_t st) {
+  // tile-layout source -> Y (copy), run the solve DAG; result in Z
+  const stiles_symbolic& s = *f->sym;
+  const size_t bytes = (size_t)s.ntr * s.T * nrhs * 8;
+  if (hipMemcpyAsync(at<double>(f, f->L.vy), d_tile_src, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return STILES_EDEVICE;
+  hipError_t e = launch_exec(s.T, at<ExecMat>(f, f->L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, f->L.ctrl_s),
+                             nrhs, nwg_for(f, f->ms.ntasks), st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_B, int64_t ldb, hipStream_t st,
+                                      stiles_solve_report* report) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (nrhs < 1 || nrhs > f->nrhs_max) { set_error_arg(2); return STILES_EINVAL; }
+  if (!d_B) { set_error_arg(3); return STILES_EINVAL; }
+  if (ldb < f->sym->N) { set_error_arg(4); return STILES_EINVAL; }
+  if (f->state == -1) return STILES_ESTATE;
+  if (f->state == 2) return STILES_ESTATE;
+  const stiles_symbolic& s = *f->sym;
+  const Layout& L = f->L;
+  if (report) { report->iterations = 0; report->converged = 1; report->backward_error = -1.0; }
+  for (int64_t c0 = 0; c0 < nrhs; c0 += 16) {
+    const int nb = (int)std::min<int64_t>(16, nrhs - c0);
+    double* B = d_B + c0 * ldb;
+    if (f->precision != STILES_MIXED32) {
+      stiles_status r = solve_sweep(f, B, ldb, nb, st);
+      if (r != STILES_OK) return r;
+      if (launch_unpack(s.T, at<double>(f, L.vz), nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
+                        at<int32_t>(f, L.row_cnt), s.ntr, at<unsigned long long>(f, L.info), B, ldb, st) != hipSuccess)
+        return STILES_EDEVICE;
+      continue;
+    }
+    // ---- mixed mode: x0 = solve(b); repeat r = b - A x, d = solve(r), x += d
+    const size_t vbytes = (size_t)s.ntr * s.T * nb * 8;
+    double* vx = at<double>(f, L.vx);
+    double* vr = at<double>(f, L.vr);
+    double* vbb = at<double>(f, L.vb);
+    double* vz = at<double>(f, L.vz);
+    unsigned long long* stats = at<unsigned long long>(f, L.stats);
+    auto resid = [&](const double* X, double* R, int absmode) {
+      return launch_residual(s.T, at<double>(f, L.orig), at<int32_t>(f, L.trow), at<int32_t>(f, L.tcol),
+                             at<int32_t>(f, L.ccol_tile), at<int32_t>(f, L.ccol_row), at<int32_t>(f, L.items),
+                             (int32_t)(f->plan.items.size() / 4), at<int32_t>(f, L.item_ptr), s.ntr, X, vbb,
+                             at<double>(f, L.rpart), R, absmode ? 1 : nb, absmode, st);
+    };
+    if (f->anorm < 0) {
+      // ||A||_inf from the row sums of |A| (one column of sums)
+      if (resid(vx, at<double>(f, L.vd), 1) != hipSuccess) return STILES_EDEVICE;
+      std::vector<double> rs((size_t)s.ntr * s.T);
+      if (hipMemcpyAsync(rs.data(), at<double>(f, L.vd), rs.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return STILES_EDEVICE;
+      double a = 0.0;
+      for (double v : rs) a = std::max(a, v);
+      f->anorm = a;
+    }
+    stiles_status r = solve_sweep(f, B, ldb, nb, st);      // packs b into Y
+    if (r != STILES_OK) return r;
+    // keep b (tile layout) and x
+    if (launch_pack(s.T, B, ldb, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
+                    s.ntr, vbb, st) != hipSuccess)
+      return STILES_EDEVICE;
+    if (hipMemcpyAsync(vx, vz, vbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return STILES_EDEVICE;
+    std::vector<double> bnorm(nb, 0.0);
+    {
+      // ||b||_inf per column, from the packed copy (host reduction of a small
+      // device-side max: reuse the norms kernel with R = b)
+      std::vector<unsigned long long> z(2 * 16, 0ull);
+      if (hipMemcpyAsync(stats, z.data(), z.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) return STILES_EDEVICE;
+      if (launch_norms(s.T, s.ntr, nb, vbb, vbb, stats, st) != hipSuccess) return STILES_EDEVICE;
+      std::vector<unsigned long long> h(2 * 16);
+      if (hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return STILES_EDEVICE;
+      for (int c = 0; c < nb; c++) { double v; std::memcpy(&v, &h[2 * c], 8); bnorm[c] = v; }
+    }
+    const double tol = f->sym->opts.refine_tol > 0 ? f->sym->opts.refine_tol
+                                                   : std::ldexp(1.0, -52) * std::sqrt((double)s.N);
+    const int maxit = f->sym->opts.refine_max_iter > 0 ? f->sym->opts.refine_max_iter : 30;
+    int it = 0;
+    bool conv = false;
+    double berr = INFINITY, prev = INFINITY;
+    for (;;) {
+      if (resid(vx, vr, 0) != hipSuccess) return STILES_EDEVICE;
+      std::vector<unsigned long long> z(2 * 16, 0ull), h(2 * 16);
+      if (hipMemcpyAsync(stats, z.data(), z.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) return STILES_EDEVICE;
+      if (launch_norms(s.T, s.ntr, nb, vr, vx, stats, st) != hipSuccess) return STILES_EDEVICE;
+      if (hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return STILES_EDEVICE;
+      berr = 0.0;
+      for (int c = 0; c < nb; c++) {
+        double rn, xn;
+        std::memcpy(&rn, &h[2 * c], 8);
+        std::memcpy(&xn, &h[2 * c + 1], 8);
+        const double den = f->anorm * xn + bnorm[c];
+        berr = std::max(berr, den > 0 ? rn / den : rn);
+      }
+      if (!(berr == berr)) break;   // NaN: failed factorization
+      if (berr <= tol) { conv = true; break; }
+      if (it >= maxit || berr > 0.5 * prev) break;   // no longer halving: stagnation
+      prev = berr;
+      stiles_status r2 = solve_tiles_from_tiles(f, vr, nb, st);
+      if (r2 != STILES_OK) return r2;
+      if (launch_axpy(s.T, s.ntr, nb, vx, vz, st) != hipSuccess) return STILES_EDEVICE;
+      it++;
+    }
+    if (launch_unpack(s.T, vx, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
+                      s.ntr, at<unsigned long long>(f, L.info), B, ldb, st) != hipSuccess)
+      return STILES_EDEVICE;
+    if (report) {
+      report->iterations = std::max(report->iterations, it);
+      report->converged = report->converged && conv;
+      report->backward_error = std::max(report->backward_error, berr);
+    }
+  }
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_logdet(stiles_factor* f, double* d_out, hipStream_t st) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_out) { set_error_arg(2); return STILES_EINVAL; }
+  if (f->state == -1 || f->state == 2) return STILES_ESTATE;
+  const Layout& L = f->L;
+  hipError_t e = launch_logdet(f->sym->T, at<double>(f, L.tiles), at<int32_t>(f, L.trow_ptr), f->sym->ntr,
+                               at<double>(f, L.ldpart), at<unsigned long long>(f, L.info), d_out, st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+// ------------------------------------------------------------------ batches
+
+extern "C" stiles_status stiles_batch_workspace_size(int32_t count, stiles_factor* const* factors, size_t* bytes) {
+  set_error_arg(0);
+  if (count < 1) { set_error_arg(1); return STILES_EINVAL; }
+  if (!factors) { set_error_arg(2); return STILES_EINVAL; }
+  if (!bytes) { set_error_arg(3); return STILES_EINVAL; }
+  size_t total = 0;
+  for (int32_t i = 0; i < count; i++) {
+    if (!factors[i]) { set_error_arg(2); return STILES_EINVAL; }
+    total += factors[i]->mf.ntasks;
+  }
+  *bytes = up(sizeof(ExecCtrl)) + up(sizeof(ExecMat) * count) + up(total * 8);
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_factorize_batch(int32_t count, stiles_factor* const* factors,
+                                                const double* const* d_values, void* d_batch_ws,
+                                                size_t batch_ws_bytes, hipStream_t st) {
+  set_error_arg(0);
+  size_t need = 0;
+  stiles_status r = stiles_batch_workspace_size(count, factors, &need);
+  if (r != STILES_OK) return r;
+  if (!d_values) { set_error_arg(3); return STILES_EINVAL; }
+  if (!d_batch_ws || (reinterpret_cast<uintptr_t>(d_batch_ws) % ALIGN) != 0) { set_error_arg(4); return STILES_EINVAL; }
+  if (batch_ws_bytes < need) { set_error_arg(5); return STILES_ENOMEM; }
+  const int T = factors[0]->sym->T;
+  for (int32_t i = 0; i < count; i++) {
+    if (factors[i]->sym->T != T) { set_error_arg(2); return STILES_ENOTSUP; }
+    for (int32_t j = 0; j < i; j++)
+      if (factors[j]->ws == factors[i]->ws) { set_error_arg(2); return STILES_EINVAL; }
+  }
+  // merge the per-matrix static schedules by their start estimates
+  struct E { float est; int32_t m, t; };
+  std::vector<E> ev;
+  for (int32_t i = 0; i < count; i++) {
+    const auto& est = factors[i]->sym->fest;
+    for (int32_t t = 0; t < factors[i]->mf.ntasks; t++) ev.push_back({est[t], i, t});
+  }
+  std::stable_sort(ev.begin(), ev.end(), [](const E& a, const E& b) { return a.est < b.est; });
+  std::vector<int32_t> order(ev.size() * 2);
+  for (size_t q = 0; q < ev.size(); q++) { order[2 * q] = ev[q].m; order[2 * q + 1] = ev[q].t; }
+  std::vector<ExecMat> mats(count);
+  for (int32_t i = 0; i < count; i++) mats[i] = factors[i]->mf;
+  char* b = static_cast<char*>(d_batch_ws);
+  const size_t o_ctrl = 0, o_mats = up(sizeof(ExecCtrl)), o_order = o_mats + up(sizeof(ExecMat) * count);
+  ExecCtrl ctrl{};
+  hipError_t e = hipMemcpyAsync(b + o_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(b + o_mats, mats.data(), sizeof(ExecMat) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(b + o_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st);
+  // host vectors must outlive the asynchronous copies
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return STILES_EDEVICE;
+  for (int32_t i = 0; i < count; i++) {
+    if (!d_values[i]) { set_error_arg(3); return STILES_EINVAL; }
+    r = scatter_values(factors[i], d_values[i], st);
+    if (r != STILES_OK) return r;
+  }
+  int cap = device_wg_capacity(T);
+  e = launch_exec(T, reinterpret_cast<const ExecMat*>(b + o_mats), reinterpret_cast<const int32_t*>(b + o_order),
+                  (int32_t)ev.size(), reinterpret_cast<ExecCtrl*>(b + o_ctrl), 0, std::min<int>(cap, (int)ev.size()), st);
+  if (e != hipSuccess) return STILES_EDEVICE;
+  for (int32_t i = 0; i < count; i++) { factors[i]->state = 0; factors[i]->anorm = -1.0; }
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_factor_extract(stiles_factor* f, double* d_L, hipStream_t st) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_L) { set_error_arg(2); return STILES_EINVAL; }
+  if (f->state == -1) return STILES_ESTATE;
+  const stiles_symbolic& s = *f->sym;
+  const Layout& L = f->L;
+  hipError_t e = launch_extract(s.T, at<double>(f, L.tiles), at<int64_t>(f, L.in_rp), at<int64_t>(f, L.fprof),
+                                at<int32_t>(f, L.trow), at<int32_t>(f, L.tcol), at<int64_t>(f, L.row_base),
+                                at<int32_t>(f, L.row_cnt), s.ntiles, d_L, st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+extern "C" void stiles_factor_release(stiles_factor* f) { delete f; }

@@ -1,0 +1,60 @@
+// launch.h -- host-callable launchers of the device kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stiles_internal.h"
+
+namespace stiles {
+
+// Persistent DAG executor: `total` tickets; order == nullptr means one matrix
+// (mats[0]) with tasks in their own order, else order[2t], order[2t+1] =
+// (matrix index, task id).
+hipError_t launch_exec(int T, const ExecMat* d_mats, const int32_t* d_order, int32_t total, ExecCtrl* d_ctrl,
+                       int nrhs, int nwg, hipStream_t st);
+
+// values (row-profile order) -> tile store (gather per tile, zero fill, unit
+// padding diagonal); also writes `orig` when not null; resets *info.
+hipError_t launch_scatter_profile(int T, const double* vals, const int64_t* in_rp, const int64_t* f,
+                                  const int32_t* trow, const int32_t* tcol, const int64_t* row_base,
+                                  const int32_t* row_cnt, int64_t ntiles, double* tiles, double* orig,
+                                  unsigned long long* info, hipStream_t st);
+
+// CSC values -> tile store through an element map (after a zero/unit fill).
+hipError_t launch_scatter_map(int T, const double* vals, const int64_t* map, int64_t nnz, const int32_t* trow,
+                              const int32_t* tcol, const int32_t* row_cnt, int64_t ntiles, double* tiles,
+                              double* orig, unsigned long long* info, hipStream_t st);
+
+// tile store -> row-profile values of the permuted envelope (lower, with diagonal)
+hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const int64_t* f, const int32_t* trow,
+                          const int32_t* tcol, const int64_t* row_base, const int32_t* row_cnt, int64_t ntiles,
+                          double* out, hipStream_t st);
+
+hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr, double* part,
+                         const unsigned long long* info, double* out, hipStream_t st);
+
+// B (original order, column-major, ldb) -> Y (tile rows, T x nrhs blocks)
+hipError_t launch_pack(int T, const double* B, int64_t ldb, int nrhs, const int64_t* perm, const int64_t* row_base,
+                       const int32_t* row_cnt, int32_t ntr, double* Y, hipStream_t st);
+// Z -> B (original order); NaN when the factorization failed
+hipError_t launch_unpack(int T, const double* Z, int nrhs, const int64_t* perm, const int64_t* row_base,
+                         const int32_t* row_cnt, int32_t ntr, const unsigned long long* info, double* B, int64_t ldb,
+                         hipStream_t st);
+
+// Mixed-mode refinement helpers (FP64, pristine tiles of A).
+// Residual items: 4 int32 each (tile row m, kind, lo, hi); kind 0 sums
+// A_(m,j) X_j over row tiles [lo,hi) (the diagonal tile used symmetrically),
+// kind 1 sums A_(i,m)^T X_i over column entries [lo,hi) of ccol_*.  Item q
+// writes partial block q; row m owns items [item_ptr[m], item_ptr[m+1]).
+// absmode != 0 replaces A by |A| and X by ones (row sums of |A|).
+hipError_t launch_residual(int T, const double* orig, const int32_t* trow, const int32_t* tcol,
+                           const int32_t* ccol_tile, const int32_t* ccol_row, const int32_t* items, int32_t nitems,
+                           const int32_t* item_ptr, int32_t ntr, const double* X, const double* B, double* part,
+                           double* R, int nrhs, int absmode, hipStream_t st);
+// stats[2c] = max_i |R_ic|, stats[2c+1] = max_i |X_ic| (bit patterns, atomically maxed)
+hipError_t launch_norms(int T, int32_t ntr, int nrhs, const double* R, const double* X, unsigned long long* stats,
+                        hipStream_t st);
+// X += D
+hipError_t launch_axpy(int T, int32_t ntr, int nrhs, double* X, const double* D, hipStream_t st);
+
+}  // namespace stiles

@@ -1,0 +1,74 @@
+// stiles_internal.h -- layouts shared by the host planner (analyze.cpp,
+// capi.cpp) and the device kernels (kernels.hip).  Not part of the public ABI.
+//
+// Tile store (CTSF, Section III-B): the permuted matrix is cut into T x T
+// tiles.  Band tile row m covers permuted rows [m*T, m*T+T) of the band part;
+// arrow tile row m >= ntb covers rows [n + (m-ntb)*T, ...) of the arrow (the
+// arrow keeps tile rows of its own).  Rows beyond the matrix are padding with
+// a unit diagonal.  Only tiles of the (tile-level) filled pattern of L are
+// stored, row by row, each T x T column-major; tile id t lives at t*T*T.
+//
+// Work is a DAG of tile tasks executed by a persistent kernel: workgroups take
+// tickets in a precomputed topological order and wait on per-task counters of
+// unfinished predecessors (the static schedule and progress table of
+// Algorithm 2, with counters instead of flags).
+#pragma once
+#include <stdint.h>
+
+namespace stiles {
+
+enum TaskType : int32_t {
+  TK_UPD = 1,    // C_t -= sum over pairs (X_p Y_p^T)            [Alg. 1 SYRK/GEMM]
+  TK_PART = 2,   // P_s  = sum over pairs (X_p Y_p^T)            [Alg. 3 partial T[ID]]
+  TK_TREE = 3,   // P_o = P_a + P_b, or C_t -= P_a (+ P_b)       [Alg. 3 GEADD tree]
+  TK_POTRF = 4,  // L_kk = chol(C_kk); Linv_k = L_kk^{-1}        [Alg. 1 POTRF]
+  TK_TRSM = 5,   // L_t = C_t Linv_k^T                           [Alg. 1 TRSM]
+  TK_FUPD = 8,   // solve, forward:  Y_m -= sum L_(m,j) Y_j
+  TK_FDIAG = 9,  // solve, forward:  Y_m  = Linv_m Y_m
+  TK_BUPD = 10,  // solve, backward: Z_m  = (first ? Y_m : Z_m) - sum L_(i,m)^T Z_i
+  TK_BDIAG = 11, // solve, backward: Z_m  = Linv_m^T (Z_m, or Y_m if no BUPD)
+};
+
+enum TaskFlag : int32_t {
+  TF_DIAG = 1 << 8,   // UPD target is a diagonal tile (lower half only)
+  TF_FIRST = 1 << 9,  // BUPD: first chunk reads Y_m; BDIAG: no BUPD, reads Y_m
+};
+
+// One task = 8 int32.
+//  w0 type | flags     w1 tile (target tile id / tile row / -1)
+//  w2 a                w3 b              w4 c
+//  w5 succ_lo          w6 succ_hi        w7 ndeps
+// UPD:  a,b = pair range          PART: a,b = pair range, c = out slot
+// TREE: a = slot, b = slot or -1, c = out slot or -1 (then subtract into tile)
+// POTRF: a = tile row k           TRSM: a = tile row k of the diagonal tile
+// FUPD/BUPD: w1 = tile row m, a,b = solve-pair range; FDIAG/BDIAG: w1 = m
+constexpr int TASK_WORDS = 8;
+
+// Device-side description of one matrix (or one solve) for the executor.
+struct ExecMat {
+  double* tiles;            // ntiles * T*T
+  double* linv;             // ntr * T*T   inverse diagonal tiles
+  float* shadow;            // ntiles * T*T FP32 copies of L tiles (mixed) or null
+  double* part;             // npart * T*T  tree partials
+  double* vy;               // solve: ntr * T * nrhs (forward result)
+  double* vz;               // solve: ntr * T * nrhs (backward result)
+  const int32_t* tasks;     // ntasks * TASK_WORDS
+  const int32_t* succ;      // successor lists
+  int32_t* remaining;       // per-task unfinished-predecessor counters
+  const int32_t* pairs;     // 2 ints per pair
+  unsigned long long* info; // first failing permuted column + 1, ~0ull if none
+  const int64_t* row_base;  // ntr: first permuted row of each tile row
+  int32_t ntasks;
+  int32_t ntr;
+  int32_t mixed;
+  int32_t pad;
+};
+
+// Launch control block (one per concurrent launch).
+struct ExecCtrl {
+  int32_t ticket;
+  int32_t exited;
+  int32_t pad[62];          // keep the next block on its own cache lines
+};
+
+}  // namespace stiles

@@ -1,0 +1,63 @@
+// symbolic.h -- host-side symbolic object (reordering, tile pattern, task
+// DAGs, schedules).  Built by analyze.cpp, consumed by capi.cpp.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/stiles.h"
+#include "stiles_internal.h"
+
+struct stiles_symbolic {
+  stiles_opts opts;
+  int64_t N = 0, n = 0, a = 0;
+  int32_t T = 64;
+  int32_t ordering_used = STILES_ORDER_NONE;
+  bool profile_input = false;
+
+  std::vector<int64_t> perm;   // permuted row i <- original row perm[i]
+  std::vector<int64_t> iperm;  // original row -> permuted row
+  std::vector<int64_t> f;      // element profile of P A P^T (first column per row)
+
+  // input value placement
+  std::vector<int64_t> in_rp;  // start of each row of the permuted envelope (N+1);
+                               // for profile input also the value layout
+  std::vector<int64_t> map;    // CSC input: value index -> element offset in the tile store
+
+  // tile rows
+  int32_t ntb = 0, nta = 0, ntr = 0;
+  std::vector<int64_t> row_base;  // ntr
+  std::vector<int32_t> row_cnt;   // real rows in each tile row (<= T)
+
+  // tile pattern of L: tiles of tile row m are ids [trow_ptr[m], trow_ptr[m+1]),
+  // ascending column; the diagonal tile is the last one of its row.
+  std::vector<int32_t> trow_ptr;
+  std::vector<int32_t> tcol;
+  std::vector<int32_t> trow;
+  int64_t ntiles = 0;
+
+  // factorization DAG (topologically sorted by the static schedule)
+  std::vector<int32_t> ftask;     // TASK_WORDS per task
+  std::vector<int32_t> fsucc;
+  std::vector<int32_t> fpairs;
+  std::vector<float> fest;        // scheduled start estimate (merging batches)
+  int32_t npart = 0;
+  int32_t tree_used = 0;
+  int64_t corner_acc = 0;
+
+  // solve DAG
+  std::vector<int32_t> stask;
+  std::vector<int32_t> ssucc;
+  std::vector<int32_t> spairs;
+
+  // statistics
+  int64_t nnzL = 0;
+  double flops_alg = 0.0;
+  double flops_exec = 0.0;
+};
+
+namespace stiles {
+// set by every entry point that rejects an argument (thread-local)
+void set_error_arg(int32_t idx);
+}
