@@ -153,6 +153,22 @@ stiles_status stiles_symbolic_perm(const stiles_symbolic* sym, int64_t* perm);
 void stiles_symbolic_destroy(stiles_symbolic* sym);
 
 /*
+ * Read-only view of the plan inside a symbolic object, for tests and tools
+ * (e.g. a host emulation of the task DAG).  `which`:
+ *   0 factorization tasks (int32, 8 per task: type|flags, tile, a, b, c,
+ *     successor begin, successor end, predecessor count), in schedule order
+ *   1 factorization successor lists (int32)   2 factorization tile pairs (int32, 2 per pair)
+ *   3 solve tasks   4 solve successor lists   5 solve pairs (tile, vector block)
+ *   6 tile-row pointers (int32, tile_rows + 1)  7 tile columns (int32, tiles)
+ *   8 first permuted row of each tile row (int64)  9 real rows per tile row (int32)
+ *   10 number of tree partial slots (int32, 1 element)
+ * With out == NULL, *count receives the number of elements; otherwise *count
+ * is the capacity of out (elements) and receives the number copied.
+ * EINVAL: unknown `which` (argument 2) or capacity too small (argument 4).
+ */
+stiles_status stiles_symbolic_export(const stiles_symbolic* sym, int32_t which, void* out, int64_t* count);
+
+/*
  * Device workspace bytes for one resident factor of `sym` in the given
  * precision, able to solve with up to nrhs_max right-hand sides at once.
  * The workspace holds the tile store of L (CTSF), the inverse diagonal tiles,
@@ -219,6 +235,23 @@ stiles_status stiles_logdet(stiles_factor* f, double* d_out, hipStream_t stream)
  * exactly the value layout of d_values).  d_L holds nnz_L doubles
  * (stiles_symbolic_info).  For tests and for callers that want L itself. */
 stiles_status stiles_factor_extract(stiles_factor* f, double* d_L, hipStream_t stream);
+
+/* Profiling hook: when enabled, the library records a pair of HIP events on
+ * the stream around every executor launch of this factor (which = 0: the
+ * factorization DAG kernel; which = 1: the solve DAG kernel).
+ * stiles_factor_kernel_ms waits for the last recorded pair and returns its
+ * elapsed time in milliseconds (ESTATE if timing is off or nothing recorded). */
+stiles_status stiles_factor_set_timing(stiles_factor* f, int32_t enable);
+stiles_status stiles_factor_kernel_ms(stiles_factor* f, int32_t which, float* ms);
+
+/* Profiling hook: per-task trace.  When d_factor_trace (d_solve_trace) is not
+ * NULL, every task of the factorization (solve) DAG writes four uint64 at
+ * index 4*task: the device wall clock (100 MHz) when a workgroup took its
+ * ticket, when its predecessors were complete, when it finished, and
+ * (workgroup << 32 | task type << 24 | ticket mod 2^24).  Buffers hold 32 bytes per task
+ * (stiles_symbolic_info: factor_tasks, solve_tasks); NULL switches it off. */
+stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_factor_trace, void* d_solve_trace,
+                                      hipStream_t stream);
 
 /* Upper bound on the workgroups a factorization launch uses (0 = fill the
  * GPU).  Lets several factorizations on different streams share the GPU. */

@@ -19,6 +19,8 @@ __all__ = [
     "stiles_factorize", "stiles_factorize_batch", "stiles_batch_workspace_size", "stiles_factor_info",
     "stiles_solve", "stiles_logdet", "stiles_factor_set_max_workgroups", "stiles_factor_release",
     "stiles_status_string", "stiles_last_error_arg", "factorize_batch", "stiles_factor_extract",
+    "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
+    "stiles_symbolic_export",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -42,6 +44,8 @@ EXPORTED = [
     "stiles_workspace_size", "stiles_workspace_init", "stiles_factorize", "stiles_batch_workspace_size",
     "stiles_factorize_batch", "stiles_factor_info", "stiles_solve", "stiles_logdet",
     "stiles_factor_set_max_workgroups", "stiles_factor_release", "stiles_factor_extract",
+    "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
+    "stiles_symbolic_export",
 ]
 
 
@@ -103,6 +107,10 @@ def load_library(path=LIB_PATH):
         "stiles_factor_set_max_workgroups": (_i32, [_vp, _i32]),
         "stiles_factor_release": (None, [_vp]),
         "stiles_factor_extract": (_i32, [_vp, _vp, _vp]),
+        "stiles_factor_set_timing": (_i32, [_vp, _i32]),
+        "stiles_factor_kernel_ms": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_float)]),
+        "stiles_factor_set_trace": (_i32, [_vp, _vp, _vp, _vp]),
+        "stiles_symbolic_export": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -186,6 +194,21 @@ def stiles_symbolic_perm(sym, N):
     return p
 
 
+EXPORT_KINDS = {"ftask": (0, np.int32), "fsucc": (1, np.int32), "fpairs": (2, np.int32), "stask": (3, np.int32),
+                "ssucc": (4, np.int32), "spairs": (5, np.int32), "trow_ptr": (6, np.int32), "tcol": (7, np.int32),
+                "row_base": (8, np.int64), "row_cnt": (9, np.int32), "npart": (10, np.int32)}
+
+
+def stiles_symbolic_export(sym, kind):
+    which, dt = EXPORT_KINDS[kind]
+    lib = load_library()
+    n = _i64()
+    _check(lib.stiles_symbolic_export(sym, which, None, ctypes.byref(n)), "stiles_symbolic_export")
+    out = np.empty(max(n.value, 1), dtype=dt)
+    _check(lib.stiles_symbolic_export(sym, which, _ptr(out), ctypes.byref(n)), "stiles_symbolic_export")
+    return out[:n.value]
+
+
 def stiles_symbolic_destroy(sym):
     load_library().stiles_symbolic_destroy(sym)
 
@@ -247,6 +270,21 @@ def stiles_factor_release(fac):
 
 def stiles_factor_extract(fac, d_L, stream=None):
     _check(load_library().stiles_factor_extract(fac, _ptr(d_L), _stream(stream)), "stiles_factor_extract")
+
+
+def stiles_factor_set_timing(fac, enable):
+    _check(load_library().stiles_factor_set_timing(fac, 1 if enable else 0), "stiles_factor_set_timing")
+
+
+def stiles_factor_kernel_ms(fac, which):
+    v = ctypes.c_float()
+    _check(load_library().stiles_factor_kernel_ms(fac, which, ctypes.byref(v)), "stiles_factor_kernel_ms")
+    return v.value
+
+
+def stiles_factor_set_trace(fac, d_factor_trace, d_solve_trace, stream=None):
+    _check(load_library().stiles_factor_set_trace(fac, _ptr(d_factor_trace), _ptr(d_solve_trace), _stream(stream)),
+           "stiles_factor_set_trace")
 
 
 def stiles_status_string(st):

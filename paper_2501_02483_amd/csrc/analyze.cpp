@@ -535,8 +535,14 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
           start = nb;
         }
       }
-      for (size_t lo = start; lo < pr.size(); lo += chunk) {
-        size_t hi = std::min(pr.size(), lo + chunk);
+      // chunks of `chunk` products in ascending column order; the product
+      // with column k-1 (available last, on the critical path) is fused into
+      // the task that finalizes the tile (POTRF or TRSM), so that everything
+      // before it runs ahead (lookahead) and the chain has one hop less
+      const bool fuse_last = pr.size() > start && pj.back() == k - 1;
+      const size_t body_end = fuse_last ? pr.size() - 1 : pr.size();
+      for (size_t lo = start; lo < body_end; lo += chunk) {
+        size_t hi = std::min(body_end, lo + chunk);
         int32_t p0 = (int32_t)(pairs.size() / 2);
         for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
         int32_t p1 = (int32_t)(pairs.size() / 2);
@@ -547,18 +553,27 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
         tb.dep(t, last);
         last = t;
       }
+      int32_t f0 = (int32_t)(pairs.size() / 2), f1 = f0;
+      if (fuse_last) {
+        pairs.push_back(pr.back().first);
+        pairs.push_back(pr.back().second);
+        f1 = f0 + 1;
+        fexec += 2.0 * T3;
+      }
       if (diag) {
-        int t = tb.add(TK_POTRF, tgt, k, 0, 0, T == 64 ? 10.f : 4.f);
+        int t = tb.add(TK_POTRF, tgt, k, f0, f1, (T == 64 ? 10.f : 4.f) + (f1 > f0 ? 1.5f * (float)t3 : 0.f));
         fexec += 2.0 * T3 / 3.0;
         tb.dep(t, last);
+        if (fuse_last) { tb.dep(t, final_task[pr.back().first]); tb.dep(t, final_task[pr.back().second]); }
         potrf_task = t;
         final_task[tgt] = t;
       } else {
         // the diagonal tile (k,k) comes first in the column list
-        int t = tb.add(TK_TRSM, tgt, k, 0, 0, 0.5f + 1.8f * (float)t3);
+        int t = tb.add(TK_TRSM, tgt, k, f0, f1, 0.5f + 1.8f * (float)t3 * (f1 > f0 ? 2.f : 1.f));
         fexec += 2.0 * T3;
         tb.dep(t, potrf_task);
         tb.dep(t, last);
+        if (fuse_last) { tb.dep(t, final_task[pr.back().first]); tb.dep(t, final_task[pr.back().second]); }
         final_task[tgt] = t;
       }
     }
@@ -577,8 +592,11 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   for (int32_t m = 0; m < ntr; m++) {
     int32_t last = -1;
     const int32_t rb = s.trow_ptr[m], re = s.trow_ptr[m + 1] - 1;
-    for (int32_t lo = rb; lo < re; lo += schunk) {
-      int32_t hi = std::min(re, lo + schunk);
+    // forward: the product with block m-1 (ready last) is fused into FDIAG
+    const bool fuse = re > rb && s.tcol[re - 1] == m - 1;
+    const int32_t body_end = fuse ? re - 1 : re;
+    for (int32_t lo = rb; lo < body_end; lo += schunk) {
+      int32_t hi = std::min(body_end, lo + schunk);
       int32_t p0 = (int32_t)(sp.size() / 2);
       for (int32_t t = lo; t < hi; t++) { sp.push_back(t); sp.push_back(s.tcol[t]); }
       int32_t p1 = (int32_t)(sp.size() / 2);
@@ -587,19 +605,25 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
       sb.dep(t, last);
       last = t;
     }
-    int t = sb.add(TK_FDIAG, m, 0, 0, 0, 0.6f);
+    int32_t f0 = (int32_t)(sp.size() / 2), f1 = f0;
+    if (fuse) { sp.push_back(re - 1); sp.push_back(m - 1); f1 = f0 + 1; }
+    int t = sb.add(TK_FDIAG, m, f0, f1, 0, 0.6f);
     sb.dep(t, last);
+    if (fuse) sb.dep(t, fdiag[m - 1]);
     fdiag[m] = t;
   }
   for (int32_t m = ntr - 1; m >= 0; m--) {
-    // tiles (i, m), i > m, in descending i (Z_i become final in that order)
+    // tiles (i, m), i > m, in descending i (Z_i become final in that order);
+    // the last one (i = m + 1 when present) is fused into BDIAG
     std::vector<std::pair<int32_t, int32_t>> below;
     for (auto& it : ctiles[m]) if (it.first > m) below.push_back(it);
     std::reverse(below.begin(), below.end());
+    const bool fuse = !below.empty() && below.back().first == m + 1;
+    const size_t body_end = fuse ? below.size() - 1 : below.size();
     int32_t last = -1;
     bool first = true;
-    for (size_t lo = 0; lo < below.size(); lo += schunk) {
-      size_t hi = std::min(below.size(), lo + schunk);
+    for (size_t lo = 0; lo < body_end; lo += schunk) {
+      size_t hi = std::min(body_end, lo + schunk);
       int32_t p0 = (int32_t)(sp.size() / 2);
       for (size_t q = lo; q < hi; q++) { sp.push_back(below[q].second); sp.push_back(below[q].first); }
       int32_t p1 = (int32_t)(sp.size() / 2);
@@ -610,9 +634,12 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
       last = t;
       first = false;
     }
-    int t = sb.add(TK_BDIAG | (below.empty() ? TF_FIRST : 0), m, 0, 0, 0, 0.6f);
+    int32_t f0 = (int32_t)(sp.size() / 2), f1 = f0;
+    if (fuse) { sp.push_back(below.back().second); sp.push_back(below.back().first); f1 = f0 + 1; }
+    int t = sb.add(TK_BDIAG | (first ? TF_FIRST : 0), m, f0, f1, 0, 0.6f);
     sb.dep(t, last);
     sb.dep(t, fdiag[m]);
+    if (fuse) sb.dep(t, bdiag[m + 1]);
     bdiag[m] = t;
   }
   s.spairs = sp;
@@ -649,6 +676,35 @@ extern "C" stiles_status stiles_symbolic_perm(const stiles_symbolic* s, int64_t*
   if (!s) { g_err_arg = 1; return STILES_EINVAL; }
   if (!perm) { g_err_arg = 2; return STILES_EINVAL; }
   std::memcpy(perm, s->perm.data(), sizeof(int64_t) * s->N);
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_symbolic_export(const stiles_symbolic* s, int32_t which, void* out, int64_t* count) {
+  g_err_arg = 0;
+  if (!s) { g_err_arg = 1; return STILES_EINVAL; }
+  if (!count) { g_err_arg = 4; return STILES_EINVAL; }
+  const void* src = nullptr;
+  int64_t n = 0;
+  size_t esz = 4;
+  int32_t npart = s->npart;
+  switch (which) {
+    case 0: src = s->ftask.data(); n = (int64_t)s->ftask.size(); break;
+    case 1: src = s->fsucc.data(); n = (int64_t)s->fsucc.size(); break;
+    case 2: src = s->fpairs.data(); n = (int64_t)s->fpairs.size(); break;
+    case 3: src = s->stask.data(); n = (int64_t)s->stask.size(); break;
+    case 4: src = s->ssucc.data(); n = (int64_t)s->ssucc.size(); break;
+    case 5: src = s->spairs.data(); n = (int64_t)s->spairs.size(); break;
+    case 6: src = s->trow_ptr.data(); n = (int64_t)s->trow_ptr.size(); break;
+    case 7: src = s->tcol.data(); n = (int64_t)s->tcol.size(); break;
+    case 8: src = s->row_base.data(); n = (int64_t)s->row_base.size(); esz = 8; break;
+    case 9: src = s->row_cnt.data(); n = (int64_t)s->row_cnt.size(); break;
+    case 10: src = &npart; n = 1; break;
+    default: g_err_arg = 2; return STILES_EINVAL;
+  }
+  if (!out) { *count = n; return STILES_OK; }
+  if (*count < n) { g_err_arg = 4; return STILES_EINVAL; }
+  if (n) std::memcpy(out, src, (size_t)n * esz);
+  *count = n;
   return STILES_OK;
 }
 

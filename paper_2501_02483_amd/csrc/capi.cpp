@@ -155,6 +155,12 @@ struct stiles_factor {
   int32_t max_wg = 0;
   int32_t state = 0;   // 0 unknown, 1 factored ok, 2 failed, -1 not factored
   double anorm = -1.0; // inf-norm of A (mixed mode), computed lazily
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // timing: factor pair, solve pair
+  bool timing = false;
+  ~stiles_factor() {
+    for (auto& e : ev)
+      if (e) hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -311,8 +317,10 @@ extern "C" stiles_status stiles_factorize(stiles_factor* f, const double* d_valu
   stiles_status r = scatter_values(f, d_values, st);
   if (r != STILES_OK) return r;
   const int32_t nt = f->mf.ntasks;
+  if (f->timing) hipEventRecord(f->ev[0], st);
   hipError_t e = launch_exec(f->sym->T, at<ExecMat>(f, f->L.mat_f), nullptr, nt, at<ExecCtrl>(f, f->L.ctrl_f), 0,
                              nwg_for(f, nt), st);
+  if (f->timing) hipEventRecord(f->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   f->state = 0;
   f->anorm = -1.0;
@@ -339,9 +347,11 @@ static stiles_status solve_sweep(stiles_factor* f, const double* d_src, int64_t 
   const Layout& L = f->L;
   hipError_t e = launch_pack(s.T, d_src, ldsrc, nrhs, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
                              at<int32_t>(f, L.row_cnt), s.ntr, at<double>(f, L.vy), st);
+  if (e == hipSuccess && f->timing) hipEventRecord(f->ev[2], st);
   if (e == hipSuccess)
     e = launch_exec(s.T, at<ExecMat>(f, L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, L.ctrl_s), nrhs,
                     nwg_for(f, f->ms.ntasks), st);
+  if (e == hipSuccess && f->timing) hipEventRecord(f->ev[3], st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
 
@@ -540,6 +550,40 @@ extern "C" stiles_status stiles_factorize_batch(int32_t count, stiles_factor* co
                   (int32_t)ev.size(), reinterpret_cast<ExecCtrl*>(b + o_ctrl), 0, std::min<int>(cap, (int)ev.size()), st);
   if (e != hipSuccess) return STILES_EDEVICE;
   for (int32_t i = 0; i < count; i++) { factors[i]->state = 0; factors[i]->anorm = -1.0; }
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_factor_trace, void* d_solve_trace,
+                                                 hipStream_t st) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  f->mf.trace = static_cast<unsigned long long*>(d_factor_trace);
+  f->ms.trace = static_cast<unsigned long long*>(d_solve_trace);
+  hipError_t e = hipMemcpyAsync(f->ws + f->L.mat_f, &f->mf, sizeof(ExecMat), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(f->ws + f->L.mat_s, &f->ms, sizeof(ExecMat), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+extern "C" stiles_status stiles_factor_set_timing(stiles_factor* f, int32_t enable) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (enable)
+    for (auto& e : f->ev)
+      if (!e && hipEventCreate(&e) != hipSuccess) return STILES_EDEVICE;
+  f->timing = enable != 0;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_factor_kernel_ms(stiles_factor* f, int32_t which, float* ms) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (which != 0 && which != 1) { set_error_arg(2); return STILES_EINVAL; }
+  if (!ms) { set_error_arg(3); return STILES_EINVAL; }
+  if (!f->timing) return STILES_ESTATE;
+  hipEvent_t a = f->ev[2 * which], b = f->ev[2 * which + 1];
+  if (hipEventSynchronize(b) != hipSuccess) return STILES_EDEVICE;
+  if (hipEventElapsedTime(ms, a, b) != hipSuccess) return STILES_ESTATE;
   return STILES_OK;
 }
 

@@ -50,11 +50,12 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 // c0 + 16 i + (lane >> 4) + 4 r (FP64 MFMA output layout on gfx950: lane l,
 // register r holds D[(l >> 4) + 4 r][l & 15]).  The A operand is taken from
 // Y (C columns), the B operand from X (C rows), so that the 16 lanes of one
-// row group touch 16 consecutive rows of a column-major tile.
+// row group touch 16 consecutive rows of a column-major tile.  Operands are
+// read from LDS, where a whole tile pair has been staged.
 
 template <int T>
-__device__ __forceinline__ void mma_f64(v4d (&acc)[T / 32][T / 32], const double* __restrict__ X,
-                                        const double* __restrict__ Y, int r0, int c0, int lane) {
+__device__ __forceinline__ void mma_f64(v4d (&acc)[T / 32][T / 32], const double* X, const double* Y, int r0, int c0,
+                                        int lane) {
   constexpr int NB = T / 32;
   const double* xp = X + r0 + (lane & 15) + (lane >> 4) * T;
   const double* yp = Y + c0 + (lane & 15) + (lane >> 4) * T;
@@ -76,8 +77,8 @@ __device__ __forceinline__ void mma_f64(v4d (&acc)[T / 32][T / 32], const double
 // FP32 variant (mixed mode); FP32 MFMA output layout: lane l, register r holds
 // D[4 (l >> 4) + r][l & 15], so acc[i][j][r] covers column c0 + 16 i + 4 (lane >> 4) + r.
 template <int T>
-__device__ __forceinline__ void mma_f32(v4f (&acc)[T / 32][T / 32], const float* __restrict__ X,
-                                        const float* __restrict__ Y, int r0, int c0, int lane) {
+__device__ __forceinline__ void mma_f32(v4f (&acc)[T / 32][T / 32], const float* X, const float* Y, int r0, int c0,
+                                        int lane) {
   constexpr int NB = T / 32;
   const float* xp = X + r0 + (lane & 15) + (lane >> 4) * T;
   const float* yp = Y + c0 + (lane & 15) + (lane >> 4) * T;
@@ -96,12 +97,33 @@ __device__ __forceinline__ void mma_f32(v4f (&acc)[T / 32][T / 32], const float*
   }
 }
 
+// Whole-tile staging through registers: every thread moves its share of a
+// T x T tile with 16-byte loads, so a tile arrives after one memory latency
+// and the next pair can be in flight while the current one is multiplied.
+template <int T, typename E>
+struct TileStage {
+  typedef E vec __attribute__((ext_vector_type(16 / sizeof(E))));
+  static constexpr int EPV = 16 / sizeof(E);
+  static constexpr int NV = T * T / NT / EPV;
+  vec r[NV];
+  __device__ __forceinline__ void load(const E* __restrict__ g) {
+    const vec* v = reinterpret_cast<const vec*>(g);
+#pragma unroll
+    for (int q = 0; q < NV; q++) r[q] = v[threadIdx.x + q * NT];
+  }
+  __device__ __forceinline__ void store(E* l) const {
+    vec* v = reinterpret_cast<vec*>(l);
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[threadIdx.x + q * NT] = r[q];
+  }
+};
+
 // ------------------------------------------------------------ task bodies
 
 // UPD / PART: acc = sum_p X_p Y_p^T over a list of tile pairs.
-// mode 0: C_t -= acc (UPD), mode 1: P = acc (PART).
+// mode 0: C_t -= acc (UPD), mode 1: P = acc (PART).  LX, LY: LDS tiles.
 template <int T>
-__device__ void task_update(const ExecMat& M, const int32_t* w, int mode) {
+__device__ __attribute__((noinline)) void task_update(const ExecMat& M, const int32_t* w, int mode, double* LX, double* LY) {
   constexpr int TT = T * T, W = T / 2, NB = T / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -111,19 +133,19 @@ __device__ void task_update(const ExecMat& M, const int32_t* w, int mode) {
   const int p0 = w[2], p1 = w[3];
   const bool mixed = M.mixed && mode == 0;
   double* out = mode == 0 ? M.tiles + (int64_t)w[1] * TT : M.part + (int64_t)w[4] * TT;
-  if (!active) {
-    if (mode == 1) {   // keep the partial fully defined
+  // the target's current value is needed only at the end: fetch it now
+  double cin[NB][NB][4];
+  if (mode == 0 && active) {
 #pragma unroll
-      for (int i = 0; i < NB; i++)
+    for (int i = 0; i < NB; i++)
 #pragma unroll
-        for (int j = 0; j < NB; j++)
+      for (int j = 0; j < NB; j++)
 #pragma unroll
-          for (int r = 0; r < 4; r++) {
-            int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
-            out[row + col * T] = 0.0;
-          }
-    }
-    return;
+        for (int r = 0; r < 4; r++) {
+          const int row = r0 + 16 * j + (lane & 15);
+          const int col = c0 + 16 * i + (mixed ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
+          cin[i][j][r] = out[row + col * T];
+        }
   }
   if (!mixed) {
     v4d acc[NB][NB];
@@ -131,77 +153,145 @@ __device__ void task_update(const ExecMat& M, const int32_t* w, int mode) {
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    TileStage<T, double> sx, sy;
+    sx.load(M.tiles + (int64_t)M.pairs[2 * p0] * TT);
+    sy.load(M.tiles + (int64_t)M.pairs[2 * p0 + 1] * TT);
     for (int p = p0; p < p1; p++) {
-      const double* X = M.tiles + (int64_t)M.pairs[2 * p] * TT;
-      const double* Y = M.tiles + (int64_t)M.pairs[2 * p + 1] * TT;
-      mma_f64<T>(acc, X, Y, r0, c0, lane);
+      __syncthreads();
+      sx.store(LX);
+      sy.store(LY);
+      __syncthreads();
+      if (p + 1 < p1) {
+        sx.load(M.tiles + (int64_t)M.pairs[2 * p + 2] * TT);
+        sy.load(M.tiles + (int64_t)M.pairs[2 * p + 3] * TT);
+      }
+      if (active) mma_f64<T>(acc, LX, LY, r0, c0, lane);
     }
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < NB; i++)
+      for (int i = 0; i < NB; i++)
 #pragma unroll
-      for (int j = 0; j < NB; j++)
+        for (int j = 0; j < NB; j++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-          int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
-          if (mode == 0) {
-            if (!diag || row >= col) out[row + col * T] -= acc[i][j][r];
-          } else {
-            out[row + col * T] = acc[i][j][r];
+          for (int r = 0; r < 4; r++) {
+            const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+            if (mode == 0) {
+              if (!diag || row >= col) out[row + col * T] = cin[i][j][r] - acc[i][j][r];
+            } else {
+              out[row + col * T] = acc[i][j][r];
+            }
           }
-        }
+    } else if (mode == 1) {   // keep the partial fully defined
+#pragma unroll
+      for (int i = 0; i < NB; i++)
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+            out[row + col * T] = 0.0;
+          }
+    }
   } else {
+    float* FX = reinterpret_cast<float*>(LX);
+    float* FY = reinterpret_cast<float*>(LY);
     v4f acc[NB][NB];
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    TileStage<T, float> sx, sy;
+    sx.load(M.shadow + (int64_t)M.pairs[2 * p0] * TT);
+    sy.load(M.shadow + (int64_t)M.pairs[2 * p0 + 1] * TT);
     for (int p = p0; p < p1; p++) {
-      const float* X = M.shadow + (int64_t)M.pairs[2 * p] * TT;
-      const float* Y = M.shadow + (int64_t)M.pairs[2 * p + 1] * TT;
-      mma_f32<T>(acc, X, Y, r0, c0, lane);
+      __syncthreads();
+      sx.store(FX);
+      sy.store(FY);
+      __syncthreads();
+      if (p + 1 < p1) {
+        sx.load(M.shadow + (int64_t)M.pairs[2 * p + 2] * TT);
+        sy.load(M.shadow + (int64_t)M.pairs[2 * p + 3] * TT);
+      }
+      if (active) mma_f32<T>(acc, FX, FY, r0, c0, lane);
     }
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < NB; i++)
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + 4 * (lane >> 4) + r;
+            if (!diag || row >= col) out[row + col * T] = cin[i][j][r] - (double)acc[i][j][r];
+          }
+    }
+  }
+}
+
+// TREE: P_c = P_a + P_b, or C_t -= P_a (+ P_b) at the root (Alg. 3 GEADD).
+template <int T>
+__device__ __attribute__((noinline)) void task_tree(const ExecMat& M, const int32_t* w) {
+  constexpr int TT = T * T;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* pa = reinterpret_cast<const d2*>(M.part + (int64_t)w[2] * TT);
+  const d2* pb = w[3] >= 0 ? reinterpret_cast<const d2*>(M.part + (int64_t)w[3] * TT) : nullptr;
+  d2* dst = w[4] >= 0 ? reinterpret_cast<d2*>(M.part + (int64_t)w[4] * TT)
+                      : reinterpret_cast<d2*>(M.tiles + (int64_t)w[1] * TT);
+  const bool apply = w[4] < 0;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < TT / 2; e += NT) {
+    const d2 s = pb ? pa[e] + pb[e] : pa[e];
+    dst[e] = apply ? dst[e] - s : s;
+  }
+}
+
+// TRSM: L_t = (C_t - [X Y^T]) Linv_k^T as staged tile products; FP32 copy
+// in mixed mode.  The optional fused product is the update with column k-1.
+template <int T>
+__device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
+  constexpr int TT = T * T, W = T / 2, NB = T / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
+  double* C = M.tiles + (int64_t)w[1] * TT;
+  const bool fused = w[4] > w[3];
+  TileStage<T, double> sx, sy;
+  v4d acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; i++)
+#pragma unroll
+    for (int j = 0; j < NB; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  if (fused) {
+    sx.load(M.tiles + (int64_t)M.pairs[2 * w[3]] * TT);
+    sy.load(M.tiles + (int64_t)M.pairs[2 * w[3] + 1] * TT);
+    sx.store(LX);
+    sy.store(LY);
+    sx.load(C);
+    sy.load(M.linv + (int64_t)w[2] * TT);
+    __syncthreads();
+    mma_f64<T>(acc, LX, LY, r0, c0, lane);   // X Y^T
+    __syncthreads();
+    sx.store(LX);
+    sy.store(LY);
+    __syncthreads();
+    // C -= X Y^T in LDS, each wave on its own quarter
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + 4 * (lane >> 4) + r;
-          if (!diag || row >= col) out[row + col * T] -= (double)acc[i][j][r];
+          const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+          LX[row + col * T] -= acc[i][j][r];
+          acc[i][j][r] = 0.0;
         }
-  }
-}
-
-// TREE: P_c = P_a + P_b, or C_t -= P_a (+ P_b) at the root (Alg. 3 GEADD).
-template <int T>
-__device__ void task_tree(const ExecMat& M, const int32_t* w) {
-  constexpr int TT = T * T;
-  const double* pa = M.part + (int64_t)w[2] * TT;
-  const double* pb = w[3] >= 0 ? M.part + (int64_t)w[3] * TT : nullptr;
-  if (w[4] >= 0) {
-    double* po = M.part + (int64_t)w[4] * TT;
-    for (int e = threadIdx.x; e < TT; e += NT) po[e] = pa[e] + (pb ? pb[e] : 0.0);
   } else {
-    double* c = M.tiles + (int64_t)w[1] * TT;
-    for (int e = threadIdx.x; e < TT; e += NT) c[e] -= (pb ? pa[e] + pb[e] : pa[e]);
+    sx.load(C);
+    sy.load(M.linv + (int64_t)w[2] * TT);
+    sx.store(LX);
+    sy.store(LY);
   }
-}
-
-// TRSM: L_t = C_t Linv_k^T as a tile product; FP32 copy in mixed mode.
-template <int T>
-__device__ void task_trsm(const ExecMat& M, const int32_t* w) {
-  constexpr int TT = T * T, W = T / 2, NB = T / 32;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
-  double* C = M.tiles + (int64_t)w[1] * TT;
-  const double* Li = M.linv + (int64_t)w[2] * TT;
-  v4d acc[NB][NB];
-#pragma unroll
-  for (int i = 0; i < NB; i++)
-#pragma unroll
-    for (int j = 0; j < NB; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  mma_f64<T>(acc, C, Li, r0, c0, lane);
-  __syncthreads();   // every wave has read C before it is overwritten
+  __syncthreads();
+  mma_f64<T>(acc, LX, LY, r0, c0, lane);
   float* S = M.mixed ? M.shadow + (int64_t)w[1] * TT : nullptr;
 #pragma unroll
   for (int i = 0; i < NB; i++)
@@ -209,63 +299,198 @@ __device__ void task_trsm(const ExecMat& M, const int32_t* w) {
     for (int j = 0; j < NB; j++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+        const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
         C[row + col * T] = acc[i][j][r];
         if (S) S[row + col * T] = (float)acc[i][j][r];
       }
 }
 
-// POTRF + TRTRI of one diagonal tile in LDS.
-// Column-by-column right-looking Cholesky; then the inverse of the lower
-// factor by forward substitution, one column per group of NT/T threads.
+// ------------------------------------------------- diagonal tile: POTRF + TRTRI
+// Blocked right-looking Cholesky of one T x T tile held in LDS, with 16-wide
+// panels.  For each panel the 16 x 16 diagonal block is factored and inverted
+// in the registers of wave 0 (lane i holds row i; values are broadcast with
+// readlane), the panel below is solved against the inverse block and the
+// trailing matrix is updated, both as 16 x 16 x 16 MFMA products.  The
+// inverse of the whole factor is then assembled block by block:
+//   X_ii = D_i^{-1},  X_ib = -D_i^{-1} sum_{b <= q < i} L_iq X_qb.
+
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// 16 x 16 x 16 product on one wave: acc += A B with A(i, l) = a(i, l), B(l, j)
+// = b(l, j); a and b are LDS column-major with leading dimension `lda`/`ldb`.
+// Output layout: acc[r] = D[(lane >> 4) + 4 r][lane & 15] ... but A is taken
+// from the B-side for coalesced rows, see mma_f64; here the mapping is:
+// D(i, j) = sum_l A(i, l) B(l, j), lane l, reg r holds D[(l>>4)+4r][l&15].
+__device__ __forceinline__ v4d mma16(v4d acc, const double* A, int lda, const double* B, int ldb, int lane) {
+#pragma unroll
+  for (int k = 0; k < 16; k += 4) {
+    const double av = A[(lane & 15) + (k + (lane >> 4)) * lda];   // A(i = lane&15, l = k + lane>>4)
+    const double bv = B[(k + (lane >> 4)) + (lane & 15) * ldb];   // B(l = k + lane>>4, j = lane&15)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 template <int T>
-__device__ void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv) {
-  constexpr int TT = T * T, G = NT / T;
-  const int tid = threadIdx.x;
+__device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv) {
+  constexpr int TT = T * T, NBK = T / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* C = M.tiles + (int64_t)w[1] * TT;
   const int k = w[2];
-  for (int e = tid; e < TT; e += NT) {
-    S[e] = C[e];
-    Xi[e] = 0.0;
+  {
+    TileStage<T, double> st;
+    st.load(C);
+    st.store(S);
+    if (w[4] > w[3]) {
+      // fused update with column k-1: C_kk -= X X^T (X = L_(k,k-1))
+      constexpr int W = T / 2, NB = T / 32;
+      const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
+      st.load(M.tiles + (int64_t)M.pairs[2 * w[3]] * TT);
+      st.store(Xi);
+      __syncthreads();
+      v4d acc[NB][NB];
+#pragma unroll
+      for (int i = 0; i < NB; i++)
+#pragma unroll
+        for (int j = 0; j < NB; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      mma_f64<T>(acc, Xi, Xi, r0, c0, lane);
+#pragma unroll
+      for (int i = 0; i < NB; i++)
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+            S[row + col * T] -= acc[i][j][r];
+          }
+      __syncthreads();
+    }
   }
+  for (int e = tid; e < TT; e += NT) Xi[e] = 0.0;
   __syncthreads();
   int fail = -1;
-  for (int j = 0; j < T; j++) {
-    const double d = S[j + j * T];
-    const double r = rsqrt_nr(d);
-    if (!(d > 0.0) && fail < 0) fail = j;
-    if (tid == 0) rinv[j] = r;
-    if (tid > j && tid < T) S[tid + j * T] *= r;
-    __syncthreads();
-    if (tid == 0) S[j + j * T] = d * r;
-    const int m = T - j - 1;
-    for (int e = tid; e < m * m; e += NT) {
-      const int i = j + 1 + e % m, c = j + 1 + e / m;
-      if (c <= i) S[i + c * T] -= S[i + j * T] * S[c + j * T];
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
-  // inverse: column c by the G threads of one group, rows in sequence
-  {
-    const int c = tid / G, q = tid % G;
-    if (c < T) {
-      if (q == 0) Xi[c + c * T] = rinv[c];
-      for (int i = c + 1; i < T; i++) {
-        double s = 0.0;
-        for (int kk = c + q; kk < i; kk += G) s += S[i + kk * T] * Xi[kk + c * T];
+#pragma unroll 1
+  for (int b = 0; b < NBK; b++) {
+    const int c0 = 16 * b;
+    if (tid < 64) {
+      // ---- factor and invert the diagonal block in registers (wave 0)
+      double r[16], piv[16];
 #pragma unroll
-        for (int o = 1; o < G; o <<= 1) s += __shfl_xor(s, o, G);
-        const double x = -s * rinv[i];
-        if (q == 0) Xi[i + c * T] = x;
-        // the group's lanes live in one wave; LDS accesses of a wave complete
-        // in order, so only the compiler must not move the next reads up
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_wave_barrier();
+      for (int q = 0; q < 16; q++) r[q] = lane < 16 ? S[(c0 + lane) + (c0 + q) * T] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        const double d = bcast(r[j], j);
+        const double rs = rsqrt_nr(d);
+        if (!(d > 0.0) && fail < 0) fail = c0 + j;
+        piv[j] = rs;
+        r[j] = lane == j ? d * rs : (lane > j ? r[j] * rs : 0.0);
+#pragma unroll
+        for (int q = j + 1; q < 16; q++) r[q] = fma(-r[j], bcast(r[j], q), r[q]);
+      }
+      double x[16];   // column `lane` of the inverse block
+#pragma unroll
+      for (int i = 0; i < 16; i++) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < i; q++) s = fma(bcast(r[q], i), x[q], s);
+        x[i] = lane == i ? piv[i] : (lane < i ? -piv[i] * s : 0.0);
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+          if (q <= lane) S[(c0 + lane) + (c0 + q) * T] = r[q];
+          if (q >= lane) Xi[(c0 + q) + (c0 + lane) * T] = x[q];
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) rinv[c0 + j] = piv[j];
       }
     }
+    __syncthreads();
+    if (b + 1 < NBK) {
+      // ---- panel: L(R, c0:c0+16) = A(R, c0:c0+16) D^{-T}, R = rows below (MFMA)
+      //      one 16-row block per wave
+      const int nrb = NBK - 1 - b;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      const int rb = c0 + 16 + 16 * wave;
+      if (wave < nrb) {
+        // D^{-T}(l, j) = Dinv(j, l): B(l, j) at Xi[(c0 + j) + (c0 + l) * T] -> ldb swap
+        const double* A = S + rb + c0 * T;
+#pragma unroll
+        for (int kq = 0; kq < 16; kq += 4) {
+          const double av = A[(lane & 15) + (kq + (lane >> 4)) * T];
+          const double bv = Xi[(c0 + (lane & 15)) + (c0 + kq + (lane >> 4)) * T];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+      }
+      __syncthreads();
+      if (wave < nrb) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) S[(rb + (lane >> 4) + 4 * q) + (c0 + (lane & 15)) * T] = acc[q];
+      }
+      __syncthreads();
+      // ---- trailing update A22 -= P P^T over lower 16 x 16 blocks (MFMA)
+      const int nb2 = nrb * (nrb + 1) / 2;
+      for (int q = wave; q < nb2; q += NT / 64) {
+        int bi = 0, rem = q;
+        while (rem > bi) { rem -= bi + 1; bi++; }
+        const int bj = rem;   // bj <= bi
+        const int gi = c0 + 16 + 16 * bi, gj = c0 + 16 + 16 * bj;
+        v4d u = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kq = 0; kq < 16; kq += 4) {
+          const double av = S[(gi + (lane & 15)) + (c0 + kq + (lane >> 4)) * T];   // P(gi + i, l)
+          const double bv = S[(gj + (lane & 15)) + (c0 + kq + (lane >> 4)) * T];   // P(gj + j, l)
+          u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) S[(gi + (lane >> 4) + 4 * rr) + (gj + (lane & 15)) * T] -= u[rr];
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
+  if (tid == 0 && fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
+  // ---- off-diagonal blocks of the inverse, by block distance d = i - b
+#pragma unroll 1
+  for (int d = 1; d < NBK; d++) {
+    const int nblk = NBK - d;
+    v4d u = v4d{0.0, 0.0, 0.0, 0.0};
+    const int b = wave, i = wave + d;
+    if (wave < nblk) {
+      // U = sum_{q=b}^{i-1} L_iq X_qb
+      for (int q = b; q < i; q++) {
+#pragma unroll
+        for (int kq = 0; kq < 16; kq += 4) {
+          const double av = S[(16 * i + (lane & 15)) + (16 * q + kq + (lane >> 4)) * T];   // L_iq(r, l)
+          const double bv = Xi[(16 * q + kq + (lane >> 4)) + (16 * b + (lane & 15)) * T]; // X_qb(l, c)
+          u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
+        }
+      }
+    }
+    // stash U in the (unused) upper triangle of S at block (b, i), transposed-free copy
+    if (wave < nblk) {
+#pragma unroll
+      for (int rr = 0; rr < 4; rr++) S[(16 * b + (lane >> 4) + 4 * rr) + (16 * i + (lane & 15)) * T] = u[rr];
+    }
+    __syncthreads();
+    if (wave < nblk) {
+      v4d xv = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kq = 0; kq < 16; kq += 4) {
+        const double av = Xi[(16 * i + (lane & 15)) + (16 * i + kq + (lane >> 4)) * T];  // Dinv_i(r, l)
+        const double bv = S[(16 * b + kq + (lane >> 4)) + (16 * i + (lane & 15)) * T];   // U(l, c)
+        xv = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, xv, 0, 0, 0);
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; rr++) Xi[(16 * i + (lane >> 4) + 4 * rr) + (16 * b + (lane & 15)) * T] = -xv[rr];
+    }
+    __syncthreads();
+  }
   double* Li = M.linv + (int64_t)k * TT;
   for (int e = tid; e < TT; e += NT) {
     const int row = e % T, col = e / T;
@@ -275,89 +500,141 @@ __device__ void task_potrf(const ExecMat& M, const int32_t* w, double* S, double
 }
 
 // ---------------------------------------------------------------- solves
-// Vector blocks are T x nrhs column-major; thread (row = tid % T, group =
-// tid / T) owns right-hand sides group, group + G, ...
+// Vector blocks are T x nrhs column-major (nrhs <= 16).  Each task computes
+// out = sum_p A_p V_p with A_p a factor tile (or its transpose) and V_p a
+// vector block, as 16 x 16 x 4 FP64 MFMA products with the right-hand sides
+// padded to 16 columns: wave w owns rows 16 w .. 16 w + 15 of the output.
+// Tiles are staged in LDS with leading dimension T + 1, so both the direct
+// and the transposed operand reads are free of bank conflicts.
 
 template <int T>
-__device__ void task_solve(const ExecMat& M, const int32_t* w, int nrhs) {
-  constexpr int TT = T * T, G = NT / T, MAXC = 16 / G;
+struct SolveStage {
+  static constexpr int NVL = T * T / NT / 2;   // double2 per thread, tile
+  static constexpr int NVV = T * 16 / NT / 2;  // double2 per thread, padded vector block
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2 lt[NVL];
+  d2 vb[NVV];
+  __device__ __forceinline__ void load_tile(const double* __restrict__ L) {
+    const d2* lv = reinterpret_cast<const d2*>(L);
+#pragma unroll
+    for (int q = 0; q < NVL; q++) lt[q] = lv[threadIdx.x + q * NT];
+  }
+  __device__ __forceinline__ void load_vec(const double* __restrict__ v, int nrhs) {
+    const d2* vv = reinterpret_cast<const d2*>(v);
+    const int nv = T * nrhs / 2;
+#pragma unroll
+    for (int q = 0; q < NVV; q++) {
+      const int e = threadIdx.x + q * NT;
+      vb[q] = e < nv ? vv[e] : d2{0.0, 0.0};
+    }
+  }
+  __device__ __forceinline__ void store_tile(double* LL) const {
+#pragma unroll
+    for (int q = 0; q < NVL; q++) {
+      const int e = 2 * (threadIdx.x + q * NT);
+      const int row = e % T, col = e / T;
+      LL[row + col * (T + 1)] = lt[q].x;
+      LL[row + 1 + col * (T + 1)] = lt[q].y;
+    }
+  }
+  __device__ __forceinline__ void store_vec(double* LV) const {
+    d2* vv = reinterpret_cast<d2*>(LV);
+#pragma unroll
+    for (int q = 0; q < NVV; q++) vv[threadIdx.x + q * NT] = vb[q];
+  }
+};
+
+// acc += A V on MFMA; A = LL (ld T+1), transposed when `trans`; V = LV (ld T)
+template <int T>
+__device__ __forceinline__ v4d solve_mma(v4d acc, const double* LL, const double* LV, bool trans, int wave, int lane) {
+  constexpr int LD = T + 1;
+  const int i = 16 * wave + (lane & 15);
+#pragma unroll 4
+  for (int kq = 0; kq < T; kq += 4) {
+    const int l = kq + (lane >> 4);
+    const double av = trans ? LL[l + i * LD] : LL[i + l * LD];
+    const double bv = LV[l + (lane & 15) * T];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int T>
+__device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int32_t* w, int nrhs, double* LL,
+                                                     double* LV) {
+  constexpr int TT = T * T;
   const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
-  const int row = threadIdx.x % T, grp = threadIdx.x / T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool act = 16 * wave < T;
   const int m = w[1];
   const int64_t vb = (int64_t)T * nrhs;
-  double acc[MAXC];
+  const bool fwd = type == TK_FUPD || type == TK_FDIAG;
+  const bool diag = type == TK_FDIAG || type == TK_BDIAG;
+  const double* vsrc = fwd ? M.vy : M.vz;
+  const int p0 = w[2], p1 = w[3];
+  // output element of this lane: row 16 wave + (lane >> 4) + 4 r, column lane & 15
+  const int col = lane & 15;
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  SolveStage<T> st;
+  if (p1 > p0) {
+    st.load_tile(M.tiles + (int64_t)M.pairs[2 * p0] * TT);
+    st.load_vec(vsrc + M.pairs[2 * p0 + 1] * vb, nrhs);
+  }
+  for (int p = p0; p < p1; p++) {
+    __syncthreads();
+    st.store_tile(LL);
+    st.store_vec(LV);
+    __syncthreads();
+    if (p + 1 < p1) {
+      st.load_tile(M.tiles + (int64_t)M.pairs[2 * p + 2] * TT);
+      st.load_vec(vsrc + M.pairs[2 * p + 3] * vb, nrhs);
+    }
+    if (act) acc = solve_mma<T>(acc, LL, LV, !fwd, wave, lane);
+  }
+  // base block: Y_m (forward), or Y_m / Z_m (backward, first chunk reads Y)
+  const double* base = fwd ? M.vy + m * vb : ((w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb);
+  double* dst = fwd ? M.vy + m * vb : M.vz + m * vb;
+  if (!diag) {
+    if (act && col < nrhs) {
 #pragma unroll
-  for (int c = 0; c < MAXC; c++) acc[c] = 0.0;
-  if (type == TK_FUPD) {
-    for (int p = w[2]; p < w[3]; p++) {
-      const double* L = M.tiles + (int64_t)M.pairs[2 * p] * TT;
-      const double* y = M.vy + M.pairs[2 * p + 1] * vb;
-      for (int l = 0; l < T; l++) {
-        const double lv = L[row + l * T];
-#pragma unroll
-        for (int c = 0; c < MAXC; c++) {
-          const int cc = grp + c * G;
-          if (cc < nrhs) acc[c] += lv * y[l + cc * T];
-        }
+      for (int r = 0; r < 4; r++) {
+        const int row = 16 * wave + (lane >> 4) + 4 * r;
+        dst[row + col * T] = base[row + col * T] - acc[r];
       }
     }
-    double* ym = M.vy + m * vb;
+    return;
+  }
+  // diagonal: out = Linv_m (base - acc)   (Linv_m^T in the backward sweep)
+  st.load_tile(M.linv + (int64_t)m * TT);
+  st.load_vec(base, nrhs);
+  __syncthreads();
+  st.store_tile(LL);
+  st.store_vec(LV);
+  __syncthreads();
+  if (act) {
 #pragma unroll
-    for (int c = 0; c < MAXC; c++) {
-      const int cc = grp + c * G;
-      if (cc < nrhs) ym[row + cc * T] -= acc[c];
-    }
-  } else if (type == TK_BUPD) {
-    for (int p = w[2]; p < w[3]; p++) {
-      const double* L = M.tiles + (int64_t)M.pairs[2 * p] * TT;
-      const double* z = M.vz + M.pairs[2 * p + 1] * vb;
-      for (int l = 0; l < T; l++) {
-        const double lv = L[l + row * T];
+    for (int r = 0; r < 4; r++) LV[(16 * wave + (lane >> 4) + 4 * r) + col * T] -= acc[r];
+  }
+  __syncthreads();
+  v4d out = v4d{0.0, 0.0, 0.0, 0.0};
+  if (act) out = solve_mma<T>(out, LL, LV, !fwd, wave, lane);
+  if (act && col < nrhs) {
 #pragma unroll
-        for (int c = 0; c < MAXC; c++) {
-          const int cc = grp + c * G;
-          if (cc < nrhs) acc[c] += lv * z[l + cc * T];
-        }
-      }
-    }
-    const double* src = (w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb;
-    double* zm = M.vz + m * vb;
-#pragma unroll
-    for (int c = 0; c < MAXC; c++) {
-      const int cc = grp + c * G;
-      if (cc < nrhs) zm[row + cc * T] = src[row + cc * T] - acc[c];
-    }
-  } else {
-    // FDIAG: Y_m = Linv_m Y_m ; BDIAG: Z_m = Linv_m^T (Z_m or Y_m)
-    const double* Li = M.linv + (int64_t)m * TT;
-    const bool fwd = type == TK_FDIAG;
-    const double* src = fwd ? M.vy + m * vb : ((w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb);
-    double* dst = fwd ? M.vy + m * vb : M.vz + m * vb;
-    for (int l = 0; l < T; l++) {
-      const double lv = fwd ? Li[row + l * T] : Li[l + row * T];
-#pragma unroll
-      for (int c = 0; c < MAXC; c++) {
-        const int cc = grp + c * G;
-        if (cc < nrhs) acc[c] += lv * src[l + cc * T];
-      }
-    }
-    __syncthreads();   // all reads of src done before dst (== src for FDIAG) changes
-#pragma unroll
-    for (int c = 0; c < MAXC; c++) {
-      const int cc = grp + c * G;
-      if (cc < nrhs) dst[row + cc * T] = acc[c];
-    }
+    for (int r = 0; r < 4; r++) dst[(16 * wave + (lane >> 4) + 4 * r) + col * T] = out[r];
   }
 }
 
 // ---------------------------------------------------------------- executor
 
-template <int T>
+// SOLVE selects the task set: factorization tasks (UPD, PART, TREE, POTRF,
+// TRSM) or triangular-solve tasks; the two are separate kernels so that each
+// carries only its own code.
+template <int T, bool SOLVE>
 __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ mats, const int32_t* __restrict__ order,
                                                   int32_t total, ExecCtrl* ctrl, int nrhs) {
-  __shared__ double S[T * T];
-  __shared__ double Xi[T * T];
-  __shared__ double rinv[T];
+  __shared__ __attribute__((aligned(16))) double S[T * (T + 1)];
+  __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : T * T];
+  __shared__ double rinv[SOLVE ? 1 : T];
   __shared__ int32_t s_ticket;
   // Control flow outside the task bodies is kept uniform across the
   // workgroup (values broadcast with readfirstlane, loops with uniform bounds
@@ -377,27 +654,47 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
     const ExecMat& M = mats[mi];
     const int32_t* w = M.tasks + (int64_t)lid * TASK_WORDS;
     int32_t* cnt = M.remaining + lid;
-    // wait until every predecessor has finished (Alg. 2 progress check)
-    while (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) > 0) __builtin_amdgcn_s_sleep(2);
+    uint64_t t_claim = 0, t_start = 0;
+    if (M.trace) t_claim = wall_clock64();
+    // wait until every predecessor has finished (Alg. 2 progress check);
+    // wave 0 polls, then acquires for the workgroup (all its waves share
+    // the CU's caches that the acquire invalidates)
+    if (threadIdx.x < 64) {
+      while (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) > 0) __builtin_amdgcn_s_sleep(1);
+      fence_acquire();
+    }
     __syncthreads();
     if (threadIdx.x == 0) st_relaxed(cnt, w[7]);   // re-arm for the next launch
-    fence_acquire();
+    if (M.trace) t_start = wall_clock64();
     const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
-    switch (type) {
-      case TK_UPD: task_update<T>(M, w, 0); break;
-      case TK_PART: task_update<T>(M, w, 1); break;
-      case TK_TREE: task_tree<T>(M, w); break;
-      case TK_POTRF: task_potrf<T>(M, w, S, Xi, rinv); break;
-      case TK_TRSM: task_trsm<T>(M, w); break;
-      default: task_solve<T>(M, w, nrhs); break;
+    if constexpr (SOLVE) {
+      task_solve<T>(M, w, nrhs, S, Xi);
+    } else {
+      switch (type) {
+        case TK_UPD: task_update<T>(M, w, 0, S, Xi); break;
+        case TK_PART: task_update<T>(M, w, 1, S, Xi); break;
+        case TK_TREE: task_tree<T>(M, w); break;
+        case TK_POTRF: task_potrf<T>(M, w, S, Xi, rinv); break;
+        default: task_trsm<T>(M, w, S, Xi); break;
+      }
     }
-    fence_release();
+    // every wave waits for its own stores, then wave 0 releases for the
+    // workgroup and notifies the successors (Alg. 2 progress update)
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // notify successors (Alg. 2 progress update)
+    if (threadIdx.x < 64) fence_release();
     const int32_t s0 = __builtin_amdgcn_readfirstlane(w[5]), s1 = __builtin_amdgcn_readfirstlane(w[6]);
-    for (int32_t q0 = s0; q0 < s1; q0 += NT) {
+    for (int32_t q0 = s0; q0 < s1; q0 += 64) {
       const int32_t q = q0 + (int32_t)threadIdx.x;
-      if (q < s1) __hip_atomic_fetch_add(M.remaining + M.succ[q], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x < 64 && q < s1)
+        __hip_atomic_fetch_add(M.remaining + M.succ[q], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (M.trace && threadIdx.x == 0) {
+      unsigned long long* tr = M.trace + 4 * (int64_t)lid;
+      tr[0] = t_claim;
+      tr[1] = t_start;
+      tr[2] = wall_clock64();
+      tr[3] = ((unsigned long long)blockIdx.x << 32) | ((unsigned)type << 24) | ((unsigned)t & 0xffffffu);
     }
   }
   if (threadIdx.x == 0) {
@@ -413,10 +710,18 @@ hipError_t launch_exec(int T, const ExecMat* d_mats, const int32_t* d_order, int
                        int nwg, hipStream_t st) {
   if (total <= 0) return hipSuccess;
   if (nwg > total) nwg = total;
-  if (T == 64)
-    hipLaunchKernelGGL(exec_kernel<64>, dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
-  else
-    hipLaunchKernelGGL(exec_kernel<32>, dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
+  const bool solve = nrhs > 0;
+  if (T == 64) {
+    if (solve)
+      hipLaunchKernelGGL((exec_kernel<64, true>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
+    else
+      hipLaunchKernelGGL((exec_kernel<64, false>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
+  } else {
+    if (solve)
+      hipLaunchKernelGGL((exec_kernel<32, true>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
+    else
+      hipLaunchKernelGGL((exec_kernel<32, false>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
+  }
   return hipGetLastError();
 }
 

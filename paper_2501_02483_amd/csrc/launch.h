@@ -7,7 +7,8 @@
 
 namespace stiles {
 
-// Persistent DAG executor: `total` tickets; order == nullptr means one matrix
+// Persistent DAG executor: `total` tickets; nrhs == 0 runs factorization
+// tasks, nrhs >= 1 triangular-solve tasks.  order == nullptr means one matrix
 // (mats[0]) with tasks in their own order, else order[2t], order[2t+1] =
 // (matrix index, task id).
 hipError_t launch_exec(int T, const ExecMat* d_mats, const int32_t* d_order, int32_t total, ExecCtrl* d_ctrl,

@@ -21,12 +21,12 @@ enum TaskType : int32_t {
   TK_UPD = 1,    // C_t -= sum over pairs (X_p Y_p^T)            [Alg. 1 SYRK/GEMM]
   TK_PART = 2,   // P_s  = sum over pairs (X_p Y_p^T)            [Alg. 3 partial T[ID]]
   TK_TREE = 3,   // P_o = P_a + P_b, or C_t -= P_a (+ P_b)       [Alg. 3 GEADD tree]
-  TK_POTRF = 4,  // L_kk = chol(C_kk); Linv_k = L_kk^{-1}        [Alg. 1 POTRF]
-  TK_TRSM = 5,   // L_t = C_t Linv_k^T                           [Alg. 1 TRSM]
+  TK_POTRF = 4,  // [C_kk -= X X^T]; L_kk = chol(C_kk); Linv_k   [Alg. 1 SYRK, POTRF]
+  TK_TRSM = 5,   // [C_t -= X Y^T]; L_t = C_t Linv_k^T           [Alg. 1 GEMM, TRSM]
   TK_FUPD = 8,   // solve, forward:  Y_m -= sum L_(m,j) Y_j
-  TK_FDIAG = 9,  // solve, forward:  Y_m  = Linv_m Y_m
+  TK_FDIAG = 9,  // solve, forward:  Y_m  = Linv_m (Y_m - [L_(m,j) Y_j])
   TK_BUPD = 10,  // solve, backward: Z_m  = (first ? Y_m : Z_m) - sum L_(i,m)^T Z_i
-  TK_BDIAG = 11, // solve, backward: Z_m  = Linv_m^T (Z_m, or Y_m if no BUPD)
+  TK_BDIAG = 11, // solve, backward: Z_m  = Linv_m^T ((Z_m or Y_m) - [L_(i,m)^T Z_i])
 };
 
 enum TaskFlag : int32_t {
@@ -40,8 +40,10 @@ enum TaskFlag : int32_t {
 //  w5 succ_lo          w6 succ_hi        w7 ndeps
 // UPD:  a,b = pair range          PART: a,b = pair range, c = out slot
 // TREE: a = slot, b = slot or -1, c = out slot or -1 (then subtract into tile)
-// POTRF: a = tile row k           TRSM: a = tile row k of the diagonal tile
-// FUPD/BUPD: w1 = tile row m, a,b = solve-pair range; FDIAG/BDIAG: w1 = m
+// POTRF: a = tile row k, b,c = fused pair range (C_kk -= X X^T first, 0 or 1 pair)
+// TRSM:  a = tile row k of the diagonal tile, b,c = fused pair range
+// FUPD/BUPD: w1 = tile row m, a,b = solve-pair range
+// FDIAG/BDIAG: w1 = m, a,b = fused solve-pair range applied before the diagonal
 constexpr int TASK_WORDS = 8;
 
 // Device-side description of one matrix (or one solve) for the executor.
@@ -58,6 +60,7 @@ struct ExecMat {
   const int32_t* pairs;     // 2 ints per pair
   unsigned long long* info; // first failing permuted column + 1, ~0ull if none
   const int64_t* row_base;  // ntr: first permuted row of each tile row
+  unsigned long long* trace;// per task {claim, start, end, wg<<32|type<<24|ticket} or null
   int32_t ntasks;
   int32_t ntr;
   int32_t mixed;

@@ -1,0 +1,177 @@
+"""Host emulation of the task DAGs that the GPU executor runs.
+
+The plan (tasks, successor lists, tile pairs, tile pattern) is read from a
+symbolic object through stiles_symbolic_export and executed here with numpy
+tile operations, in the schedule's ticket order or in a random order among
+the tasks whose predecessors are done.  This checks the planner on the CPU:
+a missing dependency, a wrong pair list or a wrong tree would change the
+result (compared with the FP64 oracle), and a cycle would leave tasks
+unexecuted.  Task semantics follow the comments of stiles_internal.h."""
+import numpy as np
+
+import paper_2501_02483_amd as S
+
+UPD, PART, TREE, POTRF, TRSM = 1, 2, 3, 4, 5
+FUPD, FDIAG, BUPD, BDIAG = 8, 9, 10, 11
+TF_DIAG, TF_FIRST = 1 << 8, 1 << 9
+
+
+class Plan:
+    def __init__(self, sym):
+        h = sym.handle
+        ex = lambda k: S.stiles_symbolic_export(h, k)
+        self.T = sym.info.tile
+        self.ftask = ex("ftask").reshape(-1, 8)
+        self.fsucc = ex("fsucc")
+        self.fpairs = ex("fpairs").reshape(-1, 2)
+        self.stask = ex("stask").reshape(-1, 8)
+        self.ssucc = ex("ssucc")
+        self.spairs = ex("spairs").reshape(-1, 2)
+        self.trow_ptr = ex("trow_ptr")
+        self.tcol = ex("tcol")
+        self.row_base = ex("row_base")
+        self.row_cnt = ex("row_cnt")
+        self.npart = int(ex("npart")[0])
+        self.ntr = len(self.trow_ptr) - 1
+        self.trow = np.repeat(np.arange(self.ntr), np.diff(self.trow_ptr))
+        self.perm = sym.perm()
+        self.N = sym.info.N
+
+
+def _order(tasks, succ, mode, rng):
+    n = len(tasks)
+    if mode == "ticket":
+        # ticket order must be topological: every successor has a larger index
+        for t in range(n):
+            for q in range(tasks[t, 5], tasks[t, 6]):
+                assert succ[q] > t
+        return list(range(n))
+    rem = tasks[:, 7].copy()
+    ready = [t for t in range(n) if rem[t] == 0]
+    out = []
+    while ready:
+        i = int(rng.integers(len(ready)))
+        t = ready.pop(i)
+        out.append(t)
+        for q in range(tasks[t, 5], tasks[t, 6]):
+            s = succ[q]
+            rem[s] -= 1
+            assert rem[s] >= 0
+            if rem[s] == 0:
+                ready.append(s)
+    assert len(out) == n, "DAG has a cycle or a wrong predecessor count"
+    return out
+
+
+def scatter(plan, Aperm):
+    """Tile store of the permuted dense matrix (lower triangle), unit padding."""
+    T = plan.T
+    tiles = np.zeros((len(plan.tcol), T, T))
+    for t in range(len(plan.tcol)):
+        m, j = plan.trow[t], plan.tcol[t]
+        rb, cb, rc, cc = plan.row_base[m], plan.row_base[j], plan.row_cnt[m], plan.row_cnt[j]
+        blk = np.zeros((T, T))
+        blk[:rc, :cc] = Aperm[rb:rb + rc, cb:cb + cc]
+        if m == j:
+            blk = np.tril(blk)
+            for r in range(rc, T):
+                blk[r, r] = 1.0
+        tiles[t] = blk
+    return tiles
+
+
+def factor(plan, Aperm, mode="ticket", seed=0):
+    rng = np.random.default_rng(seed)
+    T = plan.T
+    tiles = scatter(plan, Aperm)
+    linv = np.zeros((plan.ntr, T, T))
+    part = np.zeros((max(plan.npart, 1), T, T))
+    P = plan.fpairs
+    for t in _order(plan.ftask, plan.fsucc, mode, rng):
+        w = plan.ftask[t]
+        typ = w[0] & 0xff
+        if typ in (UPD, PART):
+            acc = sum(tiles[P[p, 0]] @ tiles[P[p, 1]].T for p in range(w[2], w[3]))
+            if typ == UPD:
+                if w[0] & TF_DIAG:
+                    tiles[w[1]] -= np.tril(acc)
+                else:
+                    tiles[w[1]] -= acc
+            else:
+                part[w[4]] = acc
+        elif typ == TREE:
+            s = part[w[2]] + (part[w[3]] if w[3] >= 0 else 0.0)
+            if w[4] >= 0:
+                part[w[4]] = s
+            else:
+                tiles[w[1]] -= s
+        elif typ == POTRF:
+            C = tiles[w[1]].copy()
+            for p in range(w[3], w[4]):
+                C -= tiles[P[p, 0]] @ tiles[P[p, 1]].T
+            Cs = np.tril(C) + np.tril(C, -1).T
+            L = np.linalg.cholesky(Cs)
+            tiles[w[1]] = L
+            linv[w[2]] = np.linalg.inv(L)
+        elif typ == TRSM:
+            C = tiles[w[1]].copy()
+            for p in range(w[3], w[4]):
+                C -= tiles[P[p, 0]] @ tiles[P[p, 1]].T
+            tiles[w[1]] = C @ linv[w[2]].T
+        else:
+            raise AssertionError("unknown factor task type %d" % typ)
+    return tiles, linv
+
+
+def dense_factor(plan, tiles):
+    """Dense lower factor of the permuted matrix from the tile store."""
+    L = np.zeros((plan.N, plan.N))
+    for t in range(len(plan.tcol)):
+        m, j = plan.trow[t], plan.tcol[t]
+        rb, cb, rc, cc = plan.row_base[m], plan.row_base[j], plan.row_cnt[m], plan.row_cnt[j]
+        L[rb:rb + rc, cb:cb + cc] = tiles[t][:rc, :cc]
+    return np.tril(L)
+
+
+def solve(plan, tiles, linv, B, mode="ticket", seed=0):
+    rng = np.random.default_rng(seed)
+    T, ntr = plan.T, plan.ntr
+    nrhs = B.shape[1]
+    Y = np.zeros((ntr, T, nrhs))
+    Bp = B[plan.perm]
+    for m in range(ntr):
+        rb, rc = plan.row_base[m], plan.row_cnt[m]
+        Y[m, :rc] = Bp[rb:rb + rc]
+    Z = np.zeros_like(Y)
+    P = plan.spairs
+    for t in _order(plan.stask, plan.ssucc, mode, rng):
+        w = plan.stask[t]
+        typ = w[0] & 0xff
+        m = w[1]
+        if typ == FUPD:
+            for p in range(w[2], w[3]):
+                Y[m] -= tiles[P[p, 0]] @ Y[P[p, 1]]
+        elif typ == FDIAG:
+            v = Y[m].copy()
+            for p in range(w[2], w[3]):
+                v -= tiles[P[p, 0]] @ Y[P[p, 1]]
+            Y[m] = linv[m] @ v
+        elif typ == BUPD:
+            v = (Y[m] if w[0] & TF_FIRST else Z[m]).copy()
+            for p in range(w[2], w[3]):
+                v -= tiles[P[p, 0]].T @ Z[P[p, 1]]
+            Z[m] = v
+        elif typ == BDIAG:
+            v = (Y[m] if w[0] & TF_FIRST else Z[m]).copy()
+            for p in range(w[2], w[3]):
+                v -= tiles[P[p, 0]].T @ Z[P[p, 1]]
+            Z[m] = linv[m].T @ v
+        else:
+            raise AssertionError("unknown solve task type %d" % typ)
+    X = np.zeros_like(B)
+    Xp = np.zeros_like(B)
+    for m in range(ntr):
+        rb, rc = plan.row_base[m], plan.row_cnt[m]
+        Xp[rb:rb + rc] = Z[m, :rc]
+    X[plan.perm] = Xp
+    return X

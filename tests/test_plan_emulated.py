@@ -1,0 +1,111 @@
+"""CPU checks of the host planner through the C ABI (no GPU): the factor and
+solve DAGs, executed by the host emulator in ticket order and in random
+topological orders, reproduce the oracle's factor and solution."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_02483_amd as S
+from paper_2501_02483_amd import inputs as I
+
+import dag_emulator as E
+
+SHAPES = [
+    # n, a, widths, seg, tile, tree ratio
+    (300, 5, 7, None, 32, 2),
+    (700, 40, 60, None, 64, 2),
+    (700, 40, 60, None, 64, 0),
+    (1000, 0, 30, None, 32, 2),
+    (400, 70, 0, None, 32, 2),
+    (2000, 100, [10, 130, 40, 90], 500, 32, 2),
+]
+
+
+def _oracle_dense_L(p, vals):
+    L, info = oracle.factor(p.f, vals)
+    assert info == 0
+    D = np.zeros((p.N, p.N))
+    rp = p.row_ptr()
+    for i in range(p.N):
+        D[i, p.f[i]:i + 1] = L[rp[i]:rp[i + 1]]
+    return D, L
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "n%d_a%d_T%d_r%d" % (s[0], s[1], s[4], s[5]))
+@pytest.mark.parametrize("mode", ["ticket", "random"])
+def test_emulated_factor_and_solve_match_oracle(shape, mode):
+    n, a, w, seg, T, ratio = shape
+    p = I.make_pattern(n, a, w, seg=seg)
+    vals = I.make_values(p, seed=n + a)
+    sym = S.Symbolic.from_pattern(p, tile=T, tree_min_ratio=ratio)
+    plan = E.Plan(sym)
+    A = I.to_dense(p, vals)
+    tiles, linv = E.factor(plan, A, mode=mode, seed=n)
+    Ld = E.dense_factor(plan, tiles)
+    Lo, Lv = _oracle_dense_L(p, vals)
+    assert np.linalg.norm(Ld - Lo) / np.linalg.norm(Lo) <= 1e-12
+    B = I.rhs(p.N, 3, seed=9)
+    X = E.solve(plan, tiles, linv, B, mode=mode, seed=n + 1)
+    Xo = oracle.solve(p.f, Lv, B)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
+
+
+def test_tree_shape_and_corner_count():
+    """With the tree, every arrow-corner tile sums one partial per chunk of
+    band columns through a binary GEADD tree; without it, one chain."""
+    p = I.make_pattern(3000, 50, 40)
+    on = S.Symbolic.from_pattern(p, tile=32, tree_min_ratio=2)
+    off = S.Symbolic.from_pattern(p, tile=32, tree_min_ratio=0)
+    assert on.info.tree_used == 1 and off.info.tree_used == 0
+    # about one corner accumulation per band tile row
+    assert on.info.corner_accumulations == on.info.band_tile_rows
+    ft = S.stiles_symbolic_export(on.handle, "ftask").reshape(-1, 8)
+    types = ft[:, 0] & 0xff
+    nparts = int((types == E.PART).sum())
+    ntree = int((types == E.TREE).sum())
+    ncorner = 3          # lower tiles of the 2 x 2 arrow-corner tile block (a = 50, T = 32)
+    # a binary tree over G partials takes G - 1 additions (the last one subtracts
+    # into the corner tile) and G - 2 intermediate slots
+    assert ntree == nparts - ncorner
+    npart_slots = int(S.stiles_symbolic_export(on.handle, "npart")[0])
+    assert npart_slots == nparts + (nparts - 2 * ncorner)
+    ft_off = S.stiles_symbolic_export(off.handle, "ftask").reshape(-1, 8)
+    assert int(((ft_off[:, 0] & 0xff) == E.PART).sum()) == 0
+
+
+def test_csc_input_with_rcm_permutation():
+    """A randomly relabelled band: partial RCM is kept by the fill check and
+    the emulated factor is the Cholesky factor of P A P^T."""
+    rng = np.random.default_rng(3)
+    p = I.make_pattern(600, 8, 12)
+    vals = I.make_values(p, seed=5)
+    A = I.to_dense(p, vals)
+    shuf = np.concatenate([rng.permutation(p.n), np.arange(p.n, p.N)])
+    As = A[np.ix_(shuf, shuf)]
+    Ls = np.tril(As)
+    colptr = np.zeros(p.N + 1, dtype=np.int64)
+    rows = []
+    for j in range(p.N):
+        r = np.nonzero(Ls[:, j])[0]
+        r = r[r >= j]
+        if r[0] != j:
+            r = np.concatenate([[j], r])
+        rows.append(r)
+        colptr[j + 1] = colptr[j] + len(r)
+    rowind = np.concatenate(rows)
+    auto = S.Symbolic.from_csc(p.N, p.a, colptr, rowind, tile=32)
+    none = S.Symbolic.from_csc(p.N, p.a, colptr, rowind, tile=32, ordering=S.STILES_ORDER_NONE)
+    assert auto.info.ordering_used == S.STILES_ORDER_PARTIAL_RCM
+    assert auto.info.tiles < none.info.tiles
+    perm = auto.perm()
+    assert np.array_equal(np.sort(perm), np.arange(p.N))
+    assert np.array_equal(perm[p.n:], np.arange(p.n, p.N))   # the arrow stays last
+    plan = E.Plan(auto)
+    Ap = As[np.ix_(perm, perm)]
+    tiles, linv = E.factor(plan, Ap, mode="random", seed=1)
+    Ld = E.dense_factor(plan, tiles)
+    Lref = np.linalg.cholesky(Ap)
+    assert np.linalg.norm(Ld - Lref) / np.linalg.norm(Lref) <= 1e-12
+    B = I.rhs(p.N, 2, seed=4)
+    X = E.solve(plan, tiles, linv, B)
+    assert np.linalg.norm(X - np.linalg.solve(As, B)) / np.linalg.norm(X) <= 1e-12
