@@ -171,6 +171,152 @@ def bench_single(args):
     return res
 
 
+def bench_batch(args):
+    """512 uneven matrices in one persistent launch; tile size by the autotuner."""
+    import torch
+
+    import paper_2501_02483_amd as S
+    from paper_2501_02483_amd import autotune
+    from paper_2501_02483_amd import inputs as I
+    from paper_2501_02483_amd.devgen import DevicePattern
+
+    pats = I.batch_patterns()[:args.count]
+    # values drawn on the device (seed 3000 + b), same law as the host generator
+    dvals = [DevicePattern(p).values(p.meta["value_seed"]) for p in pats]
+    torch.cuda.synchronize()
+    best, tried = autotune.tune_batch(pats, dvals, reps=2) if args.tile == 0 \
+        else ({"tile": args.tile}, [])
+    T = best["tile"]
+    syms = [S.Symbolic.from_pattern(p, tile=T) for p in pats]
+    facs = [S.Factor(s) for s in syms]
+    batch = S.Batch(facs)
+    lds = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in facs]
+
+    def step():
+        batch.factorize(dvals)
+        for f, o in zip(facs, lds):
+            f.logdet(o)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    infos = [f.info() for f in facs]
+    F = sum(s.info.flops_alg for s in syms)
+    ms = (t1 - t0) / args.steps * 1e3
+    return {"metric": "batched arrowhead Cholesky TFLOP/s (factorize+logdet of every matrix)",
+            "value": F / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic (device-generated values)",
+            "config": {"workload": "batch%d_uneven" % len(pats), "matrices": len(pats), "tile": T,
+                       "autotune": tried, "parallelism": "single GPU, one persistent launch"},
+            "factorizations_per_s": len(pats) * 1e3 / ms, "flops_alg": F,
+            "failed": int(sum(1 for i in infos if i != 0)),
+            "roofline": {"bound": "mfma", "achieved": F / (ms * 1e-3) / 1e12, "peak": FP64_PEAK,
+                         "unit": "TFLOP/s", "frac": F / (ms * 1e-3) / 1e12 / FP64_PEAK, "traffic": None}}
+
+
+def bench_mixed(args):
+    """n=500,000, w=1,000, a=200, Laplacian law (kappa ~ 1e6): mixed-precision
+    factorization and 16-RHS refined solve vs the FP64 path on the same GPU."""
+    import torch
+
+    import paper_2501_02483_amd as S
+    from paper_2501_02483_amd import inputs as I
+    from paper_2501_02483_amd.devgen import DevicePattern
+
+    p = I.mixed_large(n=args.n or 500_000)
+    nrhs = 16
+    dp = DevicePattern(p)
+    dv = dp.values(4, law="laplacian", kappa=1e6)
+    B = torch.randn(nrhs, p.N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(104)).t()
+    out = {}
+    for prec, name in ((S.STILES_FP64, "fp64"), (S.STILES_MIXED32, "mixed")):
+        sym = S.Symbolic.from_pattern(p, tile=args.tile or 64)
+        fac = S.Factor(sym, prec, nrhs_max=nrhs)
+        fac.factorize(dv)
+        torch.cuda.synchronize()
+        S.stiles_factor_set_timing(fac.handle, True)
+        fms = []
+        for _ in range(max(1, args.steps)):
+            fac.factorize(dv)
+            fms.append(S.stiles_factor_kernel_ms(fac.handle, 0))
+        S.stiles_factor_set_timing(fac.handle, False)
+        X = B.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = fac.solve(X)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ld = fac.logdet().item()
+        out[name] = {"factor_kernel_ms": float(np.median(fms)), "tflops": sym.info.flops_alg / np.median(fms) / 1e9,
+                     "solve_ms": (t1 - t0) * 1e3, "iterations": rep.iterations, "converged": rep.converged,
+                     "backward_error": rep.backward_error, "logdet": ld, "info": fac.info(), "X": X,
+                     "L": fac.extract() if args.n and args.n <= 200_000 else None}
+        del fac
+    xf, xm = out["fp64"].pop("X"), out["mixed"].pop("X")
+    out["mixed"]["x_rel_diff_vs_fp64"] = float(torch.linalg.norm(xm - xf) / torch.linalg.norm(xf))
+    out["mixed"]["logdet_rel_diff_vs_fp64"] = abs(out["mixed"]["logdet"] - out["fp64"]["logdet"]) / abs(out["fp64"]["logdet"])
+    Lf, Lm = out["fp64"].pop("L"), out["mixed"].pop("L")
+    if Lf is not None:
+        out["mixed"]["L_rel_diff_vs_fp64"] = float(torch.linalg.norm(Lm - Lf) / torch.linalg.norm(Lf))
+    F = sym.info.flops_alg
+    v = out["mixed"]["tflops"]
+    return {"metric": "mixed-precision arrowhead Cholesky TFLOP/s (factorization kernel)", "value": v,
+            "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": out["mixed"]["factor_kernel_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32-updates/f64", "data": "synthetic (device-generated, Laplacian law)",
+            "config": {"workload": p.name, "n": p.n, "arrow": p.a, "half_width": 1000, "nrhs": nrhs,
+                       "tile": args.tile or 64},
+            "flops_alg": F, "runs": out,
+            "roofline": {"bound": "mfma", "achieved": v, "peak": FP32_PEAK, "unit": "TFLOP/s",
+                         "frac": v / FP32_PEAK, "traffic": None}}
+
+
+def bench_serve(args):
+    """Poisson arrivals over 8 resident patterns (continuous batching)."""
+    import torch
+
+    from paper_2501_02483_amd import inputs as I
+    from paper_2501_02483_amd.serve import GpuExecutor, Request, Server, summarize
+
+    pats = I.serving_patterns()
+    if args.max_n:
+        pats = [p for p in pats if p.n <= args.max_n]
+    ex = GpuExecutor(pats, tile=args.tile or 64, slots=args.slots)
+    budget = int(args.budget_gb * 2 ** 30)
+    # closed loop: saturation rate with every slot busy
+    nsat = args.requests // 2
+    rng = np.random.default_rng(5)
+    sat = [Request(rid=i, arrival=0.0, pattern=int(rng.integers(len(pats))), op=int(rng.integers(3)),
+                   seed=5000 + i) for i in range(nsat)]
+    srv = Server(ex, budget, args.slots)
+    done = srv.run(sat)
+    span = max(r.t_done for r in done)
+    mu = len(done) / span
+    res = {"saturation_rps": mu}
+    flops = lambda r: ex.flops(r.pattern)
+    for frac in (0.5, 0.8):
+        reqs = [Request(rid=i, arrival=t, pattern=pi, op=op, seed=sd)
+                for i, (t, pi, op, sd) in enumerate(I.serving_requests(len(pats), args.requests, frac * mu))]
+        srv = Server(ex, budget, args.slots)
+        d = srv.run(reqs)
+        bad = sum(1 for r in d if r.result.get("info", 0) != 0)
+        res["load_%.1f" % frac] = dict(summarize(d, flops), failed=bad, max_used_gb=srv.max_used / 2 ** 30)
+    main = res["load_0.8"]
+    return {"metric": "serving p50/p99 request latency (ms) at 0.8 x saturation", "value": main["p99_ms"],
+            "unit": "ms (p99)", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": main["mean_ms"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic (device-generated values per request)",
+            "config": {"workload": "serve8", "patterns": [(p.n, int(p.n - p.f[p.n - 1]), p.a) for p in pats],
+                       "slots": args.slots, "budget_gb": args.budget_gb, "requests": args.requests},
+            "results": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,15 +324,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tile", type=int, default=64)
     ap.add_argument("--tree-ratio", type=int, default=2)
-    ap.add_argument("--workload", default="varband", choices=["varband", "small"])
+    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--count", type=int, default=512, help="batch: number of matrices")
+    ap.add_argument("--n", type=int, default=0, help="mixed: band rows (default 500,000)")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for in-flight requests")
+    ap.add_argument("--requests", type=int, default=60, help="serve: requests per load point")
+    ap.add_argument("--max-n", type=int, default=0, help="serve: keep patterns with n <= max-n")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent factorizations shard across GPUs without exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
-    res = bench_single(args)
+    if args.workload in ("varband", "small"):
+        res = bench_single(args)
+    elif args.workload == "batch":
+        res = bench_batch(args)
+    elif args.workload == "mixed":
+        res = bench_mixed(args)
+    else:
+        res = bench_serve(args)
     print(json.dumps(res), flush=True)
 
 

@@ -200,11 +200,23 @@ stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStre
 /*
  * Many independent factorizations in one persistent launch (Appendix A:
  * concurrent factorizations).  factors[i] must use distinct workspaces and
- * share one tile size; d_batch_ws (>= stiles_batch_workspace_size bytes) holds
- * the launch's merged task order.  Each result is bitwise identical to a
- * single stiles_factorize of the same matrix on the same symbolic object.
+ * share one tile size.  stiles_batch_create merges the per-matrix static
+ * schedules (by their start estimates) into one ticket order and uploads it
+ * into d_batch_ws (>= stiles_batch_workspace_size bytes, 256-byte aligned,
+ * caller-owned, kept alive with the batch); it synchronizes the stream once.
+ * stiles_batch_factorize then scatters every matrix's values and runs all
+ * factorizations in one launch (asynchronous); it may be called again with
+ * new values.  Each result is bitwise identical to a single stiles_factorize
+ * of the same matrix with the same symbolic object (the accumulation order of
+ * every tile is fixed by the plan, not by the schedule).
+ * stiles_factorize_batch = create + factorize + destroy.
  */
+typedef struct stiles_batch stiles_batch;
 stiles_status stiles_batch_workspace_size(int32_t count, stiles_factor* const* factors, size_t* bytes);
+stiles_status stiles_batch_create(int32_t count, stiles_factor* const* factors, void* d_batch_ws,
+                                  size_t batch_ws_bytes, hipStream_t stream, stiles_batch** out);
+stiles_status stiles_batch_factorize(stiles_batch* batch, const double* const* d_values, hipStream_t stream);
+void stiles_batch_destroy(stiles_batch* batch);
 stiles_status stiles_factorize_batch(int32_t count, stiles_factor* const* factors,
                                      const double* const* d_values, void* d_batch_ws,
                                      size_t batch_ws_bytes, hipStream_t stream);

@@ -20,7 +20,7 @@ __all__ = [
     "stiles_solve", "stiles_logdet", "stiles_factor_set_max_workgroups", "stiles_factor_release",
     "stiles_status_string", "stiles_last_error_arg", "factorize_batch", "stiles_factor_extract",
     "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
-    "stiles_symbolic_export",
+    "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_destroy", "Batch",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -45,7 +45,7 @@ EXPORTED = [
     "stiles_factorize_batch", "stiles_factor_info", "stiles_solve", "stiles_logdet",
     "stiles_factor_set_max_workgroups", "stiles_factor_release", "stiles_factor_extract",
     "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
-    "stiles_symbolic_export",
+    "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_destroy",
 ]
 
 
@@ -111,6 +111,9 @@ def load_library(path=LIB_PATH):
         "stiles_factor_kernel_ms": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_float)]),
         "stiles_factor_set_trace": (_i32, [_vp, _vp, _vp, _vp]),
         "stiles_symbolic_export": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_i64)]),
+        "stiles_batch_create": (_i32, [_i32, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+        "stiles_batch_factorize": (_i32, [_vp, _vp, _vp]),
+        "stiles_batch_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -394,6 +397,50 @@ class Factor:
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.stiles_factor_release(self.handle)
             self.handle = None
+
+
+class Batch:
+    """Many factors run in one persistent launch; the merged schedule is
+    uploaded once (stiles_batch_create) and reused by every factorize()."""
+
+    def __init__(self, factors, stream=None):
+        import torch
+        self.factors = list(factors)
+        hs = [f.handle for f in self.factors]
+        need = stiles_batch_workspace_size(hs)
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.factors[0].workspace.device)
+        addr = (self.ws.data_ptr() + 255) // 256 * 256
+        arr = (_vp * len(hs))(*[h.value for h in hs])
+        h = _vp()
+        _check(load_library().stiles_batch_create(len(hs), arr, ctypes.c_void_p(addr), need, _stream(stream),
+                                                  ctypes.byref(h)), "stiles_batch_create")
+        self.handle = h
+
+    def factorize(self, values, stream=None):
+        vals = (_vp * len(values))(*[_ptr(v) for v in values])
+        _check(load_library().stiles_batch_factorize(self.handle, vals, _stream(stream)), "stiles_batch_factorize")
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.stiles_batch_destroy(self.handle)
+            self.handle = None
+
+
+def stiles_batch_create(facs, d_batch_ws, batch_bytes, stream=None):
+    arr = (_vp * len(facs))(*[f.value for f in facs])
+    h = _vp()
+    _check(load_library().stiles_batch_create(len(facs), arr, _ptr(d_batch_ws), batch_bytes, _stream(stream),
+                                              ctypes.byref(h)), "stiles_batch_create")
+    return h
+
+
+def stiles_batch_factorize(batch, d_values, stream=None):
+    vals = (_vp * len(d_values))(*[_ptr(v) for v in d_values])
+    _check(load_library().stiles_batch_factorize(batch, vals, _stream(stream)), "stiles_batch_factorize")
+
+
+def stiles_batch_destroy(batch):
+    load_library().stiles_batch_destroy(batch)
 
 
 def factorize_batch(factors, values, batch_ws=None, stream=None):

@@ -1,0 +1,99 @@
+"""Tile-size and occupancy autotuner.
+
+The paper tunes its tile size by sweeping (Section IV-B: larger tiles on the
+GPU; Appendix B: 40 to 400 on the CPU).  Here the candidates are the tile
+sizes the kernels support (32, 64) and caps on the number of persistent
+workgroups; each candidate is timed on the device with the library's own
+event pair around the factorization kernel, and the fastest is kept.  A
+choice is made per pattern (single matrices) or per batch (one tile size per
+launch), and cached by pattern signature.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+
+TILES = (32, 64)
+
+
+def signature(pattern):
+    h = hashlib.sha1(np.ascontiguousarray(pattern.f).tobytes()).hexdigest()[:16]
+    return "n%d_a%d_%s" % (pattern.n, pattern.a, h)
+
+
+def _time_factor(fac, dv, reps):
+    import paper_2501_02483_amd as S
+    S.stiles_factor_set_timing(fac.handle, True)
+    ts = []
+    for _ in range(reps + 1):
+        fac.factorize(dv)
+        ts.append(S.stiles_factor_kernel_ms(fac.handle, 0))
+    S.stiles_factor_set_timing(fac.handle, False)
+    return float(np.median(ts[1:]))
+
+
+def tune_single(pattern, values, tiles=TILES, wg_caps=(0,), reps=3, precision=0):
+    """Time factorizations of one matrix for each candidate; returns
+    (best dict, all results)."""
+    import torch
+
+    import paper_2501_02483_amd as S
+    dv = torch.from_numpy(values).cuda()
+    results = []
+    for T in tiles:
+        sym = S.Symbolic.from_pattern(pattern, tile=T)
+        fac = S.Factor(sym, precision)
+        for cap in wg_caps:
+            fac.set_max_workgroups(cap)
+            ms = _time_factor(fac, dv, reps)
+            results.append({"tile": T, "max_wg": cap, "ms": ms, "tflops": sym.info.flops_alg / ms / 1e9,
+                            "exec_over_alg": sym.info.flops_exec / sym.info.flops_alg})
+        del fac
+    best = min(results, key=lambda r: r["ms"])
+    return best, results
+
+
+def tune_batch(patterns, values, tiles=TILES, reps=2):
+    """Time one batched launch of all matrices for each tile size (values:
+    host arrays or device tensors)."""
+    import torch
+
+    import paper_2501_02483_amd as S
+    dvals = [v if hasattr(v, "data_ptr") else torch.from_numpy(v).cuda() for v in values]
+    results = []
+    for T in tiles:
+        syms = [S.Symbolic.from_pattern(p, tile=T) for p in patterns]
+        facs = [S.Factor(s) for s in syms]
+        batch = S.Batch(facs)
+        batch.factorize(dvals)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            batch.factorize(dvals)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        F = sum(s.info.flops_alg for s in syms)
+        results.append({"tile": T, "ms": float(np.median(ts)), "tflops": F / float(np.median(ts)) / 1e9})
+        del batch, facs, syms
+    best = min(results, key=lambda r: r["ms"])
+    return best, results
+
+
+class Cache:
+    """JSON cache of tuning decisions keyed by pattern signature."""
+
+    def __init__(self, path):
+        self.path = path
+        self.data = json.load(open(path)) if os.path.exists(path) else {}
+
+    def get(self, pattern):
+        return self.data.get(signature(pattern))
+
+    def put(self, pattern, choice):
+        self.data[signature(pattern)] = choice
+        with open(self.path, "w") as fh:
+            json.dump(self.data, fh, indent=1, sort_keys=True)

@@ -6,6 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstiles.so")
+GEN_LIB = os.path.join(HERE, "libstiles_gen.so")
 SOURCES = ["analyze.cpp", "capi.cpp", "kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -35,6 +36,15 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # device-side synthetic input generator: a library of its own
+    gobj = os.path.join(objdir, "gen.hip.o")
+    cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, "gen.hip"), "-o", gobj] + COMMON + DEVICE
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    tmp = GEN_LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call([HIPCC, "-shared", "-o", tmp, gobj, "--offload-arch=gfx950", "-lamdhip64"])
+    os.replace(tmp, GEN_LIB)
     return LIB
 
 

@@ -503,16 +503,23 @@ extern "C" stiles_status stiles_batch_workspace_size(int32_t count, stiles_facto
   return STILES_OK;
 }
 
-extern "C" stiles_status stiles_factorize_batch(int32_t count, stiles_factor* const* factors,
-                                                const double* const* d_values, void* d_batch_ws,
-                                                size_t batch_ws_bytes, hipStream_t st) {
+struct stiles_batch {
+  std::vector<stiles_factor*> factors;
+  char* ws = nullptr;
+  int32_t total = 0;
+  int T = 64;
+  size_t o_ctrl = 0, o_mats = 0, o_order = 0;
+};
+
+extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const* factors, void* d_batch_ws,
+                                             size_t batch_ws_bytes, hipStream_t st, stiles_batch** out) {
   set_error_arg(0);
   size_t need = 0;
   stiles_status r = stiles_batch_workspace_size(count, factors, &need);
   if (r != STILES_OK) return r;
-  if (!d_values) { set_error_arg(3); return STILES_EINVAL; }
-  if (!d_batch_ws || (reinterpret_cast<uintptr_t>(d_batch_ws) % ALIGN) != 0) { set_error_arg(4); return STILES_EINVAL; }
-  if (batch_ws_bytes < need) { set_error_arg(5); return STILES_ENOMEM; }
+  if (!d_batch_ws || (reinterpret_cast<uintptr_t>(d_batch_ws) % ALIGN) != 0) { set_error_arg(3); return STILES_EINVAL; }
+  if (batch_ws_bytes < need) { set_error_arg(4); return STILES_ENOMEM; }
+  if (!out) { set_error_arg(6); return STILES_EINVAL; }
   const int T = factors[0]->sym->T;
   for (int32_t i = 0; i < count; i++) {
     if (factors[i]->sym->T != T) { set_error_arg(2); return STILES_ENOTSUP; }
@@ -531,26 +538,62 @@ extern "C" stiles_status stiles_factorize_batch(int32_t count, stiles_factor* co
   for (size_t q = 0; q < ev.size(); q++) { order[2 * q] = ev[q].m; order[2 * q + 1] = ev[q].t; }
   std::vector<ExecMat> mats(count);
   for (int32_t i = 0; i < count; i++) mats[i] = factors[i]->mf;
-  char* b = static_cast<char*>(d_batch_ws);
-  const size_t o_ctrl = 0, o_mats = up(sizeof(ExecCtrl)), o_order = o_mats + up(sizeof(ExecMat) * count);
+  stiles_batch* b = new stiles_batch();
+  b->factors.assign(factors, factors + count);
+  b->ws = static_cast<char*>(d_batch_ws);
+  b->total = (int32_t)ev.size();
+  b->T = T;
+  b->o_ctrl = 0;
+  b->o_mats = up(sizeof(ExecCtrl));
+  b->o_order = b->o_mats + up(sizeof(ExecMat) * count);
   ExecCtrl ctrl{};
-  hipError_t e = hipMemcpyAsync(b + o_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(b + o_mats, mats.data(), sizeof(ExecMat) * count, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(b + o_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st);
+  hipError_t e = hipMemcpyAsync(b->ws + b->o_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->ws + b->o_mats, mats.data(), sizeof(ExecMat) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->ws + b->o_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st);
   // host vectors must outlive the asynchronous copies
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return STILES_EDEVICE;
-  for (int32_t i = 0; i < count; i++) {
-    if (!d_values[i]) { set_error_arg(3); return STILES_EINVAL; }
-    r = scatter_values(factors[i], d_values[i], st);
+  if (e != hipSuccess) { delete b; return STILES_EDEVICE; }
+  *out = b;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_batch_factorize(stiles_batch* b, const double* const* d_values, hipStream_t st) {
+  set_error_arg(0);
+  if (!b) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_values) { set_error_arg(2); return STILES_EINVAL; }
+  for (size_t i = 0; i < b->factors.size(); i++) {
+    if (!d_values[i]) { set_error_arg(2); return STILES_EINVAL; }
+    stiles_status r = scatter_values(b->factors[i], d_values[i], st);
     if (r != STILES_OK) return r;
   }
-  int cap = device_wg_capacity(T);
-  e = launch_exec(T, reinterpret_cast<const ExecMat*>(b + o_mats), reinterpret_cast<const int32_t*>(b + o_order),
-                  (int32_t)ev.size(), reinterpret_cast<ExecCtrl*>(b + o_ctrl), 0, std::min<int>(cap, (int)ev.size()), st);
+  const int cap = device_wg_capacity(b->T);
+  hipError_t e = launch_exec(b->T, reinterpret_cast<const ExecMat*>(b->ws + b->o_mats),
+                             reinterpret_cast<const int32_t*>(b->ws + b->o_order), b->total,
+                             reinterpret_cast<ExecCtrl*>(b->ws + b->o_ctrl), 0, std::min<int>(cap, b->total), st);
   if (e != hipSuccess) return STILES_EDEVICE;
-  for (int32_t i = 0; i < count; i++) { factors[i]->state = 0; factors[i]->anorm = -1.0; }
+  for (auto* f : b->factors) { f->state = 0; f->anorm = -1.0; }
   return STILES_OK;
+}
+
+extern "C" void stiles_batch_destroy(stiles_batch* b) { delete b; }
+
+extern "C" stiles_status stiles_factorize_batch(int32_t count, stiles_factor* const* factors,
+                                                const double* const* d_values, void* d_batch_ws,
+                                                size_t batch_ws_bytes, hipStream_t st) {
+  set_error_arg(0);
+  if (!d_values) { set_error_arg(3); return STILES_EINVAL; }
+  stiles_batch* b = nullptr;
+  stiles_status r = stiles_batch_create(count, factors, d_batch_ws, batch_ws_bytes, st, &b);
+  if (r != STILES_OK) {
+    // keep this entry point's argument numbering
+    const int32_t a = stiles_last_error_arg();
+    set_error_arg(a >= 3 ? a + 1 : a);
+    return r;
+  }
+  r = stiles_batch_factorize(b, d_values, st);
+  stiles_batch_destroy(b);
+  if (r == STILES_EINVAL) set_error_arg(3);
+  return r;
 }
 
 extern "C" stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_factor_trace, void* d_solve_trace,

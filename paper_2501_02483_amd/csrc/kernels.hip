@@ -22,6 +22,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 256;
+// diagonal-tile factorization variant for T = 32: column-by-column (true) or
+// blocked; T = 64 always uses the blocked variant (the column variant's
+// fully unrolled 64-column loop does not fit the register file)
+#ifndef STILES_POTRF_COLS
+#define STILES_POTRF_COLS 1
+#endif
+constexpr bool POTRF_COLS = STILES_POTRF_COLS != 0;
 
 // ------------------------------------------------------------------ helpers
 
@@ -499,6 +506,120 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
   }
 }
 
+// Column-by-column variant: every thread keeps one row of the tile in
+// registers for a fixed set of columns (thread = (row i, column group g),
+// columns g, g + G, ...), the owner group of column j scales it and publishes
+// it through LDS, and one barrier per column separates publishing from the
+// rank-1 update.  The inverse is built the same way, row by row
+// (X = L^{-1}: row j of X is final once scaled by 1/L_jj, then
+// X_i -= L_ij X_j for i > j).  Per column: one pivot chain (1/sqrt estimate +
+// Newton), one LDS round trip and one barrier.
+template <int T>
+__device__ __attribute__((noinline)) void task_potrf_cols(const ExecMat& M, const int32_t* w, double* S, double* Xb,
+                                                          double* rinv) {
+  constexpr int TT = T * T, G = NT / T, NC = T / G;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i = tid % T, g = tid / T;
+  double* C = M.tiles + (int64_t)w[1] * TT;
+  const int k = w[2];
+  // column c of group g sits at position (c % G) * NC + c / G of a broadcast buffer
+  double* colbuf = Xb;            // 2 x T
+  double* xbuf = Xb + 2 * T;      // 2 x T
+  double r[NC];
+  if (w[4] > w[3]) {
+    // fused update with column k-1 first (C_kk -= X X^T), staged through LDS
+    constexpr int W = T / 2, NB = T / 32;
+    const int wave = tid >> 6;
+    const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
+    TileStage<T, double> st;
+    st.load(C);
+    st.store(S);
+    st.load(M.tiles + (int64_t)M.pairs[2 * w[3]] * TT);
+    st.store(S + TT);
+    __syncthreads();
+    v4d acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; a++)
+#pragma unroll
+      for (int b = 0; b < NB; b++) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    mma_f64<T>(acc, S + TT, S + TT, r0, c0, lane);
+#pragma unroll
+    for (int a = 0; a < NB; a++)
+#pragma unroll
+      for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int row = r0 + 16 * b + (lane & 15), col = c0 + 16 * a + (lane >> 4) + 4 * q;
+          S[row + col * T] -= acc[a][b][q];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NC; q++) r[q] = S[i + (g + G * q) * T];
+  } else {
+#pragma unroll
+    for (int q = 0; q < NC; q++) r[q] = C[i + (g + G * q) * T];
+  }
+  int fail = -1;
+#pragma clang loop unroll(full)
+  for (int j = 0; j < T; j++) {
+    const int gj = j % G, qj = j / G;
+    double* cb = colbuf + (j & 1) * T;
+    if (g == gj) {
+      // the group's threads share one wave: broadcast the pivot from row j
+      const double d = __shfl(r[qj], j, T);
+      const double rs = rsqrt_nr(d);
+      const double v = i > j ? r[qj] * rs : (i == j ? d * rs : 0.0);
+      r[qj] = v;
+      cb[i] = v;
+      if (i == j) {
+        rinv[j] = rs;
+        if (!(d > 0.0)) fail = j;
+      }
+    }
+    __syncthreads();
+    const double lij = cb[i];
+#pragma unroll
+    for (int q = 0; q < NC; q++) {
+      const int c = g + G * q;
+      if (c > j) r[q] = fma(-lij, cb[c], r[q]);
+    }
+  }
+  if (fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
+  // L out (lower part; the upper part of r is zero) and into LDS for the inverse
+#pragma unroll
+  for (int q = 0; q < NC; q++) {
+    const int c = g + G * q;
+    C[i + c * T] = r[q];
+    S[i + c * T] = r[q];
+  }
+  // inverse, row by row
+  double x[NC];
+#pragma unroll
+  for (int q = 0; q < NC; q++) x[q] = (g + G * q) == i ? 1.0 : 0.0;
+  __syncthreads();
+#pragma clang loop unroll(full)
+  for (int j = 0; j < T; j++) {
+    double* xb = xbuf + (j & 1) * T;
+    if (i == j) {
+      const double s = rinv[j];
+#pragma unroll
+      for (int q = 0; q < NC; q++) {
+        x[q] *= s;
+        xb[g + G * q] = x[q];
+      }
+    }
+    __syncthreads();
+    if (i > j) {
+      const double lij = S[i + j * T];
+#pragma unroll
+      for (int q = 0; q < NC; q++) x[q] = fma(-lij, xb[g + G * q], x[q]);
+    }
+  }
+  double* Li = M.linv + (int64_t)k * TT;
+#pragma unroll
+  for (int q = 0; q < NC; q++) Li[i + (g + G * q) * T] = x[q];
+}
+
 // ---------------------------------------------------------------- solves
 // Vector blocks are T x nrhs column-major (nrhs <= 16).  Each task computes
 // out = sum_p A_p V_p with A_p a factor tile (or its transpose) and V_p a
@@ -674,7 +795,10 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
         case TK_UPD: task_update<T>(M, w, 0, S, Xi); break;
         case TK_PART: task_update<T>(M, w, 1, S, Xi); break;
         case TK_TREE: task_tree<T>(M, w); break;
-        case TK_POTRF: task_potrf<T>(M, w, S, Xi, rinv); break;
+        case TK_POTRF:
+          if constexpr (POTRF_COLS && T == 32) task_potrf_cols<T>(M, w, S, Xi, rinv);
+          else task_potrf<T>(M, w, S, Xi, rinv);
+          break;
         default: task_trsm<T>(M, w, S, Xi); break;
       }
     }
