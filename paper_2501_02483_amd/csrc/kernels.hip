@@ -22,9 +22,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 256;
-// diagonal-tile factorization variant for T = 32: column-by-column (true) or
-// blocked; T = 64 always uses the blocked variant (the column variant's
-// fully unrolled 64-column loop does not fit the register file)
+// diagonal-tile factorization variant: column-by-column (true) or blocked
 #ifndef STILES_POTRF_COLS
 #define STILES_POTRF_COLS 1
 #endif
@@ -559,45 +557,59 @@ __device__ __attribute__((noinline)) void task_potrf_cols(const ExecMat& M, cons
 #pragma unroll
     for (int q = 0; q < NC; q++) r[q] = C[i + (g + G * q) * T];
   }
+  // Outer loop over column blocks jj (columns G jj .. G jj + G - 1, one per
+  // group); r[0] always holds the group's current column: after each block
+  // the register row is rotated by one, so no register is indexed at run time.
   int fail = -1;
-#pragma clang loop unroll(full)
-  for (int j = 0; j < T; j++) {
-    const int gj = j % G, qj = j / G;
-    double* cb = colbuf + (j & 1) * T;
-    if (g == gj) {
-      // the group's threads share one wave: broadcast the pivot from row j
-      const double d = __shfl(r[qj], j, T);
-      const double rs = rsqrt_nr(d);
-      const double v = i > j ? r[qj] * rs : (i == j ? d * rs : 0.0);
-      r[qj] = v;
-      cb[i] = v;
-      if (i == j) {
-        rinv[j] = rs;
-        if (!(d > 0.0)) fail = j;
+  double lout[NC];
+#pragma unroll 1
+  for (int jj = 0; jj < NC; jj++) {
+#pragma unroll
+    for (int gj = 0; gj < G; gj++) {
+      const int j = G * jj + gj;
+      double* cb = colbuf + (j & 1) * T;
+      if (g == gj) {
+        // the group's threads share one wave: broadcast the pivot from row j
+        const double d = __shfl(r[0], j, T);
+        const double rs = rsqrt_nr(d);
+        const double v = i > j ? r[0] * rs : (i == j ? d * rs : 0.0);
+        r[0] = v;
+        cb[i] = v;
+        if (i == j) {
+          rinv[j] = rs;
+          if (!(d > 0.0)) fail = j;
+        }
+      }
+      __syncthreads();
+      const double lij = cb[i];
+      // r[q] is column g + G (jj + q); update the columns right of j
+#pragma unroll
+      for (int q = 0; q < NC; q++) {
+        if (G * q + g > gj) r[q] = fma(-lij, cb[(g + G * (jj + q)) % T], r[q]);
       }
     }
-    __syncthreads();
-    const double lij = cb[i];
+    // column g + G jj of L is final in r[0]: keep it, rotate
 #pragma unroll
-    for (int q = 0; q < NC; q++) {
-      const int c = g + G * q;
-      if (c > j) r[q] = fma(-lij, cb[c], r[q]);
-    }
+    for (int q = 0; q < NC; q++)
+      if (q == jj) lout[q] = r[0];
+#pragma unroll
+    for (int q = 0; q + 1 < NC; q++) r[q] = r[q + 1];
+    r[NC - 1] = 0.0;
   }
   if (fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
   // L out (lower part; the upper part of r is zero) and into LDS for the inverse
 #pragma unroll
   for (int q = 0; q < NC; q++) {
     const int c = g + G * q;
-    C[i + c * T] = r[q];
-    S[i + c * T] = r[q];
+    C[i + c * T] = lout[q];
+    S[i + c * T] = lout[q];
   }
   // inverse, row by row
   double x[NC];
 #pragma unroll
   for (int q = 0; q < NC; q++) x[q] = (g + G * q) == i ? 1.0 : 0.0;
   __syncthreads();
-#pragma clang loop unroll(full)
+#pragma unroll 1
   for (int j = 0; j < T; j++) {
     double* xb = xbuf + (j & 1) * T;
     if (i == j) {
@@ -796,7 +808,7 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
         case TK_PART: task_update<T>(M, w, 1, S, Xi); break;
         case TK_TREE: task_tree<T>(M, w); break;
         case TK_POTRF:
-          if constexpr (POTRF_COLS && T == 32) task_potrf_cols<T>(M, w, S, Xi, rinv);
+          if constexpr (POTRF_COLS) task_potrf_cols<T>(M, w, S, Xi, rinv);
           else task_potrf<T>(M, w, S, Xi, rinv);
           break;
         default: task_trsm<T>(M, w, S, Xi); break;
