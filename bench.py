@@ -317,6 +317,43 @@ def bench_serve(args):
             "results": res}
 
 
+def bench_copycal(args):
+    """Plain device copy of a known size (counter calibration for HBM traffic)."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gbs = 2 * nbytes * args.steps / (t1 - t0) / 1e9
+    return {"metric": "device copy GB/s (calibration)", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 0, "ms_per_step": (t1 - t0) / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "copy_1GiB", "bytes_read": nbytes, "bytes_written": nbytes}}
+
+
+def rocpd_summary(path):
+    """Per-kernel table from a rocprofv3 rocpd database (kernel trace)."""
+    import sqlite3
+    db = sqlite3.connect(path)
+    rows = db.execute(
+        "select name, count(*), sum(duration), avg(duration), min(duration), max(duration), "
+        "max(vgpr_count), max(accum_vgpr_count), max(sgpr_count), max(lds_size), max(grid_x), max(workgroup_x) "
+        "from kernels group by name order by sum(duration) desc").fetchall()
+    total = sum(r[2] for r in rows) or 1
+    print("%-62s %6s %11s %11s %11s %11s %5s %5s %5s %6s %8s %4s %6s" % (
+        "kernel", "calls", "total_ms", "avg_us", "min_us", "max_us", "vgpr", "agpr", "sgpr", "lds", "grid", "wg", "pct"))
+    for r in rows:
+        name = r[0] if len(r[0]) <= 62 else r[0][:59] + "..."
+        print("%-62s %6d %11.3f %11.2f %11.2f %11.2f %5d %5d %5d %6d %8d %4d %6.2f" % (
+            name, r[1], r[2] / 1e6, r[3] / 1e3, r[4] / 1e3, r[5] / 1e3, r[6] or 0, r[7] or 0, r[8] or 0,
+            r[9] or 0, r[10] or 0, r[11] or 0, 100.0 * r[2] / total))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,7 +361,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tile", type=int, default=64)
     ap.add_argument("--tree-ratio", type=int, default=2)
-    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve"])
+    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal"])
+    ap.add_argument("--rocpd-summary", default="", help="print a per-kernel table of a rocprofv3 database and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count", type=int, default=512, help="batch: number of matrices")
     ap.add_argument("--n", type=int, default=0, help="mixed: band rows (default 500,000)")
@@ -333,6 +371,9 @@ def main():
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per load point")
     ap.add_argument("--max-n", type=int, default=0, help="serve: keep patterns with n <= max-n")
     args = ap.parse_args()
+    if args.rocpd_summary:
+        rocpd_summary(args.rocpd_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent factorizations shard across GPUs without exchange; see the design notes)",
@@ -344,6 +385,8 @@ def main():
         res = bench_batch(args)
     elif args.workload == "mixed":
         res = bench_mixed(args)
+    elif args.workload == "copycal":
+        res = bench_copycal(args)
     else:
         res = bench_serve(args)
     print(json.dumps(res), flush=True)

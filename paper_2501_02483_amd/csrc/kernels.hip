@@ -24,7 +24,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int NT = 256;
 // diagonal-tile factorization variant: column-by-column (true) or blocked
 #ifndef STILES_POTRF_COLS
-#define STILES_POTRF_COLS 1
+#define STILES_POTRF_COLS 0
 #endif
 constexpr bool POTRF_COLS = STILES_POTRF_COLS != 0;
 
