@@ -50,6 +50,32 @@ def to_device_cols(B):
     return t.t()
 
 
+def measured_traffic(workload, tile):
+    """HBM bytes per factorization launch from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
+    None when there is none for this workload or the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(root, "paper_2501_02483_amd", "csrc", "kernels.hip")
+    prof = os.path.join(root, "profiles")
+    if not os.path.isdir(prof):
+        return None
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    for name in sorted(os.listdir(prof)):
+        if not name.startswith("hbm_traffic_"):
+            continue
+        kv = {}
+        for line in open(os.path.join(prof, name)):
+            if ":" in line and not line.startswith(("#", "|", "-", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("workload") == "%s_T%d" % (workload, tile) and kv.get("kernels_sha1") == sha:
+            return {"bytes": int(kv["traffic_bytes_per_launch"]), "fetch": int(kv["fetch_bytes_per_launch"]),
+                    "write": int(kv["write_bytes_per_launch"]), "source": "profiles/" + name}
+    return None
+
+
 def cpu_threads():
     try:
         return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -161,10 +187,14 @@ def bench_single(args):
         "flops_alg": F,
         "flops_exec": sym.info.flops_exec,
         "info": info,
-        "roofline": {"bound": "mfma", "kernel": "exec_kernel<64,false> (factorization DAG)",
+        "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,false> (factorization DAG)" % args.tile,
                      "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
-                     "traffic": None, "kernel_ms": kernel_ms},
+                     "traffic": None, "kernel_ms": kernel_ms, "bytes_alg": 16 * p.nnz},
     }
+    tr = measured_traffic("%s_n%d_a%d" % (p.name.split("_")[0].rstrip("0123456789"), p.n, p.a), args.tile)
+    if tr is not None:
+        res["roofline"]["traffic"] = tr["bytes"]
+        res["roofline"]["traffic_detail"] = tr
     if not args.no_cpu_baseline:
         cb, _ = cpu_baseline_single(p, vals, B)
         res["cpu_baseline"] = cb
@@ -289,6 +319,12 @@ def bench_serve(args):
         pats = [p for p in pats if p.n <= args.max_n]
     ex = GpuExecutor(pats, tile=args.tile or 64, slots=args.slots)
     budget = int(args.budget_gb * 2 ** 30)
+    # warm-up: one request per pattern and slot, so every workspace the runs
+    # below need is allocated and initialized before any clock starts
+    warm = [Request(rid=i, arrival=0.0, pattern=i // args.slots, op=i % 3, seed=4000 + i)
+            for i in range(len(pats) * args.slots)]
+    Server(ex, budget, args.slots).run(warm)
+    torch.cuda.synchronize()
     # closed loop: saturation rate with every slot busy
     nsat = args.requests // 2
     rng = np.random.default_rng(5)

@@ -53,26 +53,32 @@ class DevicePattern:
             self.wmax = max(self.wmax, int(i[early].max()))
         self.tmp = torch.empty(2 * N, dtype=torch.float64, device=device)
 
-    def values(self, seed, out=None, stream=None, law="dominant", kappa=1e6):
+    def values(self, seed, out=None, stream=None, law="dominant", kappa=1e6, tmp=None):
         """Seeded values on the device; law "dominant" (diagonal = |row| + 1)
         or "laplacian" (-|z| off-diagonals, diagonal = |row| + eps with
-        eps = 2 max|row| / kappa, so that the smallest eigenvalue is eps)."""
+        eps = 2 max|row| / kappa, so that the smallest eigenvalue is eps).
+        tmp: scratch of at least 2N doubles; calls that may overlap on
+        different streams must each pass their own (the default is shared)."""
         import torch
         if out is None:
             out = torch.empty(self.nnz, dtype=torch.float64, device=self.rp.device)
+        if tmp is None:
+            tmp = self.tmp
+        elif tmp.numel() < 2 * self.N or tmp.dtype != torch.float64:
+            raise ValueError("tmp needs 2N float64 entries")
         st = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p(st.cuda_stream)
         lib = _load()
         err = lib.stiles_gen_offdiag(self.rp.data_ptr(), self.f.data_ptr(), self.N, self.wmax, self.full0, int(seed),
-                                     1 if law == "laplacian" else 0, out.data_ptr(), self.tmp.data_ptr(), h)
+                                     1 if law == "laplacian" else 0, out.data_ptr(), tmp.data_ptr(), h)
         if err == 0:
             if law == "laplacian":
                 with torch.cuda.stream(st):
-                    tot = self.tmp[:self.N] + self.tmp[self.N:]
+                    tot = tmp[:self.N] + tmp[self.N:2 * self.N]
                     shift = 2.0 * float(tot.max()) / kappa
             else:
                 shift = 1.0
-            err = lib.stiles_gen_diag(self.rp.data_ptr(), self.N, self.tmp.data_ptr(), shift, out.data_ptr(), h)
+            err = lib.stiles_gen_diag(self.rp.data_ptr(), self.N, tmp.data_ptr(), shift, out.data_ptr(), h)
         if err != 0:
             raise RuntimeError("device value generation failed (%d)" % err)
         return out

@@ -213,6 +213,10 @@ class GpuExecutor:
         self.ws_bytes = [s.workspace_size(precision, nrhs) for s in self.syms]
         self.slots = slots
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        # per-slot generator scratch: requests in flight on different slots
+        # must not share it
+        nmax = max(p.N for p in patterns)
+        self.gtmp = [torch.empty(2 * nmax, dtype=torch.float64, device="cuda") for _ in range(slots)]
         self.pool = {i: [] for i in range(len(patterns))}
         self.vals = {}            # slot -> values tensor
         self.events = {}
@@ -245,7 +249,7 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             fac = self._factor(req.pattern, st)
             fac.set_max_workgroups(max(64, 512 // self.slots))
-            v = self.devpat[req.pattern].values(req.seed, stream=st)
+            v = self.devpat[req.pattern].values(req.seed, stream=st, tmp=self.gtmp[slot])
             fac.factorize(v, stream=st)
             if req.op == OP_SOLVE:
                 b = torch.ones(self.patterns[req.pattern].N, dtype=torch.float64, device="cuda")
