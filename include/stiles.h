@@ -204,11 +204,18 @@ stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStre
  * schedules (by their start estimates) into one ticket order and uploads it
  * into d_batch_ws (>= stiles_batch_workspace_size bytes, 256-byte aligned,
  * caller-owned, kept alive with the batch); it synchronizes the stream once.
- * stiles_batch_factorize then scatters every matrix's values and runs all
+ * stiles_batch_factorize then scatters every matrix's values (one launch over
+ * all tiles when every matrix was analyzed from a row profile) and runs all
  * factorizations in one launch (asynchronous); it may be called again with
- * new values.  Each result is bitwise identical to a single stiles_factorize
+ * new values.  d_values is a host array of `count` device pointers; when it
+ * differs from the previous call's, the call waits for the stream once to
+ * upload it.  Each result is bitwise identical to a single stiles_factorize
  * of the same matrix with the same symbolic object (the accumulation order of
  * every tile is fixed by the plan, not by the schedule).
+ * stiles_batch_logdet writes the log-determinant of every matrix of the batch
+ * to d_out[0..count) (device, FP64; NaN for a matrix whose factorization
+ * failed) in two launches; each value is bitwise identical to stiles_logdet
+ * of that factor.  STILES_ESTATE if a factor is not factorized.
  * stiles_factorize_batch = create + factorize + destroy.
  */
 typedef struct stiles_batch stiles_batch;
@@ -216,6 +223,7 @@ stiles_status stiles_batch_workspace_size(int32_t count, stiles_factor* const* f
 stiles_status stiles_batch_create(int32_t count, stiles_factor* const* factors, void* d_batch_ws,
                                   size_t batch_ws_bytes, hipStream_t stream, stiles_batch** out);
 stiles_status stiles_batch_factorize(stiles_batch* batch, const double* const* d_values, hipStream_t stream);
+stiles_status stiles_batch_logdet(stiles_batch* batch, double* d_out, hipStream_t stream);
 void stiles_batch_destroy(stiles_batch* batch);
 stiles_status stiles_factorize_batch(int32_t count, stiles_factor* const* factors,
                                      const double* const* d_values, void* d_batch_ws,
@@ -252,7 +260,9 @@ stiles_status stiles_factor_extract(stiles_factor* f, double* d_L, hipStream_t s
  * the stream around every executor launch of this factor (which = 0: the
  * factorization DAG kernel; which = 1: the solve DAG kernel).
  * stiles_factor_kernel_ms waits for the last recorded pair and returns its
- * elapsed time in milliseconds (ESTATE if timing is off or nothing recorded). */
+ * elapsed time in milliseconds (ESTATE if timing is off or nothing recorded).
+ * For a batch, the factorization pair of the batch's first factor brackets
+ * the one batched executor launch. */
 stiles_status stiles_factor_set_timing(stiles_factor* f, int32_t enable);
 stiles_status stiles_factor_kernel_ms(stiles_factor* f, int32_t which, float* ms);
 

@@ -20,7 +20,8 @@ __all__ = [
     "stiles_solve", "stiles_logdet", "stiles_factor_set_max_workgroups", "stiles_factor_release",
     "stiles_status_string", "stiles_last_error_arg", "factorize_batch", "stiles_factor_extract",
     "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
-    "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_destroy", "Batch",
+    "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_logdet",
+    "stiles_batch_destroy", "Batch",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -45,7 +46,8 @@ EXPORTED = [
     "stiles_factorize_batch", "stiles_factor_info", "stiles_solve", "stiles_logdet",
     "stiles_factor_set_max_workgroups", "stiles_factor_release", "stiles_factor_extract",
     "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
-    "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_destroy",
+    "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_logdet",
+    "stiles_batch_destroy",
 ]
 
 
@@ -113,6 +115,7 @@ def load_library(path=LIB_PATH):
         "stiles_symbolic_export": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_i64)]),
         "stiles_batch_create": (_i32, [_i32, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
         "stiles_batch_factorize": (_i32, [_vp, _vp, _vp]),
+        "stiles_batch_logdet": (_i32, [_vp, _vp, _vp]),
         "stiles_batch_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
@@ -417,8 +420,21 @@ class Batch:
         self.handle = h
 
     def factorize(self, values, stream=None):
-        vals = (_vp * len(values))(*[_ptr(v) for v in values])
-        _check(load_library().stiles_batch_factorize(self.handle, vals, _stream(stream)), "stiles_batch_factorize")
+        ptrs = tuple(_ptr(v) for v in values)
+        if getattr(self, "_ptrs", None) != ptrs:
+            self._ptrs = ptrs
+            self._vals = (_vp * len(ptrs))(*ptrs)
+        _check(load_library().stiles_batch_factorize(self.handle, self._vals, _stream(stream)), "stiles_batch_factorize")
+
+    def logdet(self, out=None, stream=None):
+        """Log-determinants of all matrices (float64 device tensor of length count)."""
+        import torch
+        if out is None:
+            out = torch.empty(len(self.factors), dtype=torch.float64, device=self.ws.device)
+        if out.numel() < len(self.factors) or out.dtype != torch.float64:
+            raise ValueError("Batch.logdet: out needs %d float64 entries" % len(self.factors))
+        stiles_batch_logdet(self.handle, out, stream)
+        return out
 
     def __del__(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
@@ -437,6 +453,10 @@ def stiles_batch_create(facs, d_batch_ws, batch_bytes, stream=None):
 def stiles_batch_factorize(batch, d_values, stream=None):
     vals = (_vp * len(d_values))(*[_ptr(v) for v in d_values])
     _check(load_library().stiles_batch_factorize(batch, vals, _stream(stream)), "stiles_batch_factorize")
+
+
+def stiles_batch_logdet(batch, d_out, stream=None):
+    _check(load_library().stiles_batch_logdet(batch, _ptr(d_out), _stream(stream)), "stiles_batch_logdet")
 
 
 def stiles_batch_destroy(batch):

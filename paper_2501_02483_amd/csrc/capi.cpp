@@ -489,17 +489,54 @@ extern "C" stiles_status stiles_logdet(stiles_factor* f, double* d_out, hipStrea
 
 // ------------------------------------------------------------------ batches
 
+namespace {
+
+struct BatchSizes {
+  size_t tasks = 0, tiles = 0, rows = 0;
+};
+
+BatchSizes batch_sizes(int32_t count, stiles_factor* const* factors) {
+  BatchSizes z;
+  for (int32_t i = 0; i < count; i++) {
+    z.tasks += factors[i]->mf.ntasks;
+    z.tiles += factors[i]->sym->ntiles;
+    z.rows += factors[i]->sym->ntr;
+  }
+  return z;
+}
+
+// batch workspace: control block, executor descriptors, merged ticket order,
+// scatter/logdet descriptors, (matrix, tile) and (matrix, tile row) maps, and
+// the array of value pointers
+struct BatchLayout {
+  size_t ctrl, mats, order, desc, tmap, rmap, vptr, total;
+};
+
+BatchLayout batch_layout(int32_t count, const BatchSizes& z) {
+  BatchLayout B{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = up(o + std::max<size_t>(bytes, 1)); return r; };
+  B.ctrl = take(sizeof(ExecCtrl));
+  B.mats = take(sizeof(ExecMat) * count);
+  B.order = take(z.tasks * 8);
+  B.desc = take(sizeof(BatchDesc) * count);
+  B.tmap = take(z.tiles * 8);
+  B.rmap = take(z.rows * 8);
+  B.vptr = take(sizeof(double*) * count);
+  B.total = o;
+  return B;
+}
+
+}  // namespace
+
 extern "C" stiles_status stiles_batch_workspace_size(int32_t count, stiles_factor* const* factors, size_t* bytes) {
   set_error_arg(0);
   if (count < 1) { set_error_arg(1); return STILES_EINVAL; }
   if (!factors) { set_error_arg(2); return STILES_EINVAL; }
   if (!bytes) { set_error_arg(3); return STILES_EINVAL; }
-  size_t total = 0;
-  for (int32_t i = 0; i < count; i++) {
+  for (int32_t i = 0; i < count; i++)
     if (!factors[i]) { set_error_arg(2); return STILES_EINVAL; }
-    total += factors[i]->mf.ntasks;
-  }
-  *bytes = up(sizeof(ExecCtrl)) + up(sizeof(ExecMat) * count) + up(total * 8);
+  *bytes = batch_layout(count, batch_sizes(count, factors)).total;
   return STILES_OK;
 }
 
@@ -508,7 +545,10 @@ struct stiles_batch {
   char* ws = nullptr;
   int32_t total = 0;
   int T = 64;
-  size_t o_ctrl = 0, o_mats = 0, o_order = 0;
+  bool all_profile = true;    // every matrix has row-profile input: one scatter launch
+  BatchSizes z;
+  BatchLayout B;
+  std::vector<const double*> vptr;   // value pointers last uploaded
 };
 
 extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const* factors, void* d_batch_ws,
@@ -537,19 +577,48 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
   std::vector<int32_t> order(ev.size() * 2);
   for (size_t q = 0; q < ev.size(); q++) { order[2 * q] = ev[q].m; order[2 * q + 1] = ev[q].t; }
   std::vector<ExecMat> mats(count);
-  for (int32_t i = 0; i < count; i++) mats[i] = factors[i]->mf;
+  std::vector<BatchDesc> desc(count);
+  std::vector<int32_t> tmap, rmap;
   stiles_batch* b = new stiles_batch();
+  for (int32_t i = 0; i < count; i++) {
+    stiles_factor* f = factors[i];
+    const stiles_symbolic& s = *f->sym;
+    const Layout& L = f->L;
+    mats[i] = f->mf;
+    BatchDesc& d = desc[i];
+    d.in_rp = at<int64_t>(f, L.in_rp);
+    d.f = at<int64_t>(f, L.fprof);
+    d.trow = at<int32_t>(f, L.trow);
+    d.tcol = at<int32_t>(f, L.tcol);
+    d.trow_ptr = at<int32_t>(f, L.trow_ptr);
+    d.row_base = at<int64_t>(f, L.row_base);
+    d.row_cnt = at<int32_t>(f, L.row_cnt);
+    d.tiles = at<double>(f, L.tiles);
+    d.orig = f->precision == STILES_MIXED32 ? at<double>(f, L.orig) : nullptr;
+    d.ldpart = at<double>(f, L.ldpart);
+    d.info = at<unsigned long long>(f, L.info);
+    d.ntiles = (int32_t)s.ntiles;
+    d.ntr = s.ntr;
+    if (!s.profile_input) b->all_profile = false;
+    for (int32_t t = 0; t < (int32_t)s.ntiles; t++) { tmap.push_back(i); tmap.push_back(t); }
+    for (int32_t m = 0; m < s.ntr; m++) { rmap.push_back(i); rmap.push_back(m); }
+  }
   b->factors.assign(factors, factors + count);
   b->ws = static_cast<char*>(d_batch_ws);
   b->total = (int32_t)ev.size();
   b->T = T;
-  b->o_ctrl = 0;
-  b->o_mats = up(sizeof(ExecCtrl));
-  b->o_order = b->o_mats + up(sizeof(ExecMat) * count);
+  b->z = batch_sizes(count, factors);
+  b->B = batch_layout(count, b->z);
   ExecCtrl ctrl{};
-  hipError_t e = hipMemcpyAsync(b->ws + b->o_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(b->ws + b->o_mats, mats.data(), sizeof(ExecMat) * count, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(b->ws + b->o_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st);
+  char* w = b->ws;
+  hipError_t e = hipMemcpyAsync(w + b->B.ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.mats, mats.data(), sizeof(ExecMat) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.desc, desc.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !tmap.empty())
+    e = hipMemcpyAsync(w + b->B.tmap, tmap.data(), tmap.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !rmap.empty())
+    e = hipMemcpyAsync(w + b->B.rmap, rmap.data(), rmap.size() * 4, hipMemcpyHostToDevice, st);
   // host vectors must outlive the asynchronous copies
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) { delete b; return STILES_EDEVICE; }
@@ -561,18 +630,53 @@ extern "C" stiles_status stiles_batch_factorize(stiles_batch* b, const double* c
   set_error_arg(0);
   if (!b) { set_error_arg(1); return STILES_EINVAL; }
   if (!d_values) { set_error_arg(2); return STILES_EINVAL; }
-  for (size_t i = 0; i < b->factors.size(); i++) {
+  const size_t count = b->factors.size();
+  for (size_t i = 0; i < count; i++)
     if (!d_values[i]) { set_error_arg(2); return STILES_EINVAL; }
-    stiles_status r = scatter_values(b->factors[i], d_values[i], st);
-    if (r != STILES_OK) return r;
+  if (b->all_profile) {
+    // one scatter launch over every tile of every matrix; the value pointers
+    // are uploaded when they differ from the last call's (the upload waits
+    // for the stream, so earlier launches reading the old array are done)
+    if (b->vptr.size() != count || !std::equal(b->vptr.begin(), b->vptr.end(), d_values)) {
+      hipError_t e = hipStreamSynchronize(st);
+      b->vptr.assign(d_values, d_values + count);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + b->B.vptr, b->vptr.data(), sizeof(double*) * count, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) { b->vptr.clear(); return STILES_EDEVICE; }
+    }
+    hipError_t e = launch_scatter_batch(b->T, reinterpret_cast<const BatchDesc*>(b->ws + b->B.desc),
+                                        reinterpret_cast<const double* const*>(b->ws + b->B.vptr),
+                                        reinterpret_cast<const int2*>(b->ws + b->B.tmap), (int64_t)b->z.tiles, st);
+    if (e != hipSuccess) return STILES_EDEVICE;
+  } else {
+    for (size_t i = 0; i < count; i++) {
+      stiles_status r = scatter_values(b->factors[i], d_values[i], st);
+      if (r != STILES_OK) return r;
+    }
   }
   const int cap = device_wg_capacity(b->T);
-  hipError_t e = launch_exec(b->T, reinterpret_cast<const ExecMat*>(b->ws + b->o_mats),
-                             reinterpret_cast<const int32_t*>(b->ws + b->o_order), b->total,
-                             reinterpret_cast<ExecCtrl*>(b->ws + b->o_ctrl), 0, std::min<int>(cap, b->total), st);
+  stiles_factor* f0 = b->factors[0];
+  if (f0->timing) hipEventRecord(f0->ev[0], st);
+  hipError_t e = launch_exec(b->T, reinterpret_cast<const ExecMat*>(b->ws + b->B.mats),
+                             reinterpret_cast<const int32_t*>(b->ws + b->B.order), b->total,
+                             reinterpret_cast<ExecCtrl*>(b->ws + b->B.ctrl), 0, std::min<int>(cap, b->total), st);
+  if (f0->timing) hipEventRecord(f0->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   for (auto* f : b->factors) { f->state = 0; f->anorm = -1.0; }
   return STILES_OK;
+}
+
+extern "C" stiles_status stiles_batch_logdet(stiles_batch* b, double* d_out, hipStream_t st) {
+  set_error_arg(0);
+  if (!b) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_out) { set_error_arg(2); return STILES_EINVAL; }
+  for (auto* f : b->factors)
+    if (f->state == -1 || f->state == 2) return STILES_ESTATE;
+  hipError_t e = launch_logdet_batch(b->T, reinterpret_cast<const BatchDesc*>(b->ws + b->B.desc),
+                                     (int32_t)b->factors.size(), reinterpret_cast<const int2*>(b->ws + b->B.rmap),
+                                     (int64_t)b->z.rows, d_out, st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
 
 extern "C" void stiles_batch_destroy(stiles_batch* b) { delete b; }

@@ -863,19 +863,15 @@ hipError_t launch_exec(int T, const ExecMat* d_mats, const int32_t* d_order, int
 
 // ------------------------------------------------------------ value scatter
 
+// One T x T tile of the store from row-profile values: staged through LDS so
+// that the reads follow the input rows and the stores the column-major tile.
 template <int T>
-__global__ __launch_bounds__(NT) void scatter_profile_kernel(const double* __restrict__ vals,
-                                                             const int64_t* __restrict__ in_rp,
-                                                             const int64_t* __restrict__ f,
-                                                             const int32_t* __restrict__ trow,
-                                                             const int32_t* __restrict__ tcol,
-                                                             const int64_t* __restrict__ row_base,
-                                                             const int32_t* __restrict__ row_cnt, double* tiles,
-                                                             double* orig, unsigned long long* info) {
+__device__ __forceinline__ void scatter_tile(const double* __restrict__ vals, const int64_t* __restrict__ in_rp,
+                                             const int64_t* __restrict__ f, int m, int j,
+                                             const int64_t* __restrict__ row_base,
+                                             const int32_t* __restrict__ row_cnt, double* out, double* o2,
+                                             double* buf) {
   constexpr int TT = T * T;
-  __shared__ double buf[T * (T + 1)];
-  const int64_t t = blockIdx.x;
-  const int m = trow[t], j = tcol[t];
   const int64_t rb = row_base[m], cb = row_base[j];
   const int rc = row_cnt[m], cc = row_cnt[j];
   for (int e = threadIdx.x; e < TT; e += NT) {
@@ -891,15 +887,55 @@ __global__ __launch_bounds__(NT) void scatter_profile_kernel(const double* __res
     buf[r * (T + 1) + c] = v;
   }
   __syncthreads();
-  double* out = tiles + t * TT;
-  double* o2 = orig ? orig + t * TT : nullptr;
   for (int e = threadIdx.x; e < TT; e += NT) {
     const int c = e / T, r = e % T;   // column-major store
     const double v = buf[r * (T + 1) + c];
     out[e] = v;
     if (o2) o2[e] = v;
   }
+}
+
+template <int T>
+__global__ __launch_bounds__(NT) void scatter_profile_kernel(const double* __restrict__ vals,
+                                                             const int64_t* __restrict__ in_rp,
+                                                             const int64_t* __restrict__ f,
+                                                             const int32_t* __restrict__ trow,
+                                                             const int32_t* __restrict__ tcol,
+                                                             const int64_t* __restrict__ row_base,
+                                                             const int32_t* __restrict__ row_cnt, double* tiles,
+                                                             double* orig, unsigned long long* info) {
+  constexpr int TT = T * T;
+  __shared__ double buf[T * (T + 1)];
+  const int64_t t = blockIdx.x;
+  scatter_tile<T>(vals, in_rp, f, trow[t], tcol[t], row_base, row_cnt, tiles + t * TT, orig ? orig + t * TT : nullptr,
+                  buf);
   if (t == 0 && threadIdx.x == 0) *info = ~0ull;
+}
+
+// every tile of every matrix of a batch: block b handles tile tmap[b].y of
+// matrix tmap[b].x
+template <int T>
+__global__ __launch_bounds__(NT) void scatter_batch_kernel(const BatchDesc* __restrict__ desc,
+                                                           const double* const* __restrict__ vals,
+                                                           const int2* __restrict__ tmap) {
+  constexpr int TT = T * T;
+  __shared__ double buf[T * (T + 1)];
+  const int2 mt = tmap[blockIdx.x];
+  const BatchDesc& d = desc[mt.x];
+  const int64_t t = mt.y;
+  scatter_tile<T>(vals[mt.x], d.in_rp, d.f, d.trow[t], d.tcol[t], d.row_base, d.row_cnt, d.tiles + t * TT,
+                  d.orig ? d.orig + t * TT : nullptr, buf);
+  if (t == 0 && threadIdx.x == 0) *d.info = ~0ull;
+}
+
+hipError_t launch_scatter_batch(int T, const BatchDesc* desc, const double* const* vals, const int2* tmap,
+                                int64_t total_tiles, hipStream_t st) {
+  if (total_tiles <= 0) return hipSuccess;
+  if (T == 64)
+    hipLaunchKernelGGL(scatter_batch_kernel<64>, dim3((unsigned)total_tiles), dim3(NT), 0, st, desc, vals, tmap);
+  else
+    hipLaunchKernelGGL(scatter_batch_kernel<32>, dim3((unsigned)total_tiles), dim3(NT), 0, st, desc, vals, tmap);
+  return hipGetLastError();
 }
 
 hipError_t launch_scatter_profile(int T, const double* vals, const int64_t* in_rp, const int64_t* f,
@@ -993,28 +1029,25 @@ hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const i
 
 // ------------------------------------------------------------------ logdet
 
+// log-determinant: per tile row a fixed-shape wave reduction of log L_ii,
+// then one block sums the tile-row partials (strided, then a binary tree).
+// The single-matrix and batched launches share these two steps, so their
+// results agree bit for bit.
 template <int T>
-__global__ __launch_bounds__(NT) void logdet_partial_kernel(const double* __restrict__ tiles,
-                                                            const int32_t* __restrict__ trow_ptr, double* part) {
-  constexpr int TT = T * T;
-  __shared__ double ws[NT / 64];
-  const int m = blockIdx.x;
-  const double* D = tiles + (int64_t)(trow_ptr[m + 1] - 1) * TT;
+__device__ __forceinline__ void logdet_row(const double* __restrict__ D, double* part_m, double* ws) {
   double v = threadIdx.x < T ? log(D[threadIdx.x * (T + 1)]) : 0.0;
-  // fixed-shape wave reduction, then waves in index order
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int q = 0; q < NT / 64; q++) s += ws[q];
-    part[m] = s;
+    *part_m = s;
   }
 }
 
-__global__ __launch_bounds__(NT) void logdet_final_kernel(const double* __restrict__ part, int32_t n,
-                                                          const unsigned long long* info, double* out) {
-  __shared__ double sh[NT];
+__device__ __forceinline__ void logdet_sum(const double* __restrict__ part, int32_t n,
+                                           const unsigned long long* info, double* out, double* sh) {
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) s += part[i];
   sh[threadIdx.x] = s;
@@ -1026,6 +1059,37 @@ __global__ __launch_bounds__(NT) void logdet_final_kernel(const double* __restri
   if (threadIdx.x == 0) *out = (*info == ~0ull) ? 2.0 * sh[0] : __builtin_nan("");
 }
 
+template <int T>
+__global__ __launch_bounds__(NT) void logdet_partial_kernel(const double* __restrict__ tiles,
+                                                            const int32_t* __restrict__ trow_ptr, double* part) {
+  constexpr int TT = T * T;
+  __shared__ double ws[NT / 64];
+  const int m = blockIdx.x;
+  logdet_row<T>(tiles + (int64_t)(trow_ptr[m + 1] - 1) * TT, part + m, ws);
+}
+
+__global__ __launch_bounds__(NT) void logdet_final_kernel(const double* __restrict__ part, int32_t n,
+                                                          const unsigned long long* info, double* out) {
+  __shared__ double sh[NT];
+  logdet_sum(part, n, info, out, sh);
+}
+
+template <int T>
+__global__ __launch_bounds__(NT) void logdet_partial_batch_kernel(const BatchDesc* __restrict__ desc,
+                                                                  const int2* __restrict__ rmap) {
+  constexpr int TT = T * T;
+  __shared__ double ws[NT / 64];
+  const int2 mr = rmap[blockIdx.x];
+  const BatchDesc& d = desc[mr.x];
+  logdet_row<T>(d.tiles + (int64_t)(d.trow_ptr[mr.y + 1] - 1) * TT, d.ldpart + mr.y, ws);
+}
+
+__global__ __launch_bounds__(NT) void logdet_final_batch_kernel(const BatchDesc* __restrict__ desc, double* out) {
+  __shared__ double sh[NT];
+  const BatchDesc& d = desc[blockIdx.x];
+  logdet_sum(d.ldpart, d.ntr, d.info, out + blockIdx.x, sh);
+}
+
 hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr, double* part,
                          const unsigned long long* info, double* out, hipStream_t st) {
   if (T == 64)
@@ -1033,6 +1097,17 @@ hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, in
   else
     hipLaunchKernelGGL(logdet_partial_kernel<32>, dim3(ntr), dim3(NT), 0, st, tiles, trow_ptr, part);
   hipLaunchKernelGGL(logdet_final_kernel, dim3(1), dim3(NT), 0, st, part, ntr, info, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_logdet_batch(int T, const BatchDesc* desc, int32_t count, const int2* rmap, int64_t total_rows,
+                               double* out, hipStream_t st) {
+  if (count <= 0 || total_rows <= 0) return hipSuccess;
+  if (T == 64)
+    hipLaunchKernelGGL(logdet_partial_batch_kernel<64>, dim3((unsigned)total_rows), dim3(NT), 0, st, desc, rmap);
+  else
+    hipLaunchKernelGGL(logdet_partial_batch_kernel<32>, dim3((unsigned)total_rows), dim3(NT), 0, st, desc, rmap);
+  hipLaunchKernelGGL(logdet_final_batch_kernel, dim3((unsigned)count), dim3(NT), 0, st, desc, out);
   return hipGetLastError();
 }
 

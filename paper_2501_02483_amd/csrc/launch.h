@@ -34,6 +34,14 @@ hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const i
 hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr, double* part,
                          const unsigned long long* info, double* out, hipStream_t st);
 
+// every tile of every matrix of a batch (tmap: matrix, tile pairs)
+hipError_t launch_scatter_batch(int T, const BatchDesc* desc, const double* const* vals, const int2* tmap,
+                                int64_t total_tiles, hipStream_t st);
+
+// log-determinants of every matrix of a batch into out[0..count)
+hipError_t launch_logdet_batch(int T, const BatchDesc* desc, int32_t count, const int2* rmap, int64_t total_rows,
+                               double* out, hipStream_t st);
+
 // B (original order, column-major, ldb) -> Y (tile rows, T x nrhs blocks)
 hipError_t launch_pack(int T, const double* B, int64_t ldb, int nrhs, const int64_t* perm, const int64_t* row_base,
                        const int32_t* row_cnt, int32_t ntr, double* Y, hipStream_t st);

@@ -67,6 +67,24 @@ struct ExecMat {
   int32_t pad;
 };
 
+// Per-matrix tables for the batched scatter and log-determinant launches
+// (one launch over every matrix of a batch instead of one per matrix).
+struct BatchDesc {
+  const int64_t* in_rp;     // row pointers of the row-profile input
+  const int64_t* f;         // first column of each row
+  const int32_t* trow;      // tile row of each stored tile
+  const int32_t* tcol;      // tile column of each stored tile
+  const int32_t* trow_ptr;  // first stored tile of each tile row
+  const int64_t* row_base;
+  const int32_t* row_cnt;
+  double* tiles;
+  double* orig;             // mixed mode: copy of the scattered values, else null
+  double* ldpart;           // per tile row partial sums of log L_ii
+  unsigned long long* info;
+  int32_t ntiles;
+  int32_t ntr;
+};
+
 // Launch control block (one per concurrent launch).
 struct ExecCtrl {
   int32_t ticket;

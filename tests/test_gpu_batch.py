@@ -64,3 +64,44 @@ def test_batch_reuse_and_failure_isolated():
     # the workspaces are reusable after the batch (counters re-armed)
     S.factorize_batch(facs, [torch.from_numpy(v).cuda() for v in vals])
     assert [f.info() for f in facs] == [0, 0, 0]
+
+
+def test_batch_logdet_and_refactorize():
+    """Batched scatter + batched log-determinant: every value equals the
+    single-factor stiles_logdet bit for bit, a failed matrix gives NaN, and a
+    second factorize with new value arrays (new pointers) is picked up."""
+    import torch
+    rng = np.random.default_rng(23)
+    pats = [I.make_pattern(int(rng.integers(100, 2500)), int(rng.integers(0, 40)), int(rng.integers(5, 120)))
+            for _ in range(7)]
+    vals = [I.make_values(p, seed=500 + i) for i, p in enumerate(pats)]
+    syms = [S.Symbolic.from_pattern(p, tile=64) for p in pats]
+    facs = [S.Factor(s) for s in syms]
+    batch = S.Batch(facs)
+    dvals = [torch.from_numpy(v).cuda() for v in vals]
+    say("[gpu batch] batched logdet, %d matrices" % len(pats))
+    batch.factorize(dvals)
+    lds = batch.logdet()
+    torch.cuda.synchronize()
+    for i, f in enumerate(facs):
+        assert f.info() == 0
+        one = f.logdet()
+        assert torch.equal(one, lds[i:i + 1])
+        ref = oracle_reference(pats[i], vals[i])
+        assert abs(lds[i].item() - ref["logdet"]) <= 1e-12 * abs(ref["logdet"])
+    # new arrays (other pointers): one matrix made indefinite
+    vals2 = [I.make_values(p, seed=900 + i) for i, p in enumerate(pats)]
+    rp = pats[3].row_ptr()
+    vals2[3][rp[pats[3].N // 2 + 1] - 1] = -1.0
+    dvals2 = [torch.from_numpy(v).cuda() for v in vals2]
+    batch.factorize(dvals2)
+    lds2 = batch.logdet()
+    torch.cuda.synchronize()
+    for i, f in enumerate(facs):
+        if i == 3:
+            assert f.info() > 0
+            assert torch.isnan(lds2[i]).item()
+            continue
+        assert f.info() == 0
+        ref = oracle_reference(pats[i], vals2[i])
+        assert abs(lds2[i].item() - ref["logdet"]) <= 1e-12 * abs(ref["logdet"])
