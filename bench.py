@@ -113,7 +113,9 @@ def bench_single(args):
         p, seed, nrhs, rseed = I.variable_band(), 2, 8, 102
     vals = I.make_values(p, seed=seed)
     B = I.rhs(p.N, nrhs, seed=rseed)
-    sym = S.Symbolic.from_pattern(p, tile=args.tile, tree_min_ratio=args.tree_ratio)
+    ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
+    sym = S.Symbolic.from_pattern(p, tile=args.tile, tree_min_ratio=args.tree_ratio, ordering=ordering,
+                                  nd_parts=args.parts)
     fac = S.Factor(sym, S.STILES_FP64, nrhs_max=nrhs)
     dv = torch.from_numpy(vals).cuda()
     dB0 = to_device_cols(B)
@@ -177,6 +179,8 @@ def bench_single(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": p.name, "n": p.n, "arrow": p.a, "N": p.N, "tile": args.tile, "nrhs": nrhs,
+                   "ordering": {1: "none", 3: "adaptable_nd"}.get(sym.info.ordering_used, "other"),
+                   "nd_parts": sym.info.nd_parts,
                    "value_seed": seed, "rhs_seed": rseed, "ops": "factorize+solve+logdet",
                    "parallelism": "single GPU, persistent DAG executor"},
         "factorizations_per_s": 1e3 / ms,
@@ -407,6 +411,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tile", type=int, default=64)
     ap.add_argument("--tree-ratio", type=int, default=2)
+    ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
+                    help="single-matrix workloads: natural order or adaptable nested dissection")
+    ap.add_argument("--parts", type=int, default=0, help="adaptable ND partitions (0 = chosen by the analysis)")
     ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal"])
     ap.add_argument("--rocpd-summary", default="", help="print a per-kernel table of a rocprofv3 database and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -54,10 +54,18 @@ typedef int32_t stiles_status;
 
 /* Orderings (Section III-A).  AUTO tries partial RCM on the band part (the
  * arrow rows are left in place) and keeps it only if it reduces the number
- * of stored tiles ("if there is no improvement, the method is not used"). */
+ * of stored tiles (a method that brings no improvement is not used).
+ * ADAPTABLE_ND does the same, then cuts the band part into nd_parts
+ * partitions (0: the count with the shortest estimated dependency chain)
+ * separated by blocks of rows as wide as the local bandwidth; the separators
+ * move to the end of the band part and join the arrow, the partitions are
+ * factored concurrently, the last one in reverse row order.  It is used only
+ * if a feasible cut exists (else the ordering falls back as AUTO).  For row-
+ * profile input only NONE, AUTO (= NONE) and ADAPTABLE_ND are supported. */
 #define STILES_ORDER_AUTO 0
 #define STILES_ORDER_NONE 1
 #define STILES_ORDER_PARTIAL_RCM 2
+#define STILES_ORDER_ADAPTABLE_ND 3
 
 /* Precisions of the numerical factorization. */
 #define STILES_FP64 0     /* every step in FP64                                     */
@@ -79,25 +87,32 @@ typedef struct stiles_opts {
   double refine_tol;      /* mixed mode: stop when the backward error of every
                              right-hand side is <= refine_tol (0 = 2^-52 * N^0.5)    */
   int32_t refine_max_iter;/* mixed mode: at most this many refinement steps (0 = 30) */
-  int32_t reserved[3];
+  int32_t nd_parts;       /* ADAPTABLE_ND: number of partitions, 2..64 (0 = choose)   */
+  int32_t reserved[2];
 } stiles_opts;
 
 typedef struct stiles_symbolic_info {
-  int64_t N, n, arrow;    /* order, band part, arrow width                           */
+  int64_t N, n, arrow;    /* order, band part, arrow width of P A P^T (with adaptable
+                             ND the separators count as arrow rows)                  */
   int32_t tile;           /* tile size T                                             */
-  int32_t ordering_used;  /* STILES_ORDER_NONE or STILES_ORDER_PARTIAL_RCM           */
+  int32_t ordering_used;  /* STILES_ORDER_NONE, _PARTIAL_RCM or _ADAPTABLE_ND (the
+                             last possibly on top of partial RCM)                    */
   int64_t tile_rows;      /* band tile rows + arrow tile rows                        */
   int64_t band_tile_rows;
   int64_t tiles;          /* stored T x T tiles of the factor                       */
-  int64_t nnz_L;          /* entries of L inside the envelope (band+arrow, lower)    */
-  double flops_alg;       /* sum_j (eta_j + 1)^2, eta_j = sub-diagonal count of col j */
+  int64_t nnz_L;          /* entries inside the envelope of P A P^T (lower; the
+                             layout of stiles_factor_extract)                        */
+  double flops_alg;       /* sum_j (eta_j + 1)^2, eta_j = sub-diagonal count of col j
+                             over the envelope before adaptable ND (the same work
+                             for every partition count; ND's extra fill is in
+                             flops_exec)                                             */
   double flops_exec;      /* flops the tile kernels execute (padded tiles)           */
   int64_t factor_tasks;   /* tasks in the factorization DAG                          */
   int64_t solve_tasks;    /* tasks in the solve DAG                                  */
   int64_t corner_accumulations; /* tile products summed into the arrow-corner tile(s)
                                    from band columns (about one per band tile row)   */
   int32_t tree_used;      /* 1 if the arrow corner is reduced by a tree              */
-  int32_t reserved;
+  int32_t nd_parts;       /* partitions of the adaptable ND ordering (1 if none)     */
 } stiles_symbolic_info;
 
 typedef struct stiles_solve_report {

@@ -35,6 +35,7 @@ STILES_ESTATE = -5
 STILES_ORDER_AUTO = 0
 STILES_ORDER_NONE = 1
 STILES_ORDER_PARTIAL_RCM = 2
+STILES_ORDER_ADAPTABLE_ND = 3
 STILES_FP64 = 0
 STILES_MIXED32 = 1
 
@@ -54,7 +55,7 @@ EXPORTED = [
 class stiles_opts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("ordering", ctypes.c_int32), ("tree_min_ratio", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("nd_parts", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class stiles_symbolic_info(ctypes.Structure):
@@ -64,10 +65,10 @@ class stiles_symbolic_info(ctypes.Structure):
                 ("nnz_L", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("flops_exec", ctypes.c_double),
                 ("factor_tasks", ctypes.c_int64), ("solve_tasks", ctypes.c_int64),
                 ("corner_accumulations", ctypes.c_int64), ("tree_used", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("nd_parts", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class stiles_solve_report(ctypes.Structure):
@@ -161,11 +162,11 @@ def _stream(stream=None):
 # ------------------------------------------------------- raw C-ABI wrappers
 
 def stiles_default_opts(tile=64, ordering=STILES_ORDER_AUTO, tree_min_ratio=2, chunk=0, refine_tol=0.0,
-                        refine_max_iter=0):
+                        refine_max_iter=0, nd_parts=0):
     o = stiles_opts()
     load_library().stiles_default_opts(ctypes.byref(o))
     o.tile, o.ordering, o.tree_min_ratio, o.chunk = tile, ordering, tree_min_ratio, chunk
-    o.refine_tol, o.refine_max_iter = refine_tol, refine_max_iter
+    o.refine_tol, o.refine_max_iter, o.nd_parts = refine_tol, refine_max_iter, nd_parts
     return o
 
 

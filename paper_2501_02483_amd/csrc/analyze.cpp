@@ -205,10 +205,184 @@ int64_t envelope_tiles(const std::vector<int64_t>& f, int64_t n, int32_t T) {
   return tot;
 }
 
+// ------------------------------------------------------------ adaptable ND
+// Adaptable nested dissection (Section III-A).  The band part is cut into P
+// contiguous parts B_1..B_P by separators S_1..S_{P-1}: blocks of consecutive
+// rows such that no band row after S_j has its first column before S_j (the
+// separator is as wide as the local bandwidth).  The separators move behind
+// the parts, ahead of the arrow, and join it; the parts keep their band shape
+// and have no dependencies between them, so their tile-column chains run
+// concurrently.  The last part is reversed, so that its separator meets its
+// last columns instead of filling across it (an interior part touches two
+// separators and the one at its start still fills across it: the thicker
+// arrow of the paper's second partition).  Parts before the last are whole
+// tile rows and separators are padded to whole tile rows, so no tile mixes
+// two blocks.
+struct Seg {
+  int64_t olo, ohi, nlo;   // original rows [olo, ohi) go to new rows from nlo
+  bool rev;                // in reverse order
+};
+
+inline int64_t seg_new(const Seg& g, int64_t o) { return g.rev ? g.nlo + (g.ohi - 1 - o) : g.nlo + (o - g.olo); }
+
+struct NDPlan {
+  int32_t P = 1;
+  std::vector<int64_t> part_lo, part_hi, sep_lo, sep_hi;   // original rows
+  int64_t chain = 0;      // tile steps on the longest dependency chain (estimate)
+};
+
+// need[c]: rows a separator starting at row c must span so that no later band
+// row couples to a row before c (0 if nothing couples across c)
+std::vector<int64_t> separator_need(const std::vector<int64_t>& f, int64_t n) {
+  std::vector<int64_t> H(n + 1, -1);
+  for (int64_t i = 0; i < n; i++) H[f[i]] = std::max(H[f[i]], i);
+  std::vector<int64_t> need(n + 1, 0);
+  int64_t g = -1;   // last row whose first column is < c
+  for (int64_t c = 0; c <= n; c++) {
+    if (c > 0) g = std::max(g, H[c - 1]);
+    need[c] = std::max<int64_t>(0, g + 1 - c);
+  }
+  return need;
+}
+
+// Cut points for P parts: each cut is searched in a window around the point
+// that balances the remaining rows, minimizing separator tile rows plus half
+// the imbalance (in tile rows).
+bool nd_plan_for(const std::vector<int64_t>& need, int64_t n, int64_t arrow, int32_t T, int32_t P, NDPlan& out) {
+  if (P < 2 || n < (int64_t)P * 2 * T) return false;
+  auto padded = [&](int64_t c) { return (need[c] + T - 1) / T * T; };
+  // typical separator: median padded need over the band (sampled)
+  std::vector<int64_t> smp;
+  for (int64_t c = T; c < n; c += std::max<int64_t>(T, n / 256)) smp.push_back(padded(c));
+  if (smp.empty()) return false;
+  std::nth_element(smp.begin(), smp.begin() + smp.size() / 2, smp.end());
+  const int64_t sp_typ = smp[smp.size() / 2];
+  NDPlan pl;
+  pl.P = P;
+  int64_t start = 0;
+  for (int32_t j = 0; j < P - 1; j++) {
+    const int32_t left = P - j;
+    int64_t Lt = (n - start - (left - 1) * sp_typ) / left;
+    Lt = std::max<int64_t>(T, (Lt + T / 2) / T * T);
+    const int64_t ideal = start + Lt;
+    const int64_t W = std::max<int64_t>(T, (Lt / 4) / T * T);
+    int64_t best = -1;
+    double bestcost = 1e300;
+    for (int64_t c = std::max(start + T, ideal - W); c <= ideal + W && c < n; c += T) {
+      const int64_t sp = padded(c);
+      if (c + sp + (int64_t)(left - 1) * T > n) continue;   // room for the parts after it
+      const double cost = (double)sp / T + 0.5 * std::fabs((double)(c - ideal)) / T;
+      if (cost < bestcost) { bestcost = cost; best = c; }
+    }
+    if (best < 0) return false;
+    const int64_t sp = padded(best);
+    pl.part_lo.push_back(start);
+    pl.part_hi.push_back(best);
+    pl.sep_lo.push_back(best);
+    pl.sep_hi.push_back(best + sp);
+    start = best + sp;
+  }
+  if (n - start < T) return false;
+  pl.part_lo.push_back(start);
+  pl.part_hi.push_back(n);
+  int64_t longest = 0, seps = 0;
+  for (int32_t j = 0; j < P; j++) longest = std::max(longest, (pl.part_hi[j] - pl.part_lo[j] + T - 1) / T);
+  for (int32_t j = 0; j < P - 1; j++) seps += (pl.sep_hi[j] - pl.sep_lo[j]) / T;
+  pl.chain = longest + seps + (arrow + T - 1) / T;
+  out = pl;
+  return true;
+}
+
+// requested P >= 2: that many parts (else the best feasible); 0: the P in
+// [2, 64] with the shortest estimated chain.  False when no cut is feasible.
+bool nd_plan(const std::vector<int64_t>& f, int64_t n, int64_t arrow, int32_t T, int32_t P_req, NDPlan& out) {
+  const std::vector<int64_t> need = separator_need(f, n);
+  if (P_req >= 2 && nd_plan_for(need, n, arrow, T, P_req, out)) return true;
+  bool found = false;
+  for (int32_t P = 2; P <= 64; P++) {
+    NDPlan pl;
+    if (!nd_plan_for(need, n, arrow, T, P, pl)) break;
+    if (!found || pl.chain < out.chain) { out = pl; found = true; }
+  }
+  return found;
+}
+
+// new-order segments of a plan: parts (the last reversed), separators, arrow
+std::vector<Seg> nd_segments(const NDPlan& pl, int64_t n, int64_t N, int64_t* band_rows) {
+  std::vector<Seg> sg;
+  int64_t pos = 0;
+  for (int32_t j = 0; j < pl.P; j++) {
+    sg.push_back({pl.part_lo[j], pl.part_hi[j], pos, j == pl.P - 1});
+    pos += pl.part_hi[j] - pl.part_lo[j];
+  }
+  *band_rows = pos;
+  for (int32_t j = 0; j + 1 < pl.P; j++)
+    if (pl.sep_hi[j] > pl.sep_lo[j]) {
+      sg.push_back({pl.sep_lo[j], pl.sep_hi[j], pos, false});
+      pos += pl.sep_hi[j] - pl.sep_lo[j];
+    }
+  if (N > n) sg.push_back({n, N, pos, false});
+  return sg;
+}
+
+// Profile and tile pattern of P A P^T for a row-profile input (row i spans
+// columns [fin_i, i]) under a segment permutation: every row interval maps
+// to a few new intervals, split at the diagonal into a row part and a column
+// part (entries that land above the diagonal are stored transposed).
+void permuted_profile(stiles_symbolic& s, std::vector<Seg> segs, const std::vector<int64_t>& fin,
+                      std::vector<std::vector<int32_t>>& a_cols) {
+  const int64_t N = s.N;
+  std::sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) { return x.olo < y.olo; });
+  s.f.resize(N);
+  for (int64_t p = 0; p < N; p++) s.f[p] = p;
+  a_cols.assign(s.ntr, {});
+  size_t gi = 0;
+  for (int64_t i = 0; i < N; i++) {
+    while (segs[gi].ohi <= i) gi++;
+    const int64_t p = seg_new(segs[gi], i);
+    const int64_t tp = tile_of_col(s, p);
+    size_t k = gi;
+    while (k > 0 && segs[k].olo > fin[i]) k--;
+    for (; k < segs.size() && segs[k].olo <= i; k++) {
+      const Seg& g = segs[k];
+      const int64_t x = std::max(fin[i], g.olo), y = std::min(i, g.ohi - 1);
+      if (x > y) continue;
+      const int64_t u = seg_new(g, g.rev ? y : x), v = seg_new(g, g.rev ? x : y);
+      if (u <= p) {
+        const int64_t hi = std::min(v, p);
+        s.f[p] = std::min(s.f[p], u);
+        for (int64_t tc = tile_of_col(s, u); tc <= tile_of_col(s, hi); tc++) a_cols[tc].push_back((int32_t)tp);
+      }
+      if (v > p) {
+        const int64_t lo = std::max(u, p + 1);
+        for (int64_t q = lo; q <= v; q++) s.f[q] = std::min(s.f[q], p);
+        for (int64_t tr = tile_of_col(s, lo); tr <= tile_of_col(s, v); tr++) a_cols[tp].push_back((int32_t)tr);
+      }
+    }
+  }
+  for (auto& c : a_cols) { std::sort(c.begin(), c.end()); c.erase(std::unique(c.begin(), c.end()), c.end()); }
+}
+
+// sum_j (eta_j + 1)^2 over the element envelope of a lower profile f
+double envelope_flops(const std::vector<int64_t>& f) {
+  const int64_t N = (int64_t)f.size();
+  std::vector<int64_t> d(N + 1, 0);
+  for (int64_t i = 0; i < N; i++) { d[f[i]] += 1; d[i] -= 1; }
+  double F = 0.0;
+  int64_t run = 0;
+  for (int64_t j = 0; j < N; j++) {
+    run += d[j];          // rows i > j with f_i <= j
+    const double e = (double)run + 1.0;
+    F += e * e;
+  }
+  return F;
+}
+
 stiles_status check_opts(const stiles_opts* o, int arg) {
   if (!o) return STILES_OK;
   if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_err_arg = arg; return STILES_ENOTSUP; }
-  if (o->ordering < STILES_ORDER_AUTO || o->ordering > STILES_ORDER_PARTIAL_RCM) { g_err_arg = arg; return STILES_EINVAL; }
+  if (o->ordering < STILES_ORDER_AUTO || o->ordering > STILES_ORDER_ADAPTABLE_ND) { g_err_arg = arg; return STILES_EINVAL; }
+  if (o->nd_parts < 0 || o->nd_parts > 64) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->chunk < 0 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
   return STILES_OK;
 }
@@ -275,6 +449,37 @@ extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, c
   init_common(*s, N, arrow, opts);
   s->profile_input = true;
   s->ordering_used = STILES_ORDER_NONE;
+  if (s->opts.ordering == STILES_ORDER_ADAPTABLE_ND && n_band > 0) {
+    std::vector<int64_t> fin(N, 0);
+    for (int64_t i = 0; i < n_band; i++) fin[i] = first_col[i];
+    NDPlan pl;
+    if (nd_plan(fin, n_band, arrow, s->T, s->opts.nd_parts, pl)) {
+      int64_t nb2 = 0;
+      const std::vector<Seg> segs = nd_segments(pl, n_band, N, &nb2);
+      init_common(*s, N, N - nb2, opts);   // the separators join the arrow
+      s->ordering_used = STILES_ORDER_ADAPTABLE_ND;
+      s->nd_parts = pl.P;
+      s->perm_identity = false;
+      s->perm.resize(N);
+      for (const Seg& g : segs)
+        for (int64_t o = g.olo; o < g.ohi; o++) s->perm[seg_new(g, o)] = o;
+      s->iperm.resize(N);
+      for (int64_t i = 0; i < N; i++) s->iperm[s->perm[i]] = i;
+      s->in_rp_in.resize(N + 1);
+      s->in_rp_in[0] = 0;
+      for (int64_t i = 0; i < N; i++) s->in_rp_in[i + 1] = s->in_rp_in[i] + (i - fin[i] + 1);
+      std::vector<std::vector<int32_t>> a_cols;
+      permuted_profile(*s, segs, fin, a_cols);
+      s->f_pre = fin;
+      s->fin = std::move(fin);
+      s->in_rp.resize(N + 1);
+      s->in_rp[0] = 0;
+      for (int64_t i = 0; i < N; i++) s->in_rp[i + 1] = s->in_rp[i] + (i - s->f[i] + 1);
+      finish_symbolic(*s, a_cols);
+      *out = s;
+      return STILES_OK;
+    }
+  }
   s->perm.resize(N);
   std::iota(s->perm.begin(), s->perm.end(), 0);
   s->iperm = s->perm;
@@ -356,16 +561,44 @@ extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t*
         f_r[hi] = std::min(f_r[hi], lo);
       }
     bool use = s->opts.ordering == STILES_ORDER_PARTIAL_RCM;
-    if (s->opts.ordering == STILES_ORDER_AUTO)
+    if (s->opts.ordering == STILES_ORDER_AUTO || s->opts.ordering == STILES_ORDER_ADAPTABLE_ND)
       use = envelope_tiles(f_r, n, s->T) < envelope_tiles(f_id, n, s->T);   // fill check
     if (use) {
       for (int64_t i = 0; i < n; i++) perm[i] = ord[i];
       s->ordering_used = STILES_ORDER_PARTIAL_RCM;
     }
   }
+  if (s->opts.ordering == STILES_ORDER_ADAPTABLE_ND && n > 0) {
+    // band profile under the ordering so far, then the partition plan on it
+    std::vector<int64_t> inv(N);
+    for (int64_t i = 0; i < N; i++) inv[perm[i]] = i;
+    std::vector<int64_t> fcur(N);
+    for (int64_t i = 0; i < N; i++) fcur[i] = i;
+    for (int64_t j = 0; j < N; j++)
+      for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
+        int64_t p = inv[rowind[q]], c = inv[j];
+        int64_t hi = std::max(p, c), lo = std::min(p, c);
+        fcur[hi] = std::min(fcur[hi], lo);
+      }
+    NDPlan pl;
+    if (nd_plan(fcur, n, arrow, s->T, s->opts.nd_parts, pl)) {
+      int64_t nb2 = 0;
+      const std::vector<Seg> segs = nd_segments(pl, n, N, &nb2);
+      std::vector<int64_t> np(N);
+      for (const Seg& g : segs)
+        for (int64_t o = g.olo; o < g.ohi; o++) np[seg_new(g, o)] = perm[o];
+      perm.swap(np);
+      init_common(*s, N, N - nb2, opts);   // the separators join the arrow
+      s->ordering_used = STILES_ORDER_ADAPTABLE_ND;
+      s->nd_parts = pl.P;
+      s->f_pre = std::move(fcur);
+    }
+  }
   s->perm = perm;
   s->iperm.resize(N);
   for (int64_t i = 0; i < N; i++) s->iperm[perm[i]] = i;
+  s->perm_identity = true;
+  for (int64_t i = 0; i < N && s->perm_identity; i++) s->perm_identity = perm[i] == i;
   s->f.assign(N, 0);
   for (int64_t i = 0; i < N; i++) s->f[i] = i;
   for (int64_t j = 0; j < N; j++)
@@ -442,24 +675,9 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
     for (int32_t t = s.trow_ptr[m]; t < s.trow_ptr[m + 1]; t++) ctiles[s.tcol[t]].push_back({m, t});
 
   // ---- statistics over the element envelope
-  {
-    const int64_t N = s.N;
-    std::vector<int64_t> d(N + 1, 0);
-    s.nnzL = 0;
-    for (int64_t i = 0; i < N; i++) {
-      s.nnzL += i - s.f[i] + 1;
-      d[s.f[i]] += 1;
-      d[i] -= 1;
-    }
-    double F = 0.0;
-    int64_t run = 0;
-    for (int64_t j = 0; j < N; j++) {
-      run += d[j];          // rows i > j with f_i <= j
-      double e = (double)run + 1.0;
-      F += e * e;
-    }
-    s.flops_alg = F;
-  }
+  s.nnzL = 0;
+  for (int64_t i = 0; i < s.N; i++) s.nnzL += i - s.f[i] + 1;
+  s.flops_alg = envelope_flops(s.f_pre.empty() ? s.f : s.f_pre);
 
   // ---- factorization DAG
   const int32_t chunk = s.opts.chunk > 0 ? s.opts.chunk : (T == 64 ? 8 : 16);
@@ -663,6 +881,7 @@ extern "C" stiles_status stiles_symbolic_query(const stiles_symbolic* s, stiles_
   info->tiles = s->ntiles;
   info->nnz_L = s->nnzL;
   info->flops_alg = s->flops_alg;
+  info->nd_parts = s->nd_parts;
   info->flops_exec = s->flops_exec;
   info->factor_tasks = (int64_t)(s->ftask.size() / TASK_WORDS);
   info->solve_tasks = (int64_t)(s->stask.size() / TASK_WORDS);

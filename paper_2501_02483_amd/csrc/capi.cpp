@@ -26,7 +26,7 @@ struct Layout {
   size_t ftask, fsucc, frem, fpairs;
   size_t stask, ssucc, srem, spairs;
   size_t row_base, row_cnt, trow_ptr, trow, tcol, perm;
-  size_t in_rp, fprof, map;
+  size_t in_rp, fprof, map, fin, in_rp_in;
   size_t tiles, linv, part, shadow, orig;
   size_t vy, vz, vx, vr, vb, vd;
   size_t ldpart, stats;
@@ -95,6 +95,8 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   L.in_rp = take(s.in_rp.size() * 8);   // row pointers of the permuted envelope
   L.fprof = take(s.f.size() * 8);
   L.map = s.profile_input ? 0 : take(s.map.size() * 8);
+  L.fin = s.fin.empty() ? 0 : take(s.fin.size() * 8);
+  L.in_rp_in = s.in_rp_in.empty() ? 0 : take(s.in_rp_in.size() * 8);
   L.tiles = take(s.ntiles * TT * 8);
   L.linv = take((size_t)s.ntr * TT * 8);
   L.part = take((size_t)s.npart * TT * 8);
@@ -269,6 +271,8 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   U(L.in_rp, s->in_rp.data(), s->in_rp.size() * 8);
   U(L.fprof, s->f.data(), s->f.size() * 8);
   if (!s->profile_input) U(L.map, s->map.data(), s->map.size() * 8);
+  if (!s->fin.empty()) U(L.fin, s->fin.data(), s->fin.size() * 8);
+  if (!s->in_rp_in.empty()) U(L.in_rp_in, s->in_rp_in.data(), s->in_rp_in.size() * 8);
   if (mixed) {
     U(L.ccol_tile, f->plan.ccol_tile.data(), f->plan.ccol_tile.size() * 4);
     U(L.ccol_row, f->plan.ccol_row.data(), f->plan.ccol_row.size() * 4);
@@ -296,7 +300,12 @@ static stiles_status scatter_values(stiles_factor* f, const double* d_values, hi
   const Layout& L = f->L;
   double* orig = f->precision == STILES_MIXED32 ? at<double>(f, L.orig) : nullptr;
   hipError_t e;
-  if (s.profile_input)
+  if (s.profile_input && !s.perm_identity)
+    e = launch_scatter_perm(s.T, d_values, at<int64_t>(f, L.in_rp_in), at<int64_t>(f, L.fin), at<int64_t>(f, L.perm),
+                            at<int32_t>(f, L.trow), at<int32_t>(f, L.tcol), at<int64_t>(f, L.row_base),
+                            at<int32_t>(f, L.row_cnt), s.ntiles, at<double>(f, L.tiles), orig,
+                            at<unsigned long long>(f, L.info), st);
+  else if (s.profile_input)
     e = launch_scatter_profile(s.T, d_values, at<int64_t>(f, L.in_rp), at<int64_t>(f, L.fprof), at<int32_t>(f, L.trow),
                                at<int32_t>(f, L.tcol), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
                                s.ntiles, at<double>(f, L.tiles), orig, at<unsigned long long>(f, L.info), st);
@@ -310,7 +319,9 @@ static stiles_status scatter_values(stiles_factor* f, const double* d_values, hi
 extern "C" stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStream_t st) {
   set_error_arg(0);
   if (!f) { set_error_arg(1); return STILES_EINVAL; }
-  if (!d_values && (f->sym->profile_input ? f->sym->in_rp.back() : (int64_t)f->sym->map.size()) > 0) {
+  const stiles_symbolic& sy = *f->sym;
+  const int64_t nvals = !sy.profile_input ? (int64_t)sy.map.size() : sy.perm_identity ? sy.in_rp.back() : sy.in_rp_in.back();
+  if (!d_values && nvals > 0) {
     set_error_arg(2);
     return STILES_EINVAL;
   }
@@ -599,7 +610,7 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
     d.info = at<unsigned long long>(f, L.info);
     d.ntiles = (int32_t)s.ntiles;
     d.ntr = s.ntr;
-    if (!s.profile_input) b->all_profile = false;
+    if (!s.profile_input || !s.perm_identity) b->all_profile = false;
     for (int32_t t = 0; t < (int32_t)s.ntiles; t++) { tmap.push_back(i); tmap.push_back(t); }
     for (int32_t m = 0; m < s.ntr; m++) { rmap.push_back(i); rmap.push_back(m); }
   }

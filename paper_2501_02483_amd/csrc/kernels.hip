@@ -912,6 +912,74 @@ __global__ __launch_bounds__(NT) void scatter_profile_kernel(const double* __res
   if (t == 0 && threadIdx.x == 0) *info = ~0ull;
 }
 
+// Tile of P A P^T from row-profile values of the input ordering: element
+// (r, c) of tile (m, j) is the input entry (perm[row], perm[col]), taken from
+// the lower triangle (larger index as the row).  The gathers follow the tile
+// rows; entries of reversed blocks are read transposed.
+template <int T>
+__global__ __launch_bounds__(NT) void scatter_perm_kernel(const double* __restrict__ vals,
+                                                          const int64_t* __restrict__ in_rp,
+                                                          const int64_t* __restrict__ fin,
+                                                          const int64_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ trow,
+                                                          const int32_t* __restrict__ tcol,
+                                                          const int64_t* __restrict__ row_base,
+                                                          const int32_t* __restrict__ row_cnt, double* tiles,
+                                                          double* orig, unsigned long long* info) {
+  constexpr int TT = T * T;
+  __shared__ double buf[T * (T + 1)];
+  __shared__ int64_t pr[T], pc[T];
+  const int64_t t = blockIdx.x;
+  const int m = trow[t], j = tcol[t];
+  const int64_t rb = row_base[m], cb = row_base[j];
+  const int rc = row_cnt[m], cc = row_cnt[j];
+  if (threadIdx.x < T) {
+    pr[threadIdx.x] = (int)threadIdx.x < rc ? perm[rb + threadIdx.x] : -1;
+  } else if (threadIdx.x < 2 * T) {
+    const int c = threadIdx.x - T;
+    pc[c] = c < cc ? perm[cb + c] : -1;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TT; e += NT) {
+    const int r = e / T, c = e % T;
+    double v = 0.0;
+    if (r < rc) {
+      if (c < cc && cb + c <= rb + r) {
+        const int64_t oi = pr[r], oj = pc[c];
+        const int64_t hi = oi > oj ? oi : oj, lo = oi > oj ? oj : oi;
+        const int64_t fh = fin[hi];
+        if (lo >= fh) v = vals[in_rp[hi] + (lo - fh)];
+      }
+    } else if (m == j && r == c) {
+      v = 1.0;   // padding row: unit diagonal
+    }
+    buf[r * (T + 1) + c] = v;
+  }
+  __syncthreads();
+  double* out = tiles + t * TT;
+  double* o2 = orig ? orig + t * TT : nullptr;
+  for (int e = threadIdx.x; e < TT; e += NT) {
+    const int c = e / T, r = e % T;   // column-major store
+    const double v = buf[r * (T + 1) + c];
+    out[e] = v;
+    if (o2) o2[e] = v;
+  }
+  if (t == 0 && threadIdx.x == 0) *info = ~0ull;
+}
+
+hipError_t launch_scatter_perm(int T, const double* vals, const int64_t* in_rp, const int64_t* fin, const int64_t* perm,
+                               const int32_t* trow, const int32_t* tcol, const int64_t* row_base,
+                               const int32_t* row_cnt, int64_t ntiles, double* tiles, double* orig,
+                               unsigned long long* info, hipStream_t st) {
+  if (T == 64)
+    hipLaunchKernelGGL(scatter_perm_kernel<64>, dim3((unsigned)ntiles), dim3(NT), 0, st, vals, in_rp, fin, perm, trow,
+                       tcol, row_base, row_cnt, tiles, orig, info);
+  else
+    hipLaunchKernelGGL(scatter_perm_kernel<32>, dim3((unsigned)ntiles), dim3(NT), 0, st, vals, in_rp, fin, perm, trow,
+                       tcol, row_base, row_cnt, tiles, orig, info);
+  return hipGetLastError();
+}
+
 // every tile of every matrix of a batch: block b handles tile tmap[b].y of
 // matrix tmap[b].x
 template <int T>

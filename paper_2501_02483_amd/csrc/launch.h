@@ -34,6 +34,13 @@ hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const i
 hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr, double* part,
                          const unsigned long long* info, double* out, hipStream_t st);
 
+// row-profile values of the input ordering -> tile store of P A P^T
+// (perm: new row -> input row); same conventions as launch_scatter_profile
+hipError_t launch_scatter_perm(int T, const double* vals, const int64_t* in_rp, const int64_t* fin, const int64_t* perm,
+                               const int32_t* trow, const int32_t* tcol, const int64_t* row_base,
+                               const int32_t* row_cnt, int64_t ntiles, double* tiles, double* orig,
+                               unsigned long long* info, hipStream_t st);
+
 // every tile of every matrix of a batch (tmap: matrix, tile pairs)
 hipError_t launch_scatter_batch(int T, const BatchDesc* desc, const double* const* vals, const int2* tmap,
                                 int64_t total_tiles, hipStream_t st);

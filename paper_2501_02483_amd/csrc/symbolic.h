@@ -20,9 +20,15 @@ struct stiles_symbolic {
   std::vector<int64_t> iperm;  // original row -> permuted row
   std::vector<int64_t> f;      // element profile of P A P^T (first column per row)
 
+  bool perm_identity = true;
+  int32_t nd_parts = 1;        // adaptable ND partitions (1: not used)
+  std::vector<int64_t> f_pre;  // profile before adaptable ND (flops_alg), empty if unused
+
   // input value placement
   std::vector<int64_t> in_rp;  // start of each row of the permuted envelope (N+1);
-                               // for profile input also the value layout
+                               // for profile input with the identity also the value layout
+  std::vector<int64_t> fin;    // profile input under a permutation: input first columns (N)
+  std::vector<int64_t> in_rp_in;// ... and input row pointers (N+1)
   std::vector<int64_t> map;    // CSC input: value index -> element offset in the tile store
 
   // tile rows
