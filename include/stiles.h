@@ -266,9 +266,11 @@ stiles_status stiles_logdet(stiles_factor* f, double* d_out, hipStream_t stream)
 
 /* Copy the factor L out of the tile store into d_L, in row-profile order of
  * the permuted envelope: row i of P A P^T holds columns f_i..i, f_i being the
- * first column of row i in P A P^T (for stiles_analyze_profile input this is
- * exactly the value layout of d_values).  d_L holds nnz_L doubles
- * (stiles_symbolic_info).  For tests and for callers that want L itself. */
+ * first column of row i in P A P^T (for stiles_analyze_profile input with the
+ * natural ordering this is exactly the value layout of d_values).  d_L holds
+ * nnz_L doubles (stiles_symbolic_info); envelope entries outside the stored
+ * tiles (structural zeros of L under adaptable ND) are written as zero.  For
+ * tests and for callers that want L itself. */
 stiles_status stiles_factor_extract(stiles_factor* f, double* d_L, hipStream_t stream);
 
 /* Profiling hook: when enabled, the library records a pair of HIP events on

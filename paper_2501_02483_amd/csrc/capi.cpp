@@ -754,7 +754,7 @@ extern "C" stiles_status stiles_factor_extract(stiles_factor* f, double* d_L, hi
   const Layout& L = f->L;
   hipError_t e = launch_extract(s.T, at<double>(f, L.tiles), at<int64_t>(f, L.in_rp), at<int64_t>(f, L.fprof),
                                 at<int32_t>(f, L.trow), at<int32_t>(f, L.tcol), at<int64_t>(f, L.row_base),
-                                at<int32_t>(f, L.row_cnt), s.ntiles, d_L, st);
+                                at<int32_t>(f, L.row_cnt), s.ntiles, s.nnzL, d_L, st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
 

@@ -1083,9 +1083,18 @@ __global__ __launch_bounds__(NT) void extract_kernel(const double* __restrict__ 
   }
 }
 
+__global__ void zero_kernel(double* out, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = 0.0;
+}
+
 hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const int64_t* f, const int32_t* trow,
                           const int32_t* tcol, const int64_t* row_base, const int32_t* row_cnt, int64_t ntiles,
-                          double* out, hipStream_t st) {
+                          int64_t nnz, double* out, hipStream_t st) {
+  // envelope entries outside the stored tiles (structural zeros of L) are zero
+  if (nnz > 0)
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((nnz + NT - 1) / NT, 65536)), dim3(NT), 0, st, out,
+                       nnz);
   if (T == 64)
     hipLaunchKernelGGL(extract_kernel<64>, dim3((unsigned)ntiles), dim3(NT), 0, st, tiles, rp, f, trow, tcol, row_base,
                        row_cnt, out);

@@ -29,7 +29,7 @@ hipError_t launch_scatter_map(int T, const double* vals, const int64_t* map, int
 // tile store -> row-profile values of the permuted envelope (lower, with diagonal)
 hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const int64_t* f, const int32_t* trow,
                           const int32_t* tcol, const int64_t* row_base, const int32_t* row_cnt, int64_t ntiles,
-                          double* out, hipStream_t st);
+                          int64_t nnz, double* out, hipStream_t st);
 
 hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr, double* part,
                          const unsigned long long* info, double* out, hipStream_t st);
