@@ -285,29 +285,68 @@ bool nd_plan_for(const std::vector<int64_t>& need, int64_t n, int64_t arrow, int
   if (n - start < T) return false;
   pl.part_lo.push_back(start);
   pl.part_hi.push_back(n);
-  int64_t longest = 0, seps = 0;
+  int64_t longest = 0;
   for (int32_t j = 0; j < P; j++) longest = std::max(longest, (pl.part_hi[j] - pl.part_lo[j] + T - 1) / T);
-  for (int32_t j = 0; j < P - 1; j++) seps += (pl.sep_hi[j] - pl.sep_lo[j]) / T;
+  // separators: one bisection level after another, each level as deep as
+  // its widest separator
+  int64_t seps = 0;
+  {
+    std::vector<std::pair<int32_t, int32_t>> level{{0, P - 1}};
+    while (!level.empty()) {
+      std::vector<std::pair<int32_t, int32_t>> next;
+      int64_t widest = 0;
+      for (auto& r : level) {
+        if (r.first >= r.second) continue;
+        const int32_t mid = r.first + (r.second - r.first) / 2;
+        widest = std::max(widest, (pl.sep_hi[mid] - pl.sep_lo[mid]) / T);
+        next.push_back({r.first, mid});
+        next.push_back({mid + 1, r.second});
+      }
+      seps += widest;
+      level.swap(next);
+    }
+  }
   pl.chain = longest + seps + (arrow + T - 1) / T;
   out = pl;
   return true;
 }
 
-// requested P >= 2: that many parts (else the best feasible); 0: the P in
-// [2, 64] with the shortest estimated chain.  False when no cut is feasible.
+// requested P >= 2: that many parts (else the automatic choice); 0: the
+// fewest parts whose estimated chain is within 1.5x of the shortest one over
+// P in [2, 64].  Every interior part adds a separator's width of fill across
+// its columns (executed work grows with P while the chain shrinks), so once
+// the chain is near its floor fewer parts are preferred.  False when no cut
+// is feasible.
 bool nd_plan(const std::vector<int64_t>& f, int64_t n, int64_t arrow, int32_t T, int32_t P_req, NDPlan& out) {
   const std::vector<int64_t> need = separator_need(f, n);
   if (P_req >= 2 && nd_plan_for(need, n, arrow, T, P_req, out)) return true;
-  bool found = false;
+  std::vector<NDPlan> plans;
+  int64_t best = -1;
   for (int32_t P = 2; P <= 64; P++) {
     NDPlan pl;
     if (!nd_plan_for(need, n, arrow, T, P, pl)) break;
-    if (!found || pl.chain < out.chain) { out = pl; found = true; }
+    if (best < 0 || pl.chain < best) best = pl.chain;
+    plans.push_back(std::move(pl));
   }
-  return found;
+  for (const NDPlan& pl : plans)
+    if (2 * pl.chain <= 3 * best) { out = pl; return true; }
+  return false;
 }
 
-// new-order segments of a plan: parts (the last reversed), separators, arrow
+// separators in nested-dissection order: after the parts are eliminated the
+// separators couple as a chain (S_j to S_(j+1) through the part between
+// them); ordering the chain by a balanced bisection tree, children before
+// parents, makes its dependency depth logarithmic in the number of parts
+void bisection_postorder(int32_t lo, int32_t hi, std::vector<int32_t>& out) {
+  if (lo >= hi) return;
+  const int32_t mid = lo + (hi - lo) / 2;
+  bisection_postorder(lo, mid, out);
+  bisection_postorder(mid + 1, hi, out);
+  out.push_back(mid);
+}
+
+// new-order segments of a plan: parts (the last reversed), separators in
+// bisection post-order, arrow
 std::vector<Seg> nd_segments(const NDPlan& pl, int64_t n, int64_t N, int64_t* band_rows) {
   std::vector<Seg> sg;
   int64_t pos = 0;
@@ -316,7 +355,9 @@ std::vector<Seg> nd_segments(const NDPlan& pl, int64_t n, int64_t N, int64_t* ba
     pos += pl.part_hi[j] - pl.part_lo[j];
   }
   *band_rows = pos;
-  for (int32_t j = 0; j + 1 < pl.P; j++)
+  std::vector<int32_t> sep_order;
+  bisection_postorder(0, pl.P - 1, sep_order);
+  for (int32_t j : sep_order)
     if (pl.sep_hi[j] > pl.sep_lo[j]) {
       sg.push_back({pl.sep_lo[j], pl.sep_hi[j], pos, false});
       pos += pl.sep_hi[j] - pl.sep_lo[j];

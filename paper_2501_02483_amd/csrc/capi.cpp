@@ -161,7 +161,7 @@ struct stiles_factor {
   bool timing = false;
   ~stiles_factor() {
     for (auto& e : ev)
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -328,10 +328,10 @@ extern "C" stiles_status stiles_factorize(stiles_factor* f, const double* d_valu
   stiles_status r = scatter_values(f, d_values, st);
   if (r != STILES_OK) return r;
   const int32_t nt = f->mf.ntasks;
-  if (f->timing) hipEventRecord(f->ev[0], st);
+  if (f->timing) (void)hipEventRecord(f->ev[0], st);
   hipError_t e = launch_exec(f->sym->T, at<ExecMat>(f, f->L.mat_f), nullptr, nt, at<ExecCtrl>(f, f->L.ctrl_f), 0,
                              nwg_for(f, nt), st);
-  if (f->timing) hipEventRecord(f->ev[1], st);
+  if (f->timing) (void)hipEventRecord(f->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   f->state = 0;
   f->anorm = -1.0;
@@ -358,11 +358,11 @@ static stiles_status solve_sweep(stiles_factor* f, const double* d_src, int64_t 
   const Layout& L = f->L;
   hipError_t e = launch_pack(s.T, d_src, ldsrc, nrhs, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
                              at<int32_t>(f, L.row_cnt), s.ntr, at<double>(f, L.vy), st);
-  if (e == hipSuccess && f->timing) hipEventRecord(f->ev[2], st);
+  if (e == hipSuccess && f->timing) (void)hipEventRecord(f->ev[2], st);
   if (e == hipSuccess)
     e = launch_exec(s.T, at<ExecMat>(f, L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, L.ctrl_s), nrhs,
                     nwg_for(f, f->ms.ntasks), st);
-  if (e == hipSuccess && f->timing) hipEventRecord(f->ev[3], st);
+  if (e == hipSuccess && f->timing) (void)hipEventRecord(f->ev[3], st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
 
@@ -668,11 +668,11 @@ extern "C" stiles_status stiles_batch_factorize(stiles_batch* b, const double* c
   }
   const int cap = device_wg_capacity(b->T);
   stiles_factor* f0 = b->factors[0];
-  if (f0->timing) hipEventRecord(f0->ev[0], st);
+  if (f0->timing) (void)hipEventRecord(f0->ev[0], st);
   hipError_t e = launch_exec(b->T, reinterpret_cast<const ExecMat*>(b->ws + b->B.mats),
                              reinterpret_cast<const int32_t*>(b->ws + b->B.order), b->total,
                              reinterpret_cast<ExecCtrl*>(b->ws + b->B.ctrl), 0, std::min<int>(cap, b->total), st);
-  if (f0->timing) hipEventRecord(f0->ev[1], st);
+  if (f0->timing) (void)hipEventRecord(f0->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   for (auto* f : b->factors) { f->state = 0; f->anorm = -1.0; }
   return STILES_OK;

@@ -800,6 +800,11 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
     if (threadIdx.x == 0) st_relaxed(cnt, w[7]);   // re-arm for the next launch
     if (M.trace) t_start = wall_clock64();
     const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
+    // tasks on the pivot chain (diagonal factorization, panel solve, diagonal
+    // solve steps) raise their waves' issue priority over the co-resident
+    // update work of other workgroups on the same SIMDs
+    const bool chain = SOLVE ? (type == TK_FDIAG || type == TK_BDIAG) : (type == TK_POTRF || type == TK_TRSM);
+    if (chain) __builtin_amdgcn_s_setprio(3);
     if constexpr (SOLVE) {
       task_solve<T>(M, w, nrhs, S, Xi);
     } else {
@@ -814,6 +819,7 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
         default: task_trsm<T>(M, w, S, Xi); break;
       }
     }
+    if (chain) __builtin_amdgcn_s_setprio(0);
     // every wave waits for its own stores, then wave 0 releases for the
     // workgroup and notifies the successors (Alg. 2 progress update)
     __builtin_amdgcn_s_waitcnt(0);
