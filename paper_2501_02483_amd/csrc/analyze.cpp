@@ -848,13 +848,34 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   std::vector<int32_t> fdiag(ntr, -1), bdiag(ntr, -1);
   // forward-read tasks of each Y_j (FUPD chunks that read it) -- the backward
   // sweep writes into Z only, so no write-after-read edges are needed.
+  s.nspart = 0;
   for (int32_t m = 0; m < ntr; m++) {
     int32_t last = -1;
     const int32_t rb = s.trow_ptr[m], re = s.trow_ptr[m + 1] - 1;
     // forward: the product with block m-1 (ready last) is fused into FDIAG
     const bool fuse = re > rb && s.tcol[re - 1] == m - 1;
     const int32_t body_end = fuse ? re - 1 : re;
-    for (int32_t lo = rb; lo < body_end; lo += schunk) {
+    const bool long_row = body_end - rb > 4 * schunk;
+    if (long_row) {
+      // a long row (arrow and separator rows): chunks of products into
+      // partial slots, each as soon as its blocks are final, then one sum
+      const int32_t pchunk = 2 * schunk;
+      const int32_t s0 = s.nspart;
+      std::vector<int32_t> parts;
+      for (int32_t lo = rb; lo < body_end; lo += pchunk) {
+        int32_t hi = std::min(body_end, lo + pchunk);
+        int32_t p0 = (int32_t)(sp.size() / 2);
+        for (int32_t t = lo; t < hi; t++) { sp.push_back(t); sp.push_back(s.tcol[t]); }
+        int32_t p1 = (int32_t)(sp.size() / 2);
+        int t = sb.add(TK_FPART, m, p0, p1, s.nspart++, 0.4f + 0.15f * (hi - lo));
+        for (int32_t q = lo; q < hi; q++) sb.dep(t, fdiag[s.tcol[q]]);
+        parts.push_back(t);
+      }
+      int t = sb.add(TK_FSUM, m, s0, s.nspart, 0, 0.4f + 0.02f * (s.nspart - s0));
+      for (int q : parts) sb.dep(t, q);
+      last = t;
+    }
+    for (int32_t lo = rb; lo < body_end && !long_row; lo += schunk) {
       int32_t hi = std::min(body_end, lo + schunk);
       int32_t p0 = (int32_t)(sp.size() / 2);
       for (int32_t t = lo; t < hi; t++) { sp.push_back(t); sp.push_back(s.tcol[t]); }

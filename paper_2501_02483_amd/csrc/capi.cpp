@@ -28,7 +28,7 @@ struct Layout {
   size_t row_base, row_cnt, trow_ptr, trow, tcol, perm;
   size_t in_rp, fprof, map, fin, in_rp_in;
   size_t tiles, linv, part, shadow, orig;
-  size_t vy, vz, vx, vr, vb, vd;
+  size_t vy, vz, vpart, vx, vr, vb, vd;
   size_t ldpart, stats;
   size_t ccol_tile, ccol_row, items, item_ptr, rpart;
   size_t total;
@@ -106,6 +106,7 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   const size_t vbytes = (size_t)s.ntr * s.T * nrhs_max * 8;
   L.vy = take(vbytes);
   L.vz = take(vbytes);
+  L.vpart = take((size_t)s.nspart * s.T * nrhs_max * 8);
   L.vx = mixed ? take(vbytes) : 0;
   L.vr = mixed ? take(vbytes) : 0;
   L.vb = mixed ? take(vbytes) : 0;
@@ -229,6 +230,7 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   mf.part = at<double>(f, L.part);
   mf.vy = at<double>(f, L.vy);
   mf.vz = at<double>(f, L.vz);
+  mf.vpart = at<double>(f, L.vpart);
   mf.tasks = at<int32_t>(f, L.ftask);
   mf.succ = at<int32_t>(f, L.fsucc);
   mf.remaining = at<int32_t>(f, L.frem);

@@ -701,7 +701,7 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   const bool act = 16 * wave < T;
   const int m = w[1];
   const int64_t vb = (int64_t)T * nrhs;
-  const bool fwd = type == TK_FUPD || type == TK_FDIAG;
+  const bool fwd = type == TK_FUPD || type == TK_FDIAG || type == TK_FPART;
   const bool diag = type == TK_FDIAG || type == TK_BDIAG;
   const double* vsrc = fwd ? M.vy : M.vz;
   const int p0 = w[2], p1 = w[3];
@@ -723,6 +723,18 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
       st.load_vec(vsrc + M.pairs[2 * p + 3] * vb, nrhs);
     }
     if (act) acc = solve_mma<T>(acc, LL, LV, !fwd, wave, lane);
+  }
+  if (type == TK_FPART) {
+    // one chunk of a long row: the partial product into its slot
+    double* q = M.vpart + (int64_t)w[4] * vb;
+    if (act && col < nrhs) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = 16 * wave + (lane >> 4) + 4 * r;
+        q[row + col * T] = acc[r];
+      }
+    }
+    return;
   }
   // base block: Y_m (forward), or Y_m / Z_m (backward, first chunk reads Y)
   const double* base = fwd ? M.vy + m * vb : ((w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb);
@@ -754,6 +766,20 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   if (act && col < nrhs) {
 #pragma unroll
     for (int r = 0; r < 4; r++) dst[(16 * wave + (lane >> 4) + 4 * r) + col * T] = out[r];
+  }
+}
+
+// Y_m -= Q_a + ... + Q_(b-1): the partial products of a long row, summed in
+// slot order (fixed, so the result does not depend on the schedule)
+template <int T>
+__device__ __attribute__((noinline)) void task_fsum(const ExecMat& M, const int32_t* w, int nrhs) {
+  const int64_t vb = (int64_t)T * nrhs;
+  double* y = M.vy + (int64_t)w[1] * vb;
+  const int a = w[2], b = w[3];
+  for (int e = threadIdx.x; e < T * nrhs; e += NT) {
+    double s = 0.0;
+    for (int q = a; q < b; q++) s += M.vpart[(int64_t)q * vb + e];
+    y[e] -= s;
   }
 }
 
@@ -806,7 +832,8 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
     const bool chain = SOLVE ? (type == TK_FDIAG || type == TK_BDIAG) : (type == TK_POTRF || type == TK_TRSM);
     if (chain) __builtin_amdgcn_s_setprio(3);
     if constexpr (SOLVE) {
-      task_solve<T>(M, w, nrhs, S, Xi);
+      if (type == TK_FSUM) task_fsum<T>(M, w, nrhs);
+      else task_solve<T>(M, w, nrhs, S, Xi);
     } else {
       switch (type) {
         case TK_UPD: task_update<T>(M, w, 0, S, Xi); break;

@@ -27,6 +27,8 @@ enum TaskType : int32_t {
   TK_FDIAG = 9,  // solve, forward:  Y_m  = Linv_m (Y_m - [L_(m,j) Y_j])
   TK_BUPD = 10,  // solve, backward: Z_m  = (first ? Y_m : Z_m) - sum L_(i,m)^T Z_i
   TK_BDIAG = 11, // solve, backward: Z_m  = Linv_m^T ((Z_m or Y_m) - [L_(i,m)^T Z_i])
+  TK_FPART = 12, // solve, forward:  Q_s  = sum L_(m,j) Y_j  (one chunk of a long row)
+  TK_FSUM = 13,  // solve, forward:  Y_m -= Q_a + Q_(a+1) + ... + Q_(b-1)
 };
 
 enum TaskFlag : int32_t {
@@ -44,6 +46,8 @@ enum TaskFlag : int32_t {
 // TRSM:  a = tile row k of the diagonal tile, b,c = fused pair range
 // FUPD/BUPD: w1 = tile row m, a,b = solve-pair range
 // FDIAG/BDIAG: w1 = m, a,b = fused solve-pair range applied before the diagonal
+// FPART: w1 = m, a,b = solve-pair range, c = partial slot
+// FSUM:  w1 = m, a,b = partial slot range (summed in index order)
 constexpr int TASK_WORDS = 8;
 
 // Device-side description of one matrix (or one solve) for the executor.
@@ -54,6 +58,7 @@ struct ExecMat {
   double* part;             // npart * T*T  tree partials
   double* vy;               // solve: ntr * T * nrhs (forward result)
   double* vz;               // solve: ntr * T * nrhs (backward result)
+  double* vpart;            // solve: partial slots, T * nrhs each
   const int32_t* tasks;     // ntasks * TASK_WORDS
   const int32_t* succ;      // successor lists
   int32_t* remaining;       // per-task unfinished-predecessor counters

@@ -53,6 +53,7 @@ struct stiles_symbolic {
   int64_t corner_acc = 0;
 
   // solve DAG
+  int32_t nspart = 0;             // partial slots of long forward rows
   std::vector<int32_t> stask;
   std::vector<int32_t> ssucc;
   std::vector<int32_t> spairs;

@@ -12,7 +12,7 @@ import numpy as np
 import paper_2501_02483_amd as S
 
 UPD, PART, TREE, POTRF, TRSM = 1, 2, 3, 4, 5
-FUPD, FDIAG, BUPD, BDIAG = 8, 9, 10, 11
+FUPD, FDIAG, BUPD, BDIAG, FPART, FSUM = 8, 9, 10, 11, 12, 13
 TF_DIAG, TF_FIRST = 1 << 8, 1 << 9
 
 
@@ -143,6 +143,7 @@ def solve(plan, tiles, linv, B, mode="ticket", seed=0):
         rb, rc = plan.row_base[m], plan.row_cnt[m]
         Y[m, :rc] = Bp[rb:rb + rc]
     Z = np.zeros_like(Y)
+    Q = {}
     P = plan.spairs
     for t in _order(plan.stask, plan.ssucc, mode, rng):
         w = plan.stask[t]
@@ -151,6 +152,14 @@ def solve(plan, tiles, linv, B, mode="ticket", seed=0):
         if typ == FUPD:
             for p in range(w[2], w[3]):
                 Y[m] -= tiles[P[p, 0]] @ Y[P[p, 1]]
+        elif typ == FPART:
+            q = np.zeros_like(Y[m])
+            for p in range(w[2], w[3]):
+                q += tiles[P[p, 0]] @ Y[P[p, 1]]
+            Q[w[4]] = q
+        elif typ == FSUM:
+            for s in range(w[2], w[3]):
+                Y[m] -= Q.pop(s)
         elif typ == FDIAG:
             v = Y[m].copy()
             for p in range(w[2], w[3]):

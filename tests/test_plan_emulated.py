@@ -109,3 +109,47 @@ def test_csc_input_with_rcm_permutation():
     B = I.rhs(p.N, 2, seed=4)
     X = E.solve(plan, tiles, linv, B)
     assert np.linalg.norm(X - np.linalg.solve(As, B)) / np.linalg.norm(X) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", ["ticket", "random"])
+@pytest.mark.parametrize("n,a,w,seg,T,parts", [
+    (2400, 30, [10, 60, 25], 400, 32, 3),
+    (3000, 20, 24, None, 32, 0),
+    (1500, 70, [20, 50], 300, 64, 2),
+])
+def test_emulated_nd_plan(n, a, w, seg, T, parts, mode):
+    """Adaptable ND plans (partitions, separators in bisection order, long
+    forward rows summed from partial products) reproduce the oracle."""
+    from permute_util import permute_profile
+    p = I.make_pattern(n, a, w, seg=seg)
+    vals = I.make_values(p, seed=n + T)
+    sym = S.Symbolic.from_pattern(p, tile=T, ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=parts)
+    assert sym.info.nd_parts >= 2
+    plan = E.Plan(sym)
+    perm = plan.perm
+    A = I.to_dense(p, vals)
+    tiles, linv = E.factor(plan, A[np.ix_(perm, perm)], mode=mode, seed=n)
+    Ld = E.dense_factor(plan, tiles)
+    f2, v2 = permute_profile(p.f, vals, perm)
+    L2, info = oracle.factor(f2, v2)
+    assert info == 0
+    D2 = np.zeros((p.N, p.N))
+    rp2 = np.concatenate([[0], np.cumsum(np.arange(p.N) - f2 + 1)])
+    for i in range(p.N):
+        D2[i, f2[i]:i + 1] = L2[rp2[i]:rp2[i + 1]]
+    assert np.linalg.norm(Ld - D2) / np.linalg.norm(D2) <= 1e-12
+    B = I.rhs(p.N, 2, seed=4)
+    X = E.solve(plan, tiles, linv, B, mode=mode, seed=n + 1)
+    Lo, Lv = _oracle_dense_L(p, vals)
+    Xo = oracle.solve(p.f, Lv, B)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
+
+
+def test_long_forward_rows_use_partials():
+    """An arrow row spanning many band tiles is summed from parallel partial
+    products (FPART tasks and one FSUM) instead of one sequential chain."""
+    p = I.make_pattern(3000, 20, 24)
+    sym = S.Symbolic.from_pattern(p, tile=32)
+    plan = E.Plan(sym)
+    types = plan.stask[:, 0] & 0xff
+    assert (types == E.FPART).sum() >= 2 and (types == E.FSUM).sum() >= 1
