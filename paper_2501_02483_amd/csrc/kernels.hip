@@ -41,6 +41,16 @@ __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMI
 
 // 1/sqrt(d): hardware estimate (about 24 bits) refined by two Newton steps
 // y <- y + y (1 - d y^2) / 2, which reach full double precision (to ~1 ulp).
+// 1/sqrt(d): hardware estimate, then one third-order correction
+// y = y0 (1 + e/2 + 3 e^2 / 8), e = 1 - d y0^2 (four dependent FP64 steps
+// instead of six for two Newton steps; the estimate's error is cubed)
+__device__ __forceinline__ double rsqrt_c(double d) {
+  const double y0 = __builtin_amdgcn_rsq(d);
+  const double e = fma(-d * y0, y0, 1.0);
+  const double p = fma(0.375, e, 0.5);
+  return fma(y0 * e, p, y0);
+}
+
 __device__ __forceinline__ double rsqrt_nr(double d) {
   double y = __builtin_amdgcn_rsq(d);
   double e = fma(-d * y, y, 1.0);
@@ -313,10 +323,11 @@ __device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int3
 // ------------------------------------------------- diagonal tile: POTRF + TRTRI
 // Blocked right-looking Cholesky of one T x T tile held in LDS, with 16-wide
 // panels.  For each panel the 16 x 16 diagonal block is factored and inverted
-// in the registers of wave 0 (lane i holds row i; values are broadcast with
-// readlane), the panel below is solved against the inverse block and the
-// trailing matrix is updated, both as 16 x 16 x 16 MFMA products.  The
-// inverse of the whole factor is then assembled block by block:
+// in the registers of wave 0 (diag_block16), the panel below is solved
+// against the inverse block and the trailing matrix is updated, both as
+// 16 x 16 x 16 MFMA products.  The inverse of the whole factor is built one
+// block row at a time, as soon as its diagonal block is inverted, on the
+// waves the panel leaves idle:
 //   X_ii = D_i^{-1},  X_ib = -D_i^{-1} sum_{b <= q < i} L_iq X_qb.
 
 __device__ __forceinline__ double bcast(double v, int lane) {
@@ -340,8 +351,138 @@ __device__ __forceinline__ v4d mma16(v4d acc, const double* A, int lda, const do
   return acc;
 }
 
+// broadcast of lane r of every 16-lane row to the whole row (DPP row_newbcast)
+__device__ __forceinline__ int row_bcast32(int v, int r) {
+  switch (r) {
+    case 0: return __builtin_amdgcn_update_dpp(0, v, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(0, v, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(0, v, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(0, v, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(0, v, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(0, v, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(0, v, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(0, v, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(0, v, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(0, v, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(0, v, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0, v, 0x15F, 0xF, 0xF, false);
+  }
+}
+
+__device__ __forceinline__ double row_bcast(double v, int r) {
+  return __hiloint2double(row_bcast32(__double2hiint(v), r), row_bcast32(__double2loint(v), r));
+}
+
+// Cholesky factor and inverse of one 16 x 16 diagonal block on one wave.
+// Lane l holds row i = l & 15 of the columns g + 4 s (g = l >> 4, s = 0..3).
+// Column j: the pivot is read from its lane, the owner lanes scale the
+// column and publish it through LDS (the operations of one wave reach LDS in
+// order), and every lane applies its part of the rank-1 update.  The inverse
+// is built by forward substitution for all 16 right-hand sides at once, row
+// by row; each final row is broadcast inside its 16-lane row by DPP.
 template <int T>
-__device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv) {
+__device__ __forceinline__ void diag_block16(double* S, double* Xi, double* rinv, double* pcol, int c0, int lane,
+                                             int& fail) {
+  const int i = lane & 15, g = lane >> 4;
+  double a[4];
+#pragma unroll
+  for (int s = 0; s < 4; s++) a[s] = S[(c0 + i) + (c0 + g + 4 * s) * T];
+  double piv[16];
+  // the pivot of column j + 1 is formed from broadcast values as soon as
+  // L(j + 1, j) exists, ahead of the lane updates that go through LDS
+  double d = bcast(a[0], 0);
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const int gj = j & 3, sj = j >> 2;
+    const double rs = rsqrt_c(d);
+    if (!(d > 0.0) && fail < 0) fail = c0 + j;
+    piv[j] = rs;
+    const double v = i == j ? d * rs : (i > j ? a[sj] * rs : 0.0);
+    if (j < 15) {
+      const int gn = (j + 1) & 3, sn = (j + 1) >> 2;
+      const double pold = bcast(a[sn], (j + 1) + 16 * gn);   // A(j+1, j+1) before column j
+      const double l1 = bcast(v, (j + 1) + 16 * gj);         // L(j+1, j)
+      d = fma(-l1, l1, pold);
+    }
+    if (g == gj) {
+      a[sj] = v;
+      pcol[16 * j + i] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double lij = pcol[16 * j + i];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const int q = g + 4 * s;
+      if (q > j) a[s] = fma(-lij, pcol[16 * j + q], a[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; s++) {
+    const int c = g + 4 * s;
+    if (i >= c) S[(c0 + i) + (c0 + c) * T] = a[s];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < 16; j++) rinv[c0 + j] = piv[j];
+  }
+  double x[4];
+#pragma unroll
+  for (int s = 0; s < 4; s++) x[s] = i == g + 4 * s ? 1.0 : 0.0;
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    const double lir = pcol[16 * r + i];   // L(i, r)
+    if (i == r) {
+#pragma unroll
+      for (int s = 0; s < 4; s++) x[s] *= piv[r];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const double xb = row_bcast(x[s], r);
+      if (i > r) x[s] = fma(-lir, xb, x[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; s++) {
+    const int c = g + 4 * s;
+    if (i >= c) Xi[(c0 + i) + (c0 + c) * T] = x[s];
+  }
+}
+
+// X(b, q) = -D_b^{-1} sum_{q <= p < b} L(b, p) X(p, q) for one 16 x 16 block
+// of the inverse of the factor (one wave); the partial sum is staged in the
+// unused upper triangle of S at block (q, b)
+template <int T>
+__device__ __forceinline__ void inv_row_block(double* S, double* Xi, int b, int q, int lane) {
+  v4d u = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int p = q; p < b; p++) {
+#pragma unroll
+    for (int kq = 0; kq < 16; kq += 4) {
+      const double av = S[(16 * b + (lane & 15)) + (16 * p + kq + (lane >> 4)) * T];    // L(b, p)
+      const double bv = Xi[(16 * p + kq + (lane >> 4)) + (16 * q + (lane & 15)) * T];   // X(p, q)
+      u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; rr++) S[(16 * q + (lane >> 4) + 4 * rr) + (16 * b + (lane & 15)) * T] = u[rr];
+  __builtin_amdgcn_wave_barrier();
+  v4d xv = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kq = 0; kq < 16; kq += 4) {
+    const double av = Xi[(16 * b + (lane & 15)) + (16 * b + kq + (lane >> 4)) * T];   // D_b^{-1}
+    const double bv = S[(16 * q + kq + (lane >> 4)) + (16 * b + (lane & 15)) * T];    // U
+    xv = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, xv, 0, 0, 0);
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; rr++) Xi[(16 * b + (lane >> 4) + 4 * rr) + (16 * q + (lane & 15)) * T] = -xv[rr];
+}
+
+template <int T>
+__device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv,
+                                                     double* pcol) {
   constexpr int TT = T * T, NBK = T / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* C = M.tiles + (int64_t)w[1] * TT;
@@ -381,42 +522,15 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
 #pragma unroll 1
   for (int b = 0; b < NBK; b++) {
     const int c0 = 16 * b;
-    if (tid < 64) {
-      // ---- factor and invert the diagonal block in registers (wave 0)
-      double r[16], piv[16];
-#pragma unroll
-      for (int q = 0; q < 16; q++) r[q] = lane < 16 ? S[(c0 + lane) + (c0 + q) * T] : 0.0;
-#pragma unroll
-      for (int j = 0; j < 16; j++) {
-        const double d = bcast(r[j], j);
-        const double rs = rsqrt_nr(d);
-        if (!(d > 0.0) && fail < 0) fail = c0 + j;
-        piv[j] = rs;
-        r[j] = lane == j ? d * rs : (lane > j ? r[j] * rs : 0.0);
-#pragma unroll
-        for (int q = j + 1; q < 16; q++) r[q] = fma(-r[j], bcast(r[j], q), r[q]);
-      }
-      double x[16];   // column `lane` of the inverse block
-#pragma unroll
-      for (int i = 0; i < 16; i++) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < i; q++) s = fma(bcast(r[q], i), x[q], s);
-        x[i] = lane == i ? piv[i] : (lane < i ? -piv[i] * s : 0.0);
-      }
-      if (lane < 16) {
-#pragma unroll
-        for (int q = 0; q < 16; q++) {
-          if (q <= lane) S[(c0 + lane) + (c0 + q) * T] = r[q];
-          if (q >= lane) Xi[(c0 + q) + (c0 + lane) * T] = x[q];
-        }
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < 16; j++) rinv[c0 + j] = piv[j];
-      }
-    }
+    if (tid < 64) diag_block16<T>(S, Xi, rinv, pcol, c0, lane, fail);
     __syncthreads();
+    // ---- row block b of the inverse, X(b, q) for q < b, on the waves that
+    //      the panel below leaves idle (every input is final by now)
+    {
+      const int q = wave - (NBK - 1 - b);
+      if (q >= 0 && q < b) inv_row_block<T>(S, Xi, b, q, lane);
+    }
+    if (b + 1 == NBK) __syncthreads();
     if (b + 1 < NBK) {
       // ---- panel: L(R, c0:c0+16) = A(R, c0:c0+16) D^{-T}, R = rows below (MFMA)
       //      one 16-row block per wave
@@ -460,42 +574,6 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
     }
   }
   if (tid == 0 && fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
-  // ---- off-diagonal blocks of the inverse, by block distance d = i - b
-#pragma unroll 1
-  for (int d = 1; d < NBK; d++) {
-    const int nblk = NBK - d;
-    v4d u = v4d{0.0, 0.0, 0.0, 0.0};
-    const int b = wave, i = wave + d;
-    if (wave < nblk) {
-      // U = sum_{q=b}^{i-1} L_iq X_qb
-      for (int q = b; q < i; q++) {
-#pragma unroll
-        for (int kq = 0; kq < 16; kq += 4) {
-          const double av = S[(16 * i + (lane & 15)) + (16 * q + kq + (lane >> 4)) * T];   // L_iq(r, l)
-          const double bv = Xi[(16 * q + kq + (lane >> 4)) + (16 * b + (lane & 15)) * T]; // X_qb(l, c)
-          u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
-        }
-      }
-    }
-    // stash U in the (unused) upper triangle of S at block (b, i), transposed-free copy
-    if (wave < nblk) {
-#pragma unroll
-      for (int rr = 0; rr < 4; rr++) S[(16 * b + (lane >> 4) + 4 * rr) + (16 * i + (lane & 15)) * T] = u[rr];
-    }
-    __syncthreads();
-    if (wave < nblk) {
-      v4d xv = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kq = 0; kq < 16; kq += 4) {
-        const double av = Xi[(16 * i + (lane & 15)) + (16 * i + kq + (lane >> 4)) * T];  // Dinv_i(r, l)
-        const double bv = S[(16 * b + kq + (lane >> 4)) + (16 * i + (lane & 15)) * T];   // U(l, c)
-        xv = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, xv, 0, 0, 0);
-      }
-#pragma unroll
-      for (int rr = 0; rr < 4; rr++) Xi[(16 * i + (lane >> 4) + 4 * rr) + (16 * b + (lane & 15)) * T] = -xv[rr];
-    }
-    __syncthreads();
-  }
   double* Li = M.linv + (int64_t)k * TT;
   for (int e = tid; e < TT; e += NT) {
     const int row = e % T, col = e / T;
@@ -794,6 +872,7 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
   __shared__ __attribute__((aligned(16))) double S[T * (T + 1)];
   __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : T * T];
   __shared__ double rinv[SOLVE ? 1 : T];
+  __shared__ double pcol[SOLVE ? 1 : 256];
   __shared__ int32_t s_ticket;
   // Control flow outside the task bodies is kept uniform across the
   // workgroup (values broadcast with readfirstlane, loops with uniform bounds
@@ -841,7 +920,7 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
         case TK_TREE: task_tree<T>(M, w); break;
         case TK_POTRF:
           if constexpr (POTRF_COLS) task_potrf_cols<T>(M, w, S, Xi, rinv);
-          else task_potrf<T>(M, w, S, Xi, rinv);
+          else task_potrf<T>(M, w, S, Xi, rinv, pcol);
           break;
         default: task_trsm<T>(M, w, S, Xi); break;
       }
