@@ -280,8 +280,9 @@ def bench_mixed(args):
     dv = dp.values(4, law="laplacian", kappa=1e6)
     B = torch.randn(nrhs, p.N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(104)).t()
     out = {}
+    ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
     for prec, name in ((S.STILES_FP64, "fp64"), (S.STILES_MIXED32, "mixed")):
-        sym = S.Symbolic.from_pattern(p, tile=args.tile or 64)
+        sym = S.Symbolic.from_pattern(p, tile=args.tile or 64, ordering=ordering, nd_parts=args.parts)
         fac = S.Factor(sym, prec, nrhs_max=nrhs)
         fac.factorize(dv)
         torch.cuda.synchronize()
@@ -316,7 +317,7 @@ def bench_mixed(args):
             "ms_per_step": out["mixed"]["factor_kernel_ms"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32-updates/f64", "data": "synthetic (device-generated, Laplacian law)",
             "config": {"workload": p.name, "n": p.n, "arrow": p.a, "half_width": 1000, "nrhs": nrhs,
-                       "tile": args.tile or 64},
+                       "tile": args.tile or 64, "ordering": args.ordering, "nd_parts": sym.info.nd_parts},
             "flops_alg": F, "runs": out,
             "roofline": {"bound": "mfma", "achieved": v, "peak": FP32_PEAK, "unit": "TFLOP/s",
                          "frac": v / FP32_PEAK, "traffic": None}}
@@ -326,13 +327,15 @@ def bench_serve(args):
     """Poisson arrivals over 8 resident patterns (continuous batching)."""
     import torch
 
+    import paper_2501_02483_amd as S
     from paper_2501_02483_amd import inputs as I
     from paper_2501_02483_amd.serve import GpuExecutor, Request, Server, summarize
 
     pats = I.serving_patterns()
     if args.max_n:
         pats = [p for p in pats if p.n <= args.max_n]
-    ex = GpuExecutor(pats, tile=args.tile or 64, slots=args.slots)
+    ex = GpuExecutor(pats, tile=args.tile or 64, slots=args.slots,
+                     ordering=S.STILES_ORDER_ADAPTABLE_ND if args.ordering == "nd" else S.STILES_ORDER_NONE)
     budget = int(args.budget_gb * 2 ** 30)
     # warm-up: one request per pattern and slot, so every workspace the runs
     # below need is allocated and initialized before any clock starts
@@ -364,7 +367,8 @@ def bench_serve(args):
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic (device-generated values per request)",
             "config": {"workload": "serve8", "patterns": [(p.n, int(p.n - p.f[p.n - 1]), p.a) for p in pats],
-                       "slots": args.slots, "budget_gb": args.budget_gb, "requests": args.requests},
+                       "slots": args.slots, "budget_gb": args.budget_gb, "requests": args.requests,
+                       "nd_parts": [s.info.nd_parts for s in ex.syms]},
             "results": res}
 
 

@@ -1418,22 +1418,48 @@ hipError_t launch_residual(int T, const double* orig, const int32_t* trow, const
   return hipGetLastError();
 }
 
-__global__ void norms_kernel(int64_t n, int T, int nrhs, const double* __restrict__ R, const double* __restrict__ X,
-                             unsigned long long* stats) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+// Per-column max |R| and max |X| over the tile-row blocks (T x nrhs each).
+// Block (x, c) covers 16 tile rows of column c and reduces in LDS before one
+// atomic per value.  Maxima are taken on the bit patterns of |v|
+// (non-negative doubles order like their bits), so a NaN propagates.
+__global__ __launch_bounds__(NT) void norms_kernel(int32_t ntr, int T, int nrhs, const double* __restrict__ R,
+                                                   const double* __restrict__ X, unsigned long long* stats) {
+  __shared__ unsigned long long sr[NT], sx[NT];
+  const int c = blockIdx.y;
   const int64_t vb = (int64_t)T * nrhs;
-  const int c = (int)((e % vb) / T);
-  const double r = fabs(R[e]), x = fabs(X[e]);
-  // non-negative doubles order like their bit patterns
-  atomicMax(stats + 2 * c, (unsigned long long)__double_as_longlong(r));
-  atomicMax(stats + 2 * c + 1, (unsigned long long)__double_as_longlong(x));
+  const int m0 = blockIdx.x * 16;
+  unsigned long long rm = 0, xm = 0;
+  for (int idx = threadIdx.x; idx < 16 * T; idx += NT) {
+    const int m = m0 + idx / T, r = idx % T;
+    if (m < ntr) {
+      const int64_t e = (int64_t)m * vb + (int64_t)c * T + r;
+      const unsigned long long ur = (unsigned long long)__double_as_longlong(fabs(R[e]));
+      const unsigned long long ux = (unsigned long long)__double_as_longlong(fabs(X[e]));
+      rm = ur > rm ? ur : rm;
+      xm = ux > xm ? ux : xm;
+    }
+  }
+  sr[threadIdx.x] = rm;
+  sx[threadIdx.x] = xm;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sr[threadIdx.x] = sr[threadIdx.x + o] > sr[threadIdx.x] ? sr[threadIdx.x + o] : sr[threadIdx.x];
+      sx[threadIdx.x] = sx[threadIdx.x + o] > sx[threadIdx.x] ? sx[threadIdx.x + o] : sx[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(stats + 2 * c, sr[0]);
+    atomicMax(stats + 2 * c + 1, sx[0]);
+  }
 }
 
 hipError_t launch_norms(int T, int32_t ntr, int nrhs, const double* R, const double* X, unsigned long long* stats,
                         hipStream_t st) {
-  const int64_t n = (int64_t)T * nrhs * ntr;
-  hipLaunchKernelGGL(norms_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n, T, nrhs, R, X, stats);
+  if (ntr <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(norms_kernel, dim3((unsigned)((ntr + 15) / 16), (unsigned)nrhs), dim3(NT), 0, st, ntr, T, nrhs, R,
+                     X, stats);
   return hipGetLastError();
 }
 

@@ -199,7 +199,10 @@ class GpuExecutor:
     requests.  A request draws its values on the device (seeded), then
     factorizes, and solves one right-hand side or takes the log-determinant."""
 
-    def __init__(self, patterns, tile=64, precision=0, slots=4, nrhs=1):
+    def __init__(self, patterns, tile=64, precision=0, slots=4, nrhs=1, ordering=None, nd_min_rows=512):
+        """ordering: None/STILES_ORDER_NONE keeps the natural order; with
+        STILES_ORDER_ADAPTABLE_ND, patterns with at least nd_min_rows band
+        tile rows (long pivot chains) are partitioned, the others not."""
         import torch
         import paper_2501_02483_amd as S
         from paper_2501_02483_amd.devgen import DevicePattern
@@ -208,7 +211,14 @@ class GpuExecutor:
         self.patterns = patterns
         self.precision = precision
         self.nrhs = nrhs
-        self.syms = [S.Symbolic.from_pattern(p, tile=tile) for p in patterns]
+        nd = ordering == S.STILES_ORDER_ADAPTABLE_ND
+
+        def analyze(p):
+            if nd and (p.n + tile - 1) // tile >= nd_min_rows:
+                return S.Symbolic.from_pattern(p, tile=tile, ordering=S.STILES_ORDER_ADAPTABLE_ND)
+            return S.Symbolic.from_pattern(p, tile=tile, ordering=S.STILES_ORDER_NONE)
+
+        self.syms = [analyze(p) for p in patterns]
         self.devpat = [DevicePattern(p) for p in patterns]
         self.ws_bytes = [s.workspace_size(precision, nrhs) for s in self.syms]
         self.slots = slots
