@@ -214,8 +214,9 @@ int64_t envelope_tiles(const std::vector<int64_t>& f, int64_t n, int32_t T) {
 // and have no dependencies between them, so their tile-column chains run
 // concurrently.  The last part is reversed, so that its separator meets its
 // last columns instead of filling across it (an interior part touches two
-// separators and the one at its start still fills across it: the thicker
-// arrow of the paper's second partition).  Parts before the last are whole
+// separators and the one met first still fills across it: the thicker arrow
+// of the paper's second partition; interior parts are oriented so that this
+// is the narrower of the two).  Parts before the last are whole
 // tile rows and separators are padded to whole tile rows, so no tile mixes
 // two blocks.
 struct Seg {
@@ -351,7 +352,12 @@ std::vector<Seg> nd_segments(const NDPlan& pl, int64_t n, int64_t N, int64_t* ba
   std::vector<Seg> sg;
   int64_t pos = 0;
   for (int32_t j = 0; j < pl.P; j++) {
-    sg.push_back({pl.part_lo[j], pl.part_hi[j], pos, j == pl.P - 1});
+    // the first part keeps its order (its separator is at its end), the last
+    // is reversed; an interior part is ordered so that its narrower
+    // separator is the one met first (that one fills across the part)
+    bool rev = j == pl.P - 1;
+    if (j > 0 && j + 1 < pl.P) rev = (pl.sep_hi[j] - pl.sep_lo[j]) < (pl.sep_hi[j - 1] - pl.sep_lo[j - 1]);
+    sg.push_back({pl.part_lo[j], pl.part_hi[j], pos, rev});
     pos += pl.part_hi[j] - pl.part_lo[j];
   }
   *band_rows = pos;
@@ -364,6 +370,17 @@ std::vector<Seg> nd_segments(const NDPlan& pl, int64_t n, int64_t N, int64_t* ba
     }
   if (N > n) sg.push_back({n, N, pos, false});
   return sg;
+}
+
+// partition of every band tile row of the new order (the first P segments
+// of nd_segments are the partitions; all but the last are whole tile rows)
+void set_band_part(stiles_symbolic& s, const std::vector<Seg>& segs, int32_t P) {
+  s.band_part.assign(s.ntb, 0);
+  for (int32_t j = 0; j < P; j++) {
+    const int64_t lo = segs[j].nlo, hi = segs[j].nlo + (segs[j].ohi - segs[j].olo);
+    if (hi <= lo) continue;
+    for (int64_t t = lo / s.T; t <= (hi - 1) / s.T && t < s.ntb; t++) s.band_part[t] = j;
+  }
 }
 
 // Profile and tile pattern of P A P^T for a row-profile input (row i spans
@@ -500,6 +517,7 @@ extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, c
       init_common(*s, N, N - nb2, opts);   // the separators join the arrow
       s->ordering_used = STILES_ORDER_ADAPTABLE_ND;
       s->nd_parts = pl.P;
+      set_band_part(*s, segs, pl.P);
       s->perm_identity = false;
       s->perm.resize(N);
       for (const Seg& g : segs)
@@ -632,6 +650,7 @@ extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t*
       init_common(*s, N, N - nb2, opts);   // the separators join the arrow
       s->ordering_used = STILES_ORDER_ADAPTABLE_ND;
       s->nd_parts = pl.P;
+      set_band_part(*s, segs, pl.P);
       s->f_pre = std::move(fcur);
     }
   }
@@ -759,7 +778,58 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
         while (nb < pr.size() && pj[nb] < s.ntb) nb++;
         s.corner_acc = std::max<int64_t>(s.corner_acc, (int64_t)nb);
         const int64_t G = ((int64_t)nb + chunk - 1) / chunk;
-        if (s.opts.tree_min_ratio > 0 && G >= 2 && (int64_t)nb >= (int64_t)s.opts.tree_min_ratio * G) {
+        // under adaptable ND the band products of a corner tile come from
+        // several partitions, which progress concurrently: one chain of
+        // partial products per partition (each chunk as soon as its columns
+        // are final), then a binary tree over the partitions' partials.  A
+        // tile fed by a single partition is updated by a plain chain.
+        std::vector<std::pair<size_t, size_t>> groups;
+        if (s.nd_parts > 1 && !s.band_part.empty())
+          for (size_t q = 0; q < nb;) {
+            size_t e = q;
+            while (e < nb && s.band_part[pj[e]] == s.band_part[pj[q]]) e++;
+            groups.push_back({q, e});
+            q = e;
+          }
+        if (s.nd_parts > 1 && groups.size() >= 2 && s.opts.tree_min_ratio > 0) {
+          s.tree_used = 1;
+          std::vector<std::pair<int32_t, int32_t>> level;   // (slot, last task of its chain)
+          for (auto& gr : groups) {
+            const int32_t slot = s.npart++;
+            int prev = -1;
+            for (size_t lo = gr.first; lo < gr.second; lo += chunk) {
+              size_t hi = std::min(gr.second, lo + chunk);
+              int32_t p0 = (int32_t)(pairs.size() / 2);
+              for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+              int32_t p1 = (int32_t)(pairs.size() / 2);
+              int t = tb.add(TK_PART | (prev >= 0 ? TF_ACC : 0), -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+              fexec += 2.0 * T3 * (hi - lo);
+              for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+              tb.dep(t, prev);
+              prev = t;
+            }
+            level.push_back({slot, prev});
+          }
+          while (level.size() > 2) {
+            std::vector<std::pair<int32_t, int32_t>> next;
+            for (size_t q = 0; q + 1 < level.size(); q += 2) {
+              int32_t slot = s.npart++;
+              int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
+              tb.dep(t, level[q].second);
+              tb.dep(t, level[q + 1].second);
+              next.push_back({slot, t});
+            }
+            if (level.size() % 2) next.push_back(level.back());
+            level.swap(next);
+          }
+          int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
+          tb.dep(t, level[0].second);
+          tb.dep(t, level[1].second);
+          last = t;
+          start = nb;
+        } else if (s.nd_parts > 1) {
+          // one partition (or none): the plain chain below
+        } else if (s.opts.tree_min_ratio > 0 && G >= 2 && (int64_t)nb >= (int64_t)s.opts.tree_min_ratio * G) {
           s.tree_used = 1;
           // leaves: PART tasks over contiguous ranges of band columns (Alg. 3)
           std::vector<std::pair<int32_t, int32_t>> level;   // (slot, producing task)

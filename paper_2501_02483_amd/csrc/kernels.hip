@@ -147,10 +147,11 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
   const bool active = !(diag && wc > wr);   // strictly upper quarter of a diagonal tile
   const int p0 = w[2], p1 = w[3];
   const bool mixed = M.mixed && mode == 0;
+  const bool accum = mode == 1 && (w[0] & TF_ACC) != 0;   // partial chain: P += sum
   double* out = mode == 0 ? M.tiles + (int64_t)w[1] * TT : M.part + (int64_t)w[4] * TT;
   // the target's current value is needed only at the end: fetch it now
   double cin[NB][NB][4];
-  if (mode == 0 && active) {
+  if ((mode == 0 || accum) && active) {
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
@@ -193,7 +194,7 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
             if (mode == 0) {
               if (!diag || row >= col) out[row + col * T] = cin[i][j][r] - acc[i][j][r];
             } else {
-              out[row + col * T] = acc[i][j][r];
+              out[row + col * T] = accum ? cin[i][j][r] + acc[i][j][r] : acc[i][j][r];
             }
           }
     } else if (mode == 1) {   // keep the partial fully defined
@@ -383,7 +384,10 @@ __device__ __forceinline__ double row_bcast(double v, int r) {
 // column and publish it through LDS (the operations of one wave reach LDS in
 // order), and every lane applies its part of the rank-1 update.  The inverse
 // is built by forward substitution for all 16 right-hand sides at once, row
-// by row; each final row is broadcast inside its 16-lane row by DPP.
+// by row; each final row is broadcast inside its 16-lane row by DPP.  The
+// published columns go to pcol (16 columns with leading dimension T): the
+// caller passes the upper block (0, T/16 - 1) of the tile buffer, which no
+// other step uses while a diagonal block is factored.
 template <int T>
 __device__ __forceinline__ void diag_block16(double* S, double* Xi, double* rinv, double* pcol, int c0, int lane,
                                              int& fail) {
@@ -410,14 +414,14 @@ __device__ __forceinline__ void diag_block16(double* S, double* Xi, double* rinv
     }
     if (g == gj) {
       a[sj] = v;
-      pcol[16 * j + i] = v;
+      pcol[i + j * T] = v;
     }
     __builtin_amdgcn_wave_barrier();
-    const double lij = pcol[16 * j + i];
+    const double lij = pcol[i + j * T];
 #pragma unroll
     for (int s = 0; s < 4; s++) {
       const int q = g + 4 * s;
-      if (q > j) a[s] = fma(-lij, pcol[16 * j + q], a[s]);
+      if (q > j) a[s] = fma(-lij, pcol[q + j * T], a[s]);
     }
   }
 #pragma unroll
@@ -434,7 +438,7 @@ __device__ __forceinline__ void diag_block16(double* S, double* Xi, double* rinv
   for (int s = 0; s < 4; s++) x[s] = i == g + 4 * s ? 1.0 : 0.0;
 #pragma unroll
   for (int r = 0; r < 16; r++) {
-    const double lir = pcol[16 * r + i];   // L(i, r)
+    const double lir = pcol[i + r * T];   // L(i, r)
     if (i == r) {
 #pragma unroll
       for (int s = 0; s < 4; s++) x[s] *= piv[r];
@@ -481,8 +485,7 @@ __device__ __forceinline__ void inv_row_block(double* S, double* Xi, int b, int 
 }
 
 template <int T>
-__device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv,
-                                                     double* pcol) {
+__device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv) {
   constexpr int TT = T * T, NBK = T / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* C = M.tiles + (int64_t)w[1] * TT;
@@ -522,7 +525,7 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
 #pragma unroll 1
   for (int b = 0; b < NBK; b++) {
     const int c0 = 16 * b;
-    if (tid < 64) diag_block16<T>(S, Xi, rinv, pcol, c0, lane, fail);
+    if (tid < 64) diag_block16<T>(S, Xi, rinv, S + (T - 16) * T, c0, lane, fail);
     __syncthreads();
     // ---- row block b of the inverse, X(b, q) for q < b, on the waves that
     //      the panel below leaves idle (every input is final by now)
@@ -867,12 +870,11 @@ __device__ __attribute__((noinline)) void task_fsum(const ExecMat& M, const int3
 // TRSM) or triangular-solve tasks; the two are separate kernels so that each
 // carries only its own code.
 template <int T, bool SOLVE>
-__global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ mats, const int32_t* __restrict__ order,
+__global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__ mats, const int32_t* __restrict__ order,
                                                   int32_t total, ExecCtrl* ctrl, int nrhs) {
   __shared__ __attribute__((aligned(16))) double S[T * (T + 1)];
   __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : T * T];
   __shared__ double rinv[SOLVE ? 1 : T];
-  __shared__ double pcol[SOLVE ? 1 : 256];
   __shared__ int32_t s_ticket;
   // Control flow outside the task bodies is kept uniform across the
   // workgroup (values broadcast with readfirstlane, loops with uniform bounds
@@ -920,7 +922,7 @@ __global__ __launch_bounds__(NT) void exec_kernel(const ExecMat* __restrict__ ma
         case TK_TREE: task_tree<T>(M, w); break;
         case TK_POTRF:
           if constexpr (POTRF_COLS) task_potrf_cols<T>(M, w, S, Xi, rinv);
-          else task_potrf<T>(M, w, S, Xi, rinv, pcol);
+          else task_potrf<T>(M, w, S, Xi, rinv);
           break;
         default: task_trsm<T>(M, w, S, Xi); break;
       }

@@ -34,6 +34,7 @@ enum TaskType : int32_t {
 enum TaskFlag : int32_t {
   TF_DIAG = 1 << 8,   // UPD target is a diagonal tile (lower half only)
   TF_FIRST = 1 << 9,  // BUPD: first chunk reads Y_m; BDIAG: no BUPD, reads Y_m
+  TF_ACC = 1 << 10,   // PART: P_s += sum (continues a chain) instead of P_s = sum
 };
 
 // One task = 8 int32.

@@ -13,7 +13,7 @@ import paper_2501_02483_amd as S
 
 UPD, PART, TREE, POTRF, TRSM = 1, 2, 3, 4, 5
 FUPD, FDIAG, BUPD, BDIAG, FPART, FSUM = 8, 9, 10, 11, 12, 13
-TF_DIAG, TF_FIRST = 1 << 8, 1 << 9
+TF_DIAG, TF_FIRST, TF_ACC = 1 << 8, 1 << 9, 1 << 10
 
 
 class Plan:
@@ -97,6 +97,8 @@ def factor(plan, Aperm, mode="ticket", seed=0):
                     tiles[w[1]] -= np.tril(acc)
                 else:
                     tiles[w[1]] -= acc
+            elif w[0] & TF_ACC:
+                part[w[4]] += acc
             else:
                 part[w[4]] = acc
         elif typ == TREE:
