@@ -113,6 +113,13 @@ def bench_single(args):
         p, seed, nrhs, rseed = I.variable_band(), 2, 8, 102
     vals = I.make_values(p, seed=seed)
     B = I.rhs(p.N, nrhs, seed=rseed)
+    tuned = None
+    if args.tile == 0:
+        # autotune tile size and ordering on this matrix (timed on the device)
+        from paper_2501_02483_amd import autotune
+        best, tried = autotune.tune_single(p, vals, reps=2)
+        args.tile, args.ordering, args.parts = best["tile"], best["ordering"], best["nd_parts"]
+        tuned = tried
     ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
     sym = S.Symbolic.from_pattern(p, tile=args.tile, tree_min_ratio=args.tree_ratio, ordering=ordering,
                                   nd_parts=args.parts)
@@ -180,7 +187,7 @@ def bench_single(args):
         "data": "synthetic",
         "config": {"workload": p.name, "n": p.n, "arrow": p.a, "N": p.N, "tile": args.tile, "nrhs": nrhs,
                    "ordering": {1: "none", 3: "adaptable_nd"}.get(sym.info.ordering_used, "other"),
-                   "nd_parts": sym.info.nd_parts,
+                   "nd_parts": sym.info.nd_parts, "autotune": tuned,
                    "value_seed": seed, "rhs_seed": rseed, "ops": "factorize+solve+logdet",
                    "parallelism": "single GPU, persistent DAG executor"},
         "factorizations_per_s": 1e3 / ms,
@@ -414,7 +421,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--tile", type=int, default=64)
+    ap.add_argument("--tile", type=int, default=64, help="tile size, 0 = autotune (tile, ordering, partitions)")
     ap.add_argument("--tree-ratio", type=int, default=2)
     ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
                     help="single-matrix workloads: natural order or adaptable nested dissection")

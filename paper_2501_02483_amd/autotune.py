@@ -1,12 +1,14 @@
-"""Tile-size and occupancy autotuner.
+"""Tile-size, ordering and occupancy autotuner.
 
 The paper tunes its tile size by sweeping (Section IV-B: larger tiles on the
-GPU; Appendix B: 40 to 400 on the CPU).  Here the candidates are the tile
-sizes the kernels support (32, 64) and caps on the number of persistent
-workgroups; each candidate is timed on the device with the library's own
-event pair around the factorization kernel, and the fastest is kept.  A
-choice is made per pattern (single matrices) or per batch (one tile size per
-launch), and cached by pattern signature.
+GPU; Appendix B: 40 to 400 on the CPU) and picks an ordering per matrix
+structure (Section III-A).  Here the candidates are the tile sizes the
+kernels support (32, 64), the natural order or adaptable nested dissection
+with several partition counts (single matrices), and caps on the number of
+persistent workgroups; each candidate is timed on the device with the
+library's own event pair around the factorization kernel, and the fastest is
+kept.  A choice is made per pattern (single matrices) or per batch (one tile
+size per launch), and cached by pattern signature.
 """
 import hashlib
 import json
@@ -33,23 +35,40 @@ def _time_factor(fac, dv, reps):
     return float(np.median(ts[1:]))
 
 
-def tune_single(pattern, values, tiles=TILES, wg_caps=(0,), reps=3, precision=0):
-    """Time factorizations of one matrix for each candidate; returns
-    (best dict, all results)."""
+# orderings tried for one matrix: the natural order, and adaptable nested
+# dissection with the analysis' own partition count and a few fixed ones
+# (0 = chosen by the analysis); the schedule is the one the analysis derives
+# for each choice
+ORDERINGS = (("none", 0), ("nd", 0), ("nd", 8), ("nd", 16), ("nd", 32))
+
+
+def tune_single(pattern, values, tiles=TILES, wg_caps=(0,), reps=3, precision=0, orderings=ORDERINGS):
+    """Time factorizations of one matrix for each candidate (tile size x
+    ordering x workgroup cap); returns (best dict, all results).  values: a
+    host array or a device tensor in the pattern's row-profile order."""
     import torch
 
     import paper_2501_02483_amd as S
-    dv = torch.from_numpy(values).cuda()
+    dv = values if hasattr(values, "data_ptr") else torch.from_numpy(values).cuda()
     results = []
+    seen = set()
     for T in tiles:
-        sym = S.Symbolic.from_pattern(pattern, tile=T)
-        fac = S.Factor(sym, precision)
-        for cap in wg_caps:
-            fac.set_max_workgroups(cap)
-            ms = _time_factor(fac, dv, reps)
-            results.append({"tile": T, "max_wg": cap, "ms": ms, "tflops": sym.info.flops_alg / ms / 1e9,
-                            "exec_over_alg": sym.info.flops_exec / sym.info.flops_alg})
-        del fac
+        for oname, parts in orderings:
+            ordv = S.STILES_ORDER_ADAPTABLE_ND if oname == "nd" else S.STILES_ORDER_NONE
+            sym = S.Symbolic.from_pattern(pattern, tile=T, ordering=ordv, nd_parts=parts)
+            key = (T, sym.info.ordering_used, sym.info.nd_parts)
+            if key in seen:          # e.g. ND infeasible (falls back) or the same P twice
+                continue
+            seen.add(key)
+            fac = S.Factor(sym, precision)
+            for cap in wg_caps:
+                fac.set_max_workgroups(cap)
+                ms = _time_factor(fac, dv, reps)
+                results.append({"tile": T, "ordering": oname if sym.info.nd_parts > 1 else "none",
+                                "nd_parts": sym.info.nd_parts, "max_wg": cap, "ms": ms,
+                                "tflops": sym.info.flops_alg / ms / 1e9,
+                                "exec_over_alg": sym.info.flops_exec / sym.info.flops_alg})
+            del fac
     best = min(results, key=lambda r: r["ms"])
     return best, results
 

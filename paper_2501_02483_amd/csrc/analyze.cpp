@@ -922,9 +922,11 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   for (int32_t m = 0; m < ntr; m++) {
     int32_t last = -1;
     const int32_t rb = s.trow_ptr[m], re = s.trow_ptr[m + 1] - 1;
-    // forward: the product with block m-1 (ready last) is fused into FDIAG
-    const bool fuse = re > rb && s.tcol[re - 1] == m - 1;
-    const int32_t body_end = fuse ? re - 1 : re;
+    // forward: the products with the two previous blocks (ready last) are
+    // fused into FDIAG, so that the chunk tasks depend on blocks at least
+    // three back
+    int32_t body_end = re;
+    while (body_end > rb && body_end > re - 2 && s.tcol[body_end - 1] >= m - 2) body_end--;
     const bool long_row = body_end - rb > 4 * schunk;
     if (long_row) {
       // a long row (arrow and separator rows): chunks of products into
@@ -956,10 +958,10 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
       last = t;
     }
     int32_t f0 = (int32_t)(sp.size() / 2), f1 = f0;
-    if (fuse) { sp.push_back(re - 1); sp.push_back(m - 1); f1 = f0 + 1; }
+    for (int32_t q = body_end; q < re; q++) { sp.push_back(q); sp.push_back(s.tcol[q]); f1++; }
     int t = sb.add(TK_FDIAG, m, f0, f1, 0, 0.6f);
     sb.dep(t, last);
-    if (fuse) sb.dep(t, fdiag[m - 1]);
+    for (int32_t q = body_end; q < re; q++) sb.dep(t, fdiag[s.tcol[q]]);
     fdiag[m] = t;
   }
   for (int32_t m = ntr - 1; m >= 0; m--) {
@@ -968,8 +970,8 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
     std::vector<std::pair<int32_t, int32_t>> below;
     for (auto& it : ctiles[m]) if (it.first > m) below.push_back(it);
     std::reverse(below.begin(), below.end());
-    const bool fuse = !below.empty() && below.back().first == m + 1;
-    const size_t body_end = fuse ? below.size() - 1 : below.size();
+    size_t body_end = below.size();
+    while (body_end > 0 && body_end + 2 > below.size() && below[body_end - 1].first <= m + 2) body_end--;
     int32_t last = -1;
     bool first = true;
     for (size_t lo = 0; lo < body_end; lo += schunk) {
@@ -985,11 +987,15 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
       first = false;
     }
     int32_t f0 = (int32_t)(sp.size() / 2), f1 = f0;
-    if (fuse) { sp.push_back(below.back().second); sp.push_back(below.back().first); f1 = f0 + 1; }
+    for (size_t q = body_end; q < below.size(); q++) {
+      sp.push_back(below[q].second);
+      sp.push_back(below[q].first);
+      f1++;
+    }
     int t = sb.add(TK_BDIAG | (first ? TF_FIRST : 0), m, f0, f1, 0, 0.6f);
     sb.dep(t, last);
     sb.dep(t, fdiag[m]);
-    if (fuse) sb.dep(t, bdiag[m + 1]);
+    for (size_t q = body_end; q < below.size(); q++) sb.dep(t, bdiag[below[q].first]);
     bdiag[m] = t;
   }
   s.spairs = sp;

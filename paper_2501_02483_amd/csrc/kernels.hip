@@ -851,16 +851,25 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
 }
 
 // Y_m -= Q_a + ... + Q_(b-1): the partial products of a long row, summed in
-// slot order (fixed, so the result does not depend on the schedule)
+// a fixed order (so the result does not depend on the schedule)
 template <int T>
 __device__ __attribute__((noinline)) void task_fsum(const ExecMat& M, const int32_t* w, int nrhs) {
   const int64_t vb = (int64_t)T * nrhs;
   double* y = M.vy + (int64_t)w[1] * vb;
   const int a = w[2], b = w[3];
   for (int e = threadIdx.x; e < T * nrhs; e += NT) {
-    double s = 0.0;
-    for (int q = a; q < b; q++) s += M.vpart[(int64_t)q * vb + e];
-    y[e] -= s;
+    // four running sums (slot q goes to sum q mod 4) keep four loads in
+    // flight; the order is fixed, so the result does not depend on timing
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = a;
+    for (; q + 4 <= b; q += 4) {
+      s0 += M.vpart[(int64_t)q * vb + e];
+      s1 += M.vpart[(int64_t)(q + 1) * vb + e];
+      s2 += M.vpart[(int64_t)(q + 2) * vb + e];
+      s3 += M.vpart[(int64_t)(q + 3) * vb + e];
+    }
+    for (; q < b; q++) s0 += M.vpart[(int64_t)q * vb + e];
+    y[e] -= (s0 + s1) + (s2 + s3);
   }
 }
 
