@@ -988,6 +988,8 @@ hipError_t launch_exec(int T, const ExecMat* d_mats, const int32_t* d_order, int
 
 // One T x T tile of the store from row-profile values: staged through LDS so
 // that the reads follow the input rows and the stores the column-major tile.
+// The first column and start offset of each of the tile's rows are read once
+// into LDS, so every element costs one global load.
 template <int T>
 __device__ __forceinline__ void scatter_tile(const double* __restrict__ vals, const int64_t* __restrict__ in_rp,
                                              const int64_t* __restrict__ f, int m, int j,
@@ -995,15 +997,21 @@ __device__ __forceinline__ void scatter_tile(const double* __restrict__ vals, co
                                              const int32_t* __restrict__ row_cnt, double* out, double* o2,
                                              double* buf) {
   constexpr int TT = T * T;
+  __shared__ int64_t sf[T], sp[T];
   const int64_t rb = row_base[m], cb = row_base[j];
   const int rc = row_cnt[m], cc = row_cnt[j];
+  if ((int)threadIdx.x < rc) {
+    sf[threadIdx.x] = f[rb + threadIdx.x];
+    sp[threadIdx.x] = in_rp[rb + threadIdx.x];
+  }
+  __syncthreads();
   for (int e = threadIdx.x; e < TT; e += NT) {
     const int r = e / T, c = e % T;   // row-wise: consecutive threads read consecutive values
     double v = 0.0;
     if (r < rc) {
       const int64_t i = rb + r, g = cb + c;
-      const int64_t fi = f[i];
-      if (c < cc && g <= i && g >= fi) v = vals[in_rp[i] + (g - fi)];
+      const int64_t fi = sf[r];
+      if (c < cc && g <= i && g >= fi) v = vals[sp[r] + (g - fi)];
     } else if (m == j && r == c) {
       v = 1.0;   // padding row: unit diagonal
     }
@@ -1051,16 +1059,29 @@ __global__ __launch_bounds__(NT) void scatter_perm_kernel(const double* __restri
                                                           double* orig, unsigned long long* info) {
   constexpr int TT = T * T;
   __shared__ double buf[T * (T + 1)];
-  __shared__ int64_t pr[T], pc[T];
+  // per row and per column of the tile: input index, its first column and
+  // its value offset (the larger input index of an entry names its row)
+  __shared__ int64_t pr[T], pc[T], fr[T], fc[T], sr[T], sc[T];
   const int64_t t = blockIdx.x;
   const int m = trow[t], j = tcol[t];
   const int64_t rb = row_base[m], cb = row_base[j];
   const int rc = row_cnt[m], cc = row_cnt[j];
   if (threadIdx.x < T) {
-    pr[threadIdx.x] = (int)threadIdx.x < rc ? perm[rb + threadIdx.x] : -1;
+    const int r = threadIdx.x;
+    if (r < rc) {
+      const int64_t o = perm[rb + r];
+      pr[r] = o;
+      fr[r] = fin[o];
+      sr[r] = in_rp[o];
+    }
   } else if (threadIdx.x < 2 * T) {
     const int c = threadIdx.x - T;
-    pc[c] = c < cc ? perm[cb + c] : -1;
+    if (c < cc) {
+      const int64_t o = perm[cb + c];
+      pc[c] = o;
+      fc[c] = fin[o];
+      sc[c] = in_rp[o];
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < TT; e += NT) {
@@ -1069,9 +1090,11 @@ __global__ __launch_bounds__(NT) void scatter_perm_kernel(const double* __restri
     if (r < rc) {
       if (c < cc && cb + c <= rb + r) {
         const int64_t oi = pr[r], oj = pc[c];
-        const int64_t hi = oi > oj ? oi : oj, lo = oi > oj ? oj : oi;
-        const int64_t fh = fin[hi];
-        if (lo >= fh) v = vals[in_rp[hi] + (lo - fh)];
+        const bool rowi = oi > oj;
+        const int64_t lo = rowi ? oj : oi;
+        const int64_t fh = rowi ? fr[r] : fc[c];
+        const int64_t base = rowi ? sr[r] : sc[c];
+        if (lo >= fh) v = vals[base + (lo - fh)];
       }
     } else if (m == j && r == c) {
       v = 1.0;   // padding row: unit diagonal
@@ -1358,48 +1381,61 @@ hipError_t launch_unpack(int T, const double* Z, int nrhs, const int64_t* perm, 
 
 namespace stiles {
 
+// Residual items on MFMA: each tile of the item is staged in LDS
+// (with |.| in absmode), multiplied with the vector block (A x for row items,
+// A^T x for column items; a diagonal tile adds its strict lower part
+// transposed), and the item's partial written once.
 template <int T>
-__global__ __launch_bounds__(NT) void residual_item_kernel(const double* __restrict__ orig,
-                                                           const int32_t* __restrict__ trow,
-                                                           const int32_t* __restrict__ tcol,
-                                                           const int32_t* __restrict__ ccol_tile,
-                                                           const int32_t* __restrict__ ccol_row,
-                                                           const int32_t* __restrict__ items,
-                                                           const double* __restrict__ X, double* part, int nrhs,
-                                                           int absmode) {
-  constexpr int TT = T * T, G = NT / T, MAXC = 16 / G;
+__global__ __launch_bounds__(NT) void residual_mma_kernel(const double* __restrict__ orig,
+                                                          const int32_t* __restrict__ tcol,
+                                                          const int32_t* __restrict__ ccol_tile,
+                                                          const int32_t* __restrict__ ccol_row,
+                                                          const int32_t* __restrict__ items,
+                                                          const double* __restrict__ X, double* part, int nrhs,
+                                                          int absmode) {
+  constexpr int TT = T * T, LD = T + 1;
+  __shared__ __attribute__((aligned(16))) double LL[T * LD];
+  __shared__ __attribute__((aligned(16))) double LV[T * 16];
   const int q = blockIdx.x;
   const int m = items[4 * q], kind = items[4 * q + 1], lo = items[4 * q + 2], hi = items[4 * q + 3];
-  const int row = threadIdx.x % T, grp = threadIdx.x / T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool act = 16 * wave < T;
+  const int col = lane & 15;
   const int64_t vb = (int64_t)T * nrhs;
   const int ncol = absmode ? 1 : nrhs;
-  double acc[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; c++) acc[c] = 0.0;
+  if (absmode) {
+    for (int e = threadIdx.x; e < T * 16; e += NT) LV[e] = e < T ? 1.0 : 0.0;
+  }
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  SolveStage<T> st;
   for (int e = lo; e < hi; e++) {
     int tile, src;
     if (kind == 0) { tile = e; src = tcol[e]; } else { tile = ccol_tile[e]; src = ccol_row[e]; }
-    const double* A = orig + (int64_t)tile * TT;
-    const double* x = X + src * vb;
-    const bool dg = kind == 0 && src == m;
-    for (int l = 0; l < T; l++) {
-      double av;
-      if (kind == 1) av = A[l + row * T];
-      else if (dg) av = l <= row ? A[row + l * T] : A[l + row * T];
-      else av = A[row + l * T];
-      if (absmode) av = fabs(av);
+    st.load_tile(orig + (int64_t)tile * TT);
+    if (absmode) {
 #pragma unroll
-      for (int c = 0; c < MAXC; c++) {
-        const int cc = grp + c * G;
-        if (cc < ncol) acc[c] += av * (absmode ? 1.0 : x[l + cc * T]);
-      }
+      for (int k = 0; k < SolveStage<T>::NVL; k++) { st.lt[k].x = fabs(st.lt[k].x); st.lt[k].y = fabs(st.lt[k].y); }
+    } else {
+      st.load_vec(X + src * vb, nrhs);
+    }
+    __syncthreads();   // the previous tile's products are done with LL / LV
+    st.store_tile(LL);
+    if (!absmode) st.store_vec(LV);
+    __syncthreads();
+    if (act) acc = solve_mma<T>(acc, LL, LV, kind == 1, wave, lane);
+    if (kind == 0 && src == m) {
+      // diagonal tile: only its lower triangle is stored; add the strict
+      // lower part transposed
+      __syncthreads();
+      if ((int)threadIdx.x < T) LL[threadIdx.x * (LD + 1)] = 0.0;
+      __syncthreads();
+      if (act) acc = solve_mma<T>(acc, LL, LV, true, wave, lane);
     }
   }
   double* out = part + (int64_t)q * vb;
+  if (act && col < ncol) {
 #pragma unroll
-  for (int c = 0; c < MAXC; c++) {
-    const int cc = grp + c * G;
-    if (cc < ncol) out[row + cc * T] = acc[c];
+    for (int r = 0; r < 4; r++) out[(16 * wave + (lane >> 4) + 4 * r) + col * T] = acc[r];
   }
 }
 
@@ -1419,12 +1455,15 @@ hipError_t launch_residual(int T, const double* orig, const int32_t* trow, const
                            const int32_t* ccol_tile, const int32_t* ccol_row, const int32_t* items, int32_t nitems,
                            const int32_t* item_ptr, int32_t ntr, const double* X, const double* B, double* part,
                            double* R, int nrhs, int absmode, hipStream_t st) {
-  if (T == 64)
-    hipLaunchKernelGGL(residual_item_kernel<64>, dim3(nitems), dim3(NT), 0, st, orig, trow, tcol, ccol_tile, ccol_row,
-                       items, X, part, nrhs, absmode);
-  else
-    hipLaunchKernelGGL(residual_item_kernel<32>, dim3(nitems), dim3(NT), 0, st, orig, trow, tcol, ccol_tile, ccol_row,
-                       items, X, part, nrhs, absmode);
+  (void)trow;
+  if (nitems > 0) {
+    if (T == 64)
+      hipLaunchKernelGGL(residual_mma_kernel<64>, dim3(nitems), dim3(NT), 0, st, orig, tcol, ccol_tile, ccol_row, items,
+                         X, part, nrhs, absmode);
+    else
+      hipLaunchKernelGGL(residual_mma_kernel<32>, dim3(nitems), dim3(NT), 0, st, orig, tcol, ccol_tile, ccol_row, items,
+                         X, part, nrhs, absmode);
+  }
   hipLaunchKernelGGL(residual_combine_kernel, dim3(ntr), dim3(NT), 0, st, T, item_ptr, part, B, R, nrhs, absmode);
   return hipGetLastError();
 }
