@@ -227,9 +227,9 @@ def bench_batch(args):
     dvals = [DevicePattern(p).values(p.meta["value_seed"]) for p in pats]
     torch.cuda.synchronize()
     best, tried = autotune.tune_batch(pats, dvals, reps=2) if args.tile == 0 \
-        else ({"tile": args.tile}, [])
+        else ({"tile": args.tile, "nd_min_rows": args.nd_min_rows}, [])
     T = best["tile"]
-    syms = [S.Symbolic.from_pattern(p, tile=T) for p in pats]
+    syms = autotune.batch_symbolics(pats, T, best["nd_min_rows"])
     facs = [S.Factor(s) for s in syms]
     batch = S.Batch(facs)
     lds = torch.empty(len(facs), dtype=torch.float64, device="cuda")
@@ -263,6 +263,8 @@ def bench_batch(args):
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic (device-generated values)",
             "config": {"workload": "batch%d_uneven" % len(pats), "matrices": len(pats), "tile": T,
+                       "nd_min_rows": best["nd_min_rows"],
+                       "nd_matrices": sum(1 for s in syms if s.info.nd_parts > 1),
                        "autotune": tried, "parallelism": "single GPU, one persistent launch"},
             "factorizations_per_s": len(pats) * 1e3 / ms, "flops_alg": F,
             "failed": int(sum(1 for i in infos if i != 0)),
@@ -430,6 +432,8 @@ def main():
     ap.add_argument("--rocpd-summary", default="", help="print a per-kernel table of a rocprofv3 database and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count", type=int, default=512, help="batch: number of matrices")
+    ap.add_argument("--nd-min-rows", type=int, default=0,
+                    help="batch: adaptable ND for matrices with at least this many band tile rows (0 = none)")
     ap.add_argument("--n", type=int, default=0, help="mixed: band rows (default 500,000)")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for in-flight requests")

@@ -73,16 +73,33 @@ def tune_single(pattern, values, tiles=TILES, wg_caps=(0,), reps=3, precision=0,
     return best, results
 
 
-def tune_batch(patterns, values, tiles=TILES, reps=2):
-    """Time one batched launch of all matrices for each tile size (values:
-    host arrays or device tensors)."""
+def batch_symbolics(patterns, tile, nd_min_rows=0, nd_parts=2):
+    """Symbolic objects for a batch: matrices with at least nd_min_rows band
+    tile rows (0: none) are cut into nd_parts partitions by adaptable nested
+    dissection, so that the longest pivot chains of the batch shrink (two
+    partitions add no fill: both have their separator at their end); the
+    others keep their order."""
+    import paper_2501_02483_amd as S
+    out = []
+    for p in patterns:
+        long_chain = nd_min_rows > 0 and (p.n + tile - 1) // tile >= nd_min_rows
+        if long_chain:
+            out.append(S.Symbolic.from_pattern(p, tile=tile, ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=nd_parts))
+        else:
+            out.append(S.Symbolic.from_pattern(p, tile=tile, ordering=S.STILES_ORDER_NONE))
+    return out
+
+
+def tune_batch(patterns, values, tiles=TILES, reps=2, nd_thresholds=(0, 240, 160, 120)):
+    """Time one batched launch of all matrices for each tile size and
+    nested-dissection threshold (values: host arrays or device tensors)."""
     import torch
 
     import paper_2501_02483_amd as S
     dvals = [v if hasattr(v, "data_ptr") else torch.from_numpy(v).cuda() for v in values]
     results = []
-    for T in tiles:
-        syms = [S.Symbolic.from_pattern(p, tile=T) for p in patterns]
+    for T, thr in [(T, thr) for T in tiles for thr in nd_thresholds]:
+        syms = batch_symbolics(patterns, T, thr)
         facs = [S.Factor(s) for s in syms]
         batch = S.Batch(facs)
         batch.factorize(dvals)
@@ -96,7 +113,8 @@ def tune_batch(patterns, values, tiles=TILES, reps=2):
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
         F = sum(s.info.flops_alg for s in syms)
-        results.append({"tile": T, "ms": float(np.median(ts)), "tflops": F / float(np.median(ts)) / 1e9})
+        results.append({"tile": T, "nd_min_rows": thr, "nd_matrices": sum(1 for s in syms if s.info.nd_parts > 1),
+                        "ms": float(np.median(ts)), "tflops": F / float(np.median(ts)) / 1e9})
         del batch, facs, syms
     best = min(results, key=lambda r: r["ms"])
     return best, results

@@ -599,8 +599,15 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
     const Layout& L = f->L;
     mats[i] = f->mf;
     BatchDesc& d = desc[i];
-    d.in_rp = at<int64_t>(f, L.in_rp);
-    d.f = at<int64_t>(f, L.fprof);
+    if (s.profile_input && !s.perm_identity) {
+      d.in_rp = at<int64_t>(f, L.in_rp_in);
+      d.f = at<int64_t>(f, L.fin);
+      d.perm = at<int64_t>(f, L.perm);
+    } else {
+      d.in_rp = at<int64_t>(f, L.in_rp);
+      d.f = at<int64_t>(f, L.fprof);
+      d.perm = nullptr;
+    }
     d.trow = at<int32_t>(f, L.trow);
     d.tcol = at<int32_t>(f, L.tcol);
     d.trow_ptr = at<int32_t>(f, L.trow_ptr);
@@ -612,7 +619,7 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
     d.info = at<unsigned long long>(f, L.info);
     d.ntiles = (int32_t)s.ntiles;
     d.ntr = s.ntr;
-    if (!s.profile_input || !s.perm_identity) b->all_profile = false;
+    if (!s.profile_input) b->all_profile = false;
     for (int32_t t = 0; t < (int32_t)s.ntiles; t++) { tmap.push_back(i); tmap.push_back(t); }
     for (int32_t m = 0; m < s.ntr; m++) { rmap.push_back(i); rmap.push_back(m); }
   }

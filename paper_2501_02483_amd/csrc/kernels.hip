@@ -1047,23 +1047,19 @@ __global__ __launch_bounds__(NT) void scatter_profile_kernel(const double* __res
 // (r, c) of tile (m, j) is the input entry (perm[row], perm[col]), taken from
 // the lower triangle (larger index as the row).  The gathers follow the tile
 // rows; entries of reversed blocks are read transposed.
+// Tile of P A P^T from row-profile values of the input ordering: element
+// (r, c) of tile (m, j) is the input entry (perm[row], perm[col]), taken from
+// the lower triangle (larger index as the row).
 template <int T>
-__global__ __launch_bounds__(NT) void scatter_perm_kernel(const double* __restrict__ vals,
-                                                          const int64_t* __restrict__ in_rp,
-                                                          const int64_t* __restrict__ fin,
-                                                          const int64_t* __restrict__ perm,
-                                                          const int32_t* __restrict__ trow,
-                                                          const int32_t* __restrict__ tcol,
-                                                          const int64_t* __restrict__ row_base,
-                                                          const int32_t* __restrict__ row_cnt, double* tiles,
-                                                          double* orig, unsigned long long* info) {
+__device__ __forceinline__ void scatter_tile_perm(const double* __restrict__ vals, const int64_t* __restrict__ in_rp,
+                                                  const int64_t* __restrict__ fin, const int64_t* __restrict__ perm,
+                                                  int m, int j, const int64_t* __restrict__ row_base,
+                                                  const int32_t* __restrict__ row_cnt, double* out, double* o2,
+                                                  double* buf) {
   constexpr int TT = T * T;
-  __shared__ double buf[T * (T + 1)];
   // per row and per column of the tile: input index, its first column and
   // its value offset (the larger input index of an entry names its row)
   __shared__ int64_t pr[T], pc[T], fr[T], fc[T], sr[T], sc[T];
-  const int64_t t = blockIdx.x;
-  const int m = trow[t], j = tcol[t];
   const int64_t rb = row_base[m], cb = row_base[j];
   const int rc = row_cnt[m], cc = row_cnt[j];
   if (threadIdx.x < T) {
@@ -1102,14 +1098,29 @@ __global__ __launch_bounds__(NT) void scatter_perm_kernel(const double* __restri
     buf[r * (T + 1) + c] = v;
   }
   __syncthreads();
-  double* out = tiles + t * TT;
-  double* o2 = orig ? orig + t * TT : nullptr;
   for (int e = threadIdx.x; e < TT; e += NT) {
     const int c = e / T, r = e % T;   // column-major store
     const double v = buf[r * (T + 1) + c];
     out[e] = v;
     if (o2) o2[e] = v;
   }
+}
+
+template <int T>
+__global__ __launch_bounds__(NT) void scatter_perm_kernel(const double* __restrict__ vals,
+                                                          const int64_t* __restrict__ in_rp,
+                                                          const int64_t* __restrict__ fin,
+                                                          const int64_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ trow,
+                                                          const int32_t* __restrict__ tcol,
+                                                          const int64_t* __restrict__ row_base,
+                                                          const int32_t* __restrict__ row_cnt, double* tiles,
+                                                          double* orig, unsigned long long* info) {
+  constexpr int TT = T * T;
+  __shared__ double buf[T * (T + 1)];
+  const int64_t t = blockIdx.x;
+  scatter_tile_perm<T>(vals, in_rp, fin, perm, trow[t], tcol[t], row_base, row_cnt, tiles + t * TT,
+                       orig ? orig + t * TT : nullptr, buf);
   if (t == 0 && threadIdx.x == 0) *info = ~0ull;
 }
 
@@ -1137,8 +1148,12 @@ __global__ __launch_bounds__(NT) void scatter_batch_kernel(const BatchDesc* __re
   const int2 mt = tmap[blockIdx.x];
   const BatchDesc& d = desc[mt.x];
   const int64_t t = mt.y;
-  scatter_tile<T>(vals[mt.x], d.in_rp, d.f, d.trow[t], d.tcol[t], d.row_base, d.row_cnt, d.tiles + t * TT,
-                  d.orig ? d.orig + t * TT : nullptr, buf);
+  if (d.perm)
+    scatter_tile_perm<T>(vals[mt.x], d.in_rp, d.f, d.perm, d.trow[t], d.tcol[t], d.row_base, d.row_cnt,
+                         d.tiles + t * TT, d.orig ? d.orig + t * TT : nullptr, buf);
+  else
+    scatter_tile<T>(vals[mt.x], d.in_rp, d.f, d.trow[t], d.tcol[t], d.row_base, d.row_cnt, d.tiles + t * TT,
+                    d.orig ? d.orig + t * TT : nullptr, buf);
   if (t == 0 && threadIdx.x == 0) *d.info = ~0ull;
 }
 

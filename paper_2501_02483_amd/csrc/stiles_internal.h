@@ -78,6 +78,7 @@ struct ExecMat {
 struct BatchDesc {
   const int64_t* in_rp;     // row pointers of the row-profile input
   const int64_t* f;         // first column of each row
+  const int64_t* perm;      // new row -> input row, or null (natural order: in_rp/f are those of P A P^T)
   const int32_t* trow;      // tile row of each stored tile
   const int32_t* tcol;      // tile column of each stored tile
   const int32_t* trow_ptr;  // first stored tile of each tile row
