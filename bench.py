@@ -423,7 +423,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--tile", type=int, default=64, help="tile size, 0 = autotune (tile, ordering, partitions)")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="tile size; 0 = autotune (tile and ordering, or tile and ND threshold for the batch); "
+                         "default: 64, autotuned for the batch workload")
     ap.add_argument("--tree-ratio", type=int, default=2)
     ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
                     help="single-matrix workloads: natural order or adaptable nested dissection")
@@ -440,6 +442,8 @@ def main():
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per load point")
     ap.add_argument("--max-n", type=int, default=0, help="serve: keep patterns with n <= max-n")
     args = ap.parse_args()
+    if args.tile < 0:
+        args.tile = 0 if args.workload == "batch" else 64
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
         return

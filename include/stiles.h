@@ -83,7 +83,7 @@ typedef struct stiles_opts {
                              accumulations is >= tree_min_ratio x the number of
                              partial workers (Section IV-A recommends 2); <= 0
                              disables the tree (sequential accumulation chain)       */
-  int32_t chunk;          /* tile products per accumulation task (0 = default 8)      */
+  int32_t chunk;          /* tile products per accumulation task (0: 12 at T=64, 16 at T=32) */
   double refine_tol;      /* mixed mode: stop when the backward error of every
                              right-hand side is <= refine_tol (0 = 2^-52 * N^0.5)    */
   int32_t refine_max_iter;/* mixed mode: at most this many refinement steps (0 = 30) */

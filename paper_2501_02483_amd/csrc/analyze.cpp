@@ -740,7 +740,7 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   s.flops_alg = envelope_flops(s.f_pre.empty() ? s.f : s.f_pre);
 
   // ---- factorization DAG
-  const int32_t chunk = s.opts.chunk > 0 ? s.opts.chunk : (T == 64 ? 8 : 16);
+  const int32_t chunk = s.opts.chunk > 0 ? s.opts.chunk : (T == 64 ? 12 : 16);
   const double t3 = std::pow((double)T / 64.0, 3.0);
   TaskBuilder tb;
   std::vector<int32_t> final_task(s.ntiles, -1);
