@@ -316,8 +316,9 @@ bool nd_plan_for(const std::vector<int64_t>& need, int64_t n, int64_t arrow, int
 // fewest parts whose estimated chain is within 1.5x of the shortest one over
 // P in [2, 64].  Every interior part adds a separator's width of fill across
 // its columns (executed work grows with P while the chain shrinks), so once
-// the chain is near its floor fewer parts are preferred.  False when no cut
-// is feasible.
+// the chain is near its floor fewer parts are preferred -- except for small
+// matrices (under 2e9 flops), which take the shortest chain.  False when no
+// cut is feasible.
 bool nd_plan(const std::vector<int64_t>& f, int64_t n, int64_t arrow, int32_t T, int32_t P_req, NDPlan& out) {
   const std::vector<int64_t> need = separator_need(f, n);
   if (P_req >= 2 && nd_plan_for(need, n, arrow, T, P_req, out)) return true;
@@ -329,8 +330,16 @@ bool nd_plan(const std::vector<int64_t>& f, int64_t n, int64_t arrow, int32_t T,
     if (best < 0 || pl.chain < best) best = pl.chain;
     plans.push_back(std::move(pl));
   }
+  // a small matrix is bound by its chain alone (its extra fill costs next to
+  // nothing): take the shortest chain
+  double work = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    const double e = (double)(i - f[i] + 1 + arrow);
+    work += e * e;
+  }
+  const bool tiny = work < 2e9;
   for (const NDPlan& pl : plans)
-    if (2 * pl.chain <= 3 * best) { out = pl; return true; }
+    if (tiny ? pl.chain == best : 2 * pl.chain <= 3 * best) { out = pl; return true; }
   return false;
 }
 
