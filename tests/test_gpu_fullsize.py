@@ -81,3 +81,62 @@ def test_batch512_full_size():
         worst = max(worst, abs(ld - ref) / abs(ref))
     say("   worst logdet error %.2e" % worst)
     assert worst <= TOL
+
+
+def test_small_bench_configuration():
+    """The n = 2,000 / half-width 50 / arrow 10 workload as the bench runs it
+    (T = 64, adaptable ND with the automatic partition count, 1 RHS)."""
+    import torch
+    p = I.single_small()
+    vals = I.make_values(p, seed=1)
+    B = I.rhs(p.N, 1, seed=101)
+    L, info = oracle.factor(p.f, vals, nthreads=_threads())
+    assert info == 0
+    X_o = oracle.solve(p.f, L, B)
+    ld_o = oracle.logdet(p.f, L)
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=S.STILES_ORDER_ADAPTABLE_ND)
+    say("[gpu fullsize] small workload, %d partitions" % sym.info.nd_parts)
+    fac = S.Factor(sym)
+    fac.factorize(torch.from_numpy(vals).cuda())
+    assert fac.info() == 0
+    dB = to_device_cols(B)
+    fac.solve(dB)
+    assert rel(dB.cpu().numpy(), X_o) <= TOL
+    assert abs(fac.logdet().item() - ld_o) <= TOL * abs(ld_o)
+
+
+def test_mixed_full_size():
+    """The n = 500,000 / half-width 1,000 / arrow 200 Laplacian workload
+    (κ ≈ 1e6) in mixed precision, as the bench runs it (adaptable ND, 16
+    right-hand sides, FP64 refinement): four sampled right-hand sides and
+    the log-determinant against the oracle on the device-drawn values."""
+    import torch
+
+    from paper_2501_02483_amd.devgen import DevicePattern
+    p = I.mixed_large()
+    dv = DevicePattern(p).values(4, law="laplacian", kappa=1e6)
+    B = torch.randn(16, p.N, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(104)).t()
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=S.STILES_ORDER_ADAPTABLE_ND)
+    say("[gpu fullsize] mixed n=500,000, %d partitions" % sym.info.nd_parts)
+    fac = S.Factor(sym, S.STILES_MIXED32, nrhs_max=16)
+    fac.factorize(dv)
+    assert fac.info() == 0
+    X = B.clone()
+    rep = fac.solve(X)
+    ld = fac.logdet().item()
+    vals = dv.cpu().numpy()
+    Bh = np.ascontiguousarray(B.cpu().numpy()[:, :4])
+    Xh = np.ascontiguousarray(X.cpu().numpy()[:, :4])
+    del fac, dv
+    say("   oracle factorization (host)")
+    L, info = oracle.factor(p.f, vals, nthreads=_threads())
+    assert info == 0
+    ld_o = oracle.logdet(p.f, L)
+    X_o = oracle.solve(p.f, L, Bh)
+    eX = rel(Xh, X_o)
+    eld = abs(ld - ld_o) / abs(ld_o)
+    say("   errors: X %.2e  logdet %.2e  refinement steps %d  backward error %.2e" % (
+        eX, eld, rep.iterations, rep.backward_error))
+    assert rep.converged == 1
+    assert eX <= 1e-9 and eld <= 1e-6
