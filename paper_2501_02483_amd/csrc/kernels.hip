@@ -773,9 +773,31 @@ __device__ __forceinline__ v4d solve_mma(v4d acc, const double* LL, const double
   return acc;
 }
 
+// Static operands of a solve task (the factor is final before the solve
+// starts): the first product's L tile into LL and, for a diagonal step, the
+// inverse diagonal tile into LI.  Issued before the task waits for its
+// predecessors, so the waiting hides these loads.
+template <int T>
+__device__ __forceinline__ void solve_prefetch(const ExecMat& M, const int32_t* w, double* LL, double* LI) {
+  constexpr int TT = T * T;
+  const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
+  if (type == TK_FSUM) return;
+  const int p0 = __builtin_amdgcn_readfirstlane(w[2]), p1 = __builtin_amdgcn_readfirstlane(w[3]);
+  SolveStage<T> st;
+  if (p1 > p0) {
+    st.load_tile(M.tiles + (int64_t)M.pairs[2 * p0] * TT);
+    st.store_tile(LL);
+  }
+  if (type == TK_FDIAG || type == TK_BDIAG) {
+    st.load_tile(M.linv + (int64_t)__builtin_amdgcn_readfirstlane(w[1]) * TT);
+    st.store_tile(LI);
+  }
+}
+
+// A solve task; its static operands are already staged by solve_prefetch.
 template <int T>
 __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int32_t* w, int nrhs, double* LL,
-                                                     double* LV) {
+                                                     double* LV, const double* LI) {
   constexpr int TT = T * T;
   const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -790,13 +812,10 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   const int col = lane & 15;
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
   SolveStage<T> st;
-  if (p1 > p0) {
-    st.load_tile(M.tiles + (int64_t)M.pairs[2 * p0] * TT);
-    st.load_vec(vsrc + M.pairs[2 * p0 + 1] * vb, nrhs);
-  }
+  if (p1 > p0) st.load_vec(vsrc + M.pairs[2 * p0 + 1] * vb, nrhs);
   for (int p = p0; p < p1; p++) {
     __syncthreads();
-    st.store_tile(LL);
+    if (p > p0) st.store_tile(LL);   // the first tile was prefetched
     st.store_vec(LV);
     __syncthreads();
     if (p + 1 < p1) {
@@ -830,11 +849,10 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
     }
     return;
   }
-  // diagonal: out = Linv_m (base - acc)   (Linv_m^T in the backward sweep)
-  st.load_tile(M.linv + (int64_t)m * TT);
+  // diagonal: out = Linv_m (base - acc)   (Linv_m^T in the backward sweep);
+  // Linv_m was prefetched into LI
   st.load_vec(base, nrhs);
   __syncthreads();
-  st.store_tile(LL);
   st.store_vec(LV);
   __syncthreads();
   if (act) {
@@ -843,7 +861,7 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   }
   __syncthreads();
   v4d out = v4d{0.0, 0.0, 0.0, 0.0};
-  if (act) out = solve_mma<T>(out, LL, LV, !fwd, wave, lane);
+  if (act) out = solve_mma<T>(out, LI, LV, !fwd, wave, lane);
   if (act && col < nrhs) {
 #pragma unroll
     for (int r = 0; r < 4; r++) dst[(16 * wave + (lane >> 4) + 4 * r) + col * T] = out[r];
@@ -884,6 +902,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
   __shared__ __attribute__((aligned(16))) double S[T * (T + 1)];
   __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : T * T];
   __shared__ double rinv[SOLVE ? 1 : T];
+  __shared__ __attribute__((aligned(16))) double LI[SOLVE ? T * (T + 1) : 1];
   __shared__ int32_t s_ticket;
   // Control flow outside the task bodies is kept uniform across the
   // workgroup (values broadcast with readfirstlane, loops with uniform bounds
@@ -905,6 +924,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     int32_t* cnt = M.remaining + lid;
     uint64_t t_claim = 0, t_start = 0;
     if (M.trace) t_claim = wall_clock64();
+    if constexpr (SOLVE) solve_prefetch<T>(M, w, S, LI);
     // wait until every predecessor has finished (Alg. 2 progress check);
     // wave 0 polls, then acquires for the workgroup (all its waves share
     // the CU's caches that the acquire invalidates)
@@ -923,7 +943,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     if (chain) __builtin_amdgcn_s_setprio(3);
     if constexpr (SOLVE) {
       if (type == TK_FSUM) task_fsum<T>(M, w, nrhs);
-      else task_solve<T>(M, w, nrhs, S, Xi);
+      else task_solve<T>(M, w, nrhs, S, Xi, LI);
     } else {
       switch (type) {
         case TK_UPD: task_update<T>(M, w, 0, S, Xi); break;
