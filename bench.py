@@ -202,7 +202,8 @@ def bench_single(args):
                      "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
                      "traffic": None, "kernel_ms": kernel_ms, "bytes_alg": 16 * p.nnz},
     }
-    tr = measured_traffic("%s_n%d_a%d_%s" % (p.name.split("_")[0].rstrip("0123456789"), p.n, p.a, args.ordering),
+    order_key = "nd%d" % sym.info.nd_parts if sym.info.nd_parts > 1 else "none"
+    tr = measured_traffic("%s_n%d_a%d_%s" % (p.name.split("_")[0].rstrip("0123456789"), p.n, p.a, order_key),
                           args.tile)
     if tr is not None:
         res["roofline"]["traffic"] = tr["bytes"]

@@ -339,7 +339,7 @@ bool nd_plan(const std::vector<int64_t>& f, int64_t n, int64_t arrow, int32_t T,
   }
   const bool tiny = work < 2e9;
   for (const NDPlan& pl : plans)
-    if (tiny ? pl.chain == best : 2 * pl.chain <= 3 * best) { out = pl; return true; }
+    if (tiny ? pl.chain == best : 10 * pl.chain <= 13 * best) { out = pl; return true; }
   return false;
 }
 
