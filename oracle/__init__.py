@@ -51,6 +51,8 @@ def _load():
         lib.oracle_factor_residual.restype = None
         lib.oracle_factor_residual.argtypes = [ctypes.c_int64, _i64p, _f64p, _f64p, ctypes.c_int64,
                                                _i64p, _f64p, _f64p]
+        lib.oracle_selinv.restype = None
+        lib.oracle_selinv.argtypes = [ctypes.c_int64, _i64p, _f64p, _f64p, ctypes.c_int]
         lib.oracle_row_ptr.restype = None
         lib.oracle_row_ptr.argtypes = [ctypes.c_int64, _i64p, _i64p]
         _lib = lib
@@ -100,6 +102,15 @@ def solve(f, L, B):
     X = np.array(B.reshape(B.shape[0], -1), dtype=np.float64, order="F", copy=True)
     _load().oracle_solve(f.shape[0], _pi(f), _p64(L), X.shape[1], _p64(X), X.shape[0])
     return X[:, 0].copy() if vec else X
+
+
+def selinv(f, L, nthreads=0):
+    """Entries of A^{-1} inside the envelope, from the factor L (same layout)."""
+    f = _prof(f)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    Sg = np.zeros_like(L)
+    _load().oracle_selinv(f.shape[0], _pi(f), _p64(L), _p64(Sg), int(nthreads))
+    return Sg
 
 
 def symv(f, A, X):

@@ -28,6 +28,9 @@
  * Pins (tests/test_oracle_pins.py): LAPACK dense Cholesky on small inputs,
  * exactly planted integer factors (bit-exact), closed-form arrowhead and
  * Toeplitz-band determinants, solve backward error, permutation invariance.
+ * Selected inversion (tests/test_oracle_selinv.py): the dense inverse on small
+ * inputs, the closed-form inverses of the second-difference matrix and of a
+ * pure arrowhead, and exactly planted integer inverses (bit-exact).
  */
 #include <math.h>
 #include <stdint.h>
@@ -148,6 +151,67 @@ void oracle_solve(int64_t N, const int64_t* f, const double* L, int64_t nrhs,
       for (int64_t k = f[i]; k < i; k++) b[k] -= ri[k] * z;
     }
   }
+  free(rp);
+}
+
+/*
+ * Selected inversion: the entries of Sigma = A^{-1} inside the envelope of A,
+ * from its factor L (A = L L^T), written to S in the same row-profile layout.
+ * Inverses of block-arrowhead matrices are one of the tasks the paper's
+ * introduction lists for this class (Section I); INLA needs the diagonal of
+ * the inverse (posterior marginal variances).
+ *
+ * Textbook recursion (Takahashi, Fagan and Chen, 1973): from Sigma L = L^{-T},
+ * whose lower part below the diagonal is zero and whose diagonal is 1/L_jj,
+ * column j of Sigma on the rows R_j = {i > j : f_i <= j} of column j of L is
+ *   Sigma_ij = -(1/L_jj) sum_{k in R_j} Sigma_ik L_kj         (i in R_j)
+ *   Sigma_jj = (1/L_jj) (1/L_jj - sum_{k in R_j} L_kj Sigma_kj)
+ * for j = N-1 down to 0.  Every Sigma_ik used (i, k in R_j) lies in the
+ * envelope (row max(i,k) reaches column min(i,k), since f <= j there) and in a
+ * column > j, so it is final when column j is computed.  Sums run in
+ * ascending k.  Rows of one column are independent (parallel).
+ */
+void oracle_selinv(int64_t N, const int64_t* f, const double* L, double* S, int nthreads) {
+  int64_t* rp = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  oracle_row_ptr(N, f, rp);
+  int64_t wmax = 0;
+  for (int64_t i = 0; i < N; i++) if (i - f[i] > wmax && f[i] > 0) wmax = i - f[i];
+  int64_t nfull = 0;             /* rows with f == 0 beyond the band reach */
+  int64_t* full = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+  for (int64_t i = 0; i < N; i++) if (f[i] == 0 && i > wmax) full[nfull++] = i;
+  int64_t* R = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  for (int64_t j = N - 1; j >= 0; j--) {
+    /* R_j ascending: band candidates (j, j + wmax], then the full rows beyond */
+    int64_t nr = 0;
+    int64_t band_hi = j + wmax < N - 1 ? j + wmax : N - 1;
+    for (int64_t i = j + 1; i <= band_hi; i++) if (f[i] <= j) R[nr++] = i;
+    for (int64_t q = 0; q < nfull; q++) if (full[q] > band_hi) R[nr++] = full[q];
+    const double ljj = L[rp[j] + (j - f[j])];
+    #pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < nr; a++) {
+      const int64_t i = R[a];
+      double s = 0.0;
+      for (int64_t b = 0; b < nr; b++) {
+        const int64_t k = R[b];
+        const int64_t hi = i > k ? i : k, lo = i > k ? k : i;
+        s += S[rp[hi] + (lo - f[hi])] * L[rp[k] + (j - f[k])];
+      }
+      S[rp[i] + (j - f[i])] = -s / ljj;
+    }
+    double s = 0.0;
+    for (int64_t b = 0; b < nr; b++) {
+      const int64_t k = R[b];
+      s += L[rp[k] + (j - f[k])] * S[rp[k] + (j - f[k])];
+    }
+    S[rp[j] + (j - f[j])] = (1.0 / ljj - s) / ljj;
+  }
+  free(R);
+  free(full);
   free(rp);
 }
 
