@@ -177,6 +177,8 @@ void stiles_symbolic_destroy(stiles_symbolic* sym);
  *   6 tile-row pointers (int32, tile_rows + 1)  7 tile columns (int32, tiles)
  *   8 first permuted row of each tile row (int64)  9 real rows per tile row (int32)
  *   10 number of tree partial slots (int32, 1 element)
+ *   11 selected-inversion tasks  12 their successor lists  13 their operand
+ *     lists (int32; built on first use)
  * With out == NULL, *count receives the number of elements; otherwise *count
  * is the capacity of out (elements) and receives the number copied.
  * EINVAL: unknown `which` (argument 2) or capacity too small (argument 4).
@@ -298,6 +300,49 @@ stiles_status stiles_factor_set_max_workgroups(stiles_factor* f, int32_t max_wg)
 
 /* Releases the host handle (the caller frees the workspace). */
 void stiles_factor_release(stiles_factor* f);
+
+/*
+ * Selected inversion: the entries of Sigma = A^{-1} on the stored tiles of
+ * the factor, in particular its diagonal (inverses of block-arrowhead
+ * matrices are one of the tasks Section I lists for this class; INLA needs
+ * the diagonal, the posterior marginal variances).  Computed from a resident
+ * FP64 factor by the block form of the Takahashi recursion, tile column by
+ * tile column in reverse elimination order, as one persistent launch over a
+ * task DAG of tile products on the FP64 matrix cores.  In mixed precision
+ * it inverts the computed factor (no refinement).
+ *
+ * stiles_selinv_workspace_size: device bytes for Sigma (one T x T tile per
+ *   stored tile of L), two per-tile partial stores of the same size, and the
+ *   task tables.  The task plan is built on first use and kept in `sym`.
+ * stiles_selinv_create: binds the factor f (which must outlive the handle) to
+ *   a caller-owned workspace (>= that size, 256-byte aligned) and uploads the
+ *   task tables (synchronizes the stream once).
+ * stiles_selinv_compute: computes Sigma from f's current factor (asynchronous;
+ *   ESTATE if f is not factorized or its factorization is known to have
+ *   failed).  Refactorizing f makes Sigma stale until the next compute.
+ * stiles_selinv_diag: d_diag[i] = (A^{-1})_ii, i in the original ordering
+ *   (N doubles, device; NaN if the factorization failed).
+ * stiles_selinv_extract: the selected entries in the layout of
+ *   stiles_factor_extract (nnz_L doubles, row-profile order of the permuted
+ *   envelope; zero outside the stored tiles).
+ * stiles_selinv_query: task count, algorithmic flops sum_j 2 eta_j (eta_j + 1)
+ *   over the envelope before adaptable ND, and executed tile-product flops
+ *   (each pointer may be NULL).
+ * stiles_selinv_set_timing / stiles_selinv_kernel_ms: a pair of HIP events
+ *   around each compute launch, as for the factor.
+ * Calls that share a handle must be ordered on one stream.
+ */
+typedef struct stiles_selinv stiles_selinv;
+stiles_status stiles_selinv_query(const stiles_symbolic* sym, int64_t* tasks, double* flops_alg, double* flops_exec);
+stiles_status stiles_selinv_workspace_size(const stiles_symbolic* sym, size_t* bytes);
+stiles_status stiles_selinv_create(stiles_factor* f, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                                   stiles_selinv** out);
+stiles_status stiles_selinv_compute(stiles_selinv* si, hipStream_t stream);
+stiles_status stiles_selinv_diag(stiles_selinv* si, double* d_diag, hipStream_t stream);
+stiles_status stiles_selinv_extract(stiles_selinv* si, double* d_out, hipStream_t stream);
+stiles_status stiles_selinv_set_timing(stiles_selinv* si, int32_t enable);
+stiles_status stiles_selinv_kernel_ms(stiles_selinv* si, float* ms);
+void stiles_selinv_destroy(stiles_selinv* si);
 
 #ifdef __cplusplus
 }

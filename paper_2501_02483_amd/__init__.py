@@ -21,7 +21,9 @@ __all__ = [
     "stiles_status_string", "stiles_last_error_arg", "factorize_batch", "stiles_factor_extract",
     "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
     "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_logdet",
-    "stiles_batch_destroy", "Batch",
+    "stiles_batch_destroy", "Batch", "SelInv", "stiles_selinv_query", "stiles_selinv_workspace_size",
+    "stiles_selinv_create", "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract",
+    "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_destroy",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -48,7 +50,9 @@ EXPORTED = [
     "stiles_factor_set_max_workgroups", "stiles_factor_release", "stiles_factor_extract",
     "stiles_factor_set_timing", "stiles_factor_kernel_ms", "stiles_factor_set_trace",
     "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_logdet",
-    "stiles_batch_destroy",
+    "stiles_batch_destroy", "stiles_selinv_query", "stiles_selinv_workspace_size", "stiles_selinv_create",
+    "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract", "stiles_selinv_set_timing",
+    "stiles_selinv_kernel_ms", "stiles_selinv_destroy",
 ]
 
 
@@ -118,6 +122,16 @@ def load_library(path=LIB_PATH):
         "stiles_batch_factorize": (_i32, [_vp, _vp, _vp]),
         "stiles_batch_logdet": (_i32, [_vp, _vp, _vp]),
         "stiles_batch_destroy": (None, [_vp]),
+        "stiles_selinv_query": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
+        "stiles_selinv_workspace_size": (_i32, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "stiles_selinv_create": (_i32, [_vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+        "stiles_selinv_compute": (_i32, [_vp, _vp]),
+        "stiles_selinv_diag": (_i32, [_vp, _vp, _vp]),
+        "stiles_selinv_extract": (_i32, [_vp, _vp, _vp]),
+        "stiles_selinv_set_timing": (_i32, [_vp, _i32]),
+        "stiles_selinv_kernel_ms": (_i32, [_vp, ctypes.POINTER(ctypes.c_float)]),
+        "stiles_selinv_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -203,7 +217,8 @@ def stiles_symbolic_perm(sym, N):
 
 EXPORT_KINDS = {"ftask": (0, np.int32), "fsucc": (1, np.int32), "fpairs": (2, np.int32), "stask": (3, np.int32),
                 "ssucc": (4, np.int32), "spairs": (5, np.int32), "trow_ptr": (6, np.int32), "tcol": (7, np.int32),
-                "row_base": (8, np.int64), "row_cnt": (9, np.int32), "npart": (10, np.int32)}
+                "row_base": (8, np.int64), "row_cnt": (9, np.int32), "npart": (10, np.int32),
+                "itask": (11, np.int32), "isucc": (12, np.int32), "ilist": (13, np.int32)}
 
 
 def stiles_symbolic_export(sym, kind):
@@ -292,6 +307,53 @@ def stiles_factor_kernel_ms(fac, which):
 def stiles_factor_set_trace(fac, d_factor_trace, d_solve_trace, stream=None):
     _check(load_library().stiles_factor_set_trace(fac, _ptr(d_factor_trace), _ptr(d_solve_trace), _stream(stream)),
            "stiles_factor_set_trace")
+
+
+def stiles_selinv_query(sym):
+    """(tasks, algorithmic flops, executed flops) of the selected inversion."""
+    n, fa, fe = _i64(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().stiles_selinv_query(sym, ctypes.byref(n), ctypes.byref(fa), ctypes.byref(fe)),
+           "stiles_selinv_query")
+    return n.value, fa.value, fe.value
+
+
+def stiles_selinv_workspace_size(sym):
+    b = ctypes.c_size_t()
+    _check(load_library().stiles_selinv_workspace_size(sym, ctypes.byref(b)), "stiles_selinv_workspace_size")
+    return b.value
+
+
+def stiles_selinv_create(fac, d_ws, ws_bytes, stream=None):
+    h = _vp()
+    _check(load_library().stiles_selinv_create(fac, _ptr(d_ws), ws_bytes, _stream(stream), ctypes.byref(h)),
+           "stiles_selinv_create")
+    return h
+
+
+def stiles_selinv_compute(si, stream=None):
+    _check(load_library().stiles_selinv_compute(si, _stream(stream)), "stiles_selinv_compute")
+
+
+def stiles_selinv_diag(si, d_diag, stream=None):
+    _check(load_library().stiles_selinv_diag(si, _ptr(d_diag), _stream(stream)), "stiles_selinv_diag")
+
+
+def stiles_selinv_extract(si, d_out, stream=None):
+    _check(load_library().stiles_selinv_extract(si, _ptr(d_out), _stream(stream)), "stiles_selinv_extract")
+
+
+def stiles_selinv_set_timing(si, enable):
+    _check(load_library().stiles_selinv_set_timing(si, 1 if enable else 0), "stiles_selinv_set_timing")
+
+
+def stiles_selinv_kernel_ms(si):
+    v = ctypes.c_float()
+    _check(load_library().stiles_selinv_kernel_ms(si, ctypes.byref(v)), "stiles_selinv_kernel_ms")
+    return v.value
+
+
+def stiles_selinv_destroy(si):
+    load_library().stiles_selinv_destroy(si)
 
 
 def stiles_status_string(st):
@@ -400,6 +462,52 @@ class Factor:
     def __del__(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.stiles_factor_release(self.handle)
+            self.handle = None
+
+
+class SelInv:
+    """Selected inversion bound to a resident factor: compute() fills Sigma =
+    A^{-1} on the factor's tile pattern; diag() and extract() read it out."""
+
+    def __init__(self, factor, stream=None):
+        import torch
+        self.factor = factor
+        self.bytes = stiles_selinv_workspace_size(factor.sym.handle)
+        self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=factor.workspace.device)
+        addr = (self.ws.data_ptr() + 255) // 256 * 256
+        h = _vp()
+        _check(load_library().stiles_selinv_create(factor.handle, ctypes.c_void_p(addr), self.bytes, _stream(stream),
+                                                   ctypes.byref(h)), "stiles_selinv_create")
+        self.handle = h
+
+    def compute(self, stream=None):
+        stiles_selinv_compute(self.handle, stream)
+        return self
+
+    def diag(self, out=None, stream=None):
+        """(A^{-1})_ii in the original ordering (float64 device tensor)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.factor.sym.info.N, dtype=torch.float64, device=self.ws.device)
+        stiles_selinv_diag(self.handle, out, stream)
+        return out
+
+    def extract(self, stream=None):
+        """Selected entries in the layout of Factor.extract()."""
+        import torch
+        out = torch.empty(self.factor.sym.info.nnz_L, dtype=torch.float64, device=self.ws.device)
+        stiles_selinv_extract(self.handle, out, stream)
+        return out
+
+    def set_timing(self, enable=True):
+        stiles_selinv_set_timing(self.handle, enable)
+
+    def kernel_ms(self):
+        return stiles_selinv_kernel_ms(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.stiles_selinv_destroy(self.handle)
             self.handle = None
 
 

@@ -1011,7 +1011,146 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   schedule(sb, s.stask, s.ssucc, nullptr, nullptr, false);
 }
 
+// ---- selected inversion: Sigma = A^{-1} on the tile pattern of L.
+// Block form of the Takahashi recursion over tile columns k = ntr-1 .. 0.
+// With S(k) the tile rows below k in column k and p = min S(k):
+//   Sig_(r,k) = -(sum_{s in S(k)} Sig~_(r,s) L_(s,k)) Linv_k       (r in S(k))
+//   Sig_kk    = Linv_k^T (Linv_k - sum_{r in S(k)} L_(r,k)^T Sig_(r,k))
+// where Sig~_(r,s) is the stored tile (r,s), the full diagonal tile (r = s)
+// or the transpose of the stored (s,r).  The tile pattern is closed under
+// elimination (it is the filled pattern), so every Sig~ used is stored and
+// lies in a later column.  Only column p's results are fresh when column k
+// starts: for r != p the terms with s != p run ahead (SWE tasks) and the term
+// with s = p waits (SW); for r = p every term is fresh, so the tasks that
+// produce Sig_(s,p) push their products Sig_(s,p)^T L_(s,k) into a per-tile
+// slot (k is a child of p in the tile elimination tree) and SW(p,k) only sums
+// them.  Each SW also leaves D_(r,k) = L_(r,k)^T Sig_(r,k) in a per-tile slot
+// for SDIAG(k), which sums them in ascending r.
+void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
+  const int32_t ntr = s.ntr, T = s.T;
+  const int32_t chunk = s.opts.chunk > 0 ? s.opts.chunk : (T == 64 ? 12 : 16);
+  const float t3 = (float)std::pow((double)T / 64.0, 3.0);
+  const double T3 = (double)T * T * T;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> ctiles(ntr);   // (row, tile), ascending row
+  for (int32_t m = 0; m < ntr; m++)
+    for (int32_t t = s.trow_ptr[m]; t < s.trow_ptr[m + 1]; t++) ctiles[s.tcol[t]].push_back({m, t});
+  std::vector<std::vector<int32_t>> children(ntr);
+  for (int32_t k = 0; k < ntr; k++)
+    if (ctiles[k].size() > 1) children[ctiles[k][1].first].push_back(k);
+  auto diag_tile = [&](int32_t m) { return s.trow_ptr[m + 1] - 1; };
+  auto lookup = [&](int32_t r, int32_t c) {
+    const int32_t t = tile_lookup(s, r, c);
+    if (t < 0) { fprintf(stderr, "stiles: selected inversion needs a tile outside the pattern\n"); abort(); }
+    return t;
+  };
+  TaskBuilder tb;
+  std::vector<int32_t> sw(s.ntiles, -1), sd(ntr, -1);
+  std::vector<int32_t>& lst = P.list;
+  lst.clear();
+  double fexec = 0.0;
+  // Sig~_(r,c): (list code, producing task)
+  auto sig = [&](int32_t r, int32_t c) -> std::pair<int32_t, int32_t> {
+    if (r == c) return {diag_tile(r), sd[r]};
+    const int32_t t = lookup(std::max(r, c), std::min(r, c));
+    return {t | (r < c ? SIG_TRANS : 0), sw[t]};
+  };
+  for (int32_t k = ntr - 1; k >= 0; k--) {
+    const auto& col = ctiles[k];   // col[0] is the diagonal tile
+    const size_t ns = col.size() - 1;
+    const int32_t p = ns ? col[1].first : -1;
+    for (size_t a = 1; a <= ns; a++) {
+      const int32_t r = col[a].first, t = col[a].second;
+      std::vector<int32_t> push;   // tiles (r,c) of the children c of k
+      for (int32_t c : children[k]) {
+        const int32_t u = tile_lookup(s, r, c);
+        if (u >= 0) push.push_back(u);
+      }
+      int last = -1;
+      std::vector<int32_t> prod, sums, deps;
+      if (r != p) {
+        std::vector<std::pair<int32_t, int32_t>> pr;
+        std::vector<int32_t> pdep;
+        for (size_t b = 2; b <= ns; b++) {
+          const auto x = sig(r, col[b].first);
+          pr.push_back({x.first, col[b].second});
+          pdep.push_back(x.second);
+        }
+        for (size_t lo = 0; lo < pr.size(); lo += chunk) {
+          const size_t hi = std::min(pr.size(), lo + (size_t)chunk);
+          const int32_t off = (int32_t)lst.size();
+          for (size_t q = lo; q < hi; q++) { lst.push_back(pr[q].first); lst.push_back(pr[q].second); }
+          const int tk = tb.add(TK_SWE | (last >= 0 ? TF_ACC : 0), t, off, (int32_t)(hi - lo), 0,
+                                0.5f + 1.8f * t3 * (float)(hi - lo));
+          fexec += 2.0 * T3 * (double)(hi - lo);
+          for (size_t q = lo; q < hi; q++) tb.dep(tk, pdep[q]);
+          tb.dep(tk, last);
+          last = tk;
+        }
+        const auto x = sig(r, p);
+        prod = {x.first, col[1].second};
+        deps.push_back(x.second);
+      } else {
+        const auto x = sig(p, p);
+        prod = {x.first, col[1].second};
+        deps.push_back(x.second);
+        for (size_t b = 2; b <= ns; b++) {
+          sums.push_back(col[b].second);                      // slot of tile (s,k)
+          deps.push_back(sw[lookup(col[b].first, p)]);       // pushed by SW(s,p)
+        }
+      }
+      const int32_t off = (int32_t)lst.size();
+      const int32_t nprod = (int32_t)prod.size() / 2;
+      lst.push_back(nprod);
+      lst.push_back((int32_t)sums.size());
+      lst.push_back((int32_t)push.size());
+      lst.insert(lst.end(), prod.begin(), prod.end());
+      lst.insert(lst.end(), sums.begin(), sums.end());
+      lst.insert(lst.end(), push.begin(), push.end());
+      const int tk = tb.add(TK_SW | (last >= 0 ? TF_ACC : 0), t, k, off, 0,
+                            0.5f + 1.8f * t3 * (float)(nprod + 2 + push.size()) + 0.1f * (float)sums.size());
+      fexec += 2.0 * T3 * (double)(nprod + 2 + push.size());
+      tb.dep(tk, last);
+      for (int d : deps) tb.dep(tk, d);
+      sw[t] = tk;
+    }
+    const int32_t off = (int32_t)lst.size();
+    lst.push_back((int32_t)ns);
+    for (size_t a = 1; a <= ns; a++) lst.push_back(col[a].second);
+    const int tk = tb.add(TK_SDIAG, diag_tile(k), k, off, 0, 0.5f + 1.8f * t3 + 0.1f * (float)ns);
+    fexec += 2.0 * T3;
+    for (size_t a = 1; a <= ns; a++) tb.dep(tk, sw[col[a].second]);
+    sd[k] = tk;
+  }
+  P.flops_exec = fexec;
+  schedule(tb, P.task, P.succ, nullptr, nullptr, false);
+  // algorithmic work of the element recursion, over the envelope before
+  // adaptable ND: column j costs eta_j dot products of length eta_j plus one
+  const std::vector<int64_t>& f = s.f_pre.empty() ? s.f : s.f_pre;
+  const int64_t N = (int64_t)f.size();
+  std::vector<int64_t> d(N + 1, 0);
+  for (int64_t i = 0; i < N; i++) { d[f[i]] += 1; d[i] -= 1; }
+  double F = 0.0;
+  int64_t run = 0;
+  for (int64_t j = 0; j < N; j++) {
+    run += d[j];
+    F += 2.0 * (double)run * ((double)run + 1.0);
+  }
+  P.flops_alg = F;
+}
+
 }  // namespace
+
+namespace stiles {
+const SelinvPlan& selinv_plan(const stiles_symbolic& s) {
+  std::lock_guard<std::mutex> g(s.selinv_mu);
+  if (!s.selinv) {
+    std::unique_ptr<SelinvPlan> p(new SelinvPlan());
+    build_selinv(s, *p);
+    s.selinv = std::move(p);
+  }
+  return *s.selinv;
+}
+}  // namespace stiles
 
 extern "C" stiles_status stiles_symbolic_query(const stiles_symbolic* s, stiles_symbolic_info* info) {
   g_err_arg = 0;
@@ -1065,6 +1204,9 @@ extern "C" stiles_status stiles_symbolic_export(const stiles_symbolic* s, int32_
     case 8: src = s->row_base.data(); n = (int64_t)s->row_base.size(); esz = 8; break;
     case 9: src = s->row_cnt.data(); n = (int64_t)s->row_cnt.size(); break;
     case 10: src = &npart; n = 1; break;
+    case 11: src = selinv_plan(*s).task.data(); n = (int64_t)selinv_plan(*s).task.size(); break;
+    case 12: src = selinv_plan(*s).succ.data(); n = (int64_t)selinv_plan(*s).succ.size(); break;
+    case 13: src = selinv_plan(*s).list.data(); n = (int64_t)selinv_plan(*s).list.size(); break;
     default: g_err_arg = 2; return STILES_EINVAL;
   }
   if (!out) { *count = n; return STILES_OK; }

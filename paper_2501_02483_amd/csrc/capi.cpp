@@ -331,7 +331,7 @@ extern "C" stiles_status stiles_factorize(stiles_factor* f, const double* d_valu
   if (r != STILES_OK) return r;
   const int32_t nt = f->mf.ntasks;
   if (f->timing) (void)hipEventRecord(f->ev[0], st);
-  hipError_t e = launch_exec(f->sym->T, at<ExecMat>(f, f->L.mat_f), nullptr, nt, at<ExecCtrl>(f, f->L.ctrl_f), 0,
+  hipError_t e = launch_exec(f->sym->T, EXEC_FACTOR, at<ExecMat>(f, f->L.mat_f), nullptr, nt, at<ExecCtrl>(f, f->L.ctrl_f), 0,
                              nwg_for(f, nt), st);
   if (f->timing) (void)hipEventRecord(f->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
@@ -362,7 +362,7 @@ static stiles_status solve_sweep(stiles_factor* f, const double* d_src, int64_t 
                              at<int32_t>(f, L.row_cnt), s.ntr, at<double>(f, L.vy), st);
   if (e == hipSuccess && f->timing) (void)hipEventRecord(f->ev[2], st);
   if (e == hipSuccess)
-    e = launch_exec(s.T, at<ExecMat>(f, L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, L.ctrl_s), nrhs,
+    e = launch_exec(s.T, EXEC_SOLVE, at<ExecMat>(f, L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, L.ctrl_s), nrhs,
                     nwg_for(f, f->ms.ntasks), st);
   if (e == hipSuccess && f->timing) (void)hipEventRecord(f->ev[3], st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
@@ -374,7 +374,7 @@ static stiles_status solve_tiles_from_tiles(stiles_factor* f, const double* d_ti
   const size_t bytes = (size_t)s.ntr * s.T * nrhs * 8;
   if (hipMemcpyAsync(at<double>(f, f->L.vy), d_tile_src, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return STILES_EDEVICE;
-  hipError_t e = launch_exec(s.T, at<ExecMat>(f, f->L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, f->L.ctrl_s),
+  hipError_t e = launch_exec(s.T, EXEC_SOLVE, at<ExecMat>(f, f->L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, f->L.ctrl_s),
                              nrhs, nwg_for(f, f->ms.ntasks), st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
@@ -678,7 +678,7 @@ extern "C" stiles_status stiles_batch_factorize(stiles_batch* b, const double* c
   const int cap = device_wg_capacity(b->T);
   stiles_factor* f0 = b->factors[0];
   if (f0->timing) (void)hipEventRecord(f0->ev[0], st);
-  hipError_t e = launch_exec(b->T, reinterpret_cast<const ExecMat*>(b->ws + b->B.mats),
+  hipError_t e = launch_exec(b->T, EXEC_FACTOR, reinterpret_cast<const ExecMat*>(b->ws + b->B.mats),
                              reinterpret_cast<const int32_t*>(b->ws + b->B.order), b->total,
                              reinterpret_cast<ExecCtrl*>(b->ws + b->B.ctrl), 0, std::min<int>(cap, b->total), st);
   if (f0->timing) (void)hipEventRecord(f0->ev[1], st);
@@ -768,3 +768,177 @@ extern "C" stiles_status stiles_factor_extract(stiles_factor* f, double* d_L, hi
 }
 
 extern "C" void stiles_factor_release(stiles_factor* f) { delete f; }
+
+// ------------------------------------------------------- selected inversion
+
+namespace {
+
+// selected-inversion workspace: control block, executor descriptor, task
+// tables and progress counters, then Sigma and the two per-tile partial stores
+struct SelinvLayout {
+  size_t ctrl, mat, task, succ, rem, list, sigma, dpart, qpart, total;
+};
+
+SelinvLayout selinv_layout(const stiles_symbolic& s, const SelinvPlan& P) {
+  SelinvLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = up(o + std::max<size_t>(bytes, 1)); return r; };
+  const size_t tile_bytes = (size_t)s.ntiles * s.T * s.T * 8;
+  L.ctrl = take(sizeof(ExecCtrl));
+  L.mat = take(sizeof(ExecMat));
+  L.task = take(P.task.size() * 4);
+  L.succ = take(P.succ.size() * 4);
+  L.rem = take(P.task.size() / TASK_WORDS * 4);
+  L.list = take(P.list.size() * 4);
+  L.sigma = take(tile_bytes);
+  L.dpart = take(tile_bytes);
+  L.qpart = take(tile_bytes);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct stiles_selinv {
+  stiles_factor* f = nullptr;
+  char* ws = nullptr;
+  SelinvLayout L{};
+  int32_t ntasks = 0;
+  bool done = false;
+  bool timing = false;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~stiles_selinv() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+extern "C" stiles_status stiles_selinv_query(const stiles_symbolic* s, int64_t* tasks, double* flops_alg,
+                                             double* flops_exec) {
+  set_error_arg(0);
+  if (!s) { set_error_arg(1); return STILES_EINVAL; }
+  const SelinvPlan& P = selinv_plan(*s);
+  if (tasks) *tasks = (int64_t)(P.task.size() / TASK_WORDS);
+  if (flops_alg) *flops_alg = P.flops_alg;
+  if (flops_exec) *flops_exec = P.flops_exec;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_selinv_workspace_size(const stiles_symbolic* s, size_t* bytes) {
+  set_error_arg(0);
+  if (!s) { set_error_arg(1); return STILES_EINVAL; }
+  if (!bytes) { set_error_arg(2); return STILES_EINVAL; }
+  *bytes = selinv_layout(*s, selinv_plan(*s)).total;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_selinv_create(stiles_factor* f, void* d_ws, size_t ws_bytes, hipStream_t st,
+                                              stiles_selinv** out) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % ALIGN) != 0) { set_error_arg(2); return STILES_EINVAL; }
+  if (!out) { set_error_arg(5); return STILES_EINVAL; }
+  const stiles_symbolic& s = *f->sym;
+  const SelinvPlan& P = selinv_plan(s);
+  const SelinvLayout L = selinv_layout(s, P);
+  if (ws_bytes < L.total) { set_error_arg(3); return STILES_ENOMEM; }
+  stiles_selinv* si = new stiles_selinv();
+  si->f = f;
+  si->ws = static_cast<char*>(d_ws);
+  si->L = L;
+  si->ntasks = (int32_t)(P.task.size() / TASK_WORDS);
+  ExecMat m = f->mf;
+  m.tasks = reinterpret_cast<const int32_t*>(si->ws + L.task);
+  m.succ = reinterpret_cast<const int32_t*>(si->ws + L.succ);
+  m.remaining = reinterpret_cast<int32_t*>(si->ws + L.rem);
+  m.pairs = reinterpret_cast<const int32_t*>(si->ws + L.list);
+  m.sigma = reinterpret_cast<double*>(si->ws + L.sigma);
+  m.dpart = reinterpret_cast<double*>(si->ws + L.dpart);
+  m.qpart = reinterpret_cast<double*>(si->ws + L.qpart);
+  m.shadow = nullptr;
+  m.trace = nullptr;
+  m.ntasks = si->ntasks;
+  m.mixed = 0;
+  std::vector<int32_t> rem(si->ntasks);
+  for (int32_t t = 0; t < si->ntasks; t++) rem[t] = P.task[(size_t)t * TASK_WORDS + 7];
+  ExecCtrl ctrl{};
+  hipError_t e = hipSuccess;
+  auto U = [&](size_t off, const void* src, size_t b) {
+    if (e == hipSuccess && b) e = hipMemcpyAsync(si->ws + off, src, b, hipMemcpyHostToDevice, st);
+  };
+  U(L.ctrl, &ctrl, sizeof(ctrl));
+  U(L.mat, &m, sizeof(m));
+  U(L.task, P.task.data(), P.task.size() * 4);
+  U(L.succ, P.succ.data(), P.succ.size() * 4);
+  U(L.rem, rem.data(), rem.size() * 4);
+  U(L.list, P.list.data(), P.list.size() * 4);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors above die here
+  if (e != hipSuccess) { delete si; return STILES_EDEVICE; }
+  *out = si;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_selinv_compute(stiles_selinv* si, hipStream_t st) {
+  set_error_arg(0);
+  if (!si) { set_error_arg(1); return STILES_EINVAL; }
+  stiles_factor* f = si->f;
+  if (f->state == -1 || f->state == 2) return STILES_ESTATE;
+  if (si->timing) (void)hipEventRecord(si->ev[0], st);
+  hipError_t e = launch_exec(f->sym->T, EXEC_SELINV, reinterpret_cast<const ExecMat*>(si->ws + si->L.mat), nullptr,
+                             si->ntasks, reinterpret_cast<ExecCtrl*>(si->ws + si->L.ctrl), 0,
+                             nwg_for(f, si->ntasks), st);
+  if (si->timing) (void)hipEventRecord(si->ev[1], st);
+  if (e != hipSuccess) return STILES_EDEVICE;
+  si->done = true;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_selinv_diag(stiles_selinv* si, double* d_diag, hipStream_t st) {
+  set_error_arg(0);
+  if (!si) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_diag) { set_error_arg(2); return STILES_EINVAL; }
+  if (!si->done) return STILES_ESTATE;
+  stiles_factor* f = si->f;
+  const stiles_symbolic& s = *f->sym;
+  const Layout& L = f->L;
+  hipError_t e = launch_selinv_diag(s.T, reinterpret_cast<const double*>(si->ws + si->L.sigma),
+                                    at<int32_t>(f, L.trow_ptr), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
+                                    at<int64_t>(f, L.perm), s.ntr, at<unsigned long long>(f, L.info), d_diag, st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+extern "C" stiles_status stiles_selinv_extract(stiles_selinv* si, double* d_out, hipStream_t st) {
+  set_error_arg(0);
+  if (!si) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_out) { set_error_arg(2); return STILES_EINVAL; }
+  if (!si->done) return STILES_ESTATE;
+  stiles_factor* f = si->f;
+  const stiles_symbolic& s = *f->sym;
+  const Layout& L = f->L;
+  hipError_t e = launch_extract(s.T, reinterpret_cast<const double*>(si->ws + si->L.sigma), at<int64_t>(f, L.in_rp),
+                                at<int64_t>(f, L.fprof), at<int32_t>(f, L.trow), at<int32_t>(f, L.tcol),
+                                at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt), s.ntiles, s.nnzL, d_out, st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+extern "C" stiles_status stiles_selinv_set_timing(stiles_selinv* si, int32_t enable) {
+  set_error_arg(0);
+  if (!si) { set_error_arg(1); return STILES_EINVAL; }
+  if (enable)
+    for (auto& e : si->ev)
+      if (!e && hipEventCreate(&e) != hipSuccess) return STILES_EDEVICE;
+  si->timing = enable != 0;
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_selinv_kernel_ms(stiles_selinv* si, float* ms) {
+  set_error_arg(0);
+  if (!si) { set_error_arg(1); return STILES_EINVAL; }
+  if (!ms) { set_error_arg(2); return STILES_EINVAL; }
+  if (!si->timing || !si->done) return STILES_ESTATE;
+  if (hipEventSynchronize(si->ev[1]) != hipSuccess) return STILES_EDEVICE;
+  if (hipEventElapsedTime(ms, si->ev[0], si->ev[1]) != hipSuccess) return STILES_ESTATE;
+  return STILES_OK;
+}
+
+extern "C" void stiles_selinv_destroy(stiles_selinv* si) { delete si; }

@@ -891,17 +891,246 @@ __device__ __attribute__((noinline)) void task_fsum(const ExecMat& M, const int3
   }
 }
 
+// ------------------------------------------------------- selected inversion
+// Tile products of the form C = op(X) op(Y)^T, op = identity or transpose,
+// on tiles staged in LDS with leading dimension LP = T + 2: reading a
+// column-major tile directly or transposed is then free of bank conflicts
+// within each group of 16 lanes, and the 16-byte staging stores stay aligned.
+// Output layout as in mma_f64 (each wave owns one (T/2) x (T/2) quarter).
+
+template <int T>
+struct PadStage {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  static constexpr int LP = T + 2;
+  static constexpr int NV = T * T / NT / 2;
+  d2 r[NV];
+  __device__ __forceinline__ void load(const double* __restrict__ g) {
+    const d2* v = reinterpret_cast<const d2*>(g);
+#pragma unroll
+    for (int q = 0; q < NV; q++) r[q] = v[threadIdx.x + q * NT];
+  }
+  __device__ __forceinline__ void store(double* l) const {
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+      const int e = 2 * ((int)threadIdx.x + q * NT);
+      *reinterpret_cast<d2*>(l + (e % T) + (e / T) * LP) = r[q];
+    }
+  }
+};
+
+// acc += op(X) op(Y)^T: Xe(row, kk) = TX ? X[kk + row LP] : X[row + kk LP],
+// the same for Y (rows of C from X, columns from Y)
+template <int T, bool TX, bool TY>
+__device__ __forceinline__ void mma_lp(v4d (&acc)[T / 32][T / 32], const double* X, const double* Y, int r0, int c0,
+                                       int lane) {
+  constexpr int NB = T / 32, LP = T + 2;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < T; k += 4) {
+    const int kk = k + lk;
+    double a[NB], b[NB];
+#pragma unroll
+    for (int q = 0; q < NB; q++) {
+      const int yi = c0 + 16 * q + li, xi = r0 + 16 * q + li;
+      a[q] = TY ? Y[kk + yi * LP] : Y[yi + kk * LP];
+      b[q] = TX ? X[kk + xi * LP] : X[xi + kk * LP];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+#pragma unroll
+      for (int j = 0; j < NB; j++) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void zero_acc(v4d (&acc)[T / 32][T / 32]) {
+#pragma unroll
+  for (int i = 0; i < T / 32; i++)
+#pragma unroll
+    for (int j = 0; j < T / 32; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+// out (column-major, leading dimension ld) <- s * acc, element by element
+template <int T>
+__device__ __forceinline__ void put_acc(const v4d (&acc)[T / 32][T / 32], double* out, int ld, double sc, int r0,
+                                        int c0, int lane) {
+#pragma unroll
+  for (int i = 0; i < T / 32; i++)
+#pragma unroll
+    for (int j = 0; j < T / 32; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+        out[row + col * ld] = sc * acc[i][j][r];
+      }
+}
+
+// acc += tile g (column-major T x T, global), element by element
+template <int T>
+__device__ __forceinline__ void add_tile(v4d (&acc)[T / 32][T / 32], const double* __restrict__ g, int r0, int c0,
+                                         int lane) {
+#pragma unroll
+  for (int i = 0; i < T / 32; i++)
+#pragma unroll
+    for (int j = 0; j < T / 32; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+        acc[i][j][r] += g[row + col * T];
+      }
+}
+
+// acc += sum over pairs of op(Sig_x) L_y^T... as C = Sig~ L: the pairs are
+// (Sigma tile code, L tile); LX, LY: padded LDS tiles
+template <int T>
+__device__ __forceinline__ void sig_products(v4d (&acc)[T / 32][T / 32], const ExecMat& M, const int32_t* pr, int np,
+                                             double* LX, double* LY, int r0, int c0, int lane) {
+  constexpr int TT = T * T;
+  if (np <= 0) return;
+  PadStage<T> sx, sy;
+  sx.load(M.sigma + (int64_t)(__builtin_amdgcn_readfirstlane(pr[0]) & ~SIG_TRANS) * TT);
+  sy.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(pr[1]) * TT);
+  for (int p = 0; p < np; p++) {
+    const int xc = __builtin_amdgcn_readfirstlane(pr[2 * p]);
+    __syncthreads();
+    sx.store(LX);
+    sy.store(LY);
+    __syncthreads();
+    if (p + 1 < np) {
+      sx.load(M.sigma + (int64_t)(__builtin_amdgcn_readfirstlane(pr[2 * p + 2]) & ~SIG_TRANS) * TT);
+      sy.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(pr[2 * p + 3]) * TT);
+    }
+    // C = Sig~ L: op(X) = Sig or Sig^T, op(Y)^T = L
+    if (xc & SIG_TRANS) mma_lp<T, true, true>(acc, LX, LY, r0, c0, lane);
+    else mma_lp<T, false, true>(acc, LX, LY, r0, c0, lane);
+  }
+}
+
+// SWE: W_t (+)= sum over pairs of Sig~ L, kept in the Sigma tile of t until
+// its SW task finishes it
+template <int T>
+__device__ __attribute__((noinline)) void task_swe(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
+  constexpr int TT = T * T, W = T / 2, NB = T / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
+  double* out = M.sigma + (int64_t)w[1] * TT;
+  v4d acc[NB][NB];
+  zero_acc<T>(acc);
+  if (w[0] & TF_ACC) add_tile<T>(acc, out, r0, c0, lane);
+  sig_products<T>(acc, M, M.pairs + w[2], __builtin_amdgcn_readfirstlane(w[3]), LX, LY, r0, c0, lane);
+  put_acc<T>(acc, out, T, 1.0, r0, c0, lane);
+}
+
+// SW: Sig_t = -(W + products + pushed partials) Linv_k, then
+// D_t = L_t^T Sig_t and, for every listed tile u = (r,c), Q_u = Sig_t^T L_u
+template <int T>
+__device__ __attribute__((noinline)) void task_sw(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
+  constexpr int TT = T * T, W = T / 2, NB = T / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
+  const int32_t* lst = M.pairs + __builtin_amdgcn_readfirstlane(w[3]);
+  const int nprod = __builtin_amdgcn_readfirstlane(lst[0]);
+  const int nsum = __builtin_amdgcn_readfirstlane(lst[1]);
+  const int npush = __builtin_amdgcn_readfirstlane(lst[2]);
+  const int32_t* prod = lst + 3;
+  const int32_t* sums = prod + 2 * nprod;
+  const int32_t* push = sums + nsum;
+  const int64_t t = __builtin_amdgcn_readfirstlane(w[1]);
+  const int64_t k = __builtin_amdgcn_readfirstlane(w[2]);
+  double* sig = M.sigma + t * TT;
+  v4d acc[NB][NB];
+  zero_acc<T>(acc);
+  if (w[0] & TF_ACC) add_tile<T>(acc, sig, r0, c0, lane);
+  for (int q = 0; q < nsum; q++)
+    add_tile<T>(acc, M.qpart + (int64_t)__builtin_amdgcn_readfirstlane(sums[q]) * TT, r0, c0, lane);
+  sig_products<T>(acc, M, prod, nprod, LX, LY, r0, c0, lane);
+  // Sig_t = -W Linv_k  (op(X) = W, op(Y)^T = Linv_k)
+  PadStage<T> st;
+  st.load(M.linv + k * TT);
+  __syncthreads();
+  put_acc<T>(acc, LX, T + 2, 1.0, r0, c0, lane);
+  st.store(LY);
+  __syncthreads();
+  st.load(M.tiles + t * TT);
+  zero_acc<T>(acc);
+  mma_lp<T, false, true>(acc, LX, LY, r0, c0, lane);
+  put_acc<T>(acc, sig, T, -1.0, r0, c0, lane);
+  __syncthreads();
+  put_acc<T>(acc, LX, T + 2, -1.0, r0, c0, lane);   // LX = Sig_t
+  st.store(LY);                                      // LY = L_t
+  __syncthreads();
+  if (npush > 0) st.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(push[0]) * TT);
+  // D_t = L_t^T Sig_t  (op(X) = L_t^T, op(Y)^T = Sig_t)
+  zero_acc<T>(acc);
+  mma_lp<T, true, true>(acc, LY, LX, r0, c0, lane);
+  put_acc<T>(acc, M.dpart + t * TT, T, 1.0, r0, c0, lane);
+  for (int q = 0; q < npush; q++) {
+    const int64_t u = __builtin_amdgcn_readfirstlane(push[q]);
+    __syncthreads();
+    st.store(LY);                                    // LY = L_u
+    __syncthreads();
+    if (q + 1 < npush) st.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(push[q + 1]) * TT);
+    // Q_u = Sig_t^T L_u  (op(X) = Sig_t^T, op(Y)^T = L_u)
+    zero_acc<T>(acc);
+    mma_lp<T, true, true>(acc, LX, LY, r0, c0, lane);
+    put_acc<T>(acc, M.qpart + u * TT, T, 1.0, r0, c0, lane);
+  }
+}
+
+// SDIAG: Sig_kk = Linv_k^T (Linv_k - sum_r D_(r,k)), the D in list order;
+// the lower triangle is kept and mirrored, so the stored tile is symmetric
+template <int T>
+__device__ __attribute__((noinline)) void task_sdiag(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
+  constexpr int TT = T * T, W = T / 2, NB = T / 32;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
+  const int32_t* lst = M.pairs + __builtin_amdgcn_readfirstlane(w[3]);
+  const int nd = __builtin_amdgcn_readfirstlane(lst[0]);
+  const int64_t k = __builtin_amdgcn_readfirstlane(w[2]);
+  PadStage<T> li, z;
+  li.load(M.linv + k * TT);
+#pragma unroll
+  for (int v = 0; v < PadStage<T>::NV; v++) z.r[v] = li.r[v];
+  for (int q = 0; q < nd; q++) {
+    const d2* dp = reinterpret_cast<const d2*>(M.dpart + (int64_t)__builtin_amdgcn_readfirstlane(lst[1 + q]) * TT);
+#pragma unroll
+    for (int v = 0; v < PadStage<T>::NV; v++) z.r[v] -= dp[threadIdx.x + v * NT];
+  }
+  li.store(LX);
+  z.store(LY);
+  __syncthreads();
+  v4d acc[NB][NB];
+  zero_acc<T>(acc);
+  // op(X) = Linv_k^T, op(Y)^T = Z
+  mma_lp<T, true, true>(acc, LX, LY, r0, c0, lane);
+  double* out = M.sigma + (int64_t)__builtin_amdgcn_readfirstlane(w[1]) * TT;
+#pragma unroll
+  for (int i = 0; i < NB; i++)
+#pragma unroll
+    for (int j = 0; j < NB; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+        if (row >= col) {
+          out[row + col * T] = acc[i][j][r];
+          out[col + row * T] = acc[i][j][r];
+        }
+      }
+}
+
 // ---------------------------------------------------------------- executor
 
-// SOLVE selects the task set: factorization tasks (UPD, PART, TREE, POTRF,
-// TRSM) or triangular-solve tasks; the two are separate kernels so that each
-// carries only its own code.
-template <int T, bool SOLVE>
+// KIND selects the task set: factorization tasks (UPD, PART, TREE, POTRF,
+// TRSM), triangular-solve tasks, or selected-inversion tasks; they are
+// separate kernels so that each carries only its own code.
+template <int T, int KIND>
 __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__ mats, const int32_t* __restrict__ order,
                                                   int32_t total, ExecCtrl* ctrl, int nrhs) {
-  __shared__ __attribute__((aligned(16))) double S[T * (T + 1)];
-  __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : T * T];
-  __shared__ double rinv[SOLVE ? 1 : T];
+  constexpr bool SOLVE = KIND == EXEC_SOLVE, SELINV = KIND == EXEC_SELINV;
+  __shared__ __attribute__((aligned(16))) double S[SELINV ? T * (T + 2) : T * (T + 1)];
+  __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : SELINV ? T * (T + 2) : T * T];
+  __shared__ double rinv[KIND == EXEC_FACTOR ? T : 1];
   __shared__ __attribute__((aligned(16))) double LI[SOLVE ? T * (T + 1) : 1];
   __shared__ int32_t s_ticket;
   // Control flow outside the task bodies is kept uniform across the
@@ -939,9 +1168,15 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     // tasks on the pivot chain (diagonal factorization, panel solve, diagonal
     // solve steps) raise their waves' issue priority over the co-resident
     // update work of other workgroups on the same SIMDs
-    const bool chain = SOLVE ? (type == TK_FDIAG || type == TK_BDIAG) : (type == TK_POTRF || type == TK_TRSM);
+    const bool chain = SOLVE    ? (type == TK_FDIAG || type == TK_BDIAG)
+                       : SELINV ? (type == TK_SW || type == TK_SDIAG)
+                                : (type == TK_POTRF || type == TK_TRSM);
     if (chain) __builtin_amdgcn_s_setprio(3);
-    if constexpr (SOLVE) {
+    if constexpr (SELINV) {
+      if (type == TK_SWE) task_swe<T>(M, w, S, Xi);
+      else if (type == TK_SW) task_sw<T>(M, w, S, Xi);
+      else task_sdiag<T>(M, w, S, Xi);
+    } else if constexpr (SOLVE) {
       if (type == TK_FSUM) task_fsum<T>(M, w, nrhs);
       else task_solve<T>(M, w, nrhs, S, Xi, LI);
     } else {
@@ -985,22 +1220,48 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
   }
 }
 
-hipError_t launch_exec(int T, const ExecMat* d_mats, const int32_t* d_order, int32_t total, ExecCtrl* d_ctrl, int nrhs,
-                       int nwg, hipStream_t st) {
+hipError_t launch_exec(int T, int kind, const ExecMat* d_mats, const int32_t* d_order, int32_t total,
+                       ExecCtrl* d_ctrl, int nrhs, int nwg, hipStream_t st) {
   if (total <= 0) return hipSuccess;
   if (nwg > total) nwg = total;
-  const bool solve = nrhs > 0;
+#define STILES_EXEC(TT, KK) \
+  hipLaunchKernelGGL((exec_kernel<TT, KK>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs)
   if (T == 64) {
-    if (solve)
-      hipLaunchKernelGGL((exec_kernel<64, true>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
-    else
-      hipLaunchKernelGGL((exec_kernel<64, false>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
+    if (kind == EXEC_SOLVE) STILES_EXEC(64, EXEC_SOLVE);
+    else if (kind == EXEC_SELINV) STILES_EXEC(64, EXEC_SELINV);
+    else STILES_EXEC(64, EXEC_FACTOR);
   } else {
-    if (solve)
-      hipLaunchKernelGGL((exec_kernel<32, true>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
-    else
-      hipLaunchKernelGGL((exec_kernel<32, false>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs);
+    if (kind == EXEC_SOLVE) STILES_EXEC(32, EXEC_SOLVE);
+    else if (kind == EXEC_SELINV) STILES_EXEC(32, EXEC_SELINV);
+    else STILES_EXEC(32, EXEC_FACTOR);
   }
+#undef STILES_EXEC
+  return hipGetLastError();
+}
+
+// diagonal of Sigma (selected inversion) in the original ordering; NaN when
+// the factorization failed.  One workgroup per tile row, one thread per row.
+template <int T>
+__global__ void selinv_diag_kernel(const double* __restrict__ sigma, const int32_t* __restrict__ trow_ptr,
+                                   const int64_t* __restrict__ row_base, const int32_t* __restrict__ row_cnt,
+                                   const int64_t* __restrict__ perm, int32_t ntr, const unsigned long long* info,
+                                   double* __restrict__ out) {
+  const int m = blockIdx.x, i = threadIdx.x;
+  if (m >= ntr || i >= row_cnt[m]) return;
+  const double v = sigma[(int64_t)(trow_ptr[m + 1] - 1) * T * T + i + i * T];
+  out[perm[row_base[m] + i]] = *info != ~0ull ? __builtin_nan("") : v;
+}
+
+hipError_t launch_selinv_diag(int T, const double* sigma, const int32_t* trow_ptr, const int64_t* row_base,
+                              const int32_t* row_cnt, const int64_t* perm, int32_t ntr,
+                              const unsigned long long* info, double* out, hipStream_t st) {
+  if (ntr <= 0) return hipSuccess;
+  if (T == 64)
+    hipLaunchKernelGGL((selinv_diag_kernel<64>), dim3(ntr), dim3(64), 0, st, sigma, trow_ptr, row_base, row_cnt, perm,
+                       ntr, info, out);
+  else
+    hipLaunchKernelGGL((selinv_diag_kernel<32>), dim3(ntr), dim3(32), 0, st, sigma, trow_ptr, row_base, row_cnt, perm,
+                       ntr, info, out);
   return hipGetLastError();
 }
 

@@ -7,12 +7,18 @@
 
 namespace stiles {
 
-// Persistent DAG executor: `total` tickets; nrhs == 0 runs factorization
-// tasks, nrhs >= 1 triangular-solve tasks.  order == nullptr means one matrix
-// (mats[0]) with tasks in their own order, else order[2t], order[2t+1] =
-// (matrix index, task id).
-hipError_t launch_exec(int T, const ExecMat* d_mats, const int32_t* d_order, int32_t total, ExecCtrl* d_ctrl,
-                       int nrhs, int nwg, hipStream_t st);
+// Persistent DAG executor: `total` tickets of factorization, triangular-solve
+// (nrhs >= 1 right-hand sides) or selected-inversion tasks.  order == nullptr
+// means one matrix (mats[0]) with tasks in their own order, else order[2t],
+// order[2t+1] = (matrix index, task id).
+enum ExecKind { EXEC_FACTOR = 0, EXEC_SOLVE = 1, EXEC_SELINV = 2 };
+hipError_t launch_exec(int T, int kind, const ExecMat* d_mats, const int32_t* d_order, int32_t total,
+                       ExecCtrl* d_ctrl, int nrhs, int nwg, hipStream_t st);
+
+// diagonal of the selected inverse in the original ordering (NaN on failure)
+hipError_t launch_selinv_diag(int T, const double* sigma, const int32_t* trow_ptr, const int64_t* row_base,
+                              const int32_t* row_cnt, const int64_t* perm, int32_t ntr,
+                              const unsigned long long* info, double* out, hipStream_t st);
 
 // values (row-profile order) -> tile store (gather per tile, zero fill, unit
 // padding diagonal); also writes `orig` when not null; resets *info.

@@ -29,6 +29,12 @@ enum TaskType : int32_t {
   TK_BDIAG = 11, // solve, backward: Z_m  = Linv_m^T ((Z_m or Y_m) - [L_(i,m)^T Z_i])
   TK_FPART = 12, // solve, forward:  Q_s  = sum L_(m,j) Y_j  (one chunk of a long row)
   TK_FSUM = 13,  // solve, forward:  Y_m -= Q_a + Q_(a+1) + ... + Q_(b-1)
+  // selected inversion (Sigma = A^{-1} on the tile pattern of L), by tile
+  // columns k in reverse order; S(k) = tile rows below k in column k,
+  // p = min S(k) (the parent of k in the tile elimination tree)
+  TK_SWE = 16,   // W_(r,k) [+]= sum_s Sig~_(r,s) L_(s,k), s in S(k) \ {p}  (r != p)
+  TK_SW = 17,    // Sig_(r,k) = -(W + products + pushed partials) Linv_k; D, pushes
+  TK_SDIAG = 18, // Sig_kk = Linv_k^T (Linv_k - sum_r D_(r,k))
 };
 
 enum TaskFlag : int32_t {
@@ -49,7 +55,15 @@ enum TaskFlag : int32_t {
 // FDIAG/BDIAG: w1 = m, a,b = fused solve-pair range applied before the diagonal
 // FPART: w1 = m, a,b = solve-pair range, c = partial slot
 // FSUM:  w1 = m, a,b = partial slot range (summed in index order)
+// SWE:   w1 = target tile, a = offset of its pairs in the list array, b = pair
+//        count; TF_ACC adds to the target (a later chunk).  A pair is
+//        (Sigma tile | SIG_TRANS if used transposed, L tile).
+// SW:    w1 = target tile (r,k), a = k, b = list offset: [nprod, nsum, npush,
+//        nprod pairs as in SWE, nsum pushed-partial slots, npush L tiles];
+//        TF_ACC: the target holds an early sum W to add.
+// SDIAG: w1 = diagonal tile of k, a = k, b = list offset: [nD, nD slots]
 constexpr int TASK_WORDS = 8;
+constexpr int32_t SIG_TRANS = 1 << 30;
 
 // Device-side description of one matrix (or one solve) for the executor.
 struct ExecMat {
@@ -60,6 +74,9 @@ struct ExecMat {
   double* vy;               // solve: ntr * T * nrhs (forward result)
   double* vz;               // solve: ntr * T * nrhs (backward result)
   double* vpart;            // solve: partial slots, T * nrhs each
+  double* sigma;            // selected inversion: ntiles * T*T (the pattern of L)
+  double* dpart;            // selected inversion: D_(r,k) = L_(r,k)^T Sig_(r,k), per tile
+  double* qpart;            // selected inversion: pushed partials Sig_(s,p)^T L_(s,k), per tile
   const int32_t* tasks;     // ntasks * TASK_WORDS
   const int32_t* succ;      // successor lists
   int32_t* remaining;       // per-task unfinished-predecessor counters

@@ -3,11 +3,20 @@
 #pragma once
 #include <stdint.h>
 
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/stiles.h"
 #include "stiles_internal.h"
+
+// Selected-inversion DAG (task words as in stiles_internal.h, ticket order)
+struct SelinvPlan {
+  std::vector<int32_t> task, succ, list;
+  double flops_alg = 0.0;    // sum_j 2 eta_j (eta_j + 1) over the envelope
+  double flops_exec = 0.0;   // tile products executed (padded tiles)
+};
 
 struct stiles_symbolic {
   stiles_opts opts;
@@ -59,6 +68,11 @@ struct stiles_symbolic {
   std::vector<int32_t> ssucc;
   std::vector<int32_t> spairs;
 
+  // selected inversion: built on first use (guarded; the object stays
+  // logically immutable)
+  mutable std::mutex selinv_mu;
+  mutable std::unique_ptr<SelinvPlan> selinv;
+
   // statistics
   int64_t nnzL = 0;
   double flops_alg = 0.0;
@@ -68,4 +82,6 @@ struct stiles_symbolic {
 namespace stiles {
 // set by every entry point that rejects an argument (thread-local)
 void set_error_arg(int32_t idx);
+// the selected-inversion plan of a symbolic object (built once, thread-safe)
+const SelinvPlan& selinv_plan(const stiles_symbolic& s);
 }

@@ -13,7 +13,9 @@ import paper_2501_02483_amd as S
 
 UPD, PART, TREE, POTRF, TRSM = 1, 2, 3, 4, 5
 FUPD, FDIAG, BUPD, BDIAG, FPART, FSUM = 8, 9, 10, 11, 12, 13
+SWE, SW, SDIAG = 16, 17, 18
 TF_DIAG, TF_FIRST, TF_ACC = 1 << 8, 1 << 9, 1 << 10
+SIG_TRANS = 1 << 30
 
 
 class Plan:
@@ -36,6 +38,11 @@ class Plan:
         self.trow = np.repeat(np.arange(self.ntr), np.diff(self.trow_ptr))
         self.perm = sym.perm()
         self.N = sym.info.N
+        self._sym = sym
+
+    def selinv_tables(self):
+        ex = lambda k: S.stiles_symbolic_export(self._sym.handle, k)
+        return ex("itask").reshape(-1, 8), ex("isucc"), ex("ilist")
 
 
 def _order(tasks, succ, mode, rng):
@@ -186,3 +193,52 @@ def solve(plan, tiles, linv, B, mode="ticket", seed=0):
         Xp[rb:rb + rc] = Z[m, :rc]
     X[plan.perm] = Xp
     return X
+
+
+def selinv(plan, tiles, linv, mode="ticket", seed=0):
+    """Selected inversion (Sigma = A^{-1} on the tile pattern) by the plan's
+    SWE / SW / SDIAG tasks; returns the Sigma tiles."""
+    rng = np.random.default_rng(seed)
+    itask, isucc, lst = plan.selinv_tables()
+    sigma = np.full_like(tiles, np.nan)
+    dpart, qpart = {}, {}
+
+    def sig(code):
+        x = sigma[code & ~SIG_TRANS]
+        assert not np.isnan(x).any(), "Sigma tile read before it was written"
+        return x.T if code & SIG_TRANS else x
+
+    for t in _order(itask, isucc, mode, rng):
+        w = itask[t]
+        typ = w[0] & 0xff
+        if typ == SWE:
+            acc = sum(sig(lst[w[2] + 2 * q]) @ tiles[lst[w[2] + 2 * q + 1]] for q in range(w[3]))
+            sigma[w[1]] = sigma[w[1]] + acc if w[0] & TF_ACC else acc
+        elif typ == SW:
+            o = w[3]
+            nprod, nsum, npush = lst[o:o + 3]
+            prod = lst[o + 3:o + 3 + 2 * nprod]
+            sums = lst[o + 3 + 2 * nprod:o + 3 + 2 * nprod + nsum]
+            push = lst[o + 3 + 2 * nprod + nsum:o + 3 + 2 * nprod + nsum + npush]
+            W = sigma[w[1]].copy() if w[0] & TF_ACC else np.zeros_like(tiles[0])
+            for q in sums:
+                W += qpart.pop(q)
+            for q in range(nprod):
+                W += sig(prod[2 * q]) @ tiles[prod[2 * q + 1]]
+            Sg = -W @ linv[w[2]]
+            sigma[w[1]] = Sg
+            dpart[w[1]] = tiles[w[1]].T @ Sg
+            for u in push:
+                assert u not in qpart
+                qpart[u] = Sg.T @ tiles[u]
+        elif typ == SDIAG:
+            o = w[3]
+            Z = linv[w[2]].copy()
+            for q in lst[o + 1:o + 1 + lst[o]]:
+                Z -= dpart.pop(q)
+            R = linv[w[2]].T @ Z
+            sigma[w[1]] = np.tril(R) + np.tril(R, -1).T
+        else:
+            raise AssertionError("unknown selected-inversion task type %d" % typ)
+    assert not qpart and not dpart, "partials produced but never consumed"
+    return sigma
