@@ -83,7 +83,8 @@ typedef struct stiles_opts {
                              accumulations is >= tree_min_ratio x the number of
                              partial workers (Section IV-A recommends 2); <= 0
                              disables the tree (sequential accumulation chain)       */
-  int32_t chunk;          /* tile products per accumulation task (0: 12 at T=64, 16 at T=32) */
+  int32_t chunk;          /* tile products per accumulation task, at most 32
+                             (0: 12 at T=64, 16 at T=32)                              */
   double refine_tol;      /* mixed mode: stop when the backward error of every
                              right-hand side is <= refine_tol (0 = 2^-52 * N^0.5)    */
   int32_t refine_max_iter;/* mixed mode: at most this many refinement steps (0 = 30) */
@@ -330,6 +331,8 @@ void stiles_factor_release(stiles_factor* f);
  *   (each pointer may be NULL).
  * stiles_selinv_set_timing / stiles_selinv_kernel_ms: a pair of HIP events
  *   around each compute launch, as for the factor.
+ * stiles_selinv_set_trace: per-task trace of the compute launch in the format
+ *   of stiles_factor_set_trace (32 bytes per task; NULL switches it off).
  * Calls that share a handle must be ordered on one stream.
  */
 typedef struct stiles_selinv stiles_selinv;
@@ -342,6 +345,7 @@ stiles_status stiles_selinv_diag(stiles_selinv* si, double* d_diag, hipStream_t 
 stiles_status stiles_selinv_extract(stiles_selinv* si, double* d_out, hipStream_t stream);
 stiles_status stiles_selinv_set_timing(stiles_selinv* si, int32_t enable);
 stiles_status stiles_selinv_kernel_ms(stiles_selinv* si, float* ms);
+stiles_status stiles_selinv_set_trace(stiles_selinv* si, void* d_trace, hipStream_t stream);
 void stiles_selinv_destroy(stiles_selinv* si);
 
 #ifdef __cplusplus

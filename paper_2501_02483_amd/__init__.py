@@ -23,7 +23,7 @@ __all__ = [
     "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_logdet",
     "stiles_batch_destroy", "Batch", "SelInv", "stiles_selinv_query", "stiles_selinv_workspace_size",
     "stiles_selinv_create", "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract",
-    "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_destroy",
+    "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -52,7 +52,7 @@ EXPORTED = [
     "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_logdet",
     "stiles_batch_destroy", "stiles_selinv_query", "stiles_selinv_workspace_size", "stiles_selinv_create",
     "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract", "stiles_selinv_set_timing",
-    "stiles_selinv_kernel_ms", "stiles_selinv_destroy",
+    "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
 ]
 
 
@@ -131,6 +131,7 @@ def load_library(path=LIB_PATH):
         "stiles_selinv_extract": (_i32, [_vp, _vp, _vp]),
         "stiles_selinv_set_timing": (_i32, [_vp, _i32]),
         "stiles_selinv_kernel_ms": (_i32, [_vp, ctypes.POINTER(ctypes.c_float)]),
+        "stiles_selinv_set_trace": (_i32, [_vp, _vp, _vp]),
         "stiles_selinv_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
@@ -350,6 +351,10 @@ def stiles_selinv_kernel_ms(si):
     v = ctypes.c_float()
     _check(load_library().stiles_selinv_kernel_ms(si, ctypes.byref(v)), "stiles_selinv_kernel_ms")
     return v.value
+
+
+def stiles_selinv_set_trace(si, d_trace, stream=None):
+    _check(load_library().stiles_selinv_set_trace(si, _ptr(d_trace), _stream(stream)), "stiles_selinv_set_trace")
 
 
 def stiles_selinv_destroy(si):

@@ -450,7 +450,7 @@ stiles_status check_opts(const stiles_opts* o, int arg) {
   if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_err_arg = arg; return STILES_ENOTSUP; }
   if (o->ordering < STILES_ORDER_AUTO || o->ordering > STILES_ORDER_ADAPTABLE_ND) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->nd_parts < 0 || o->nd_parts > 64) { g_err_arg = arg; return STILES_EINVAL; }
-  if (o->chunk < 0 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
+  if (o->chunk < 0 || o->chunk > 32 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
   return STILES_OK;
 }
 
@@ -1020,12 +1020,17 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
 // or the transpose of the stored (s,r).  The tile pattern is closed under
 // elimination (it is the filled pattern), so every Sig~ used is stored and
 // lies in a later column.  Only column p's results are fresh when column k
-// starts: for r != p the terms with s != p run ahead (SWE tasks) and the term
-// with s = p waits (SW); for r = p every term is fresh, so the tasks that
-// produce Sig_(s,p) push their products Sig_(s,p)^T L_(s,k) into a per-tile
-// slot (k is a child of p in the tile elimination tree) and SW(p,k) only sums
-// them.  Each SW also leaves D_(r,k) = L_(r,k)^T Sig_(r,k) in a per-tile slot
-// for SDIAG(k), which sums them in ascending r.
+// starts: for r != p the terms with s != p run ahead (SWE tasks, oldest
+// columns first) except the next most recent one, and the terms with s = p
+// and that one are left to SW; for r = p every term is
+// fresh, so the tasks that produce Sig_(s,p) push their products
+// Sig_(s,p)^T L_(s,k) into a per-tile slot (k is a child of p in the tile
+// elimination tree), a TSUM task adds them up while Sig_pp is being formed,
+// and SW(p,k) adds one tile.  Each SW also leaves D_(r,k) = L_(r,k)^T Sig_(r,k)
+// in a per-tile slot; the D of rows r != p are summed by a TSUM while SW(p,k)
+// runs, so SDIAG(k) adds two tiles.  The per-step chain is then
+// SDIAG(p) -> SW(p,k) -> SDIAG(k), about five tile products.  The diagonal
+// tile's slots hold the two sums.
 void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
   const int32_t ntr = s.ntr, T = s.T;
   const int32_t chunk = s.opts.chunk > 0 ? s.opts.chunk : (T == 64 ? 12 : 16);
@@ -1054,10 +1059,20 @@ void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
     const int32_t t = lookup(std::max(r, c), std::min(r, c));
     return {t | (r < c ? SIG_TRANS : 0), sw[t]};
   };
+  // TSUM of slots into `out`; kind 0: D slots, 1: pushed partials
+  auto tsum = [&](int32_t out, const std::vector<int32_t>& slots, int32_t kind,
+                  const std::vector<int32_t>& deps) {
+    const int32_t off = (int32_t)lst.size();
+    lst.insert(lst.end(), slots.begin(), slots.end());
+    const int tk = tb.add(TK_TSUM, out, off, (int32_t)slots.size(), kind, 0.4f + 0.1f * (float)slots.size());
+    for (int d : deps) tb.dep(tk, d);
+    return tk;
+  };
   for (int32_t k = ntr - 1; k >= 0; k--) {
     const auto& col = ctiles[k];   // col[0] is the diagonal tile
     const size_t ns = col.size() - 1;
     const int32_t p = ns ? col[1].first : -1;
+    const bool presum = ns >= 3;   // two or more slots besides row p
     for (size_t a = 1; a <= ns; a++) {
       const int32_t r = col[a].first, t = col[a].second;
       std::vector<int32_t> push;   // tiles (r,c) of the children c of k
@@ -1068,9 +1083,13 @@ void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
       int last = -1;
       std::vector<int32_t> prod, sums, deps;
       if (r != p) {
+        // the products with the two most recent columns (s = p and the next
+        // row of S(k)) are done by SW itself; the others run ahead as SWE
+        // chunks, oldest columns first, so that the last chunk does not wait
+        // for the latest results
         std::vector<std::pair<int32_t, int32_t>> pr;
         std::vector<int32_t> pdep;
-        for (size_t b = 2; b <= ns; b++) {
+        for (size_t b = ns; b >= 3; b--) {
           const auto x = sig(r, col[b].first);
           pr.push_back({x.first, col[b].second});
           pdep.push_back(x.second);
@@ -1086,39 +1105,63 @@ void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
           tb.dep(tk, last);
           last = tk;
         }
-        const auto x = sig(r, p);
-        prod = {x.first, col[1].second};
-        deps.push_back(x.second);
+        for (size_t b = 1; b <= 2; b++) {   // ns >= 2 here: S(k) holds p and r
+          const auto x = sig(r, col[b].first);
+          prod.push_back(x.first);
+          prod.push_back(col[b].second);
+          deps.push_back(x.second);
+        }
       } else {
         const auto x = sig(p, p);
         prod = {x.first, col[1].second};
         deps.push_back(x.second);
+        std::vector<int32_t> qs, qd;
         for (size_t b = 2; b <= ns; b++) {
-          sums.push_back(col[b].second);                      // slot of tile (s,k)
-          deps.push_back(sw[lookup(col[b].first, p)]);       // pushed by SW(s,p)
+          qs.push_back(col[b].second);                 // slot of tile (s,k)
+          qd.push_back(sw[lookup(col[b].first, p)]);   // pushed by SW(s,p)
+        }
+        if (presum) {
+          const int tk = tsum(diag_tile(k), qs, 1, qd);
+          sums.push_back(diag_tile(k));
+          deps.push_back(tk);
+        } else {
+          sums = qs;
+          deps.insert(deps.end(), qd.begin(), qd.end());
         }
       }
-      const int32_t off = (int32_t)lst.size();
       const int32_t nprod = (int32_t)prod.size() / 2;
-      lst.push_back(nprod);
-      lst.push_back((int32_t)sums.size());
-      lst.push_back((int32_t)push.size());
+      const int32_t off = (int32_t)lst.size();
+      if (prod.size() + sums.size() + push.size() > 64 || push.size() > 255 || sums.size() > 255) {
+        fprintf(stderr, "stiles: selected-inversion operand list too long\n");
+        abort();
+      }
       lst.insert(lst.end(), prod.begin(), prod.end());
       lst.insert(lst.end(), sums.begin(), sums.end());
       lst.insert(lst.end(), push.begin(), push.end());
-      const int tk = tb.add(TK_SW | (last >= 0 ? TF_ACC : 0), t, k, off, 0,
+      const int32_t counts = (int32_t)sums.size() | ((int32_t)push.size() << 8) | (nprod << 16);
+      const int tk = tb.add(TK_SW | (last >= 0 ? TF_ACC : 0), t, k, off, counts,
                             0.5f + 1.8f * t3 * (float)(nprod + 2 + push.size()) + 0.1f * (float)sums.size());
       fexec += 2.0 * T3 * (double)(nprod + 2 + push.size());
       tb.dep(tk, last);
       for (int d : deps) tb.dep(tk, d);
       sw[t] = tk;
     }
+    std::vector<int32_t> dslots, ddeps;
+    if (presum) {
+      std::vector<int32_t> rs, rd;
+      for (size_t a = 2; a <= ns; a++) { rs.push_back(col[a].second); rd.push_back(sw[col[a].second]); }
+      ddeps.push_back(tsum(diag_tile(k), rs, 0, rd));
+      dslots = {diag_tile(k), col[1].second};
+      ddeps.push_back(sw[col[1].second]);
+    } else {
+      for (size_t a = 1; a <= ns; a++) { dslots.push_back(col[a].second); ddeps.push_back(sw[col[a].second]); }
+    }
     const int32_t off = (int32_t)lst.size();
-    lst.push_back((int32_t)ns);
-    for (size_t a = 1; a <= ns; a++) lst.push_back(col[a].second);
-    const int tk = tb.add(TK_SDIAG, diag_tile(k), k, off, 0, 0.5f + 1.8f * t3 + 0.1f * (float)ns);
+    lst.insert(lst.end(), dslots.begin(), dslots.end());   // at most 2 with the presum, else <= 2 rows
+    const int tk = tb.add(TK_SDIAG, diag_tile(k), k, off, (int32_t)dslots.size(),
+                          0.5f + 1.8f * t3 + 0.1f * (float)dslots.size());
     fexec += 2.0 * T3;
-    for (size_t a = 1; a <= ns; a++) tb.dep(tk, sw[col[a].second]);
+    for (int d : ddeps) tb.dep(tk, d);
     sd[k] = tk;
   }
   P.flops_exec = fexec;

@@ -941,4 +941,16 @@ extern "C" stiles_status stiles_selinv_kernel_ms(stiles_selinv* si, float* ms) {
   return STILES_OK;
 }
 
+extern "C" stiles_status stiles_selinv_set_trace(stiles_selinv* si, void* d_trace, hipStream_t st) {
+  set_error_arg(0);
+  if (!si) { set_error_arg(1); return STILES_EINVAL; }
+  ExecMat m;
+  hipError_t e = hipMemcpyAsync(&m, si->ws + si->L.mat, sizeof(ExecMat), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  m.trace = static_cast<unsigned long long*>(d_trace);
+  if (e == hipSuccess) e = hipMemcpyAsync(si->ws + si->L.mat, &m, sizeof(ExecMat), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
 extern "C" void stiles_selinv_destroy(stiles_selinv* si) { delete si; }

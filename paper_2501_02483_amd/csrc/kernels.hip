@@ -22,6 +22,38 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 256;
+
+// Global-memory accesses go through address-space-1 pointers, so that they
+// are global (not flat) instructions: they then count only in vmcnt, and a
+// wait for LDS data (lgkmcnt) never waits for a tile prefetch in flight.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename E>
+__device__ __forceinline__ GLOBAL E* gp(E* p) { return (GLOBAL E*)p; }
+template <typename E>
+__device__ __forceinline__ const GLOBAL E* gp(const E* p) { return (const GLOBAL E*)p; }
+
+// The pair (or slot) words of a task, read once: lane l of every wave holds
+// word l (at most 64 words); word i is then taken with readlane into a scalar
+// register, so the loop over the pairs issues no dependent metadata loads.
+__device__ __forceinline__ int load_words(const int32_t* w, int n) {
+  const int l = threadIdx.x & 63;
+  return l < n ? gp(w)[l] : 0;
+}
+__device__ __forceinline__ int word(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+
+// Stores of task results are device-scope (sc1) stores: they are written
+// through to the point of coherence of all XCDs, so once they have completed
+// (s_waitcnt) they are visible to a task on any XCD that acquires after it.
+// A task's release then needs no L2 write-back (buffer_wbl2), which costs
+// about as much as several tile products.  Every global store of the task
+// bodies must go through these.
+__device__ __forceinline__ void st_dev(GLOBAL double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(GLOBAL float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) { st_dev(gp(p), v); }
 // diagonal-tile factorization variant: column-by-column (true) or blocked
 #ifndef STILES_POTRF_COLS
 #define STILES_POTRF_COLS 0
@@ -74,18 +106,36 @@ __device__ __forceinline__ void mma_f64(v4d (&acc)[T / 32][T / 32], const double
   constexpr int NB = T / 32;
   const double* xp = X + r0 + (lane & 15) + (lane >> 4) * T;
   const double* yp = Y + c0 + (lane & 15) + (lane >> 4) * T;
-#pragma unroll 4
-  for (int k = 0; k < T; k += 4) {
-    double a[NB], b[NB];
+  // the operands of step k + 4 are read from LDS while step k's MFMAs run
+  double a[NB], b[NB];
 #pragma unroll
-    for (int q = 0; q < NB; q++) {
-      a[q] = yp[q * 16 + k * T];
-      b[q] = xp[q * 16 + k * T];
+  for (int q = 0; q < NB; q++) {
+    a[q] = yp[q * 16];
+    b[q] = xp[q * 16];
+  }
+#pragma unroll
+  for (int k = 0; k < T; k += 4) {
+    double an[NB], bn[NB];
+    if (k + 4 < T) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) {
+        an[q] = yp[q * 16 + (k + 4) * T];
+        bn[q] = xp[q * 16 + (k + 4) * T];
+      }
     }
+    // keep the next step's LDS reads ahead of this step's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (k + 4 < T) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) {
+        a[q] = an[q];
+        b[q] = bn[q];
+      }
+    }
   }
 }
 
@@ -122,7 +172,7 @@ struct TileStage {
   static constexpr int NV = T * T / NT / EPV;
   vec r[NV];
   __device__ __forceinline__ void load(const E* __restrict__ g) {
-    const vec* v = reinterpret_cast<const vec*>(g);
+    const GLOBAL vec* v = (const GLOBAL vec*)g;
 #pragma unroll
     for (int q = 0; q < NV; q++) r[q] = v[threadIdx.x + q * NT];
   }
@@ -135,7 +185,7 @@ struct TileStage {
 
 // ------------------------------------------------------------ task bodies
 
-// UPD / PART: acc = sum_p X_p Y_p^T over a list of tile pairs.
+// UPD / PART: acc = sum_p X_p Y_p^T over a list of tile pairs (at most 32).
 // mode 0: C_t -= acc (UPD), mode 1: P = acc (PART).  LX, LY: LDS tiles.
 template <int T>
 __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const int32_t* w, int mode, double* LX, double* LY) {
@@ -145,10 +195,11 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
   const int r0 = wr * W, c0 = wc * W;
   const bool diag = (w[0] & TF_DIAG) != 0;
   const bool active = !(diag && wc > wr);   // strictly upper quarter of a diagonal tile
-  const int p0 = w[2], p1 = w[3];
+  const int p0 = __builtin_amdgcn_readfirstlane(w[2]), np = __builtin_amdgcn_readfirstlane(w[3]) - p0;
   const bool mixed = M.mixed && mode == 0;
   const bool accum = mode == 1 && (w[0] & TF_ACC) != 0;   // partial chain: P += sum
-  double* out = mode == 0 ? M.tiles + (int64_t)w[1] * TT : M.part + (int64_t)w[4] * TT;
+  GLOBAL double* out = gp(mode == 0 ? M.tiles + (int64_t)w[1] * TT : M.part + (int64_t)w[4] * TT);
+  const int pv = load_words(M.pairs + 2 * p0, 2 * np);
   // the target's current value is needed only at the end: fetch it now
   double cin[NB][NB][4];
   if ((mode == 0 || accum) && active) {
@@ -164,22 +215,23 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
         }
   }
   if (!mixed) {
+    const double* tiles = M.tiles;
     v4d acc[NB][NB];
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     TileStage<T, double> sx, sy;
-    sx.load(M.tiles + (int64_t)M.pairs[2 * p0] * TT);
-    sy.load(M.tiles + (int64_t)M.pairs[2 * p0 + 1] * TT);
-    for (int p = p0; p < p1; p++) {
+    sx.load(tiles + (int64_t)word(pv, 0) * TT);
+    sy.load(tiles + (int64_t)word(pv, 1) * TT);
+    for (int p = 0; p < np; p++) {
       __syncthreads();
       sx.store(LX);
       sy.store(LY);
       __syncthreads();
-      if (p + 1 < p1) {
-        sx.load(M.tiles + (int64_t)M.pairs[2 * p + 2] * TT);
-        sy.load(M.tiles + (int64_t)M.pairs[2 * p + 3] * TT);
+      if (p + 1 < np) {
+        sx.load(tiles + (int64_t)word(pv, 2 * p + 2) * TT);
+        sy.load(tiles + (int64_t)word(pv, 2 * p + 3) * TT);
       }
       if (active) mma_f64<T>(acc, LX, LY, r0, c0, lane);
     }
@@ -192,9 +244,9 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
           for (int r = 0; r < 4; r++) {
             const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
             if (mode == 0) {
-              if (!diag || row >= col) out[row + col * T] = cin[i][j][r] - acc[i][j][r];
+              if (!diag || row >= col) st_dev(out + row + col * T, cin[i][j][r] - acc[i][j][r]);
             } else {
-              out[row + col * T] = accum ? cin[i][j][r] + acc[i][j][r] : acc[i][j][r];
+              st_dev(out + row + col * T, accum ? cin[i][j][r] + acc[i][j][r] : acc[i][j][r]);
             }
           }
     } else if (mode == 1) {   // keep the partial fully defined
@@ -205,10 +257,11 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
 #pragma unroll
           for (int r = 0; r < 4; r++) {
             const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
-            out[row + col * T] = 0.0;
+            st_dev(out + row + col * T, 0.0);
           }
     }
   } else {
+    const float* shadow = M.shadow;
     float* FX = reinterpret_cast<float*>(LX);
     float* FY = reinterpret_cast<float*>(LY);
     v4f acc[NB][NB];
@@ -217,16 +270,16 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     TileStage<T, float> sx, sy;
-    sx.load(M.shadow + (int64_t)M.pairs[2 * p0] * TT);
-    sy.load(M.shadow + (int64_t)M.pairs[2 * p0 + 1] * TT);
-    for (int p = p0; p < p1; p++) {
+    sx.load(shadow + (int64_t)word(pv, 0) * TT);
+    sy.load(shadow + (int64_t)word(pv, 1) * TT);
+    for (int p = 0; p < np; p++) {
       __syncthreads();
       sx.store(FX);
       sy.store(FY);
       __syncthreads();
-      if (p + 1 < p1) {
-        sx.load(M.shadow + (int64_t)M.pairs[2 * p + 2] * TT);
-        sy.load(M.shadow + (int64_t)M.pairs[2 * p + 3] * TT);
+      if (p + 1 < np) {
+        sx.load(shadow + (int64_t)word(pv, 2 * p + 2) * TT);
+        sy.load(shadow + (int64_t)word(pv, 2 * p + 3) * TT);
       }
       if (active) mma_f32<T>(acc, FX, FY, r0, c0, lane);
     }
@@ -238,7 +291,7 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
 #pragma unroll
           for (int r = 0; r < 4; r++) {
             const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + 4 * (lane >> 4) + r;
-            if (!diag || row >= col) out[row + col * T] = cin[i][j][r] - (double)acc[i][j][r];
+            if (!diag || row >= col) st_dev(out + row + col * T, cin[i][j][r] - (double)acc[i][j][r]);
           }
     }
   }
@@ -249,15 +302,17 @@ template <int T>
 __device__ __attribute__((noinline)) void task_tree(const ExecMat& M, const int32_t* w) {
   constexpr int TT = T * T;
   typedef double d2 __attribute__((ext_vector_type(2)));
-  const d2* pa = reinterpret_cast<const d2*>(M.part + (int64_t)w[2] * TT);
-  const d2* pb = w[3] >= 0 ? reinterpret_cast<const d2*>(M.part + (int64_t)w[3] * TT) : nullptr;
-  d2* dst = w[4] >= 0 ? reinterpret_cast<d2*>(M.part + (int64_t)w[4] * TT)
-                      : reinterpret_cast<d2*>(M.tiles + (int64_t)w[1] * TT);
+  const GLOBAL d2* pa = (const GLOBAL d2*)(M.part + (int64_t)w[2] * TT);
+  const GLOBAL d2* pb = w[3] >= 0 ? (const GLOBAL d2*)(M.part + (int64_t)w[3] * TT) : nullptr;
+  GLOBAL d2* dst = w[4] >= 0 ? (GLOBAL d2*)(M.part + (int64_t)w[4] * TT) : (GLOBAL d2*)(M.tiles + (int64_t)w[1] * TT);
   const bool apply = w[4] < 0;
 #pragma unroll 4
   for (int e = threadIdx.x; e < TT / 2; e += NT) {
     const d2 s = pb ? pa[e] + pb[e] : pa[e];
-    dst[e] = apply ? dst[e] - s : s;
+    const d2 v = apply ? dst[e] - s : s;
+    GLOBAL double* o = (GLOBAL double*)(dst + e);
+    st_dev(o, v.x);
+    st_dev(o + 1, v.y);
   }
 }
 
@@ -269,6 +324,7 @@ __device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int3
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
   double* C = M.tiles + (int64_t)w[1] * TT;
+  GLOBAL double* Cg = gp(C);
   const bool fused = w[4] > w[3];
   TileStage<T, double> sx, sy;
   v4d acc[NB][NB];
@@ -308,7 +364,7 @@ __device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int3
   }
   __syncthreads();
   mma_f64<T>(acc, LX, LY, r0, c0, lane);
-  float* S = M.mixed ? M.shadow + (int64_t)w[1] * TT : nullptr;
+  GLOBAL float* S = M.mixed ? gp(M.shadow + (int64_t)w[1] * TT) : nullptr;
 #pragma unroll
   for (int i = 0; i < NB; i++)
 #pragma unroll
@@ -316,8 +372,8 @@ __device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int3
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
-        C[row + col * T] = acc[i][j][r];
-        if (S) S[row + col * T] = (float)acc[i][j][r];
+        st_dev(Cg + row + col * T, acc[i][j][r]);
+        if (S) st_dev(S + row + col * T, (float)acc[i][j][r]);
       }
 }
 
@@ -580,8 +636,8 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
   double* Li = M.linv + (int64_t)k * TT;
   for (int e = tid; e < TT; e += NT) {
     const int row = e % T, col = e / T;
-    C[e] = row >= col ? S[e] : 0.0;
-    Li[e] = Xi[e];
+    st_dev(C + e, row >= col ? S[e] : 0.0);
+    st_dev(Li + e, Xi[e]);
   }
 }
 
@@ -682,7 +738,7 @@ __device__ __attribute__((noinline)) void task_potrf_cols(const ExecMat& M, cons
 #pragma unroll
   for (int q = 0; q < NC; q++) {
     const int c = g + G * q;
-    C[i + c * T] = lout[q];
+    st_dev(C + i + c * T, lout[q]);
     S[i + c * T] = lout[q];
   }
   // inverse, row by row
@@ -710,7 +766,7 @@ __device__ __attribute__((noinline)) void task_potrf_cols(const ExecMat& M, cons
   }
   double* Li = M.linv + (int64_t)k * TT;
 #pragma unroll
-  for (int q = 0; q < NC; q++) Li[i + (g + G * q) * T] = x[q];
+  for (int q = 0; q < NC; q++) st_dev(Li + i + (g + G * q) * T, x[q]);
 }
 
 // ---------------------------------------------------------------- solves
@@ -729,12 +785,12 @@ struct SolveStage {
   d2 lt[NVL];
   d2 vb[NVV];
   __device__ __forceinline__ void load_tile(const double* __restrict__ L) {
-    const d2* lv = reinterpret_cast<const d2*>(L);
+    const GLOBAL d2* lv = (const GLOBAL d2*)L;
 #pragma unroll
     for (int q = 0; q < NVL; q++) lt[q] = lv[threadIdx.x + q * NT];
   }
   __device__ __forceinline__ void load_vec(const double* __restrict__ v, int nrhs) {
-    const d2* vv = reinterpret_cast<const d2*>(v);
+    const GLOBAL d2* vv = (const GLOBAL d2*)v;
     const int nv = T * nrhs / 2;
 #pragma unroll
     for (int q = 0; q < NVV; q++) {
@@ -763,14 +819,20 @@ template <int T>
 __device__ __forceinline__ v4d solve_mma(v4d acc, const double* LL, const double* LV, bool trans, int wave, int lane) {
   constexpr int LD = T + 1;
   const int i = 16 * wave + (lane & 15);
-#pragma unroll 4
-  for (int kq = 0; kq < T; kq += 4) {
-    const int l = kq + (lane >> 4);
-    const double av = trans ? LL[l + i * LD] : LL[i + l * LD];
-    const double bv = LV[l + (lane & 15) * T];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  // two accumulation chains (k = 0, 8, ... and k = 4, 12, ...) halve the
+  // dependent MFMA latency; their sum is added at the end
+  v4d acc1 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kq = 0; kq < T; kq += 8) {
+    const int l0 = kq + (lane >> 4), l1 = l0 + 4;
+    const double a0 = trans ? LL[l0 + i * LD] : LL[i + l0 * LD];
+    const double b0 = LV[l0 + (lane & 15) * T];
+    const double a1 = trans ? LL[l1 + i * LD] : LL[i + l1 * LD];
+    const double b1 = LV[l1 + (lane & 15) * T];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
   }
-  return acc;
+  return acc + acc1;
 }
 
 // Static operands of a solve task (the factor is final before the solve
@@ -807,44 +869,46 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   const bool fwd = type == TK_FUPD || type == TK_FDIAG || type == TK_FPART;
   const bool diag = type == TK_FDIAG || type == TK_BDIAG;
   const double* vsrc = fwd ? M.vy : M.vz;
-  const int p0 = w[2], p1 = w[3];
+  const double* tiles = M.tiles;
+  const int p0 = __builtin_amdgcn_readfirstlane(w[2]), np = __builtin_amdgcn_readfirstlane(w[3]) - p0;
+  const int pv = load_words(M.pairs + 2 * p0, 2 * np);
   // output element of this lane: row 16 wave + (lane >> 4) + 4 r, column lane & 15
   const int col = lane & 15;
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
   SolveStage<T> st;
-  if (p1 > p0) st.load_vec(vsrc + M.pairs[2 * p0 + 1] * vb, nrhs);
-  for (int p = p0; p < p1; p++) {
+  if (np > 0) st.load_vec(vsrc + word(pv, 1) * vb, nrhs);
+  for (int p = 0; p < np; p++) {
     __syncthreads();
-    if (p > p0) st.store_tile(LL);   // the first tile was prefetched
+    if (p > 0) st.store_tile(LL);   // the first tile was prefetched
     st.store_vec(LV);
     __syncthreads();
-    if (p + 1 < p1) {
-      st.load_tile(M.tiles + (int64_t)M.pairs[2 * p + 2] * TT);
-      st.load_vec(vsrc + M.pairs[2 * p + 3] * vb, nrhs);
+    if (p + 1 < np) {
+      st.load_tile(tiles + (int64_t)word(pv, 2 * p + 2) * TT);
+      st.load_vec(vsrc + word(pv, 2 * p + 3) * vb, nrhs);
     }
     if (act) acc = solve_mma<T>(acc, LL, LV, !fwd, wave, lane);
   }
   if (type == TK_FPART) {
     // one chunk of a long row: the partial product into its slot
-    double* q = M.vpart + (int64_t)w[4] * vb;
+    GLOBAL double* q = gp(M.vpart + (int64_t)w[4] * vb);
     if (act && col < nrhs) {
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = 16 * wave + (lane >> 4) + 4 * r;
-        q[row + col * T] = acc[r];
+        st_dev(q + row + col * T, acc[r]);
       }
     }
     return;
   }
   // base block: Y_m (forward), or Y_m / Z_m (backward, first chunk reads Y)
   const double* base = fwd ? M.vy + m * vb : ((w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb);
-  double* dst = fwd ? M.vy + m * vb : M.vz + m * vb;
+  GLOBAL double* dst = gp(fwd ? M.vy + m * vb : M.vz + m * vb);
   if (!diag) {
     if (act && col < nrhs) {
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = 16 * wave + (lane >> 4) + 4 * r;
-        dst[row + col * T] = base[row + col * T] - acc[r];
+        st_dev(dst + row + col * T, gp(base)[row + col * T] - acc[r]);
       }
     }
     return;
@@ -864,7 +928,7 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   if (act) out = solve_mma<T>(out, LI, LV, !fwd, wave, lane);
   if (act && col < nrhs) {
 #pragma unroll
-    for (int r = 0; r < 4; r++) dst[(16 * wave + (lane >> 4) + 4 * r) + col * T] = out[r];
+    for (int r = 0; r < 4; r++) st_dev(dst + (16 * wave + (lane >> 4) + 4 * r) + col * T, out[r]);
   }
 }
 
@@ -887,7 +951,7 @@ __device__ __attribute__((noinline)) void task_fsum(const ExecMat& M, const int3
       s3 += M.vpart[(int64_t)(q + 3) * vb + e];
     }
     for (; q < b; q++) s0 += M.vpart[(int64_t)q * vb + e];
-    y[e] -= (s0 + s1) + (s2 + s3);
+    st_dev(y + e, y[e] - ((s0 + s1) + (s2 + s3)));
   }
 }
 
@@ -905,7 +969,7 @@ struct PadStage {
   static constexpr int NV = T * T / NT / 2;
   d2 r[NV];
   __device__ __forceinline__ void load(const double* __restrict__ g) {
-    const d2* v = reinterpret_cast<const d2*>(g);
+    const GLOBAL d2* v = (const GLOBAL d2*)g;
 #pragma unroll
     for (int q = 0; q < NV; q++) r[q] = v[threadIdx.x + q * NT];
   }
@@ -925,20 +989,36 @@ __device__ __forceinline__ void mma_lp(v4d (&acc)[T / 32][T / 32], const double*
                                        int lane) {
   constexpr int NB = T / 32, LP = T + 2;
   const int li = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int k = 0; k < T; k += 4) {
-    const int kk = k + lk;
-    double a[NB], b[NB];
+  auto ya = [&](int q, int kk) { const int yi = c0 + 16 * q + li; return TY ? Y[kk + yi * LP] : Y[yi + kk * LP]; };
+  auto xb = [&](int q, int kk) { const int xi = r0 + 16 * q + li; return TX ? X[kk + xi * LP] : X[xi + kk * LP]; };
+  double a[NB], b[NB];
 #pragma unroll
-    for (int q = 0; q < NB; q++) {
-      const int yi = c0 + 16 * q + li, xi = r0 + 16 * q + li;
-      a[q] = TY ? Y[kk + yi * LP] : Y[yi + kk * LP];
-      b[q] = TX ? X[kk + xi * LP] : X[xi + kk * LP];
+  for (int q = 0; q < NB; q++) {
+    a[q] = ya(q, lk);
+    b[q] = xb(q, lk);
+  }
+#pragma unroll
+  for (int k = 0; k < T; k += 4) {
+    double an[NB], bn[NB];
+    if (k + 4 < T) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) {
+        an[q] = ya(q, k + 4 + lk);
+        bn[q] = xb(q, k + 4 + lk);
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (k + 4 < T) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) {
+        a[q] = an[q];
+        b[q] = bn[q];
+      }
+    }
   }
 }
 
@@ -950,10 +1030,55 @@ __device__ __forceinline__ void zero_acc(v4d (&acc)[T / 32][T / 32]) {
     for (int j = 0; j < T / 32; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 }
 
-// out (column-major, leading dimension ld) <- s * acc, element by element
+// acc += sum over pairs of Sig~ L: the pair words (Sigma tile code, L tile)
+// are in pv (at most 32 pairs); LX, LY: padded LDS tiles.  Two register
+// stages alternate, so the global loads of a pair are issued two products
+// before it is used.
 template <int T>
-__device__ __forceinline__ void put_acc(const v4d (&acc)[T / 32][T / 32], double* out, int ld, double sc, int r0,
-                                        int c0, int lane) {
+__device__ __forceinline__ void sig_pair_load(PadStage<T>& sx, PadStage<T>& sy, const ExecMat& M, int pv, int p) {
+  constexpr int TT = T * T;
+  sx.load(M.sigma + (int64_t)(word(pv, 2 * p) & ~SIG_TRANS) * TT);
+  sy.load(M.tiles + (int64_t)word(pv, 2 * p + 1) * TT);
+}
+
+template <int T>
+__device__ __forceinline__ void sig_pair_mma(v4d (&acc)[T / 32][T / 32], int code, const double* LX, const double* LY,
+                                             int r0, int c0, int lane) {
+  // C = Sig~ L: op(X) = Sig or Sig^T, op(Y)^T = L
+  if (code & SIG_TRANS) mma_lp<T, true, true>(acc, LX, LY, r0, c0, lane);
+  else mma_lp<T, false, true>(acc, LX, LY, r0, c0, lane);
+}
+
+template <int T>
+__device__ __forceinline__ void sig_products(v4d (&acc)[T / 32][T / 32], const ExecMat& M, int pv, int np,
+                                             double* LX, double* LY, int r0, int c0, int lane) {
+  if (np <= 0) return;
+  PadStage<T> ax, ay, bx, by;
+  sig_pair_load<T>(ax, ay, M, pv, 0);
+  if (np > 1) sig_pair_load<T>(bx, by, M, pv, 1);
+  for (int p = 0; p < np; p += 2) {
+    __syncthreads();
+    ax.store(LX);
+    ay.store(LY);
+    __syncthreads();
+    if (p + 2 < np) sig_pair_load<T>(ax, ay, M, pv, p + 2);
+    sig_pair_mma<T>(acc, word(pv, 2 * p), LX, LY, r0, c0, lane);
+    if (p + 1 < np) {
+      __syncthreads();
+      bx.store(LX);
+      by.store(LY);
+      __syncthreads();
+      if (p + 3 < np) sig_pair_load<T>(bx, by, M, pv, p + 3);
+      sig_pair_mma<T>(acc, word(pv, 2 * p + 2), LX, LY, r0, c0, lane);
+    }
+  }
+}
+
+// out (global, column-major T x T) <- s * acc, element by element
+template <int T>
+__device__ __forceinline__ void put_acc_g(const v4d (&acc)[T / 32][T / 32], double* out, double sc, int r0, int c0,
+                                          int lane) {
+  GLOBAL double* o = gp(out);
 #pragma unroll
   for (int i = 0; i < T / 32; i++)
 #pragma unroll
@@ -961,7 +1086,22 @@ __device__ __forceinline__ void put_acc(const v4d (&acc)[T / 32][T / 32], double
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
-        out[row + col * ld] = sc * acc[i][j][r];
+        st_dev(o + row + col * T, sc * acc[i][j][r]);
+      }
+}
+
+// out (LDS, leading dimension T + 2) <- s * acc
+template <int T>
+__device__ __forceinline__ void put_acc_l(const v4d (&acc)[T / 32][T / 32], double* out, double sc, int r0, int c0,
+                                          int lane) {
+#pragma unroll
+  for (int i = 0; i < T / 32; i++)
+#pragma unroll
+    for (int j = 0; j < T / 32; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
+        out[row + col * (T + 2)] = sc * acc[i][j][r];
       }
 }
 
@@ -969,6 +1109,7 @@ __device__ __forceinline__ void put_acc(const v4d (&acc)[T / 32][T / 32], double
 template <int T>
 __device__ __forceinline__ void add_tile(v4d (&acc)[T / 32][T / 32], const double* __restrict__ g, int r0, int c0,
                                          int lane) {
+  const GLOBAL double* s = gp(g);
 #pragma unroll
   for (int i = 0; i < T / 32; i++)
 #pragma unroll
@@ -976,34 +1117,8 @@ __device__ __forceinline__ void add_tile(v4d (&acc)[T / 32][T / 32], const doubl
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
-        acc[i][j][r] += g[row + col * T];
+        acc[i][j][r] += s[row + col * T];
       }
-}
-
-// acc += sum over pairs of op(Sig_x) L_y^T... as C = Sig~ L: the pairs are
-// (Sigma tile code, L tile); LX, LY: padded LDS tiles
-template <int T>
-__device__ __forceinline__ void sig_products(v4d (&acc)[T / 32][T / 32], const ExecMat& M, const int32_t* pr, int np,
-                                             double* LX, double* LY, int r0, int c0, int lane) {
-  constexpr int TT = T * T;
-  if (np <= 0) return;
-  PadStage<T> sx, sy;
-  sx.load(M.sigma + (int64_t)(__builtin_amdgcn_readfirstlane(pr[0]) & ~SIG_TRANS) * TT);
-  sy.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(pr[1]) * TT);
-  for (int p = 0; p < np; p++) {
-    const int xc = __builtin_amdgcn_readfirstlane(pr[2 * p]);
-    __syncthreads();
-    sx.store(LX);
-    sy.store(LY);
-    __syncthreads();
-    if (p + 1 < np) {
-      sx.load(M.sigma + (int64_t)(__builtin_amdgcn_readfirstlane(pr[2 * p + 2]) & ~SIG_TRANS) * TT);
-      sy.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(pr[2 * p + 3]) * TT);
-    }
-    // C = Sig~ L: op(X) = Sig or Sig^T, op(Y)^T = L
-    if (xc & SIG_TRANS) mma_lp<T, true, true>(acc, LX, LY, r0, c0, lane);
-    else mma_lp<T, false, true>(acc, LX, LY, r0, c0, lane);
-  }
 }
 
 // SWE: W_t (+)= sum over pairs of Sig~ L, kept in the Sigma tile of t until
@@ -1013,98 +1128,135 @@ __device__ __attribute__((noinline)) void task_swe(const ExecMat& M, const int32
   constexpr int TT = T * T, W = T / 2, NB = T / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
-  double* out = M.sigma + (int64_t)w[1] * TT;
+  double* out = M.sigma + (int64_t)__builtin_amdgcn_readfirstlane(w[1]) * TT;
+  const int np = __builtin_amdgcn_readfirstlane(w[3]);
+  const int pv = load_words(M.pairs + __builtin_amdgcn_readfirstlane(w[2]), 2 * np);
   v4d acc[NB][NB];
   zero_acc<T>(acc);
   if (w[0] & TF_ACC) add_tile<T>(acc, out, r0, c0, lane);
-  sig_products<T>(acc, M, M.pairs + w[2], __builtin_amdgcn_readfirstlane(w[3]), LX, LY, r0, c0, lane);
-  put_acc<T>(acc, out, T, 1.0, r0, c0, lane);
+  sig_products<T>(acc, M, pv, np, LX, LY, r0, c0, lane);
+  put_acc_g<T>(acc, out, 1.0, r0, c0, lane);
 }
 
-// SW: Sig_t = -(W + products + pushed partials) Linv_k, then
-// D_t = L_t^T Sig_t and, for every listed tile u = (r,c), Q_u = Sig_t^T L_u
+// Static operands of a selected-inversion task (the factor is final), staged
+// before the task waits for its predecessors: the L tile of SW's first
+// product into LY, the inverse diagonal tile of SDIAG into LX.
+template <int T>
+__device__ __forceinline__ void selinv_prefetch(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
+  constexpr int TT = T * T;
+  const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
+  PadStage<T> st;
+  if (type == TK_SW) {
+    const int32_t* lst = M.pairs + __builtin_amdgcn_readfirstlane(w[3]);
+    st.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(lst[1]) * TT);
+    st.store(LY);
+  } else if (type == TK_SDIAG) {
+    st.load(M.linv + (int64_t)__builtin_amdgcn_readfirstlane(w[2]) * TT);
+    st.store(LX);
+  }
+}
+
+// SW: Sig_t = -(W + pushed partials + sum of its one or two products Sig~ L_y)
+// Linv_k, then D_t = L_t^T Sig_t and, for every listed tile u = (r,c),
+// Q_u = Sig_t^T L_u.  The first product's L_y was staged in LY by
+// selinv_prefetch.  w4 = nsum | npush << 8 | nprod << 16; the list holds the
+// product pairs, then the slots, then the push tiles (at most 64 words).
 template <int T>
 __device__ __attribute__((noinline)) void task_sw(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
   constexpr int TT = T * T, W = T / 2, NB = T / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
-  const int32_t* lst = M.pairs + __builtin_amdgcn_readfirstlane(w[3]);
-  const int nprod = __builtin_amdgcn_readfirstlane(lst[0]);
-  const int nsum = __builtin_amdgcn_readfirstlane(lst[1]);
-  const int npush = __builtin_amdgcn_readfirstlane(lst[2]);
-  const int32_t* prod = lst + 3;
-  const int32_t* sums = prod + 2 * nprod;
-  const int32_t* push = sums + nsum;
+  const int cnt = __builtin_amdgcn_readfirstlane(w[4]);
+  const int nsum = cnt & 0xff, npush = (cnt >> 8) & 0xff, nprod = cnt >> 16;
+  const int pv = load_words(M.pairs + __builtin_amdgcn_readfirstlane(w[3]), 2 * nprod + nsum + npush);
+  const int sw0 = 2 * nprod, pw0 = 2 * nprod + nsum;   // first slot word, first push word
   const int64_t t = __builtin_amdgcn_readfirstlane(w[1]);
   const int64_t k = __builtin_amdgcn_readfirstlane(w[2]);
   double* sig = M.sigma + t * TT;
+  PadStage<T> sx, sy, st;
+  sx.load(M.sigma + (int64_t)(word(pv, 0) & ~SIG_TRANS) * TT);
+  if (nprod > 1) {
+    sy.load(M.tiles + (int64_t)word(pv, 3) * TT);
+    st.load(M.sigma + (int64_t)(word(pv, 2) & ~SIG_TRANS) * TT);
+  } else {
+    st.load(M.linv + k * TT);
+  }
   v4d acc[NB][NB];
   zero_acc<T>(acc);
   if (w[0] & TF_ACC) add_tile<T>(acc, sig, r0, c0, lane);
-  for (int q = 0; q < nsum; q++)
-    add_tile<T>(acc, M.qpart + (int64_t)__builtin_amdgcn_readfirstlane(sums[q]) * TT, r0, c0, lane);
-  sig_products<T>(acc, M, prod, nprod, LX, LY, r0, c0, lane);
-  // Sig_t = -W Linv_k  (op(X) = W, op(Y)^T = Linv_k)
-  PadStage<T> st;
-  st.load(M.linv + k * TT);
+  for (int q = 0; q < nsum; q++) add_tile<T>(acc, M.qpart + (int64_t)word(pv, sw0 + q) * TT, r0, c0, lane);
+  sx.store(LX);
   __syncthreads();
-  put_acc<T>(acc, LX, T + 2, 1.0, r0, c0, lane);
+  // W += Sig~ L_y  (op(X) = Sig or Sig^T, op(Y)^T = L_y)
+  sig_pair_mma<T>(acc, word(pv, 0), LX, LY, r0, c0, lane);
+  if (nprod > 1) {
+    __syncthreads();
+    st.store(LX);
+    sy.store(LY);
+    __syncthreads();
+    st.load(M.linv + k * TT);
+    sig_pair_mma<T>(acc, word(pv, 2), LX, LY, r0, c0, lane);
+  }
+  // Sig_t = -W Linv_k  (op(X) = W, op(Y)^T = Linv_k)
+  __syncthreads();
+  put_acc_l<T>(acc, LX, 1.0, r0, c0, lane);
   st.store(LY);
   __syncthreads();
   st.load(M.tiles + t * TT);
   zero_acc<T>(acc);
   mma_lp<T, false, true>(acc, LX, LY, r0, c0, lane);
-  put_acc<T>(acc, sig, T, -1.0, r0, c0, lane);
+  put_acc_g<T>(acc, sig, -1.0, r0, c0, lane);
   __syncthreads();
-  put_acc<T>(acc, LX, T + 2, -1.0, r0, c0, lane);   // LX = Sig_t
-  st.store(LY);                                      // LY = L_t
+  put_acc_l<T>(acc, LX, -1.0, r0, c0, lane);   // LX = Sig_t
+  st.store(LY);                                // LY = L_t
   __syncthreads();
-  if (npush > 0) st.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(push[0]) * TT);
+  if (npush > 0) st.load(M.tiles + (int64_t)word(pv, pw0) * TT);
   // D_t = L_t^T Sig_t  (op(X) = L_t^T, op(Y)^T = Sig_t)
   zero_acc<T>(acc);
   mma_lp<T, true, true>(acc, LY, LX, r0, c0, lane);
-  put_acc<T>(acc, M.dpart + t * TT, T, 1.0, r0, c0, lane);
+  put_acc_g<T>(acc, M.dpart + t * TT, 1.0, r0, c0, lane);
   for (int q = 0; q < npush; q++) {
-    const int64_t u = __builtin_amdgcn_readfirstlane(push[q]);
+    const int64_t u = word(pv, pw0 + q);
     __syncthreads();
-    st.store(LY);                                    // LY = L_u
+    st.store(LY);                              // LY = L_u
     __syncthreads();
-    if (q + 1 < npush) st.load(M.tiles + (int64_t)__builtin_amdgcn_readfirstlane(push[q + 1]) * TT);
+    if (q + 1 < npush) st.load(M.tiles + (int64_t)word(pv, pw0 + q + 1) * TT);
     // Q_u = Sig_t^T L_u  (op(X) = Sig_t^T, op(Y)^T = L_u)
     zero_acc<T>(acc);
     mma_lp<T, true, true>(acc, LX, LY, r0, c0, lane);
-    put_acc<T>(acc, M.qpart + u * TT, T, 1.0, r0, c0, lane);
+    put_acc_g<T>(acc, M.qpart + u * TT, 1.0, r0, c0, lane);
   }
 }
 
-// SDIAG: Sig_kk = Linv_k^T (Linv_k - sum_r D_(r,k)), the D in list order;
-// the lower triangle is kept and mirrored, so the stored tile is symmetric
+// SDIAG: Sig_kk = Linv_k^T (Linv_k - sum_r D_(r,k)), the D in list order
+// (w4 = count, at most 64); the lower triangle is kept and mirrored, so the
+// stored tile is symmetric.  Linv_k was staged in LX by selinv_prefetch.
 template <int T>
 __device__ __attribute__((noinline)) void task_sdiag(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
-  constexpr int TT = T * T, W = T / 2, NB = T / 32;
+  constexpr int TT = T * T, W = T / 2, NB = T / 32, LP = T + 2;
   typedef double d2 __attribute__((ext_vector_type(2)));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
-  const int32_t* lst = M.pairs + __builtin_amdgcn_readfirstlane(w[3]);
-  const int nd = __builtin_amdgcn_readfirstlane(lst[0]);
-  const int64_t k = __builtin_amdgcn_readfirstlane(w[2]);
-  PadStage<T> li, z;
-  li.load(M.linv + k * TT);
+  const int nd = __builtin_amdgcn_readfirstlane(w[4]);
+  const int pv = load_words(M.pairs + __builtin_amdgcn_readfirstlane(w[3]), nd);
+  PadStage<T> z;
 #pragma unroll
-  for (int v = 0; v < PadStage<T>::NV; v++) z.r[v] = li.r[v];
+  for (int v = 0; v < PadStage<T>::NV; v++) {
+    const int e = 2 * ((int)threadIdx.x + v * NT);
+    z.r[v] = *reinterpret_cast<const d2*>(LX + (e % T) + (e / T) * LP);
+  }
   for (int q = 0; q < nd; q++) {
-    const d2* dp = reinterpret_cast<const d2*>(M.dpart + (int64_t)__builtin_amdgcn_readfirstlane(lst[1 + q]) * TT);
+    const GLOBAL d2* dp = (const GLOBAL d2*)(M.dpart + (int64_t)word(pv, q) * TT);
 #pragma unroll
     for (int v = 0; v < PadStage<T>::NV; v++) z.r[v] -= dp[threadIdx.x + v * NT];
   }
-  li.store(LX);
   z.store(LY);
   __syncthreads();
   v4d acc[NB][NB];
   zero_acc<T>(acc);
   // op(X) = Linv_k^T, op(Y)^T = Z
   mma_lp<T, true, true>(acc, LX, LY, r0, c0, lane);
-  double* out = M.sigma + (int64_t)__builtin_amdgcn_readfirstlane(w[1]) * TT;
+  GLOBAL double* out = gp(M.sigma + (int64_t)__builtin_amdgcn_readfirstlane(w[1]) * TT);
 #pragma unroll
   for (int i = 0; i < NB; i++)
 #pragma unroll
@@ -1113,10 +1265,58 @@ __device__ __attribute__((noinline)) void task_sdiag(const ExecMat& M, const int
       for (int r = 0; r < 4; r++) {
         const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
         if (row >= col) {
-          out[row + col * T] = acc[i][j][r];
-          out[col + row * T] = acc[i][j][r];
+          st_dev(out + row + col * T, acc[i][j][r]);
+          st_dev(out + col + row * T, acc[i][j][r]);
         }
       }
+}
+
+// TSUM: slot w1 = sum of the listed slots of dpart (c = 0) or qpart (c = 1),
+// in list order; four running sums keep four loads in flight
+template <int T>
+__device__ __attribute__((noinline)) void task_tsum(const ExecMat& M, const int32_t* w) {
+  constexpr int TT = T * T;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const double* base = __builtin_amdgcn_readfirstlane(w[4]) == 1 ? M.qpart : M.dpart;
+  const int32_t* lst = M.pairs + __builtin_amdgcn_readfirstlane(w[2]);
+  const int n = __builtin_amdgcn_readfirstlane(w[3]);
+  GLOBAL d2* out = (GLOBAL d2*)(base + (int64_t)__builtin_amdgcn_readfirstlane(w[1]) * TT);
+  constexpr int NV = TT / 2 / NT;
+  d2 s0[NV], s1[NV], s2[NV], s3[NV];
+#pragma unroll
+  for (int v = 0; v < NV; v++) s0[v] = s1[v] = s2[v] = s3[v] = d2{0.0, 0.0};
+  auto slot = [&](int id) { return (const GLOBAL d2*)(base + (int64_t)id * TT); };
+  for (int blk = 0; blk < n; blk += 64) {   // 64 slot words per load
+    const int nb = n - blk < 64 ? n - blk : 64;
+    const int pv = load_words(lst + blk, nb);
+    int q = 0;
+    for (; q + 4 <= nb; q += 4) {
+      const GLOBAL d2* a = slot(word(pv, q));
+      const GLOBAL d2* b = slot(word(pv, q + 1));
+      const GLOBAL d2* c = slot(word(pv, q + 2));
+      const GLOBAL d2* d = slot(word(pv, q + 3));
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        const int e = threadIdx.x + v * NT;
+        s0[v] += a[e];
+        s1[v] += b[e];
+        s2[v] += c[e];
+        s3[v] += d[e];
+      }
+    }
+    for (; q < nb; q++) {
+      const GLOBAL d2* a = slot(word(pv, q));
+#pragma unroll
+      for (int v = 0; v < NV; v++) s0[v] += a[threadIdx.x + v * NT];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; v++) {
+    const d2 t = (s0[v] + s1[v]) + (s2[v] + s3[v]);
+    GLOBAL double* o = (GLOBAL double*)(out + threadIdx.x + v * NT);
+    st_dev(o, t.x);
+    st_dev(o + 1, t.y);
+  }
 }
 
 // ---------------------------------------------------------------- executor
@@ -1154,6 +1354,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     uint64_t t_claim = 0, t_start = 0;
     if (M.trace) t_claim = wall_clock64();
     if constexpr (SOLVE) solve_prefetch<T>(M, w, S, LI);
+    if constexpr (SELINV) selinv_prefetch<T>(M, w, S, Xi);
     // wait until every predecessor has finished (Alg. 2 progress check);
     // wave 0 polls, then acquires for the workgroup (all its waves share
     // the CU's caches that the acquire invalidates)
@@ -1175,7 +1376,8 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     if constexpr (SELINV) {
       if (type == TK_SWE) task_swe<T>(M, w, S, Xi);
       else if (type == TK_SW) task_sw<T>(M, w, S, Xi);
-      else task_sdiag<T>(M, w, S, Xi);
+      else if (type == TK_SDIAG) task_sdiag<T>(M, w, S, Xi);
+      else task_tsum<T>(M, w);
     } else if constexpr (SOLVE) {
       if (type == TK_FSUM) task_fsum<T>(M, w, nrhs);
       else task_solve<T>(M, w, nrhs, S, Xi, LI);
@@ -1192,11 +1394,13 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       }
     }
     if (chain) __builtin_amdgcn_s_setprio(0);
-    // every wave waits for its own stores, then wave 0 releases for the
-    // workgroup and notifies the successors (Alg. 2 progress update)
+    // every wave waits for its own stores (device-scope stores, coherent
+    // once complete), then wave 0 notifies the successors (Alg. 2 progress
+    // update); the workgroup-scope release only orders the notification
+    // after the stores in the compiler
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x < 64) fence_release();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     const int32_t s0 = __builtin_amdgcn_readfirstlane(w[5]), s1 = __builtin_amdgcn_readfirstlane(w[6]);
     for (int32_t q0 = s0; q0 < s1; q0 += 64) {
       const int32_t q = q0 + (int32_t)threadIdx.x;

@@ -35,6 +35,7 @@ enum TaskType : int32_t {
   TK_SWE = 16,   // W_(r,k) [+]= sum_s Sig~_(r,s) L_(s,k), s in S(k) \ {p}  (r != p)
   TK_SW = 17,    // Sig_(r,k) = -(W + products + pushed partials) Linv_k; D, pushes
   TK_SDIAG = 18, // Sig_kk = Linv_k^T (Linv_k - sum_r D_(r,k))
+  TK_TSUM = 19,  // a per-tile partial slot = sum of listed slots (off the chain)
 };
 
 enum TaskFlag : int32_t {
@@ -58,10 +59,13 @@ enum TaskFlag : int32_t {
 // SWE:   w1 = target tile, a = offset of its pairs in the list array, b = pair
 //        count; TF_ACC adds to the target (a later chunk).  A pair is
 //        (Sigma tile | SIG_TRANS if used transposed, L tile).
-// SW:    w1 = target tile (r,k), a = k, b = list offset: [nprod, nsum, npush,
-//        nprod pairs as in SWE, nsum pushed-partial slots, npush L tiles];
-//        TF_ACC: the target holds an early sum W to add.
-// SDIAG: w1 = diagonal tile of k, a = k, b = list offset: [nD, nD slots]
+// SW:    w1 = target tile (r,k), a = k, b = list offset, c = nsum | npush << 8
+//        | nprod << 16; list: nprod (1 or 2) pairs as in SWE, nsum pushed-
+//        partial slots, npush L tiles (at most 64 words); TF_ACC: the target
+//        holds an early sum W to add.
+// SDIAG: w1 = diagonal tile of k, a = k, b = list offset, c = count of D slots
+// TSUM:  w1 = output slot, a = list offset, b = count, c = 0: D slots (dpart),
+//        1: pushed-partial slots (qpart); summed in list order
 constexpr int TASK_WORDS = 8;
 constexpr int32_t SIG_TRANS = 1 << 30;
 

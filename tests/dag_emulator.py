@@ -13,7 +13,7 @@ import paper_2501_02483_amd as S
 
 UPD, PART, TREE, POTRF, TRSM = 1, 2, 3, 4, 5
 FUPD, FDIAG, BUPD, BDIAG, FPART, FSUM = 8, 9, 10, 11, 12, 13
-SWE, SW, SDIAG = 16, 17, 18
+SWE, SW, SDIAG, TSUM = 16, 17, 18, 19
 TF_DIAG, TF_FIRST, TF_ACC = 1 << 8, 1 << 9, 1 << 10
 SIG_TRANS = 1 << 30
 
@@ -216,10 +216,10 @@ def selinv(plan, tiles, linv, mode="ticket", seed=0):
             sigma[w[1]] = sigma[w[1]] + acc if w[0] & TF_ACC else acc
         elif typ == SW:
             o = w[3]
-            nprod, nsum, npush = lst[o:o + 3]
-            prod = lst[o + 3:o + 3 + 2 * nprod]
-            sums = lst[o + 3 + 2 * nprod:o + 3 + 2 * nprod + nsum]
-            push = lst[o + 3 + 2 * nprod + nsum:o + 3 + 2 * nprod + nsum + npush]
+            nsum, npush, nprod = w[4] & 0xff, (w[4] >> 8) & 0xff, w[4] >> 16
+            prod = lst[o:o + 2 * nprod]
+            sums = lst[o + 2 * nprod:o + 2 * nprod + nsum]
+            push = lst[o + 2 * nprod + nsum:o + 2 * nprod + nsum + npush]
             W = sigma[w[1]].copy() if w[0] & TF_ACC else np.zeros_like(tiles[0])
             for q in sums:
                 W += qpart.pop(q)
@@ -231,10 +231,17 @@ def selinv(plan, tiles, linv, mode="ticket", seed=0):
             for u in push:
                 assert u not in qpart
                 qpart[u] = Sg.T @ tiles[u]
+        elif typ == TSUM:
+            src = qpart if w[4] == 1 else dpart
+            acc = np.zeros_like(tiles[0])
+            for q in lst[w[2]:w[2] + w[3]]:
+                acc += src.pop(q)
+            assert w[1] not in src
+            src[w[1]] = acc
         elif typ == SDIAG:
             o = w[3]
             Z = linv[w[2]].copy()
-            for q in lst[o + 1:o + 1 + lst[o]]:
+            for q in lst[o:o + w[4]]:
                 Z -= dpart.pop(q)
             R = linv[w[2]].T @ Z
             sigma[w[1]] = np.tril(R) + np.tril(R, -1).T
