@@ -14,7 +14,9 @@ step time; the roofline object reports the factorization kernel alone.
 
 Other workloads (--workload): small (n=2,000, w=50, a=10, tile 64, 1 RHS),
 batch (512 uneven matrices in one launch), mixed (n=500,000, w=1,000,
-a=200, FP32 updates + FP64 refinement, 16 RHS).
+a=200, FP32 updates + FP64 refinement, 16 RHS), selinv (selected inversion
+of the variable-bandwidth matrix's factor: A^{-1} on the tile pattern of L
+and its diagonal; F = sum_j 2 eta_j (eta_j + 1)).
 """
 import argparse
 import json
@@ -211,6 +213,92 @@ def bench_single(args):
     if not args.no_cpu_baseline:
         cb, _ = cpu_baseline_single(p, vals, B)
         res["cpu_baseline"] = cb
+    return res
+
+
+def bench_selinv(args):
+    """Selected inversion on the variable-bandwidth workload: the factor is
+    computed once (untimed); a step is one selected inversion (Sigma = A^{-1}
+    on the stored tiles of L) plus the diagonal of A^{-1} in the original
+    ordering."""
+    import torch
+
+    import paper_2501_02483_amd as S
+    from paper_2501_02483_amd import inputs as I
+
+    p, seed = I.variable_band(), 2
+    vals = I.make_values(p, seed=seed)
+    ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
+    sym = S.Symbolic.from_pattern(p, tile=args.tile, tree_min_ratio=args.tree_ratio, ordering=ordering,
+                                  nd_parts=args.parts)
+    fac = S.Factor(sym, S.STILES_FP64)
+    fac.factorize(torch.from_numpy(vals).cuda())
+    assert fac.info() == 0
+    ntasks, F, Fexec = S.stiles_selinv_query(sym.handle)
+    si = S.SelInv(fac)
+    diag = torch.empty(p.N, dtype=torch.float64, device="cuda")
+
+    def step():
+        si.compute()
+        si.diag(diag)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    si.set_timing(True)
+    kms = []
+    for _ in range(args.steps):
+        step()
+        kms.append(si.kernel_ms())
+    si.set_timing(False)
+    kernel_ms = float(np.mean(kms))
+    achieved = F / (kernel_ms * 1e-3) / 1e12
+    res = {
+        "metric": "selected inversion TFLOP/s (A^{-1} on the factor pattern + its diagonal)",
+        "value": F / (ms * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": p.name, "n": p.n, "arrow": p.a, "N": p.N, "tile": args.tile,
+                   "ordering": {1: "none", 3: "adaptable_nd"}.get(sym.info.ordering_used, "other"),
+                   "nd_parts": sym.info.nd_parts, "value_seed": seed, "ops": "selected inversion + diagonal",
+                   "parallelism": "single GPU, persistent DAG executor"},
+        "flops_alg": F,
+        "flops_exec": Fexec,
+        "tasks": ntasks,
+        "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,2> (selected-inversion DAG)" % args.tile,
+                     "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
+                     "traffic": None, "kernel_ms": kernel_ms, "bytes_alg": 16 * p.nnz},
+    }
+    order_key = "nd%d" % sym.info.nd_parts if sym.info.nd_parts > 1 else "none"
+    tr = measured_traffic("selinv_varband_n%d_a%d_%s" % (p.n, p.a, order_key), args.tile)
+    if tr is not None:
+        res["roofline"]["traffic"] = tr["bytes"]
+        res["roofline"]["traffic_detail"] = tr
+    if not args.no_cpu_baseline:
+        import oracle
+        nt = cpu_threads()
+        L, info = oracle.factor(p.f, vals, nthreads=nt)
+        t2 = time.perf_counter()
+        Sg = oracle.selinv(p.f, L, nthreads=nt)
+        t3 = time.perf_counter()
+        del Sg
+        res["cpu_baseline"] = {"value": F / (t3 - t2) / 1e12, "unit": "TFLOP/s", "cores": nt, "kind": "oracle",
+                               "sample": "the full workload, one selected inversion of the oracle's factor "
+                                         "(%.2f s with %d threads; the factorization is not counted)" % (t3 - t2, nt)}
     return res
 
 
@@ -431,7 +519,7 @@ def main():
     ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
                     help="single-matrix workloads: natural order or adaptable nested dissection")
     ap.add_argument("--parts", type=int, default=0, help="adaptable ND partitions (0 = chosen by the analysis)")
-    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal"])
+    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal", "selinv"])
     ap.add_argument("--rocpd-summary", default="", help="print a per-kernel table of a rocprofv3 database and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count", type=int, default=512, help="batch: number of matrices")
@@ -461,6 +549,8 @@ def main():
         res = bench_mixed(args)
     elif args.workload == "copycal":
         res = bench_copycal(args)
+    elif args.workload == "selinv":
+        res = bench_selinv(args)
     else:
         res = bench_serve(args)
     print(json.dumps(res), flush=True)

@@ -58,6 +58,39 @@ def test_varband_full_size(varband, ordering, parts):
         assert eL <= TOL
 
 
+@pytest.fixture(scope="module")
+def varband_selinv(varband):
+    p, vals, B, L, ldref, Xref = varband
+    say("[gpu fullsize] oracle selected inversion (N=%d)" % p.N)
+    return oracle.selinv(p.f, L, nthreads=_threads())
+
+
+@pytest.mark.parametrize("ordering", [S.STILES_ORDER_NONE, S.STILES_ORDER_ADAPTABLE_ND], ids=["natural", "nd"])
+def test_varband_selinv_full_size(varband, varband_selinv, ordering):
+    """Selected inversion at the benchmarked size: the diagonal of A^{-1}
+    (original ordering) against the oracle's Takahashi recursion, entry by
+    entry; under the natural ordering every envelope entry as well."""
+    import torch
+    p, vals = varband[0], varband[1]
+    Sref = varband_selinv
+    rp = p.row_ptr()
+    dref = Sref[rp[1:] - 1]
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=ordering)
+    say("[gpu fullsize] selinv ordering=%d parts=%d" % (ordering, sym.info.nd_parts))
+    fac = S.Factor(sym)
+    fac.factorize(torch.from_numpy(vals).cuda())
+    assert fac.info() == 0
+    si = S.SelInv(fac).compute()
+    d = si.diag().cpu().numpy()
+    ed = float(np.max(np.abs(d - dref) / dref))
+    say("   diagonal error %.2e" % ed)
+    assert ed <= TOL
+    if ordering == S.STILES_ORDER_NONE:
+        e = rel(si.extract().cpu().numpy(), Sref)
+        say("   entries error %.2e" % e)
+        assert e <= TOL
+
+
 def test_batch512_full_size():
     """All 512 matrices of the batched workload (device-generated values,
     read back for the oracle): every log-determinant within 1e-12."""
