@@ -547,15 +547,18 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
   double* C = M.tiles + (int64_t)w[1] * TT;
   const int k = w[2];
   {
-    TileStage<T, double> st;
+    // C and the fused operand X = L_(k,k-1) are loaded together
+    const bool fused = w[4] > w[3];
+    const int64_t xt = fused ? __builtin_amdgcn_readfirstlane(M.pairs[2 * w[3]]) : 0;
+    TileStage<T, double> st, sx;
     st.load(C);
+    if (fused) sx.load(M.tiles + xt * TT);
     st.store(S);
-    if (w[4] > w[3]) {
-      // fused update with column k-1: C_kk -= X X^T (X = L_(k,k-1))
+    if (fused) {
+      // fused update with column k-1: C_kk -= X X^T
       constexpr int W = T / 2, NB = T / 32;
       const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
-      st.load(M.tiles + (int64_t)M.pairs[2 * w[3]] * TT);
-      st.store(Xi);
+      sx.store(Xi);
       __syncthreads();
       v4d acc[NB][NB];
 #pragma unroll
@@ -578,11 +581,12 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
   for (int e = tid; e < TT; e += NT) Xi[e] = 0.0;
   __syncthreads();
   int fail = -1;
+  double* pcol = S + (T - 16) * T;   // upper block (0, T/16 - 1), unused by the factorization
+  if (tid < 64) diag_block16<T>(S, Xi, rinv, pcol, 0, lane, fail);
 #pragma unroll 1
   for (int b = 0; b < NBK; b++) {
     const int c0 = 16 * b;
-    if (tid < 64) diag_block16<T>(S, Xi, rinv, S + (T - 16) * T, c0, lane, fail);
-    __syncthreads();
+    __syncthreads();   // diagonal block b factored, trailing updates of step b-1 done
     // ---- row block b of the inverse, X(b, q) for q < b, on the waves that
     //      the panel below leaves idle (every input is final by now)
     {
@@ -612,9 +616,13 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
         for (int q = 0; q < 4; q++) S[(rb + (lane >> 4) + 4 * q) + (c0 + (lane & 15)) * T] = acc[q];
       }
       __syncthreads();
-      // ---- trailing update A22 -= P P^T over lower 16 x 16 blocks (MFMA)
+      // ---- trailing update A22 -= P P^T over lower 16 x 16 blocks (MFMA).
+      //      Lookahead: wave 0 updates the next diagonal block (block 0 of
+      //      the trailing matrix) and factors it at once; waves 1..3 update
+      //      the other blocks meanwhile (disjoint LDS regions)
       const int nb2 = nrb * (nrb + 1) / 2;
-      for (int q = wave; q < nb2; q += NT / 64) {
+      const int q0 = wave, qstep = wave == 0 ? nb2 : NT / 64 - 1;
+      for (int q = q0; q < nb2; q += qstep) {
         int bi = 0, rem = q;
         while (rem > bi) { rem -= bi + 1; bi++; }
         const int bj = rem;   // bj <= bi
@@ -629,7 +637,10 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) S[(gi + (lane >> 4) + 4 * rr) + (gj + (lane & 15)) * T] -= u[rr];
       }
-      __syncthreads();
+      if (tid < 64) {
+        __builtin_amdgcn_wave_barrier();
+        diag_block16<T>(S, Xi, rinv, pcol, c0 + 16, lane, fail);
+      }
     }
   }
   if (tid == 0 && fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
