@@ -1482,6 +1482,22 @@ hipError_t launch_selinv_diag(int T, const double* sigma, const int32_t* trow_pt
 
 // ------------------------------------------------------------ value scatter
 
+// column-major T x T tile out (and o2) from the row-major LDS buffer
+// (leading dimension T + 1): two rows per 16-byte streaming store
+template <int T>
+__device__ __forceinline__ void store_tile_cm(const double* buf, double* out, double* o2) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  constexpr int TT = T * T;
+  GLOBAL d2* go = (GLOBAL d2*)out;
+  GLOBAL d2* g2 = o2 ? (GLOBAL d2*)o2 : nullptr;
+  for (int e2 = threadIdx.x; e2 < TT / 2; e2 += NT) {
+    const int e = 2 * e2, c = e / T, r = e % T;
+    const d2 v = d2{buf[r * (T + 1) + c], buf[(r + 1) * (T + 1) + c]};
+    __builtin_nontemporal_store(v, go + e2);
+    if (g2) __builtin_nontemporal_store(v, g2 + e2);
+  }
+}
+
 // One T x T tile of the store from row-profile values: staged through LDS so
 // that the reads follow the input rows and the stores the column-major tile.
 // The first column and start offset of each of the tile's rows are read once
@@ -1507,19 +1523,14 @@ __device__ __forceinline__ void scatter_tile(const double* __restrict__ vals, co
     if (r < rc) {
       const int64_t i = rb + r, g = cb + c;
       const int64_t fi = sf[r];
-      if (c < cc && g <= i && g >= fi) v = vals[sp[r] + (g - fi)];
+      if (c < cc && g <= i && g >= fi) v = gp(vals)[sp[r] + (g - fi)];
     } else if (m == j && r == c) {
       v = 1.0;   // padding row: unit diagonal
     }
     buf[r * (T + 1) + c] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TT; e += NT) {
-    const int c = e / T, r = e % T;   // column-major store
-    const double v = buf[r * (T + 1) + c];
-    out[e] = v;
-    if (o2) o2[e] = v;
-  }
+  store_tile_cm<T>(buf, out, o2);
 }
 
 template <int T>
@@ -1586,7 +1597,7 @@ __device__ __forceinline__ void scatter_tile_perm(const double* __restrict__ val
         const int64_t lo = rowi ? oj : oi;
         const int64_t fh = rowi ? fr[r] : fc[c];
         const int64_t base = rowi ? sr[r] : sc[c];
-        if (lo >= fh) v = vals[base + (lo - fh)];
+        if (lo >= fh) v = gp(vals)[base + (lo - fh)];
       }
     } else if (m == j && r == c) {
       v = 1.0;   // padding row: unit diagonal
@@ -1594,12 +1605,7 @@ __device__ __forceinline__ void scatter_tile_perm(const double* __restrict__ val
     buf[r * (T + 1) + c] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TT; e += NT) {
-    const int c = e / T, r = e % T;   // column-major store
-    const double v = buf[r * (T + 1) + c];
-    out[e] = v;
-    if (o2) o2[e] = v;
-  }
+  store_tile_cm<T>(buf, out, o2);
 }
 
 template <int T>
