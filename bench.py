@@ -200,7 +200,7 @@ def bench_single(args):
         "flops_alg": F,
         "flops_exec": sym.info.flops_exec,
         "info": info,
-        "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,false> (factorization DAG)" % args.tile,
+        "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,0> (factorization DAG)" % args.tile,
                      "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
                      "traffic": None, "kernel_ms": kernel_ms, "bytes_alg": 16 * p.nnz},
     }
@@ -358,7 +358,7 @@ def bench_batch(args):
             "factorizations_per_s": len(pats) * 1e3 / ms, "flops_alg": F,
             "failed": int(sum(1 for i in infos if i != 0)),
             "logdet_finite": bool(torch.isfinite(lds).all().item()),
-            "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,false> (batched factorization DAG)" % T,
+            "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,0> (batched factorization DAG)" % T,
                          "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
                          "traffic": None, "kernel_ms": kernel_ms}}
 
