@@ -14,7 +14,8 @@ step time; the roofline object reports the factorization kernel alone.
 
 Other workloads (--workload): small (n=2,000, w=50, a=10, tile 64, 1 RHS),
 batch (512 uneven matrices in one launch), mixed (n=500,000, w=1,000,
-a=200, FP32 updates + FP64 refinement, 16 RHS), selinv (selected inversion
+a=200, FP32 updates + FP64 refinement, 16 RHS), spde (spatio-temporal CSC
+input: 40 x 40 grid x 60 time steps, arrow 50), selinv (selected inversion
 of the variable-bandwidth matrix's factor: A^{-1} on the tile pattern of L
 and its diagonal; F = sum_j 2 eta_j (eta_j + 1)).
 """
@@ -302,6 +303,82 @@ def bench_selinv(args):
     return res
 
 
+def bench_spde(args):
+    """Spatio-temporal (SPDE-shaped) CSC input: 40 x 40 grid, 60 time steps,
+    arrow 50 (n = 96,000); a step = scatter through the value map +
+    factorization + 8-RHS solve + logdet."""
+    import torch
+
+    import paper_2501_02483_amd as S
+    from paper_2501_02483_amd import inputs as I
+
+    nx, ny, nt, a = 40, 40, 60, 50
+    g = I.spde_space_time(nx, ny, nt, a, seed=6)
+    ordering = {"none": S.STILES_ORDER_AUTO, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
+    sym = S.Symbolic.from_csc(g["N"], g["a"], g["colptr"], g["rowind"], tile=args.tile, ordering=ordering,
+                              nd_parts=args.parts)
+    fac = S.Factor(sym, S.STILES_FP64, nrhs_max=8)
+    dv = torch.from_numpy(g["values"]).cuda()
+    B = I.rhs(g["N"], 8, seed=106)
+    dB0 = to_device_cols(B)
+    work = to_device_cols(B)
+    ld = torch.empty(1, dtype=torch.float64, device="cuda")
+    F = sym.info.flops_alg
+
+    def step():
+        fac.factorize(dv)
+        work.copy_(dB0)
+        fac.solve(work)
+        fac.logdet(ld)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert fac.info() == 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    S.stiles_factor_set_timing(fac.handle, True)
+    kms = []
+    for _ in range(args.steps):
+        step()
+        kms.append(S.stiles_factor_kernel_ms(fac.handle, 0))
+    S.stiles_factor_set_timing(fac.handle, False)
+    kernel_ms = float(np.mean(kms))
+    achieved = F / (kernel_ms * 1e-3) / 1e12
+    res = {
+        "metric": "arrowhead Cholesky TFLOP/s (factorize+solve+logdet step, CSC input)",
+        "value": F / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": g["pattern"].name, "n": g["n"], "arrow": a, "N": g["N"], "nnz_lower": int(len(g["rowind"])),
+                   "nnz_envelope": int(g["pattern"].nnz), "tile": args.tile,
+                   "ordering": {1: "none", 2: "partial_rcm", 3: "adaptable_nd"}.get(sym.info.ordering_used, "other"),
+                   "nd_parts": sym.info.nd_parts, "value_seed": 6, "rhs_seed": 106,
+                   "ops": "factorize+solve+logdet", "parallelism": "single GPU, persistent DAG executor"},
+        "flops_alg": F, "flops_exec": sym.info.flops_exec,
+        "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,0> (factorization DAG)" % args.tile,
+                     "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
+                     "traffic": None, "kernel_ms": kernel_ms},
+    }
+    if not args.no_cpu_baseline:
+        # bounded sample: the same generator with 10 time steps (n = 16,000)
+        import oracle
+        gs = I.spde_space_time(nx, ny, 10, a, seed=6)
+        ps = gs["pattern"]
+        nthr = cpu_threads()
+        t2 = time.perf_counter()
+        L, info = oracle.factor(ps.f, gs["profile_values"], nthreads=nthr)
+        t3 = time.perf_counter()
+        res["cpu_baseline"] = {"value": flops_alg(ps.f) / (t3 - t2) / 1e12, "unit": "TFLOP/s", "cores": nthr,
+                               "kind": "oracle", "sample": "factorization of the same generator with 10 time steps "
+                               "(n = 16,000; %.2f s with %d threads)" % (t3 - t2, nthr)}
+    return res
+
+
 def bench_batch(args):
     """512 uneven matrices in one persistent launch; tile size by the autotuner."""
     import torch
@@ -519,7 +596,7 @@ def main():
     ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
                     help="single-matrix workloads: natural order or adaptable nested dissection")
     ap.add_argument("--parts", type=int, default=0, help="adaptable ND partitions (0 = chosen by the analysis)")
-    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal", "selinv"])
+    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal", "selinv", "spde"])
     ap.add_argument("--rocpd-summary", default="", help="print a per-kernel table of a rocprofv3 database and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count", type=int, default=512, help="batch: number of matrices")
@@ -551,6 +628,8 @@ def main():
         res = bench_copycal(args)
     elif args.workload == "selinv":
         res = bench_selinv(args)
+    elif args.workload == "spde":
+        res = bench_spde(args)
     else:
         res = bench_serve(args)
     print(json.dumps(res), flush=True)

@@ -210,6 +210,64 @@ def serving_requests(npat, count, qps, seed=55, value_seed0=5000):
     return [(float(t[i]), int(pats[i]), int(ops[i]), value_seed0 + i) for i in range(count)]
 
 
+def spde_space_time(nx, ny, nt, a, seed, name=""):
+    """Sparse-inside-the-envelope input shaped like the spatio-temporal
+    precision matrices INLA factors (Section I): nodes (t, y, x) in time-major,
+    then row-major order; node i couples to the nodes of its own and of the
+    adjacent time steps within spatial distance |dx| + |dy| <= 2 (the stencil
+    of (kappa^2 - Laplacian)^2 on a grid, times an AR(1) coupling in time);
+    `a` dense arrow rows (fixed effects).  Values: N(0,1) off the diagonal in
+    (row, column) order, diagonal = absolute sum of the full symmetric row + 1.
+    Returns a dict: N, n, a, CSC of the lower triangle (colptr, rowind,
+    values in CSC order) and the natural order's row profile (a Pattern and
+    the values in row-profile order, zeros where the envelope has no entry)."""
+    n = nx * ny * nt
+    N = n + a
+    idx = np.arange(n, dtype=np.int64)
+    t, rem = np.divmod(idx, nx * ny)
+    y, x = np.divmod(rem, nx)
+    rows, cols = [], []
+    # lower neighbours: the whole stencil at t - 1, the part before (y, x) at t
+    for dt in (-1, 0):
+        for dy in range(-2, 3):
+            for dx in range(-2, 3):
+                if abs(dx) + abs(dy) > 2 or (dt == 0 and (dy, dx) >= (0, 0)):
+                    continue
+                ok = (t + dt >= 0) & (y + dy >= 0) & (y + dy < ny) & (x + dx >= 0) & (x + dx < nx)
+                i = idx[ok]
+                rows.append(i)
+                cols.append(i + dt * nx * ny + dy * nx + dx)
+    # arrow rows: dense
+    ar = np.repeat(np.arange(n, N, dtype=np.int64), np.arange(n, N))
+    ac = np.concatenate([np.arange(r, dtype=np.int64) for r in range(n, N)]) if a else np.zeros(0, np.int64)
+    rows.append(ar)
+    cols.append(ac)
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    order = np.lexsort((c, r))            # (row, column) order for the draws
+    r, c = r[order], c[order]
+    rng = np.random.default_rng(seed)
+    off = rng.standard_normal(r.shape[0])
+    dsum = np.zeros(N)
+    np.add.at(dsum, r, np.abs(off))
+    np.add.at(dsum, c, np.abs(off))
+    dr = np.arange(N, dtype=np.int64)
+    R = np.concatenate([r, dr])
+    C = np.concatenate([c, dr])
+    V = np.concatenate([off, dsum + 1.0])
+    co = np.lexsort((R, C))               # CSC: column, then row
+    colptr = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(C, minlength=N), out=colptr[1:])
+    f = np.arange(N, dtype=np.int64)
+    np.minimum.at(f, R, C)
+    pat = Pattern(n=n, a=a, f=f, name=name or "spde%dx%dx%d_a%d" % (nx, ny, nt, a))
+    rp = pat.row_ptr()
+    prof = np.zeros(int(rp[-1]))
+    prof[rp[R] + (C - f[R])] = V
+    return {"N": N, "n": n, "a": a, "colptr": colptr, "rowind": R[co].copy(), "values": np.ascontiguousarray(V[co]),
+            "pattern": pat, "profile_values": prof}
+
+
 # ------------------------------------------------------------ format helpers
 
 def to_dense(pattern, values):
