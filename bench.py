@@ -6,11 +6,12 @@ Default workload (one "step" = the whole hot path on one matrix):
   half-width is piecewise constant per 5,000-row segment and uniform in
   [200, 800] (seed 2), a dense arrow of 100 rows (N = 200,100), values N(0,1)
   with diagonal = absolute row sum + 1; tile 64;
-  step = value scatter + factorization + solve with 8 right-hand sides
-  (seed 102) + log-determinant.
+  step = value scatter + factorization and solve with 8 right-hand sides
+  (seed 102) as one launch of the merged task graph + log-determinant.
 Inputs are resident in HBM before the timed region.  `value` is TFLOP/s of
 the algorithmic factorization flops F = sum_j (eta_j + 1)^2 over the whole
-step time; the roofline object reports the factorization kernel alone.
+step time; the roofline object reports the merged factorization + solve
+launch (algorithmic flops: F + 4 nnz(L) nrhs for the two solve sweeps).
 
 Other workloads (--workload): small (n=2,000, w=50, a=10, tile 64, 1 RHS),
 batch (512 uneven matrices in one launch), mixed (n=500,000, w=1,000,
@@ -134,13 +135,15 @@ def bench_single(args):
     F = sym.info.flops_alg
 
     def step(ev=None):
+        # factorization and solve as one launch of the merged task graph
+        # (FP64): rows whose factor is final are solved while the rest is
+        # still being factored
+        work.copy_(dB0)
         if ev:
             ev[0].record()
-        fac.factorize(dv)
+        fac.factorize_solve(dv, work)
         if ev:
             ev[1].record()
-        work.copy_(dB0)
-        fac.solve(work)
         if ev:
             ev[2].record()
         fac.logdet(ld)
@@ -160,21 +163,28 @@ def bench_single(args):
     t1 = time.perf_counter()
     info = fac.info()
     fact_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    solve_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     logdet_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
     ms = (t1 - t0) / args.steps * 1e3
-    # the factorization executor kernel alone: HIP events recorded by the
-    # library around that launch, on the same stream, over K further steps
+    # the merged executor launch alone: HIP events recorded by the library
+    # around that launch, on the same stream, over K further steps; and, for
+    # reference, the factorization and solve launches of separate calls
     S.stiles_factor_set_timing(fac.handle, True)
-    kms, sms = [], []
+    kms = []
     for _ in range(args.steps):
         step()
         kms.append(S.stiles_factor_kernel_ms(fac.handle, 0))
-        sms.append(S.stiles_factor_kernel_ms(fac.handle, 1))
+    sep_f, sep_s = [], []
+    for _ in range(args.steps):
+        fac.factorize(dv)
+        work.copy_(dB0)
+        fac.solve(work)
+        sep_f.append(S.stiles_factor_kernel_ms(fac.handle, 0))
+        sep_s.append(S.stiles_factor_kernel_ms(fac.handle, 1))
     S.stiles_factor_set_timing(fac.handle, False)
     kernel_ms = float(np.mean(kms))
-    solve_kernel_ms = float(np.mean(sms))
-    achieved = F / (kernel_ms * 1e-3) / 1e12
+    solve_kernel_ms = float(np.mean(sep_s))
+    F_solve = 4.0 * sym.info.nnz_L * nrhs      # algorithmic solve flops (two sweeps)
+    achieved = (F + F_solve) / (kernel_ms * 1e-3) / 1e12
     res = {
         "metric": "arrowhead Cholesky TFLOP/s (factorize+solve+logdet step)",
         "value": F / (ms * 1e-3) / 1e12,
@@ -194,16 +204,16 @@ def bench_single(args):
                    "value_seed": seed, "rhs_seed": rseed, "ops": "factorize+solve+logdet",
                    "parallelism": "single GPU, persistent DAG executor"},
         "factorizations_per_s": 1e3 / ms,
-        "factorize_ms": fact_ms,
-        "solve_kernel_ms": solve_kernel_ms,
-        "solve_ms": solve_ms,
+        "factorize_solve_ms": fact_ms,
+        "separate_launches_ms": {"factorization": float(np.mean(sep_f)), "solve": solve_kernel_ms},
         "logdet_ms": logdet_ms,
         "flops_alg": F,
         "flops_exec": sym.info.flops_exec,
         "info": info,
-        "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,0> (factorization DAG)" % args.tile,
+        "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,3> (merged factorization + solve DAG)" % args.tile,
                      "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
-                     "traffic": None, "kernel_ms": kernel_ms, "bytes_alg": 16 * p.nnz},
+                     "traffic": None, "kernel_ms": kernel_ms, "flops_per_launch": F + F_solve,
+                     "bytes_alg": 16 * p.nnz},
     }
     order_key = "nd%d" % sym.info.nd_parts if sym.info.nd_parts > 1 else "none"
     tr = measured_traffic("%s_n%d_a%d_%s" % (p.name.split("_")[0].rstrip("0123456789"), p.n, p.a, order_key),

@@ -180,6 +180,8 @@ void stiles_symbolic_destroy(stiles_symbolic* sym);
  *   10 number of tree partial slots (int32, 1 element)
  *   11 selected-inversion tasks  12 their successor lists  13 their operand
  *     lists (int32; built on first use)
+ *   14 merged factorization + solve tasks  15 their successor lists  16 their
+ *     pairs (the factorization pairs, then the solve pairs; built on first use)
  * With out == NULL, *count receives the number of elements; otherwise *count
  * is the capacity of out (elements) and receives the number copied.
  * EINVAL: unknown `which` (argument 2) or capacity too small (argument 4).
@@ -262,6 +264,23 @@ stiles_status stiles_factor_info(stiles_factor* f, hipStream_t stream, int64_t* 
  */
 stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_B, int64_t ldb, hipStream_t stream,
                            stiles_solve_report* report);
+
+/*
+ * Factorization and solve in one persistent launch (FP64 only; ENOTSUP in
+ * mixed precision): stiles_factorize(f, d_values) followed by
+ * stiles_solve(f, nrhs, d_B, ldb), with the two task graphs merged, so that
+ * tile rows whose factor is final are solved while the rest of the matrix is
+ * still being factored (the forward sweep of the adaptable-ND partitions
+ * overlaps the factorization of the separators).  Results are bitwise those
+ * of the two separate calls (the same tasks in the same accumulation order).
+ * d_B: N x nrhs column-major (ldb >= N), original ordering, overwritten by X;
+ * right-hand sides beyond the first 16 are solved by ordinary solve sweeps
+ * after the launch.  If the factorization fails, X is NaN and
+ * stiles_factor_info reports the column.  The timing hook's factorization
+ * event pair brackets the merged launch.
+ */
+stiles_status stiles_factorize_solve(stiles_factor* f, const double* d_values, int64_t nrhs, double* d_B, int64_t ldb,
+                                     hipStream_t stream);
 
 /* logdet A = 2 sum log L_ii, written to *d_out (one FP64 on the device).
  * Deterministic fixed-shape reduction.  NaN if the factorization failed. */

@@ -24,6 +24,7 @@ __all__ = [
     "stiles_batch_destroy", "Batch", "SelInv", "stiles_selinv_query", "stiles_selinv_workspace_size",
     "stiles_selinv_create", "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract",
     "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
+    "stiles_factorize_solve",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -52,7 +53,7 @@ EXPORTED = [
     "stiles_symbolic_export", "stiles_batch_create", "stiles_batch_factorize", "stiles_batch_logdet",
     "stiles_batch_destroy", "stiles_selinv_query", "stiles_selinv_workspace_size", "stiles_selinv_create",
     "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract", "stiles_selinv_set_timing",
-    "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
+    "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy", "stiles_factorize_solve",
 ]
 
 
@@ -132,6 +133,7 @@ def load_library(path=LIB_PATH):
         "stiles_selinv_set_timing": (_i32, [_vp, _i32]),
         "stiles_selinv_kernel_ms": (_i32, [_vp, ctypes.POINTER(ctypes.c_float)]),
         "stiles_selinv_set_trace": (_i32, [_vp, _vp, _vp]),
+        "stiles_factorize_solve": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp]),
         "stiles_selinv_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
@@ -219,7 +221,8 @@ def stiles_symbolic_perm(sym, N):
 EXPORT_KINDS = {"ftask": (0, np.int32), "fsucc": (1, np.int32), "fpairs": (2, np.int32), "stask": (3, np.int32),
                 "ssucc": (4, np.int32), "spairs": (5, np.int32), "trow_ptr": (6, np.int32), "tcol": (7, np.int32),
                 "row_base": (8, np.int64), "row_cnt": (9, np.int32), "npart": (10, np.int32),
-                "itask": (11, np.int32), "isucc": (12, np.int32), "ilist": (13, np.int32)}
+                "itask": (11, np.int32), "isucc": (12, np.int32), "ilist": (13, np.int32),
+                "mtask": (14, np.int32), "msucc": (15, np.int32), "mpairs": (16, np.int32)}
 
 
 def stiles_symbolic_export(sym, kind):
@@ -277,6 +280,11 @@ def stiles_solve(fac, nrhs, d_B, ldb, stream=None):
     rep = stiles_solve_report()
     _check(load_library().stiles_solve(fac, nrhs, _ptr(d_B), ldb, _stream(stream), ctypes.byref(rep)), "stiles_solve")
     return rep
+
+
+def stiles_factorize_solve(fac, d_values, nrhs, d_B, ldb, stream=None):
+    _check(load_library().stiles_factorize_solve(fac, _ptr(d_values), nrhs, _ptr(d_B), ldb, _stream(stream)),
+           "stiles_factorize_solve")
 
 
 def stiles_logdet(fac, d_out, stream=None):
@@ -449,6 +457,17 @@ class Factor:
                 raise ValueError("B must be column-major (use X.t().contiguous().t())")
             rep = stiles_solve(self.handle, B.shape[1], B, B.stride(1), stream)
         return rep
+
+    def factorize_solve(self, d_values, B, stream=None):
+        """factorize(d_values) then an in-place solve of B, as one launch
+        (FP64); B as for solve()."""
+        if B.dim() == 1:
+            stiles_factorize_solve(self.handle, d_values, 1, B, B.shape[0], stream)
+        else:
+            if B.stride(0) != 1:
+                raise ValueError("B must be column-major (use X.t().contiguous().t())")
+            stiles_factorize_solve(self.handle, d_values, B.shape[1], B, B.stride(1), stream)
+        return self
 
     def extract(self, stream=None):
         """L in row-profile order of the permuted envelope (device tensor)."""

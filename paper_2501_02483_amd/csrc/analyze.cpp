@@ -1181,6 +1181,97 @@ void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
   P.flops_alg = F;
 }
 
+// Merged factorization + solve DAG (FP64): every solve task also waits for
+// the factorization tasks that finalize the factor tiles it reads and, for a
+// diagonal step, for the POTRF of its tile row (which stores L_kk^-1).  Rows
+// whose factor is final are then solved while the rest of the matrix is
+// still being factored (under adaptable ND the forward sweep of the
+// partitions overlaps the separator phase).  Ticket order: the factorization
+// tasks keep theirs; each solve task goes right after its last predecessor
+// (Kahn's algorithm on that key), which keeps the order topological.
+void build_merged(const stiles_symbolic& s, MergedPlan& D) {
+  const int32_t nf = (int32_t)(s.ftask.size() / TASK_WORDS), ns = (int32_t)(s.stask.size() / TASK_WORDS);
+  const int32_t nfp = (int32_t)(s.fpairs.size() / 2);
+  const int32_t n = nf + ns;
+  std::vector<std::vector<int32_t>> pred(n);
+  for (int32_t t = 0; t < nf; t++)
+    for (int32_t q = s.ftask[(size_t)t * TASK_WORDS + 5]; q < s.ftask[(size_t)t * TASK_WORDS + 6]; q++)
+      pred[s.fsucc[q]].push_back(t);
+  for (int32_t t = 0; t < ns; t++)
+    for (int32_t q = s.stask[(size_t)t * TASK_WORDS + 5]; q < s.stask[(size_t)t * TASK_WORDS + 6]; q++)
+      pred[nf + s.ssucc[q]].push_back(nf + t);
+  std::vector<int32_t> final_task(s.ntiles, -1), potrf_row(s.ntr, -1);
+  for (int32_t t = 0; t < nf; t++) {
+    const int32_t* w = &s.ftask[(size_t)t * TASK_WORDS];
+    const int type = w[0] & 0xff;
+    if (type == TK_POTRF || type == TK_TRSM) final_task[w[1]] = t;
+    if (type == TK_POTRF) potrf_row[w[2]] = t;
+  }
+  for (int32_t t = 0; t < ns; t++) {
+    const int32_t* w = &s.stask[(size_t)t * TASK_WORDS];
+    const int type = w[0] & 0xff;
+    if (type == TK_FSUM) continue;
+    for (int32_t q = w[2]; q < w[3]; q++) pred[nf + t].push_back(final_task[s.spairs[2 * (size_t)q]]);
+    if (type == TK_FDIAG || type == TK_BDIAG) pred[nf + t].push_back(potrf_row[w[1]]);
+  }
+  std::vector<double> key(n);
+  for (int32_t t = 0; t < n; t++) {
+    auto& p = pred[t];
+    std::sort(p.begin(), p.end());
+    p.erase(std::unique(p.begin(), p.end()), p.end());
+    if (!p.empty() && p[0] < 0) { fprintf(stderr, "stiles: merged DAG: tile without a final task\n"); abort(); }
+    if (t < nf) { key[t] = t; continue; }
+    double k = -1.0;
+    for (int32_t x : p) k = std::max(k, key[x]);
+    key[t] = k + 0.5;
+  }
+  std::vector<std::vector<int32_t>> succ(n);
+  std::vector<int32_t> npred(n);
+  for (int32_t t = 0; t < n; t++) {
+    npred[t] = (int32_t)pred[t].size();
+    for (int32_t x : pred[t]) succ[x].push_back(t);
+  }
+  auto later = [&](int32_t x, int32_t y) { return key[x] != key[y] ? key[x] > key[y] : x > y; };
+  std::priority_queue<int32_t, std::vector<int32_t>, decltype(later)> ready(later);
+  for (int32_t t = 0; t < n; t++)
+    if (npred[t] == 0) ready.push(t);
+  std::vector<int32_t> order;
+  order.reserve(n);
+  while (!ready.empty()) {
+    const int32_t t = ready.top();
+    ready.pop();
+    order.push_back(t);
+    for (int32_t x : succ[t])
+      if (--npred[x] == 0) ready.push(x);
+  }
+  if ((int32_t)order.size() != n) { fprintf(stderr, "stiles: merged DAG has a cycle\n"); abort(); }
+  std::vector<int32_t> newid(n);
+  for (int32_t i = 0; i < n; i++) newid[order[i]] = i;
+  D.task.assign((size_t)n * TASK_WORDS, 0);
+  D.succ.clear();
+  for (int32_t i = 0; i < n; i++) {
+    const int32_t t = order[i];
+    int32_t* w = &D.task[(size_t)i * TASK_WORDS];
+    if (t < nf) {
+      std::memcpy(w, &s.ftask[(size_t)t * TASK_WORDS], sizeof(int32_t) * TASK_WORDS);
+    } else {
+      std::memcpy(w, &s.stask[(size_t)(t - nf) * TASK_WORDS], sizeof(int32_t) * TASK_WORDS);
+      if ((w[0] & 0xff) != TK_FSUM) { w[2] += nfp; w[3] += nfp; }   // solve pairs follow the factor pairs
+    }
+    std::vector<int32_t> sl;
+    for (int32_t x : succ[t]) sl.push_back(newid[x]);
+    std::sort(sl.begin(), sl.end());
+    for (int32_t x : sl)
+      if (x <= i) { fprintf(stderr, "stiles: merged DAG order is not topological\n"); abort(); }
+    w[5] = (int32_t)D.succ.size();
+    D.succ.insert(D.succ.end(), sl.begin(), sl.end());
+    w[6] = (int32_t)D.succ.size();
+    w[7] = (int32_t)pred[t].size();
+  }
+  D.pairs = s.fpairs;
+  D.pairs.insert(D.pairs.end(), s.spairs.begin(), s.spairs.end());
+}
+
 }  // namespace
 
 namespace stiles {
@@ -1192,6 +1283,16 @@ const SelinvPlan& selinv_plan(const stiles_symbolic& s) {
     s.selinv = std::move(p);
   }
   return *s.selinv;
+}
+
+const MergedPlan& merged_plan(const stiles_symbolic& s) {
+  std::lock_guard<std::mutex> g(s.merged_mu);
+  if (!s.merged) {
+    std::unique_ptr<MergedPlan> p(new MergedPlan());
+    build_merged(s, *p);
+    s.merged = std::move(p);
+  }
+  return *s.merged;
 }
 }  // namespace stiles
 
@@ -1250,6 +1351,9 @@ extern "C" stiles_status stiles_symbolic_export(const stiles_symbolic* s, int32_
     case 11: src = selinv_plan(*s).task.data(); n = (int64_t)selinv_plan(*s).task.size(); break;
     case 12: src = selinv_plan(*s).succ.data(); n = (int64_t)selinv_plan(*s).succ.size(); break;
     case 13: src = selinv_plan(*s).list.data(); n = (int64_t)selinv_plan(*s).list.size(); break;
+    case 14: src = merged_plan(*s).task.data(); n = (int64_t)merged_plan(*s).task.size(); break;
+    case 15: src = merged_plan(*s).succ.data(); n = (int64_t)merged_plan(*s).succ.size(); break;
+    case 16: src = merged_plan(*s).pairs.data(); n = (int64_t)merged_plan(*s).pairs.size(); break;
     default: g_err_arg = 2; return STILES_EINVAL;
   }
   if (!out) { *count = n; return STILES_OK; }

@@ -23,6 +23,7 @@ inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t ctrl_f, ctrl_s, info, mat_f, mat_s;
+  size_t ctrl_m, mat_m, mtask, msucc, mrem, mpairs;   // merged factorization + solve DAG (FP64)
   size_t ftask, fsucc, frem, fpairs;
   size_t stask, ssucc, srem, spairs;
   size_t row_base, row_cnt, trow_ptr, trow, tcol, perm;
@@ -37,6 +38,8 @@ struct Layout {
 struct Plan {   // host-side refinement tables (mixed mode)
   std::vector<int32_t> ccol_tile, ccol_row, items, item_ptr;
 };
+
+
 
 void make_plan(const stiles_symbolic& s, Plan& p) {
   std::vector<std::vector<std::pair<int32_t, int32_t>>> below(s.ntr);
@@ -75,6 +78,17 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   const size_t nft = s.ftask.size() / TASK_WORDS, nst = s.stask.size() / TASK_WORDS;
   L.ctrl_f = take(sizeof(ExecCtrl));
   L.ctrl_s = take(sizeof(ExecCtrl));
+  if (precision == STILES_FP64) {
+    const size_t nm = nft + nst;
+    L.ctrl_m = take(sizeof(ExecCtrl));
+    L.mat_m = take(sizeof(ExecMat));
+    L.mtask = take(nm * TASK_WORDS * 4);
+    // successors: the two DAGs' own edges plus at most one cross edge per
+    // solve pair and one per diagonal solve step
+    L.msucc = take((s.fsucc.size() + s.ssucc.size() + s.spairs.size() / 2 + nst) * 4);
+    L.mrem = take(nm * 4);
+    L.mpairs = take((s.fpairs.size() + s.spairs.size()) * 4);
+  }
   L.info = take(8);
   L.mat_f = take(sizeof(ExecMat));
   L.mat_s = take(sizeof(ExecMat));
@@ -155,6 +169,7 @@ struct stiles_factor {
   Layout L{};
   Plan plan;
   ExecMat mf{}, ms{};
+  int32_t nmerged = 0;   // tasks of the merged factorization + solve DAG (FP64)
   int32_t max_wg = 0;
   int32_t state = 0;   // 0 unknown, 1 factored ok, 2 failed, -1 not factored
   double anorm = -1.0; // inf-norm of A (mixed mode), computed lazily
@@ -275,6 +290,26 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   if (!s->profile_input) U(L.map, s->map.data(), s->map.size() * 8);
   if (!s->fin.empty()) U(L.fin, s->fin.data(), s->fin.size() * 8);
   if (!s->in_rp_in.empty()) U(L.in_rp_in, s->in_rp_in.data(), s->in_rp_in.size() * 8);
+  std::vector<int32_t> mrem;
+  ExecMat mm{};
+  if (!mixed) {
+    const MergedPlan& md = merged_plan(*s);
+    f->nmerged = (int32_t)(md.task.size() / TASK_WORDS);
+    mrem.resize(f->nmerged);
+    for (int32_t t = 0; t < f->nmerged; t++) mrem[t] = md.task[(size_t)t * TASK_WORDS + 7];
+    mm = mf;
+    mm.tasks = at<int32_t>(f, L.mtask);
+    mm.succ = at<int32_t>(f, L.msucc);
+    mm.remaining = at<int32_t>(f, L.mrem);
+    mm.pairs = at<int32_t>(f, L.mpairs);
+    mm.ntasks = f->nmerged;
+    U(L.ctrl_m, &ctrl, sizeof(ctrl));
+    U(L.mat_m, &mm, sizeof(mm));
+    U(L.mtask, md.task.data(), md.task.size() * 4);
+    U(L.msucc, md.succ.data(), md.succ.size() * 4);
+    U(L.mrem, mrem.data(), mrem.size() * 4);
+    U(L.mpairs, md.pairs.data(), md.pairs.size() * 4);
+  }
   if (mixed) {
     U(L.ccol_tile, f->plan.ccol_tile.data(), f->plan.ccol_tile.size() * 4);
     U(L.ccol_row, f->plan.ccol_row.data(), f->plan.ccol_row.size() * 4);
@@ -485,6 +520,47 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
       report->converged = report->converged && conv;
       report->backward_error = std::max(report->backward_error, berr);
     }
+  }
+  return STILES_OK;
+}
+
+extern "C" stiles_status stiles_factorize_solve(stiles_factor* f, const double* d_values, int64_t nrhs, double* d_B,
+                                                int64_t ldb, hipStream_t st) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  const stiles_symbolic& sy = *f->sym;
+  const int64_t nvals = !sy.profile_input ? (int64_t)sy.map.size() : sy.perm_identity ? sy.in_rp.back() : sy.in_rp_in.back();
+  if (!d_values && nvals > 0) { set_error_arg(2); return STILES_EINVAL; }
+  if (nrhs < 1 || nrhs > f->nrhs_max) { set_error_arg(3); return STILES_EINVAL; }
+  if (!d_B) { set_error_arg(4); return STILES_EINVAL; }
+  if (ldb < sy.N) { set_error_arg(5); return STILES_EINVAL; }
+  if (f->precision != STILES_FP64) return STILES_ENOTSUP;
+  stiles_status r = scatter_values(f, d_values, st);
+  if (r != STILES_OK) return r;
+  const Layout& L = f->L;
+  const int nb = (int)std::min<int64_t>(16, nrhs);
+  hipError_t e = launch_pack(sy.T, d_B, ldb, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
+                             at<int32_t>(f, L.row_cnt), sy.ntr, at<double>(f, L.vy), st);
+  if (e != hipSuccess) return STILES_EDEVICE;
+  if (f->timing) (void)hipEventRecord(f->ev[0], st);
+  e = launch_exec(sy.T, EXEC_FACTOR_SOLVE, at<ExecMat>(f, L.mat_m), nullptr, f->nmerged, at<ExecCtrl>(f, L.ctrl_m), nb,
+                  nwg_for(f, f->nmerged), st);
+  if (f->timing) (void)hipEventRecord(f->ev[1], st);
+  if (e != hipSuccess) return STILES_EDEVICE;
+  f->state = 0;
+  f->anorm = -1.0;
+  if (launch_unpack(sy.T, at<double>(f, L.vz), nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
+                    at<int32_t>(f, L.row_cnt), sy.ntr, at<unsigned long long>(f, L.info), d_B, ldb, st) != hipSuccess)
+    return STILES_EDEVICE;
+  // right-hand sides beyond the first 16: ordinary solve sweeps
+  for (int64_t c0 = nb; c0 < nrhs; c0 += 16) {
+    const int nb2 = (int)std::min<int64_t>(16, nrhs - c0);
+    double* B = d_B + c0 * ldb;
+    r = solve_sweep(f, B, ldb, nb2, st);
+    if (r != STILES_OK) return r;
+    if (launch_unpack(sy.T, at<double>(f, L.vz), nb2, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
+                      at<int32_t>(f, L.row_cnt), sy.ntr, at<unsigned long long>(f, L.info), B, ldb, st) != hipSuccess)
+      return STILES_EDEVICE;
   }
   return STILES_OK;
 }

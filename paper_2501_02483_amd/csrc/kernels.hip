@@ -187,7 +187,7 @@ struct TileStage {
 
 // UPD / PART: acc = sum_p X_p Y_p^T over a list of tile pairs (at most 32).
 // mode 0: C_t -= acc (UPD), mode 1: P = acc (PART).  LX, LY: LDS tiles.
-template <int T>
+template <int T, int K>
 __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const int32_t* w, int mode, double* LX, double* LY) {
   constexpr int TT = T * T, W = T / 2, NB = T / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -298,7 +298,7 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
 }
 
 // TREE: P_c = P_a + P_b, or C_t -= P_a (+ P_b) at the root (Alg. 3 GEADD).
-template <int T>
+template <int T, int K>
 __device__ __attribute__((noinline)) void task_tree(const ExecMat& M, const int32_t* w) {
   constexpr int TT = T * T;
   typedef double d2 __attribute__((ext_vector_type(2)));
@@ -318,7 +318,7 @@ __device__ __attribute__((noinline)) void task_tree(const ExecMat& M, const int3
 
 // TRSM: L_t = (C_t - [X Y^T]) Linv_k^T as staged tile products; FP32 copy
 // in mixed mode.  The optional fused product is the update with column k-1.
-template <int T>
+template <int T, int K>
 __device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
   constexpr int TT = T * T, W = T / 2, NB = T / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -540,7 +540,7 @@ __device__ __forceinline__ void inv_row_block(double* S, double* Xi, int b, int 
   for (int rr = 0; rr < 4; rr++) Xi[(16 * b + (lane >> 4) + 4 * rr) + (16 * q + (lane & 15)) * T] = -xv[rr];
 }
 
-template <int T>
+template <int T, int K>
 __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv) {
   constexpr int TT = T * T, NBK = T / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -660,7 +660,7 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
 // (X = L^{-1}: row j of X is final once scaled by 1/L_jj, then
 // X_i -= L_ij X_j for i > j).  Per column: one pivot chain (1/sqrt estimate +
 // Newton), one LDS round trip and one barrier.
-template <int T>
+template <int T, int K>
 __device__ __attribute__((noinline)) void task_potrf_cols(const ExecMat& M, const int32_t* w, double* S, double* Xb,
                                                           double* rinv) {
   constexpr int TT = T * T, G = NT / T, NC = T / G;
@@ -868,7 +868,7 @@ __device__ __forceinline__ void solve_prefetch(const ExecMat& M, const int32_t* 
 }
 
 // A solve task; its static operands are already staged by solve_prefetch.
-template <int T>
+template <int T, int K>
 __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int32_t* w, int nrhs, double* LL,
                                                      double* LV, const double* LI) {
   constexpr int TT = T * T;
@@ -945,7 +945,7 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
 
 // Y_m -= Q_a + ... + Q_(b-1): the partial products of a long row, summed in
 // a fixed order (so the result does not depend on the schedule)
-template <int T>
+template <int T, int K>
 __device__ __attribute__((noinline)) void task_fsum(const ExecMat& M, const int32_t* w, int nrhs) {
   const int64_t vb = (int64_t)T * nrhs;
   double* y = M.vy + (int64_t)w[1] * vb;
@@ -1332,17 +1332,26 @@ __device__ __attribute__((noinline)) void task_tsum(const ExecMat& M, const int3
 
 // ---------------------------------------------------------------- executor
 
+// The task bodies take the kernel kind as a template argument so that every
+// executor kernel gets its own copies: a noinline function shared by two
+// kernels is compiled for both call sites at once, which cost the
+// factorization kernel register spills.
 // KIND selects the task set: factorization tasks (UPD, PART, TREE, POTRF,
 // TRSM), triangular-solve tasks, or selected-inversion tasks; they are
 // separate kernels so that each carries only its own code.
 template <int T, int KIND>
 __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__ mats, const int32_t* __restrict__ order,
                                                   int32_t total, ExecCtrl* ctrl, int nrhs) {
-  constexpr bool SOLVE = KIND == EXEC_SOLVE, SELINV = KIND == EXEC_SELINV;
+  constexpr bool SOLVE = KIND == EXEC_SOLVE, SELINV = KIND == EXEC_SELINV, BOTH = KIND == EXEC_FACTOR_SOLVE;
+  // LDS: factorization tasks use S (tile, ld T+1 room), Xi (T x T) and rinv;
+  // solve tasks use S (factor tile), a T x 16 vector block and an inverse
+  // diagonal tile (ld T+1); selected-inversion tasks two padded tiles.  The
+  // combined factorization + solve kernel gives the solve's inverse tile the
+  // (enlarged) Xi and its vector block a buffer of its own.
   __shared__ __attribute__((aligned(16))) double S[SELINV ? T * (T + 2) : T * (T + 1)];
-  __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : SELINV ? T * (T + 2) : T * T];
-  __shared__ double rinv[KIND == EXEC_FACTOR ? T : 1];
-  __shared__ __attribute__((aligned(16))) double LI[SOLVE ? T * (T + 1) : 1];
+  __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : SELINV ? T * (T + 2) : BOTH ? T * (T + 1) : T * T];
+  __shared__ double rinv[(KIND == EXEC_FACTOR || BOTH) ? T : 1];
+  __shared__ __attribute__((aligned(16))) double LI[SOLVE ? T * (T + 1) : BOTH ? T * 16 : 1];
   __shared__ int32_t s_ticket;
   // Control flow outside the task bodies is kept uniform across the
   // workgroup (values broadcast with readfirstlane, loops with uniform bounds
@@ -1366,6 +1375,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     if (M.trace) t_claim = wall_clock64();
     if constexpr (SOLVE) solve_prefetch<T>(M, w, S, LI);
     if constexpr (SELINV) selinv_prefetch<T>(M, w, S, Xi);
+
     // wait until every predecessor has finished (Alg. 2 progress check);
     // wave 0 polls, then acquires for the workgroup (all its waves share
     // the CU's caches that the acquire invalidates)
@@ -1377,12 +1387,18 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     if (threadIdx.x == 0) st_relaxed(cnt, w[7]);   // re-arm for the next launch
     if (M.trace) t_start = wall_clock64();
     const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
+    // in the merged factorization + solve DAG the factor tiles of a solve
+    // task are final only now: its operands are staged after the wait (the
+    // task body synchronizes before it reads them)
+    if constexpr (BOTH) {
+      if (type >= TK_FUPD) solve_prefetch<T>(M, w, S, Xi);
+    }
     // tasks on the pivot chain (diagonal factorization, panel solve, diagonal
     // solve steps) raise their waves' issue priority over the co-resident
     // update work of other workgroups on the same SIMDs
     const bool chain = SOLVE    ? (type == TK_FDIAG || type == TK_BDIAG)
                        : SELINV ? (type == TK_SW || type == TK_SDIAG)
-                                : (type == TK_POTRF || type == TK_TRSM);
+                                : (type == TK_POTRF || type == TK_TRSM || type == TK_FDIAG || type == TK_BDIAG);
     if (chain) __builtin_amdgcn_s_setprio(3);
     if constexpr (SELINV) {
       if (type == TK_SWE) task_swe<T>(M, w, S, Xi);
@@ -1390,18 +1406,21 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       else if (type == TK_SDIAG) task_sdiag<T>(M, w, S, Xi);
       else task_tsum<T>(M, w);
     } else if constexpr (SOLVE) {
-      if (type == TK_FSUM) task_fsum<T>(M, w, nrhs);
-      else task_solve<T>(M, w, nrhs, S, Xi, LI);
+      if (type == TK_FSUM) task_fsum<T, KIND>(M, w, nrhs);
+      else task_solve<T, KIND>(M, w, nrhs, S, Xi, LI);
+    } else if (BOTH && type >= TK_FUPD) {
+      if (type == TK_FSUM) task_fsum<T, KIND>(M, w, nrhs);
+      else task_solve<T, KIND>(M, w, nrhs, S, LI, Xi);
     } else {
       switch (type) {
-        case TK_UPD: task_update<T>(M, w, 0, S, Xi); break;
-        case TK_PART: task_update<T>(M, w, 1, S, Xi); break;
-        case TK_TREE: task_tree<T>(M, w); break;
+        case TK_UPD: task_update<T, KIND>(M, w, 0, S, Xi); break;
+        case TK_PART: task_update<T, KIND>(M, w, 1, S, Xi); break;
+        case TK_TREE: task_tree<T, KIND>(M, w); break;
         case TK_POTRF:
-          if constexpr (POTRF_COLS) task_potrf_cols<T>(M, w, S, Xi, rinv);
-          else task_potrf<T>(M, w, S, Xi, rinv);
+          if constexpr (POTRF_COLS) task_potrf_cols<T, KIND>(M, w, S, Xi, rinv);
+          else task_potrf<T, KIND>(M, w, S, Xi, rinv);
           break;
-        default: task_trsm<T>(M, w, S, Xi); break;
+        default: task_trsm<T, KIND>(M, w, S, Xi); break;
       }
     }
     if (chain) __builtin_amdgcn_s_setprio(0);
@@ -1444,10 +1463,12 @@ hipError_t launch_exec(int T, int kind, const ExecMat* d_mats, const int32_t* d_
   if (T == 64) {
     if (kind == EXEC_SOLVE) STILES_EXEC(64, EXEC_SOLVE);
     else if (kind == EXEC_SELINV) STILES_EXEC(64, EXEC_SELINV);
+    else if (kind == EXEC_FACTOR_SOLVE) STILES_EXEC(64, EXEC_FACTOR_SOLVE);
     else STILES_EXEC(64, EXEC_FACTOR);
   } else {
     if (kind == EXEC_SOLVE) STILES_EXEC(32, EXEC_SOLVE);
     else if (kind == EXEC_SELINV) STILES_EXEC(32, EXEC_SELINV);
+    else if (kind == EXEC_FACTOR_SOLVE) STILES_EXEC(32, EXEC_FACTOR_SOLVE);
     else STILES_EXEC(32, EXEC_FACTOR);
   }
 #undef STILES_EXEC

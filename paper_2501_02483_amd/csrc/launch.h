@@ -11,7 +11,8 @@ namespace stiles {
 // (nrhs >= 1 right-hand sides) or selected-inversion tasks.  order == nullptr
 // means one matrix (mats[0]) with tasks in their own order, else order[2t],
 // order[2t+1] = (matrix index, task id).
-enum ExecKind { EXEC_FACTOR = 0, EXEC_SOLVE = 1, EXEC_SELINV = 2 };
+// EXEC_FACTOR_SOLVE runs a merged DAG of factorization and solve tasks.
+enum ExecKind { EXEC_FACTOR = 0, EXEC_SOLVE = 1, EXEC_SELINV = 2, EXEC_FACTOR_SOLVE = 3 };
 hipError_t launch_exec(int T, int kind, const ExecMat* d_mats, const int32_t* d_order, int32_t total,
                        ExecCtrl* d_ctrl, int nrhs, int nwg, hipStream_t st);
 

@@ -18,6 +18,12 @@ struct SelinvPlan {
   double flops_exec = 0.0;   // tile products executed (padded tiles)
 };
 
+// Merged factorization + solve DAG (ticket order; solve pairs follow the
+// factorization pairs)
+struct MergedPlan {
+  std::vector<int32_t> task, succ, pairs;
+};
+
 struct stiles_symbolic {
   stiles_opts opts;
   int64_t N = 0, n = 0, a = 0;
@@ -72,6 +78,8 @@ struct stiles_symbolic {
   // logically immutable)
   mutable std::mutex selinv_mu;
   mutable std::unique_ptr<SelinvPlan> selinv;
+  mutable std::mutex merged_mu;
+  mutable std::unique_ptr<MergedPlan> merged;
 
   // statistics
   int64_t nnzL = 0;
@@ -84,4 +92,6 @@ namespace stiles {
 void set_error_arg(int32_t idx);
 // the selected-inversion plan of a symbolic object (built once, thread-safe)
 const SelinvPlan& selinv_plan(const stiles_symbolic& s);
+// the merged factorization + solve plan (built once, thread-safe)
+const MergedPlan& merged_plan(const stiles_symbolic& s);
 }

@@ -249,3 +249,96 @@ def selinv(plan, tiles, linv, mode="ticket", seed=0):
             raise AssertionError("unknown selected-inversion task type %d" % typ)
     assert not qpart and not dpart, "partials produced but never consumed"
     return sigma
+
+
+def factor_solve(plan, Aperm, B, mode="ticket", seed=0):
+    """The merged factorization + solve DAG (one ticket order for both task
+    kinds); returns (tiles, linv, X) like factor() and solve()."""
+    rng = np.random.default_rng(seed)
+    ex = lambda k: S.stiles_symbolic_export(plan._sym.handle, k)
+    tasks, succ, P = ex("mtask").reshape(-1, 8), ex("msucc"), ex("mpairs").reshape(-1, 2)
+    T, ntr = plan.T, plan.ntr
+    tiles = scatter(plan, Aperm)
+    linv = np.zeros((ntr, T, T))
+    part = np.zeros((max(plan.npart, 1), T, T))
+    done_tile = np.zeros(len(plan.tcol), dtype=bool)   # final value written
+    nrhs = B.shape[1]
+    Y = np.zeros((ntr, T, nrhs))
+    Bp = B[plan.perm]
+    for m in range(ntr):
+        rb, rc = plan.row_base[m], plan.row_cnt[m]
+        Y[m, :rc] = Bp[rb:rb + rc]
+    Z = np.zeros_like(Y)
+    Q = {}
+
+    def tile(t):
+        assert done_tile[t], "solve task read a factor tile before it was final"
+        return tiles[t]
+
+    for t in _order(tasks, succ, mode, rng):
+        w = tasks[t]
+        typ = w[0] & 0xff
+        m = w[1]
+        if typ in (UPD, PART):
+            acc = sum(tiles[P[p, 0]] @ tiles[P[p, 1]].T for p in range(w[2], w[3]))
+            if typ == UPD:
+                tiles[w[1]] -= np.tril(acc) if w[0] & TF_DIAG else acc
+            elif w[0] & TF_ACC:
+                part[w[4]] += acc
+            else:
+                part[w[4]] = acc
+        elif typ == TREE:
+            s_ = part[w[2]] + (part[w[3]] if w[3] >= 0 else 0.0)
+            if w[4] >= 0:
+                part[w[4]] = s_
+            else:
+                tiles[w[1]] -= s_
+        elif typ == POTRF:
+            C = tiles[w[1]].copy()
+            for p in range(w[3], w[4]):
+                C -= tiles[P[p, 0]] @ tiles[P[p, 1]].T
+            L = np.linalg.cholesky(np.tril(C) + np.tril(C, -1).T)
+            tiles[w[1]] = L
+            linv[w[2]] = np.linalg.inv(L)
+            done_tile[w[1]] = True
+        elif typ == TRSM:
+            C = tiles[w[1]].copy()
+            for p in range(w[3], w[4]):
+                C -= tiles[P[p, 0]] @ tiles[P[p, 1]].T
+            tiles[w[1]] = C @ linv[w[2]].T
+            done_tile[w[1]] = True
+        elif typ == FUPD:
+            for p in range(w[2], w[3]):
+                Y[m] -= tile(P[p, 0]) @ Y[P[p, 1]]
+        elif typ == FPART:
+            q = np.zeros_like(Y[m])
+            for p in range(w[2], w[3]):
+                q += tile(P[p, 0]) @ Y[P[p, 1]]
+            Q[w[4]] = q
+        elif typ == FSUM:
+            for s_ in range(w[2], w[3]):
+                Y[m] -= Q.pop(s_)
+        elif typ == FDIAG:
+            v = Y[m].copy()
+            for p in range(w[2], w[3]):
+                v -= tile(P[p, 0]) @ Y[P[p, 1]]
+            Y[m] = linv[m] @ v
+        elif typ == BUPD:
+            v = (Y[m] if w[0] & TF_FIRST else Z[m]).copy()
+            for p in range(w[2], w[3]):
+                v -= tile(P[p, 0]).T @ Z[P[p, 1]]
+            Z[m] = v
+        elif typ == BDIAG:
+            v = (Y[m] if w[0] & TF_FIRST else Z[m]).copy()
+            for p in range(w[2], w[3]):
+                v -= tile(P[p, 0]).T @ Z[P[p, 1]]
+            Z[m] = linv[m].T @ v
+        else:
+            raise AssertionError("unknown task type %d" % typ)
+    X = np.zeros_like(B)
+    Xp = np.zeros_like(B)
+    for m in range(ntr):
+        rb, rc = plan.row_base[m], plan.row_cnt[m]
+        Xp[rb:rb + rc] = Z[m, :rc]
+    X[plan.perm] = Xp
+    return tiles, linv, X

@@ -1,0 +1,76 @@
+"""stiles_factorize_solve: factorization and solve as one launch of the
+merged task graph.  The factor, the solution and the log-determinant must be
+bitwise those of stiles_factorize + stiles_solve (same tasks, same
+accumulation orders), and match the oracle within 1e-12."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_02483_amd as S
+from paper_2501_02483_amd import inputs as I
+
+from gpu_util import oracle_reference, rel, say, to_device_cols
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # n, arrow, widths, segment, tile, ordering, parts, nrhs
+    (3000, 20, [20, 90, 40], 500, 64, S.STILES_ORDER_NONE, 0, 1),
+    (3001, 33, [10, 120, 60], 400, 32, S.STILES_ORDER_NONE, 0, 8),
+    (5000, 70, [30, 150, 80, 40], 600, 64, S.STILES_ORDER_ADAPTABLE_ND, 0, 8),
+    (4000, 0, 50, None, 64, S.STILES_ORDER_ADAPTABLE_ND, 3, 16),
+    (2500, 100, [8, 60], 250, 32, S.STILES_ORDER_ADAPTABLE_ND, 5, 20),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "n%d_T%d_o%d_P%d_r%d" % (c[0], c[4], c[5], c[6], c[7]))
+def test_factorize_solve_matches_separate_calls(case):
+    import torch
+    n, a, w, seg, T, ordering, parts, nrhs = case
+    p = I.make_pattern(n, a, w, seg=seg)
+    vals = I.make_values(p, seed=n + T)
+    B = I.rhs(p.N, nrhs, seed=13)
+    ref = oracle_reference(p, vals, B)
+    sym = S.Symbolic.from_pattern(p, tile=T, ordering=ordering, nd_parts=parts)
+    say("[gpu factorize_solve] n=%d T=%d ordering %d P=%d nrhs %d" % (n, T, ordering, sym.info.nd_parts, nrhs))
+    dv = torch.from_numpy(vals).cuda()
+    one = S.Factor(sym, nrhs_max=nrhs)
+    one.factorize(dv)
+    X1 = to_device_cols(B)
+    one.solve(X1)
+    both = S.Factor(sym, nrhs_max=nrhs)
+    X2 = to_device_cols(B)
+    both.factorize_solve(dv, X2)
+    assert both.info() == 0
+    assert torch.equal(X1, X2)
+    assert torch.equal(one.logdet(), both.logdet())
+    if ordering == S.STILES_ORDER_NONE:
+        assert torch.equal(one.extract(), both.extract())
+    eX = rel(X2.cpu().numpy(), ref["X"])
+    say("   X error %.2e" % eX)
+    assert eX <= 1e-12
+    # the same workspace again (counters re-armed), new values
+    vals2 = I.make_values(p, seed=n + T + 1)
+    X3 = to_device_cols(B)
+    both.factorize_solve(torch.from_numpy(vals2).cuda(), X3)
+    ref2 = oracle_reference(p, vals2, B)
+    assert rel(X3.cpu().numpy(), ref2["X"]) <= 1e-12
+
+
+def test_factorize_solve_failure_and_mixed():
+    import torch
+    p = I.make_pattern(2000, 10, 40)
+    vals = I.make_values(p, seed=9)
+    rp = p.row_ptr()
+    vals[rp[1501] - 1] = -2.0
+    sym = S.Symbolic.from_pattern(p, tile=64)
+    fac = S.Factor(sym)
+    b = torch.ones(p.N, dtype=torch.float64, device="cuda")
+    say("[gpu factorize_solve] non-SPD and mixed precision")
+    fac.factorize_solve(torch.from_numpy(vals).cuda(), b)
+    assert fac.info() > 0
+    assert torch.isnan(b).all()
+    mixed = S.Factor(sym, S.STILES_MIXED32)
+    with pytest.raises(S.StilesError) as e:
+        mixed.factorize_solve(torch.from_numpy(vals).cuda(), b)
+    assert e.value.status == S.STILES_ENOTSUP

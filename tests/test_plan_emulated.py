@@ -153,3 +153,35 @@ def test_long_forward_rows_use_partials():
     plan = E.Plan(sym)
     types = plan.stask[:, 0] & 0xff
     assert (types == E.FPART).sum() >= 2 and (types == E.FSUM).sum() >= 1
+
+
+@pytest.mark.parametrize("shape", SHAPES[:4] + SHAPES[5:], ids=lambda s: "n%d_a%d_T%d" % (s[0], s[1], s[4]))
+@pytest.mark.parametrize("mode", ["ticket", "random"])
+def test_emulated_merged_factor_solve(shape, mode):
+    """The merged factorization + solve DAG: every solve task runs only after
+    the factor tiles it reads are final, and the result is the oracle's."""
+    n, a, w, seg, T, ratio = shape
+    p = I.make_pattern(n, a, w, seg=seg)
+    vals = I.make_values(p, seed=n + a)
+    sym = S.Symbolic.from_pattern(p, tile=T, tree_min_ratio=ratio)
+    plan = E.Plan(sym)
+    B = I.rhs(p.N, 3, seed=9)
+    tiles, linv, X = E.factor_solve(plan, I.to_dense(p, vals), B, mode=mode, seed=n + 3)
+    Lo, Lv = _oracle_dense_L(p, vals)
+    assert np.linalg.norm(E.dense_factor(plan, tiles) - Lo) / np.linalg.norm(Lo) <= 1e-12
+    Xo = oracle.solve(p.f, Lv, B)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
+
+
+@pytest.mark.parametrize("parts", [2, 0])
+def test_emulated_merged_factor_solve_nd(parts):
+    p = I.make_pattern(3000, 24, [20, 90, 45], seg=600)
+    vals = I.make_values(p, seed=31)
+    sym = S.Symbolic.from_pattern(p, tile=32, ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=parts)
+    plan = E.Plan(sym)
+    A = I.to_dense(p, vals)
+    B = I.rhs(p.N, 2, seed=4)
+    _, _, X = E.factor_solve(plan, A[np.ix_(plan.perm, plan.perm)], B, mode="random", seed=parts)
+    L, info = oracle.factor(p.f, vals)
+    Xo = oracle.solve(p.f, L, B)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
