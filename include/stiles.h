@@ -89,7 +89,12 @@ typedef struct stiles_opts {
                              right-hand side is <= refine_tol (0 = 2^-52 * N^0.5)    */
   int32_t refine_max_iter;/* mixed mode: at most this many refinement steps (0 = 30) */
   int32_t nd_parts;       /* ADAPTABLE_ND: number of partitions, 2..64 (0 = choose)   */
-  int32_t reserved[2];
+  int32_t sched_workers;  /* ticket order of the task DAGs: the start order of a list
+                             schedule (longest remaining path first) on this many
+                             workgroups (0 = 512, a full MI355X launch); -1 = order by
+                             earliest start with unlimited workgroups.  Only the speed
+                             depends on it: every order gives bitwise the same results */
+  int32_t reserved[1];
 } stiles_opts;
 
 typedef struct stiles_symbolic_info {
@@ -313,6 +318,12 @@ stiles_status stiles_factor_kernel_ms(stiles_factor* f, int32_t which, float* ms
  * (stiles_symbolic_info: factor_tasks, solve_tasks); NULL switches it off. */
 stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_factor_trace, void* d_solve_trace,
                                       hipStream_t stream);
+
+/* The same per-task trace for the merged launch of stiles_factorize_solve
+ * (32 bytes per task of that DAG: stiles_symbolic_export kind 14 holds 8
+ * words per task).  FP64 factors only (STILES_ENOTSUP otherwise); NULL
+ * switches it off. */
+stiles_status stiles_factor_set_merged_trace(stiles_factor* f, void* d_trace, hipStream_t stream);
 
 /* Upper bound on the workgroups a factorization launch uses (0 = fill the
  * GPU).  Lets several factorizations on different streams share the GPU. */

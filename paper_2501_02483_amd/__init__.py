@@ -24,7 +24,7 @@ __all__ = [
     "stiles_batch_destroy", "Batch", "SelInv", "stiles_selinv_query", "stiles_selinv_workspace_size",
     "stiles_selinv_create", "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract",
     "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
-    "stiles_factorize_solve",
+    "stiles_factorize_solve", "stiles_factor_set_merged_trace",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -54,13 +54,14 @@ EXPORTED = [
     "stiles_batch_destroy", "stiles_selinv_query", "stiles_selinv_workspace_size", "stiles_selinv_create",
     "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract", "stiles_selinv_set_timing",
     "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy", "stiles_factorize_solve",
+    "stiles_factor_set_merged_trace",
 ]
 
 
 class stiles_opts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("ordering", ctypes.c_int32), ("tree_min_ratio", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
-                ("nd_parts", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("nd_parts", ctypes.c_int32), ("sched_workers", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class stiles_symbolic_info(ctypes.Structure):
@@ -118,6 +119,7 @@ def load_library(path=LIB_PATH):
         "stiles_factor_set_timing": (_i32, [_vp, _i32]),
         "stiles_factor_kernel_ms": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_float)]),
         "stiles_factor_set_trace": (_i32, [_vp, _vp, _vp, _vp]),
+        "stiles_factor_set_merged_trace": (_i32, [_vp, _vp, _vp]),
         "stiles_symbolic_export": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_i64)]),
         "stiles_batch_create": (_i32, [_i32, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
         "stiles_batch_factorize": (_i32, [_vp, _vp, _vp]),
@@ -179,11 +181,12 @@ def _stream(stream=None):
 # ------------------------------------------------------- raw C-ABI wrappers
 
 def stiles_default_opts(tile=64, ordering=STILES_ORDER_AUTO, tree_min_ratio=2, chunk=0, refine_tol=0.0,
-                        refine_max_iter=0, nd_parts=0):
+                        refine_max_iter=0, nd_parts=0, sched_workers=0):
     o = stiles_opts()
     load_library().stiles_default_opts(ctypes.byref(o))
     o.tile, o.ordering, o.tree_min_ratio, o.chunk = tile, ordering, tree_min_ratio, chunk
     o.refine_tol, o.refine_max_iter, o.nd_parts = refine_tol, refine_max_iter, nd_parts
+    o.sched_workers = sched_workers
     return o
 
 
@@ -316,6 +319,11 @@ def stiles_factor_kernel_ms(fac, which):
 def stiles_factor_set_trace(fac, d_factor_trace, d_solve_trace, stream=None):
     _check(load_library().stiles_factor_set_trace(fac, _ptr(d_factor_trace), _ptr(d_solve_trace), _stream(stream)),
            "stiles_factor_set_trace")
+
+
+def stiles_factor_set_merged_trace(fac, d_trace, stream=None):
+    _check(load_library().stiles_factor_set_merged_trace(fac, _ptr(d_trace), _stream(stream)),
+           "stiles_factor_set_merged_trace")
 
 
 def stiles_selinv_query(sym):

@@ -5,7 +5,9 @@
 // (Algorithm 1 task types, Algorithm 2 progress counters, Algorithm 3 trees).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <numeric>
 #include <queue>
 #include <utility>
@@ -36,11 +38,17 @@ struct TaskBuilder {
   }
 };
 
+// workgroups of the list schedule: a full-GPU executor launch has two per CU
+// on 256 CUs; -1 (option) = unbounded earliest-start order
+int sched_workers(const stiles_opts& o) { return o.sched_workers == 0 ? 512 : o.sched_workers < 0 ? 0 : o.sched_workers; }
+
 // Static schedule: earliest start in an unbounded-resource model (hop latency
-// on every edge), ties broken by longer remaining path.  Tasks are renumbered
-// in that order, which is topological; workgroups take them in this order.
+// on every edge), ties broken by longer remaining path, or (workers > 0) the
+// start order of a list schedule on that many workgroups.  Tasks are
+// renumbered in that order, which is topological; workgroups take them in
+// this order.  est_out always receives the unbounded-resource estimate.
 void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int32_t>& succ_out,
-              std::vector<float>* est_out, std::vector<int32_t>* pair_words, bool remap_pairs) {
+              std::vector<float>* est_out, std::vector<int32_t>* pair_words, bool remap_pairs, int workers) {
   (void)pair_words;
   (void)remap_pairs;
   const int nt = (int)tb.cost.size();
@@ -68,11 +76,55 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
     bl[t] = b + tb.cost[t];
   }
   std::vector<int32_t> order(nt);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    if (est[x] != est[y]) return est[x] < est[y];
-    return bl[x] > bl[y];
-  });
+  if (workers <= 0) {
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      if (est[x] != est[y]) return est[x] < est[y];
+      return bl[x] > bl[y];
+    });
+  } else {
+    // list scheduling on `workers` workgroups: whenever one is free it
+    // starts the ready task with the longest remaining path; tickets follow
+    // the simulated start order (topological: a task starts only after its
+    // predecessors have finished)
+    order.clear();
+    std::vector<int32_t> npred(nt);
+    std::vector<float> rdy(nt, 0.f);
+    typedef std::pair<float, int32_t> FI;
+    std::priority_queue<FI, std::vector<FI>, std::greater<FI>> pending, running;   // by ready / finish time
+    auto prio = [&](int32_t x, int32_t y) { return bl[x] != bl[y] ? bl[x] < bl[y] : x > y; };
+    std::priority_queue<int32_t, std::vector<int32_t>, decltype(prio)> ready(prio);
+    for (int t = 0; t < nt; t++) {
+      npred[t] = (int32_t)tb.preds[t].size();
+      if (npred[t] == 0) pending.push({0.f, t});
+    }
+    float now = 0.f;
+    int free_w = workers;
+    while ((int)order.size() < nt) {
+      while (!pending.empty() && pending.top().first <= now) { ready.push(pending.top().second); pending.pop(); }
+      while (free_w > 0 && !ready.empty()) {
+        const int32_t t = ready.top();
+        ready.pop();
+        order.push_back(t);
+        running.push({now + tb.cost[t], t});
+        free_w--;
+      }
+      float next = std::numeric_limits<float>::infinity();
+      if (!running.empty()) next = running.top().first;
+      if (free_w > 0 && !pending.empty()) next = std::min(next, pending.top().first);
+      if (!(next < std::numeric_limits<float>::infinity())) { fprintf(stderr, "stiles: list schedule stalled\n"); abort(); }
+      now = std::max(now, next);
+      while (!running.empty() && running.top().first <= now) {
+        const FI f = running.top();
+        running.pop();
+        free_w++;
+        for (int32_t x : succ[f.second]) {
+          rdy[x] = std::max(rdy[x], f.first + hop);
+          if (--npred[x] == 0) pending.push({rdy[x], x});
+        }
+      }
+    }
+  }
   std::vector<int32_t> newid(nt);
   for (int i = 0; i < nt; i++) newid[order[i]] = i;
   tasks_out.assign((size_t)nt * TASK_WORDS, 0);
@@ -97,6 +149,24 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
     for (int q = w[5]; q < w[6]; q++)
       if (succ_out[q] <= i) { fprintf(stderr, "stiles: schedule is not topological\n"); abort(); }
   }
+}
+
+// Chunks [lo, hi) of n products of a solve row that are ordered oldest first:
+// the chunks nearest the diagonal step, whose blocks are solved last, hold
+// c/4 and c/2 products (they run between two diagonal steps of the chain),
+// the others c.
+std::vector<std::pair<int32_t, int32_t>> chunk_bounds(int32_t n, int32_t c) {
+  std::vector<std::pair<int32_t, int32_t>> out;
+  int32_t hi = n;
+  const int32_t tail[2] = {std::max(1, c / 4), std::max(1, c / 2)};
+  for (int k = 0; hi > 0; k++) {
+    const int32_t len = k < 2 ? tail[k] : c;
+    const int32_t lo = std::max(0, hi - len);
+    out.push_back({lo, hi});
+    hi = lo;
+  }
+  std::reverse(out.begin(), out.end());
+  return out;
 }
 
 inline int64_t tile_of_col(const stiles_symbolic& s, int64_t g) {
@@ -451,6 +521,7 @@ stiles_status check_opts(const stiles_opts* o, int arg) {
   if (o->ordering < STILES_ORDER_AUTO || o->ordering > STILES_ORDER_ADAPTABLE_ND) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->nd_parts < 0 || o->nd_parts > 64) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->chunk < 0 || o->chunk > 32 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
+  if (o->sched_workers < -1 || o->sched_workers > 65536) { g_err_arg = arg; return STILES_EINVAL; }
   return STILES_OK;
 }
 
@@ -918,7 +989,7 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   }
   s.flops_exec = fexec;
   s.fpairs = pairs;
-  schedule(tb, s.ftask, s.fsucc, &s.fest, nullptr, false);
+  schedule(tb, s.ftask, s.fsucc, &s.fest, nullptr, false, sched_workers(s.opts));
 
   // ---- solve DAG (forward then backward sweep over tile rows)
   TaskBuilder sb;
@@ -956,8 +1027,8 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
       for (int q : parts) sb.dep(t, q);
       last = t;
     }
-    for (int32_t lo = rb; lo < body_end && !long_row; lo += schunk) {
-      int32_t hi = std::min(body_end, lo + schunk);
+    for (auto [lo0, hi0] : chunk_bounds(long_row ? 0 : body_end - rb, schunk)) {
+      const int32_t lo = rb + lo0, hi = rb + hi0;
       int32_t p0 = (int32_t)(sp.size() / 2);
       for (int32_t t = lo; t < hi; t++) { sp.push_back(t); sp.push_back(s.tcol[t]); }
       int32_t p1 = (int32_t)(sp.size() / 2);
@@ -983,8 +1054,8 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
     while (body_end > 0 && body_end + 2 > below.size() && below[body_end - 1].first <= m + 2) body_end--;
     int32_t last = -1;
     bool first = true;
-    for (size_t lo = 0; lo < body_end; lo += schunk) {
-      size_t hi = std::min(body_end, lo + schunk);
+    for (auto [lo0, hi0] : chunk_bounds((int32_t)body_end, schunk)) {
+      const size_t lo = (size_t)lo0, hi = (size_t)hi0;
       int32_t p0 = (int32_t)(sp.size() / 2);
       for (size_t q = lo; q < hi; q++) { sp.push_back(below[q].second); sp.push_back(below[q].first); }
       int32_t p1 = (int32_t)(sp.size() / 2);
@@ -1008,7 +1079,7 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
     bdiag[m] = t;
   }
   s.spairs = sp;
-  schedule(sb, s.stask, s.ssucc, nullptr, nullptr, false);
+  schedule(sb, s.stask, s.ssucc, nullptr, nullptr, false, sched_workers(s.opts));
 }
 
 // ---- selected inversion: Sigma = A^{-1} on the tile pattern of L.
@@ -1165,7 +1236,7 @@ void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
     sd[k] = tk;
   }
   P.flops_exec = fexec;
-  schedule(tb, P.task, P.succ, nullptr, nullptr, false);
+  schedule(tb, P.task, P.succ, nullptr, nullptr, false, sched_workers(s.opts));
   // algorithmic work of the element recursion, over the envelope before
   // adaptable ND: column j costs eta_j dot products of length eta_j plus one
   const std::vector<int64_t>& f = s.f_pre.empty() ? s.f : s.f_pre;
@@ -1264,9 +1335,18 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
     for (int32_t x : sl)
       if (x <= i) { fprintf(stderr, "stiles: merged DAG order is not topological\n"); abort(); }
     w[5] = (int32_t)D.succ.size();
-    D.succ.insert(D.succ.end(), sl.begin(), sl.end());
+    // edges from a factorization task to a solve task carry SUCC_FDEP
+    for (int32_t x : sl) D.succ.push_back(t < nf && order[x] >= nf ? (x | SUCC_FDEP) : x);
     w[6] = (int32_t)D.succ.size();
-    w[7] = (int32_t)pred[t].size();
+    if (t < nf) {
+      w[7] = (int32_t)pred[t].size();
+    } else {
+      int32_t nfd = 0;
+      for (int32_t x : pred[t]) nfd += x < nf;
+      const int32_t nsd = (int32_t)pred[t].size() - nfd;
+      if (nsd >= MERGED_FDEP || nfd >= (1 << 14)) { fprintf(stderr, "stiles: merged DAG: too many predecessors\n"); abort(); }
+      w[7] = nsd + nfd * MERGED_FDEP;
+    }
   }
   D.pairs = s.fpairs;
   D.pairs.insert(D.pairs.end(), s.spairs.begin(), s.spairs.end());

@@ -168,7 +168,7 @@ struct stiles_factor {
   size_t bytes = 0;
   Layout L{};
   Plan plan;
-  ExecMat mf{}, ms{};
+  ExecMat mf{}, ms{}, mm{};   // executor descriptors: factorization, solve, merged
   int32_t nmerged = 0;   // tasks of the merged factorization + solve DAG (FP64)
   int32_t max_wg = 0;
   int32_t state = 0;   // 0 unknown, 1 factored ok, 2 failed, -1 not factored
@@ -291,7 +291,7 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   if (!s->fin.empty()) U(L.fin, s->fin.data(), s->fin.size() * 8);
   if (!s->in_rp_in.empty()) U(L.in_rp_in, s->in_rp_in.data(), s->in_rp_in.size() * 8);
   std::vector<int32_t> mrem;
-  ExecMat mm{};
+  ExecMat& mm = f->mm;
   if (!mixed) {
     const MergedPlan& md = merged_plan(*s);
     f->nmerged = (int32_t)(md.task.size() / TASK_WORDS);
@@ -804,6 +804,16 @@ extern "C" stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_facto
   f->ms.trace = static_cast<unsigned long long*>(d_solve_trace);
   hipError_t e = hipMemcpyAsync(f->ws + f->L.mat_f, &f->mf, sizeof(ExecMat), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(f->ws + f->L.mat_s, &f->ms, sizeof(ExecMat), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
+extern "C" stiles_status stiles_factor_set_merged_trace(stiles_factor* f, void* d_trace, hipStream_t st) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (f->precision != STILES_FP64) return STILES_ENOTSUP;
+  f->mm.trace = static_cast<unsigned long long*>(d_trace);
+  hipError_t e = hipMemcpyAsync(f->ws + f->L.mat_m, &f->mm, sizeof(ExecMat), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }

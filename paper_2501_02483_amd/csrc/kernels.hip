@@ -800,15 +800,16 @@ struct SolveStage {
 #pragma unroll
     for (int q = 0; q < NVL; q++) lt[q] = lv[threadIdx.x + q * NT];
   }
-  __device__ __forceinline__ void load_vec(const double* __restrict__ v, int nrhs) {
+  static __device__ __forceinline__ void load_vec_to(d2* dst, const double* __restrict__ v, int nrhs) {
     const GLOBAL d2* vv = (const GLOBAL d2*)v;
     const int nv = T * nrhs / 2;
 #pragma unroll
     for (int q = 0; q < NVV; q++) {
       const int e = threadIdx.x + q * NT;
-      vb[q] = e < nv ? vv[e] : d2{0.0, 0.0};
+      dst[q] = e < nv ? vv[e] : d2{0.0, 0.0};
     }
   }
+  __device__ __forceinline__ void load_vec(const double* __restrict__ v, int nrhs) { load_vec_to(vb, v, nrhs); }
   __device__ __forceinline__ void store_tile(double* LL) const {
 #pragma unroll
     for (int q = 0; q < NVL; q++) {
@@ -886,7 +887,12 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   // output element of this lane: row 16 wave + (lane >> 4) + 4 r, column lane & 15
   const int col = lane & 15;
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  // base block: Y_m (forward), or Y_m / Z_m (backward, first chunk reads Y);
+  // a diagonal step loads it together with its first operands
+  const double* base = fwd ? M.vy + m * vb : ((w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb);
   SolveStage<T> st;
+  typename SolveStage<T>::d2 bv[SolveStage<T>::NVV];
+  if (diag) SolveStage<T>::load_vec_to(bv, base, nrhs);
   if (np > 0) st.load_vec(vsrc + word(pv, 1) * vb, nrhs);
   for (int p = 0; p < np; p++) {
     __syncthreads();
@@ -911,8 +917,6 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
     }
     return;
   }
-  // base block: Y_m (forward), or Y_m / Z_m (backward, first chunk reads Y)
-  const double* base = fwd ? M.vy + m * vb : ((w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb);
   GLOBAL double* dst = gp(fwd ? M.vy + m * vb : M.vz + m * vb);
   if (!diag) {
     if (act && col < nrhs) {
@@ -926,7 +930,8 @@ __device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int
   }
   // diagonal: out = Linv_m (base - acc)   (Linv_m^T in the backward sweep);
   // Linv_m was prefetched into LI
-  st.load_vec(base, nrhs);
+#pragma unroll
+  for (int q = 0; q < SolveStage<T>::NVV; q++) st.vb[q] = bv[q];
   __syncthreads();
   st.store_vec(LV);
   __syncthreads();
@@ -1373,8 +1378,22 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     int32_t* cnt = M.remaining + lid;
     uint64_t t_claim = 0, t_start = 0;
     if (M.trace) t_claim = wall_clock64();
+    const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
     if constexpr (SOLVE) solve_prefetch<T>(M, w, S, LI);
     if constexpr (SELINV) selinv_prefetch<T>(M, w, S, Xi);
+    // merged factorization + solve DAG: a solve task first waits for its
+    // factorization predecessors only (the counter falls below MERGED_FDEP),
+    // stages its factor tiles, then waits for its solve predecessors below
+    if constexpr (BOTH) {
+      if (type >= TK_FUPD) {
+        if (threadIdx.x < 64) {
+          while (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) >= MERGED_FDEP) __builtin_amdgcn_s_sleep(1);
+          fence_acquire();
+        }
+        __syncthreads();
+        solve_prefetch<T>(M, w, S, Xi);
+      }
+    }
 
     // wait until every predecessor has finished (Alg. 2 progress check);
     // wave 0 polls, then acquires for the workgroup (all its waves share
@@ -1386,13 +1405,6 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     __syncthreads();
     if (threadIdx.x == 0) st_relaxed(cnt, w[7]);   // re-arm for the next launch
     if (M.trace) t_start = wall_clock64();
-    const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
-    // in the merged factorization + solve DAG the factor tiles of a solve
-    // task are final only now: its operands are staged after the wait (the
-    // task body synchronizes before it reads them)
-    if constexpr (BOTH) {
-      if (type >= TK_FUPD) solve_prefetch<T>(M, w, S, Xi);
-    }
     // tasks on the pivot chain (diagonal factorization, panel solve, diagonal
     // solve steps) raise their waves' issue priority over the co-resident
     // update work of other workgroups on the same SIMDs
@@ -1434,8 +1446,14 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     const int32_t s0 = __builtin_amdgcn_readfirstlane(w[5]), s1 = __builtin_amdgcn_readfirstlane(w[6]);
     for (int32_t q0 = s0; q0 < s1; q0 += 64) {
       const int32_t q = q0 + (int32_t)threadIdx.x;
-      if (threadIdx.x < 64 && q < s1)
-        __hip_atomic_fetch_add(M.remaining + M.succ[q], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x < 64 && q < s1) {
+        int32_t sq = M.succ[q], dec = 1;
+        if constexpr (BOTH) {
+          dec = (sq & SUCC_FDEP) ? MERGED_FDEP : 1;
+          sq &= ~SUCC_FDEP;
+        }
+        __hip_atomic_fetch_add(M.remaining + sq, -dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     if (M.trace && threadIdx.x == 0) {
       unsigned long long* tr = M.trace + 4 * (int64_t)lid;

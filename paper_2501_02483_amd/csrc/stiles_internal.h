@@ -68,6 +68,14 @@ enum TaskFlag : int32_t {
 //        1: pushed-partial slots (qpart); summed in list order
 constexpr int TASK_WORDS = 8;
 constexpr int32_t SIG_TRANS = 1 << 30;
+// Merged factorization + solve DAG: a solve task's counter holds its solve
+// predecessors plus MERGED_FDEP per factorization predecessor, and a
+// successor entry with SUCC_FDEP set (an edge from a factorization task to a
+// solve task) subtracts MERGED_FDEP.  A solve task can therefore stage its
+// factor tiles as soon as the counter falls below MERGED_FDEP, while its
+// solve predecessors are still running.
+constexpr int32_t MERGED_FDEP = 1 << 16;
+constexpr int32_t SUCC_FDEP = 1 << 30;
 
 // Device-side description of one matrix (or one solve) for the executor.
 struct ExecMat {

@@ -16,6 +16,15 @@ FUPD, FDIAG, BUPD, BDIAG, FPART, FSUM = 8, 9, 10, 11, 12, 13
 SWE, SW, SDIAG, TSUM = 16, 17, 18, 19
 TF_DIAG, TF_FIRST, TF_ACC = 1 << 8, 1 << 9, 1 << 10
 SIG_TRANS = 1 << 30
+MERGED_FDEP, SUCC_FDEP = 1 << 16, 1 << 30
+
+
+def succ_edge(v):
+    """(successor, counter decrement) of a successor entry: an entry with
+    SUCC_FDEP (merged DAG, factorization task -> solve task) subtracts
+    MERGED_FDEP."""
+    v = int(v)
+    return (v & ~SUCC_FDEP, MERGED_FDEP) if v & SUCC_FDEP else (v, 1)
 
 
 class Plan:
@@ -51,7 +60,7 @@ def _order(tasks, succ, mode, rng):
         # ticket order must be topological: every successor has a larger index
         for t in range(n):
             for q in range(tasks[t, 5], tasks[t, 6]):
-                assert succ[q] > t
+                assert succ_edge(succ[q])[0] > t
         return list(range(n))
     rem = tasks[:, 7].copy()
     ready = [t for t in range(n) if rem[t] == 0]
@@ -61,8 +70,8 @@ def _order(tasks, succ, mode, rng):
         t = ready.pop(i)
         out.append(t)
         for q in range(tasks[t, 5], tasks[t, 6]):
-            s = succ[q]
-            rem[s] -= 1
+            s, dec = succ_edge(succ[q])
+            rem[s] -= dec
             assert rem[s] >= 0
             if rem[s] == 0:
                 ready.append(s)

@@ -185,3 +185,48 @@ def test_emulated_merged_factor_solve_nd(parts):
     L, info = oracle.factor(p.f, vals)
     Xo = oracle.solve(p.f, L, B)
     assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
+
+
+@pytest.mark.parametrize("parts", [None, 3])
+def test_merged_counters_split_factor_and_solve_predecessors(parts):
+    """Merged DAG counters: a solve task counts each factorization predecessor
+    as MERGED_FDEP and each solve predecessor as 1, the flagged successor
+    entries are exactly the factorization -> solve edges, and the
+    factorization predecessors of a solve task include the final task of
+    every factor tile it reads and, for a diagonal step, the POTRF of its
+    row -- so its tiles may be staged once the counter is below MERGED_FDEP."""
+    p = I.make_pattern(2500, 18, [16, 70, 30], seg=500)
+    kw = dict(ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=parts) if parts else {}
+    sym = S.Symbolic.from_pattern(p, tile=32, **kw)
+    ex = lambda k: S.stiles_symbolic_export(sym.handle, k)
+    tasks, succ, P = ex("mtask").reshape(-1, 8), ex("msucc"), ex("mpairs").reshape(-1, 2)
+    typ = tasks[:, 0] & 0xff
+    is_fac = typ < E.FUPD
+    n = len(tasks)
+    fpred = [set() for _ in range(n)]
+    spred = [0] * n
+    final_of, potrf_of = {}, {}
+    for t in range(n):
+        if typ[t] in (E.POTRF, E.TRSM):
+            final_of[int(tasks[t, 1])] = t
+        if typ[t] == E.POTRF:
+            potrf_of[int(tasks[t, 2])] = t
+        for q in range(tasks[t, 5], tasks[t, 6]):
+            x, dec = E.succ_edge(succ[q])
+            assert x > t
+            assert (dec == E.MERGED_FDEP) == (is_fac[t] and not is_fac[x])
+            if is_fac[t]:
+                fpred[x].add(t)
+            else:
+                spred[x] += 1
+    for t in range(n):
+        if is_fac[t]:
+            assert tasks[t, 7] == len(fpred[t]) and spred[t] == 0
+            continue
+        assert tasks[t, 7] == spred[t] + E.MERGED_FDEP * len(fpred[t])
+        if typ[t] == E.FSUM:
+            continue
+        for q in range(tasks[t, 2], tasks[t, 3]):
+            assert final_of[int(P[q, 0])] in fpred[t]
+        if typ[t] in (E.FDIAG, E.BDIAG):
+            assert potrf_of[int(tasks[t, 1])] in fpred[t]
