@@ -847,105 +847,192 @@ __device__ __forceinline__ v4d solve_mma(v4d acc, const double* LL, const double
   return acc + acc1;
 }
 
-// Static operands of a solve task (the factor is final before the solve
-// starts): the first product's L tile into LL and, for a diagonal step, the
-// inverse diagonal tile into LI.  Issued before the task waits for its
-// predecessors, so the waiting hides these loads.
+// ---------------------------------------------------------- solve tasks
+// MFMA operands are read from global memory straight into registers.  At
+// MFMA step s the four k-groups of the 16 x 16 x 4 instruction (lane >> 4 =
+// g) take k = (T/4) g + s, so that one lane's operands are contiguous: the
+// B operand (vector block, column lane & 15) is one run of T/4 doubles, and
+// so is the A operand of a transposed tile (backward sweep: A(r, k) =
+// L(k, r), a piece of column r); a direct tile (forward sweep) is read as
+// T/4 loads whose 16 lanes cover 16 consecutive rows.  Wave w owns rows
+// 16 w .. 16 w + 15 of the T x 16 result (waves past T/16 idle).
 template <int T>
-__device__ __forceinline__ void solve_prefetch(const ExecMat& M, const int32_t* w, double* LL, double* LI) {
-  constexpr int TT = T * T;
-  const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
-  if (type == TK_FSUM) return;
-  const int p0 = __builtin_amdgcn_readfirstlane(w[2]), p1 = __builtin_amdgcn_readfirstlane(w[3]);
-  SolveStage<T> st;
-  if (p1 > p0) {
-    st.load_tile(M.tiles + (int64_t)M.pairs[2 * p0] * TT);
-    st.store_tile(LL);
+struct SolveOps {
+  static constexpr int NS = T / 4;   // MFMA steps per tile
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  // A operand of tile Lt for rows 16 w + (lane & 15)
+  static __device__ __forceinline__ void load_a(double (&a)[NS], const double* Lt, bool trans, int wave, int lane) {
+    const int r = 16 * wave + (lane & 15), g = lane >> 4;
+    if (trans) {
+      const GLOBAL d2* p = (const GLOBAL d2*)(Lt + NS * g + (int64_t)r * T);
+#pragma unroll
+      for (int q = 0; q < NS / 2; q++) {
+        const d2 v = p[q];
+        a[2 * q] = v.x;
+        a[2 * q + 1] = v.y;
+      }
+    } else {
+      const GLOBAL double* p = gp(Lt) + r + (int64_t)NS * g * T;
+#pragma unroll
+      for (int q = 0; q < NS; q++) a[q] = p[(int64_t)q * T];
+    }
   }
-  if (type == TK_FDIAG || type == TK_BDIAG) {
-    st.load_tile(M.linv + (int64_t)__builtin_amdgcn_readfirstlane(w[1]) * TT);
-    st.store_tile(LI);
+  // B operand of a vector block (T x nrhs, leading dimension T) in global memory
+  static __device__ __forceinline__ void load_b(double (&b)[NS], const double* V, int nrhs, int lane) {
+    const int j = lane & 15, g = lane >> 4;
+    const GLOBAL d2* p = (const GLOBAL d2*)(V + NS * g + (int64_t)j * T);
+    const bool ok = j < nrhs;
+#pragma unroll
+    for (int q = 0; q < NS / 2; q++) {
+      const d2 v = ok ? p[q] : d2{0.0, 0.0};
+      b[2 * q] = v.x;
+      b[2 * q + 1] = v.y;
+    }
   }
+  // the same from a T x 16 block in LDS
+  static __device__ __forceinline__ void load_b_lds(double (&b)[NS], const double* V, int lane) {
+    const int j = lane & 15, g = lane >> 4;
+    const d2* p = (const d2*)(V + NS * g + j * T);
+#pragma unroll
+    for (int q = 0; q < NS / 2; q++) {
+      const d2 v = p[q];
+      b[2 * q] = v.x;
+      b[2 * q + 1] = v.y;
+    }
+  }
+  // acc += A B over the T/4 steps, two accumulation chains
+  static __device__ __forceinline__ v4d mma(v4d acc, const double (&a)[NS], const double (&b)[NS]) {
+    v4d acc1 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NS; q += 2) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q + 1], b[q + 1], acc1, 0, 0, 0);
+    }
+    return acc + acc1;
+  }
+};
+
+// the calling workgroup waits until *cnt is zero, then acquires
+__device__ __forceinline__ void wait_zero(int32_t* cnt) {
+  if (threadIdx.x < 64) {
+    while (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) > 0) __builtin_amdgcn_s_sleep(1);
+    fence_acquire();
+  }
+  __syncthreads();
 }
 
-// A solve task; its static operands are already staged by solve_prefetch.
+// A solve task (FUPD, FDIAG, BUPD, BDIAG, FPART).  It waits for its
+// predecessors itself (*cnt): the factor tiles of a diagonal step (at most
+// two fused products and the inverse diagonal tile) are read into registers
+// first, so that only the small vector blocks are loaded once the
+// predecessors are done.  The factor tiles must be final when it is called.
 template <int T, int K>
-__device__ __attribute__((noinline)) void task_solve(const ExecMat& M, const int32_t* w, int nrhs, double* LL,
-                                                     double* LV, const double* LI) {
-  constexpr int TT = T * T;
+__device__ __forceinline__ uint64_t task_solve_r(const ExecMat& M, const int32_t* w, int nrhs, int32_t* cnt,
+                                                           double* LV) {
+  typedef SolveOps<T> O;
+  constexpr int TT = T * T, NS = O::NS;
   const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = 16 * wave < T;
-  const int m = w[1];
+  const int m = __builtin_amdgcn_readfirstlane(w[1]);
   const int64_t vb = (int64_t)T * nrhs;
   const bool fwd = type == TK_FUPD || type == TK_FDIAG || type == TK_FPART;
   const bool diag = type == TK_FDIAG || type == TK_BDIAG;
   const double* vsrc = fwd ? M.vy : M.vz;
-  const double* tiles = M.tiles;
   const int p0 = __builtin_amdgcn_readfirstlane(w[2]), np = __builtin_amdgcn_readfirstlane(w[3]) - p0;
   const int pv = load_words(M.pairs + 2 * p0, 2 * np);
-  // output element of this lane: row 16 wave + (lane >> 4) + 4 r, column lane & 15
+  // output element of this lane, register r: row 16 wave + (lane >> 4) + 4 r, column lane & 15
   const int col = lane & 15;
-  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-  // base block: Y_m (forward), or Y_m / Z_m (backward, first chunk reads Y);
-  // a diagonal step loads it together with its first operands
   const double* base = fwd ? M.vy + m * vb : ((w[0] & TF_FIRST) ? M.vy + m * vb : M.vz + m * vb);
-  SolveStage<T> st;
-  typename SolveStage<T>::d2 bv[SolveStage<T>::NVV];
-  if (diag) SolveStage<T>::load_vec_to(bv, base, nrhs);
-  if (np > 0) st.load_vec(vsrc + word(pv, 1) * vb, nrhs);
-  for (int p = 0; p < np; p++) {
-    __syncthreads();
-    if (p > 0) st.store_tile(LL);   // the first tile was prefetched
-    st.store_vec(LV);
-    __syncthreads();
-    if (p + 1 < np) {
-      st.load_tile(tiles + (int64_t)word(pv, 2 * p + 2) * TT);
-      st.load_vec(vsrc + word(pv, 2 * p + 3) * vb, nrhs);
+  GLOBAL double* dst = gp(fwd ? M.vy + m * vb : M.vz + m * vb);
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  if (diag) {
+    // static operands first (at most two fused products), then the wait
+    double a0[NS], a1[NS], ai[NS], b0[NS], b1[NS];
+    if (act) {
+      if (np > 0) O::load_a(a0, M.tiles + (int64_t)word(pv, 0) * TT, !fwd, wave, lane);
+      if (np > 1) O::load_a(a1, M.tiles + (int64_t)word(pv, 2) * TT, !fwd, wave, lane);
+      O::load_a(ai, M.linv + (int64_t)m * TT, !fwd, wave, lane);
     }
-    if (act) acc = solve_mma<T>(acc, LL, LV, !fwd, wave, lane);
+    wait_zero(cnt);
+    const uint64_t t_start = M.trace ? wall_clock64() : 0;
+    double bs[4];
+    if (act) {
+      if (np > 0) O::load_b(b0, vsrc + word(pv, 1) * vb, nrhs, lane);
+      if (np > 1) O::load_b(b1, vsrc + word(pv, 3) * vb, nrhs, lane);
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = 16 * wave + (lane >> 4) + 4 * r;
+        bs[r] = col < nrhs ? gp(base)[row + col * T] : 0.0;
+      }
+      if (np > 0) acc = O::mma(acc, a0, b0);
+      if (np > 1) acc = O::mma(acc, a1, b1);
+      // base - acc into LDS (T x 16, leading dimension T) for the product
+      // with the inverse diagonal tile
+#pragma unroll
+      for (int r = 0; r < 4; r++) LV[(16 * wave + (lane >> 4) + 4 * r) + col * T] = bs[r] - acc[r];
+    }
+    __syncthreads();
+    if (act) {
+      O::load_b_lds(b0, LV, lane);
+      const v4d out = O::mma(v4d{0.0, 0.0, 0.0, 0.0}, ai, b0);
+      if (col < nrhs) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) st_dev(dst + (16 * wave + (lane >> 4) + 4 * r) + col * T, out[r]);
+      }
+    }
+    return t_start;
   }
+  // a chunk of products: the factor tiles of the first two pairs are read
+  // before the wait; then two pairs stay in flight (the operands of pair
+  // p + 2 are loaded while pair p + 1 is multiplied)
+  double a[2][NS], b[2][NS], bs[4];
+  if (act && np > 0) {
+    O::load_a(a[0], M.tiles + (int64_t)word(pv, 0) * TT, !fwd, wave, lane);
+    if (np > 1) O::load_a(a[1], M.tiles + (int64_t)word(pv, 2) * TT, !fwd, wave, lane);
+  }
+  wait_zero(cnt);
+  const uint64_t t_start = M.trace ? wall_clock64() : 0;
+  if (act) {
+    if (np > 0) O::load_b(b[0], vsrc + word(pv, 1) * vb, nrhs, lane);
+    if (np > 1) O::load_b(b[1], vsrc + word(pv, 3) * vb, nrhs, lane);
+    if (type != TK_FPART) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = 16 * wave + (lane >> 4) + 4 * r;
+        bs[r] = col < nrhs ? gp(base)[row + col * T] : 0.0;
+      }
+    }
+    for (int p = 0; p < np; p += 2) {
+      acc = O::mma(acc, a[0], b[0]);
+      if (p + 2 < np) {
+        O::load_a(a[0], M.tiles + (int64_t)word(pv, 2 * p + 4) * TT, !fwd, wave, lane);
+        O::load_b(b[0], vsrc + word(pv, 2 * p + 5) * vb, nrhs, lane);
+      }
+      if (p + 1 < np) {
+        acc = O::mma(acc, a[1], b[1]);
+        if (p + 3 < np) {
+          O::load_a(a[1], M.tiles + (int64_t)word(pv, 2 * p + 6) * TT, !fwd, wave, lane);
+          O::load_b(b[1], vsrc + word(pv, 2 * p + 7) * vb, nrhs, lane);
+        }
+      }
+    }
+  }
+  if (!act) return t_start;
   if (type == TK_FPART) {
     // one chunk of a long row: the partial product into its slot
     GLOBAL double* q = gp(M.vpart + (int64_t)w[4] * vb);
-    if (act && col < nrhs) {
+    if (col < nrhs) {
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int row = 16 * wave + (lane >> 4) + 4 * r;
-        st_dev(q + row + col * T, acc[r]);
-      }
+      for (int r = 0; r < 4; r++) st_dev(q + (16 * wave + (lane >> 4) + 4 * r) + col * T, acc[r]);
     }
-    return;
+    return t_start;
   }
-  GLOBAL double* dst = gp(fwd ? M.vy + m * vb : M.vz + m * vb);
-  if (!diag) {
-    if (act && col < nrhs) {
+  if (col < nrhs) {
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int row = 16 * wave + (lane >> 4) + 4 * r;
-        st_dev(dst + row + col * T, gp(base)[row + col * T] - acc[r]);
-      }
-    }
-    return;
+    for (int r = 0; r < 4; r++) st_dev(dst + (16 * wave + (lane >> 4) + 4 * r) + col * T, bs[r] - acc[r]);
   }
-  // diagonal: out = Linv_m (base - acc)   (Linv_m^T in the backward sweep);
-  // Linv_m was prefetched into LI
-#pragma unroll
-  for (int q = 0; q < SolveStage<T>::NVV; q++) st.vb[q] = bv[q];
-  __syncthreads();
-  st.store_vec(LV);
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int r = 0; r < 4; r++) LV[(16 * wave + (lane >> 4) + 4 * r) + col * T] -= acc[r];
-  }
-  __syncthreads();
-  v4d out = v4d{0.0, 0.0, 0.0, 0.0};
-  if (act) out = solve_mma<T>(out, LI, LV, !fwd, wave, lane);
-  if (act && col < nrhs) {
-#pragma unroll
-    for (int r = 0; r < 4; r++) st_dev(dst + (16 * wave + (lane >> 4) + 4 * r) + col * T, out[r]);
-  }
+  return t_start;
 }
 
 // Y_m -= Q_a + ... + Q_(b-1): the partial products of a long row, summed in
@@ -1379,11 +1466,10 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     uint64_t t_claim = 0, t_start = 0;
     if (M.trace) t_claim = wall_clock64();
     const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
-    if constexpr (SOLVE) solve_prefetch<T>(M, w, S, LI);
     if constexpr (SELINV) selinv_prefetch<T>(M, w, S, Xi);
     // merged factorization + solve DAG: a solve task first waits for its
-    // factorization predecessors only (the counter falls below MERGED_FDEP),
-    // stages its factor tiles, then waits for its solve predecessors below
+    // factorization predecessors only (the counter falls below MERGED_FDEP);
+    // its factor tiles are final then
     if constexpr (BOTH) {
       if (type >= TK_FUPD) {
         if (threadIdx.x < 64) {
@@ -1391,19 +1477,15 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
           fence_acquire();
         }
         __syncthreads();
-        solve_prefetch<T>(M, w, S, Xi);
       }
     }
-
+    // solve tasks other than FSUM wait for their predecessors themselves,
+    // after reading their factor tiles
+    const bool self_wait = (SOLVE || BOTH) && type >= TK_FUPD && type != TK_FSUM;
     // wait until every predecessor has finished (Alg. 2 progress check);
     // wave 0 polls, then acquires for the workgroup (all its waves share
     // the CU's caches that the acquire invalidates)
-    if (threadIdx.x < 64) {
-      while (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) > 0) __builtin_amdgcn_s_sleep(1);
-      fence_acquire();
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) st_relaxed(cnt, w[7]);   // re-arm for the next launch
+    if (!self_wait) wait_zero(cnt);
     if (M.trace) t_start = wall_clock64();
     // tasks on the pivot chain (diagonal factorization, panel solve, diagonal
     // solve steps) raise their waves' issue priority over the co-resident
@@ -1419,10 +1501,10 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       else task_tsum<T>(M, w);
     } else if constexpr (SOLVE) {
       if (type == TK_FSUM) task_fsum<T, KIND>(M, w, nrhs);
-      else task_solve<T, KIND>(M, w, nrhs, S, Xi, LI);
+      else t_start = task_solve_r<T, KIND>(M, w, nrhs, cnt, Xi);
     } else if (BOTH && type >= TK_FUPD) {
       if (type == TK_FSUM) task_fsum<T, KIND>(M, w, nrhs);
-      else task_solve<T, KIND>(M, w, nrhs, S, LI, Xi);
+      else t_start = task_solve_r<T, KIND>(M, w, nrhs, cnt, LI);
     } else {
       switch (type) {
         case TK_UPD: task_update<T, KIND>(M, w, 0, S, Xi); break;
@@ -1443,6 +1525,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (threadIdx.x == 0) st_relaxed(cnt, w[7]);   // re-arm for the next launch
     const int32_t s0 = __builtin_amdgcn_readfirstlane(w[5]), s1 = __builtin_amdgcn_readfirstlane(w[6]);
     for (int32_t q0 = s0; q0 < s1; q0 += 64) {
       const int32_t q = q0 + (int32_t)threadIdx.x;
