@@ -944,6 +944,51 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
           start = nb;
         }
       }
+      // corner tiles: the products over arrow and separator columns become
+      // available only as the separators are factored, and an arrow row
+      // meets every separator.  When there are many, they are independent
+      // partial products (each as soon as its columns are final) summed by a
+      // binary tree in index order, instead of a sequential chain of updates
+      if (corner && s.opts.tree_min_ratio > 0) {
+        const bool fl = pr.size() > start && pj.back() == k - 1;
+        // the last `chunk` products (the most recent columns, on the pivot
+        // chain) stay in an update task after the tree
+        const size_t be = (fl ? pr.size() - 1 : pr.size()) - std::min(pr.size() - (fl ? 1 : 0), (size_t)chunk);
+        if (be > start && be - start > (size_t)(2 * chunk)) {
+          s.tree_used = 1;
+          std::vector<std::pair<int32_t, int32_t>> level;   // (slot, producing task)
+          for (size_t lo = start; lo < be; lo += chunk) {
+            const size_t hi = std::min(be, lo + chunk);
+            int32_t p0 = (int32_t)(pairs.size() / 2);
+            for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+            int32_t p1 = (int32_t)(pairs.size() / 2);
+            const int32_t slot = s.npart++;
+            int t = tb.add(TK_PART, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+            fexec += 2.0 * T3 * (hi - lo);
+            for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+            level.push_back({slot, t});
+          }
+          while (level.size() > 2) {
+            std::vector<std::pair<int32_t, int32_t>> next;
+            for (size_t q = 0; q + 1 < level.size(); q += 2) {
+              int32_t slot = s.npart++;
+              int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
+              tb.dep(t, level[q].second);
+              tb.dep(t, level[q + 1].second);
+              next.push_back({slot, t});
+            }
+            if (level.size() % 2) next.push_back(level.back());
+            level.swap(next);
+          }
+          // be - start > 2 chunk gives at least three leaves, so two partials remain
+          int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
+          tb.dep(t, level[0].second);
+          tb.dep(t, level[1].second);
+          tb.dep(t, last);   // after the band tree's subtraction from the same tile
+          last = t;
+          start = be;
+        }
+      }
       // chunks of `chunk` products in ascending column order; the product
       // with column k-1 (available last, on the critical path) is fused into
       // the task that finalizes the tile (POTRF or TRSM), so that everything

@@ -54,11 +54,6 @@ __device__ __forceinline__ void st_dev(GLOBAL float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_dev(double* p, double v) { st_dev(gp(p), v); }
-// diagonal-tile factorization variant: column-by-column (true) or blocked
-#ifndef STILES_POTRF_COLS
-#define STILES_POTRF_COLS 0
-#endif
-constexpr bool POTRF_COLS = STILES_POTRF_COLS != 0;
 
 // ------------------------------------------------------------------ helpers
 
@@ -652,133 +647,6 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
   }
 }
 
-// Column-by-column variant: every thread keeps one row of the tile in
-// registers for a fixed set of columns (thread = (row i, column group g),
-// columns g, g + G, ...), the owner group of column j scales it and publishes
-// it through LDS, and one barrier per column separates publishing from the
-// rank-1 update.  The inverse is built the same way, row by row
-// (X = L^{-1}: row j of X is final once scaled by 1/L_jj, then
-// X_i -= L_ij X_j for i > j).  Per column: one pivot chain (1/sqrt estimate +
-// Newton), one LDS round trip and one barrier.
-template <int T, int K>
-__device__ __attribute__((noinline)) void task_potrf_cols(const ExecMat& M, const int32_t* w, double* S, double* Xb,
-                                                          double* rinv) {
-  constexpr int TT = T * T, G = NT / T, NC = T / G;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int i = tid % T, g = tid / T;
-  double* C = M.tiles + (int64_t)w[1] * TT;
-  const int k = w[2];
-  // column c of group g sits at position (c % G) * NC + c / G of a broadcast buffer
-  double* colbuf = Xb;            // 2 x T
-  double* xbuf = Xb + 2 * T;      // 2 x T
-  double r[NC];
-  if (w[4] > w[3]) {
-    // fused update with column k-1 first (C_kk -= X X^T), staged through LDS
-    constexpr int W = T / 2, NB = T / 32;
-    const int wave = tid >> 6;
-    const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
-    TileStage<T, double> st;
-    st.load(C);
-    st.store(S);
-    st.load(M.tiles + (int64_t)M.pairs[2 * w[3]] * TT);
-    st.store(S + TT);
-    __syncthreads();
-    v4d acc[NB][NB];
-#pragma unroll
-    for (int a = 0; a < NB; a++)
-#pragma unroll
-      for (int b = 0; b < NB; b++) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-    mma_f64<T>(acc, S + TT, S + TT, r0, c0, lane);
-#pragma unroll
-    for (int a = 0; a < NB; a++)
-#pragma unroll
-      for (int b = 0; b < NB; b++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          const int row = r0 + 16 * b + (lane & 15), col = c0 + 16 * a + (lane >> 4) + 4 * q;
-          S[row + col * T] -= acc[a][b][q];
-        }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NC; q++) r[q] = S[i + (g + G * q) * T];
-  } else {
-#pragma unroll
-    for (int q = 0; q < NC; q++) r[q] = C[i + (g + G * q) * T];
-  }
-  // Outer loop over column blocks jj (columns G jj .. G jj + G - 1, one per
-  // group); r[0] always holds the group's current column: after each block
-  // the register row is rotated by one, so no register is indexed at run time.
-  int fail = -1;
-  double lout[NC];
-#pragma unroll 1
-  for (int jj = 0; jj < NC; jj++) {
-#pragma unroll
-    for (int gj = 0; gj < G; gj++) {
-      const int j = G * jj + gj;
-      double* cb = colbuf + (j & 1) * T;
-      if (g == gj) {
-        // the group's threads share one wave: broadcast the pivot from row j
-        const double d = __shfl(r[0], j, T);
-        const double rs = rsqrt_nr(d);
-        const double v = i > j ? r[0] * rs : (i == j ? d * rs : 0.0);
-        r[0] = v;
-        cb[i] = v;
-        if (i == j) {
-          rinv[j] = rs;
-          if (!(d > 0.0)) fail = j;
-        }
-      }
-      __syncthreads();
-      const double lij = cb[i];
-      // r[q] is column g + G (jj + q); update the columns right of j
-#pragma unroll
-      for (int q = 0; q < NC; q++) {
-        if (G * q + g > gj) r[q] = fma(-lij, cb[(g + G * (jj + q)) % T], r[q]);
-      }
-    }
-    // column g + G jj of L is final in r[0]: keep it, rotate
-#pragma unroll
-    for (int q = 0; q < NC; q++)
-      if (q == jj) lout[q] = r[0];
-#pragma unroll
-    for (int q = 0; q + 1 < NC; q++) r[q] = r[q + 1];
-    r[NC - 1] = 0.0;
-  }
-  if (fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
-  // L out (lower part; the upper part of r is zero) and into LDS for the inverse
-#pragma unroll
-  for (int q = 0; q < NC; q++) {
-    const int c = g + G * q;
-    st_dev(C + i + c * T, lout[q]);
-    S[i + c * T] = lout[q];
-  }
-  // inverse, row by row
-  double x[NC];
-#pragma unroll
-  for (int q = 0; q < NC; q++) x[q] = (g + G * q) == i ? 1.0 : 0.0;
-  __syncthreads();
-#pragma unroll 1
-  for (int j = 0; j < T; j++) {
-    double* xb = xbuf + (j & 1) * T;
-    if (i == j) {
-      const double s = rinv[j];
-#pragma unroll
-      for (int q = 0; q < NC; q++) {
-        x[q] *= s;
-        xb[g + G * q] = x[q];
-      }
-    }
-    __syncthreads();
-    if (i > j) {
-      const double lij = S[i + j * T];
-#pragma unroll
-      for (int q = 0; q < NC; q++) x[q] = fma(-lij, xb[g + G * q], x[q]);
-    }
-  }
-  double* Li = M.linv + (int64_t)k * TT;
-#pragma unroll
-  for (int q = 0; q < NC; q++) st_dev(Li + i + (g + G * q) * T, x[q]);
-}
 
 // ---------------------------------------------------------------- solves
 // Vector blocks are T x nrhs column-major (nrhs <= 16).  Each task computes
@@ -1510,10 +1378,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
         case TK_UPD: task_update<T, KIND>(M, w, 0, S, Xi); break;
         case TK_PART: task_update<T, KIND>(M, w, 1, S, Xi); break;
         case TK_TREE: task_tree<T, KIND>(M, w); break;
-        case TK_POTRF:
-          if constexpr (POTRF_COLS) task_potrf_cols<T, KIND>(M, w, S, Xi, rinv);
-          else task_potrf<T, KIND>(M, w, S, Xi, rinv);
-          break;
+        case TK_POTRF: task_potrf<T, KIND>(M, w, S, Xi, rinv); break;
         default: task_trsm<T, KIND>(M, w, S, Xi); break;
       }
     }
