@@ -38,6 +38,52 @@ struct TaskBuilder {
   }
 };
 
+// Start order of a list schedule on `workers` workers: whenever one is free
+// it starts the ready task with the longest remaining path (bl); a task is
+// ready `hop` after its last predecessor has finished.  The order is
+// topological: a task starts only after its predecessors have finished.
+std::vector<int32_t> list_order(int32_t nt, const float* cost, const int32_t* succ_ptr, const int32_t* succ,
+                                const int32_t* npred_in, const float* bl, int workers, float hop) {
+  std::vector<int32_t> order;
+  order.reserve(nt);
+  std::vector<int32_t> npred(npred_in, npred_in + nt);
+  std::vector<float> rdy(nt, 0.f);
+  typedef std::pair<float, int32_t> FI;
+  std::priority_queue<FI, std::vector<FI>, std::greater<FI>> pending, running;   // by ready / finish time
+  auto prio = [&](int32_t x, int32_t y) { return bl[x] != bl[y] ? bl[x] < bl[y] : x > y; };
+  std::priority_queue<int32_t, std::vector<int32_t>, decltype(prio)> ready(prio);
+  for (int32_t t = 0; t < nt; t++)
+    if (npred[t] == 0) pending.push({0.f, t});
+  float now = 0.f;
+  int free_w = workers;
+  while ((int32_t)order.size() < nt) {
+    while (!pending.empty() && pending.top().first <= now) { ready.push(pending.top().second); pending.pop(); }
+    while (free_w > 0 && !ready.empty()) {
+      const int32_t t = ready.top();
+      ready.pop();
+      order.push_back(t);
+      running.push({now + cost[t], t});
+      free_w--;
+    }
+    float next = std::numeric_limits<float>::infinity();
+    if (!running.empty()) next = running.top().first;
+    if (free_w > 0 && !pending.empty()) next = std::min(next, pending.top().first);
+    if (!(next < std::numeric_limits<float>::infinity())) { fprintf(stderr, "stiles: list schedule stalled\n"); abort(); }
+    now = std::max(now, next);
+    while (!running.empty() && running.top().first <= now) {
+      const FI f = running.top();
+      running.pop();
+      free_w++;
+      for (int32_t q = succ_ptr[f.second]; q < succ_ptr[f.second + 1]; q++) {
+        const int32_t x = succ[q];
+        rdy[x] = std::max(rdy[x], f.first + hop);
+        if (--npred[x] == 0) pending.push({rdy[x], x});
+      }
+    }
+  }
+  return order;
+}
+
 // workgroups of the list schedule: a full-GPU executor launch has two per CU
 // on 256 CUs; -1 (option) = unbounded earliest-start order
 int sched_workers(const stiles_opts& o) { return o.sched_workers == 0 ? 512 : o.sched_workers < 0 ? 0 : o.sched_workers; }
@@ -48,9 +94,7 @@ int sched_workers(const stiles_opts& o) { return o.sched_workers == 0 ? 512 : o.
 // renumbered in that order, which is topological; workgroups take them in
 // this order.  est_out always receives the unbounded-resource estimate.
 void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int32_t>& succ_out,
-              std::vector<float>* est_out, std::vector<int32_t>* pair_words, bool remap_pairs, int workers) {
-  (void)pair_words;
-  (void)remap_pairs;
+              std::vector<float>* est_out, std::vector<float>* cost_out, int workers) {
   const int nt = (int)tb.cost.size();
   const float hop = 0.8f;
   for (auto& p : tb.preds) {
@@ -83,53 +127,20 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
       return bl[x] > bl[y];
     });
   } else {
-    // list scheduling on `workers` workgroups: whenever one is free it
-    // starts the ready task with the longest remaining path; tickets follow
-    // the simulated start order (topological: a task starts only after its
-    // predecessors have finished)
-    order.clear();
-    std::vector<int32_t> npred(nt);
-    std::vector<float> rdy(nt, 0.f);
-    typedef std::pair<float, int32_t> FI;
-    std::priority_queue<FI, std::vector<FI>, std::greater<FI>> pending, running;   // by ready / finish time
-    auto prio = [&](int32_t x, int32_t y) { return bl[x] != bl[y] ? bl[x] < bl[y] : x > y; };
-    std::priority_queue<int32_t, std::vector<int32_t>, decltype(prio)> ready(prio);
+    std::vector<int32_t> sptr(nt + 1, 0), sflat, npred(nt);
     for (int t = 0; t < nt; t++) {
+      sptr[t + 1] = sptr[t] + (int32_t)succ[t].size();
+      sflat.insert(sflat.end(), succ[t].begin(), succ[t].end());
       npred[t] = (int32_t)tb.preds[t].size();
-      if (npred[t] == 0) pending.push({0.f, t});
     }
-    float now = 0.f;
-    int free_w = workers;
-    while ((int)order.size() < nt) {
-      while (!pending.empty() && pending.top().first <= now) { ready.push(pending.top().second); pending.pop(); }
-      while (free_w > 0 && !ready.empty()) {
-        const int32_t t = ready.top();
-        ready.pop();
-        order.push_back(t);
-        running.push({now + tb.cost[t], t});
-        free_w--;
-      }
-      float next = std::numeric_limits<float>::infinity();
-      if (!running.empty()) next = running.top().first;
-      if (free_w > 0 && !pending.empty()) next = std::min(next, pending.top().first);
-      if (!(next < std::numeric_limits<float>::infinity())) { fprintf(stderr, "stiles: list schedule stalled\n"); abort(); }
-      now = std::max(now, next);
-      while (!running.empty() && running.top().first <= now) {
-        const FI f = running.top();
-        running.pop();
-        free_w++;
-        for (int32_t x : succ[f.second]) {
-          rdy[x] = std::max(rdy[x], f.first + hop);
-          if (--npred[x] == 0) pending.push({rdy[x], x});
-        }
-      }
-    }
+    order = list_order(nt, tb.cost.data(), sptr.data(), sflat.data(), npred.data(), bl.data(), workers, hop);
   }
   std::vector<int32_t> newid(nt);
   for (int i = 0; i < nt; i++) newid[order[i]] = i;
   tasks_out.assign((size_t)nt * TASK_WORDS, 0);
   succ_out.clear();
   if (est_out) est_out->assign(nt, 0.f);
+  if (cost_out) cost_out->assign(nt, 0.f);
   for (int i = 0; i < nt; i++) {
     int t = order[i];
     int32_t* w = &tasks_out[(size_t)i * TASK_WORDS];
@@ -142,6 +153,7 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
     w[6] = (int32_t)succ_out.size();
     w[7] = (int32_t)tb.preds[t].size();
     if (est_out) (*est_out)[i] = est[t];
+    if (cost_out) (*cost_out)[i] = tb.cost[t];
   }
   // topological check of the final numbering
   for (int i = 0; i < nt; i++) {
@@ -531,6 +543,11 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
 
 namespace stiles {
 void set_error_arg(int32_t idx) { g_err_arg = idx; }
+std::vector<int32_t> list_schedule(int32_t nt, const float* cost, const int32_t* succ_ptr, const int32_t* succ,
+                                   const int32_t* npred, const float* bl, int workers, float hop) {
+  return list_order(nt, cost, succ_ptr, succ, npred, bl, workers, hop);
+}
+int schedule_workers(const stiles_opts& o) { return sched_workers(o); }
 }
 
 extern "C" int32_t stiles_last_error_arg(void) { return g_err_arg; }
@@ -1034,7 +1051,7 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   }
   s.flops_exec = fexec;
   s.fpairs = pairs;
-  schedule(tb, s.ftask, s.fsucc, &s.fest, nullptr, false, sched_workers(s.opts));
+  schedule(tb, s.ftask, s.fsucc, &s.fest, &s.fcost, sched_workers(s.opts));
 
   // ---- solve DAG (forward then backward sweep over tile rows)
   TaskBuilder sb;
@@ -1124,7 +1141,7 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
     bdiag[m] = t;
   }
   s.spairs = sp;
-  schedule(sb, s.stask, s.ssucc, nullptr, nullptr, false, sched_workers(s.opts));
+  schedule(sb, s.stask, s.ssucc, nullptr, nullptr, sched_workers(s.opts));
 }
 
 // ---- selected inversion: Sigma = A^{-1} on the tile pattern of L.
@@ -1281,7 +1298,7 @@ void build_selinv(const stiles_symbolic& s, SelinvPlan& P) {
     sd[k] = tk;
   }
   P.flops_exec = fexec;
-  schedule(tb, P.task, P.succ, nullptr, nullptr, false, sched_workers(s.opts));
+  schedule(tb, P.task, P.succ, nullptr, nullptr, sched_workers(s.opts));
   // algorithmic work of the element recursion, over the envelope before
   // adaptable ND: column j costs eta_j dot products of length eta_j plus one
   const std::vector<int64_t>& f = s.f_pre.empty() ? s.f : s.f_pre;

@@ -655,16 +655,60 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
     for (int32_t j = 0; j < i; j++)
       if (factors[j]->ws == factors[i]->ws) { set_error_arg(2); return STILES_EINVAL; }
   }
-  // merge the per-matrix static schedules by their start estimates
-  struct E { float est; int32_t m, t; };
-  std::vector<E> ev;
-  for (int32_t i = 0; i < count; i++) {
-    const auto& est = factors[i]->sym->fest;
-    for (int32_t t = 0; t < factors[i]->mf.ntasks; t++) ev.push_back({est[t], i, t});
+  // one ticket order for the union of the matrices' DAGs: a list schedule on
+  // the workgroups of the launch (longest remaining path first), or, when
+  // the options ask for the earliest-start order, the per-matrix schedules
+  // merged by their start estimates
+  const int workers = schedule_workers(factors[0]->sym->opts);
+  std::vector<int32_t> order;
+  if (workers > 0) {
+    const float hop = 0.8f;
+    std::vector<int32_t> off(count + 1, 0);
+    for (int32_t i = 0; i < count; i++) off[i + 1] = off[i] + factors[i]->mf.ntasks;
+    const int32_t n = off[count];
+    std::vector<float> cost(n), bl(n);
+    std::vector<int32_t> sptr(n + 1, 0), sflat, npred(n), owner(n);
+    for (int32_t i = 0; i < count; i++) {
+      const stiles_symbolic& sy = *factors[i]->sym;
+      for (int32_t t = 0; t < factors[i]->mf.ntasks; t++) {
+        const int32_t g = off[i] + t;
+        const int32_t* w = &sy.ftask[(size_t)t * TASK_WORDS];
+        cost[g] = sy.fcost[t];
+        npred[g] = w[7];
+        owner[g] = i;
+        for (int32_t q = w[5]; q < w[6]; q++) sflat.push_back(off[i] + sy.fsucc[q]);
+        sptr[g + 1] = (int32_t)sflat.size();
+      }
+    }
+    // remaining path lengths: each matrix's tasks are in topological order
+    for (int32_t g = n - 1; g >= 0; g--) {
+      float b2 = 0.f;
+      for (int32_t q = sptr[g]; q < sptr[g + 1]; q++) b2 = std::max(b2, bl[sflat[q]] + hop);
+      bl[g] = b2 + cost[g];
+    }
+    const std::vector<int32_t> ord = list_schedule(n, cost.data(), sptr.data(), sflat.data(), npred.data(), bl.data(),
+                                                   workers, hop);
+    // the executor needs a topological ticket order: verify it
+    std::vector<int32_t> pos(n, -1);
+    for (int32_t q = 0; q < (int32_t)ord.size(); q++) pos[ord[q]] = q;
+    for (int32_t g = 0; g < n; g++) {
+      bool ok = pos[g] >= 0;
+      for (int32_t q = sptr[g]; ok && q < sptr[g + 1]; q++) ok = pos[sflat[q]] > pos[g];
+      if (!ok) { fprintf(stderr, "stiles: batch schedule is not topological\n"); abort(); }
+    }
+    order.resize((size_t)n * 2);
+    for (int32_t q = 0; q < n; q++) { order[2 * q] = owner[ord[q]]; order[2 * q + 1] = ord[q] - off[owner[ord[q]]]; }
+  } else {
+    struct E { float est; int32_t m, t; };
+    std::vector<E> ev;
+    for (int32_t i = 0; i < count; i++) {
+      const auto& est = factors[i]->sym->fest;
+      for (int32_t t = 0; t < factors[i]->mf.ntasks; t++) ev.push_back({est[t], i, t});
+    }
+    std::stable_sort(ev.begin(), ev.end(), [](const E& a, const E& b) { return a.est < b.est; });
+    order.resize(ev.size() * 2);
+    for (size_t q = 0; q < ev.size(); q++) { order[2 * q] = ev[q].m; order[2 * q + 1] = ev[q].t; }
   }
-  std::stable_sort(ev.begin(), ev.end(), [](const E& a, const E& b) { return a.est < b.est; });
-  std::vector<int32_t> order(ev.size() * 2);
-  for (size_t q = 0; q < ev.size(); q++) { order[2 * q] = ev[q].m; order[2 * q + 1] = ev[q].t; }
   std::vector<ExecMat> mats(count);
   std::vector<BatchDesc> desc(count);
   std::vector<int32_t> tmap, rmap;
@@ -701,7 +745,7 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
   }
   b->factors.assign(factors, factors + count);
   b->ws = static_cast<char*>(d_batch_ws);
-  b->total = (int32_t)ev.size();
+  b->total = (int32_t)(order.size() / 2);
   b->T = T;
   b->z = batch_sizes(count, factors);
   b->B = batch_layout(count, b->z);

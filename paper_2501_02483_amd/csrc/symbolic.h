@@ -64,6 +64,7 @@ struct stiles_symbolic {
   std::vector<int32_t> fsucc;
   std::vector<int32_t> fpairs;
   std::vector<float> fest;        // scheduled start estimate (merging batches)
+  std::vector<float> fcost;       // cost model of each factorization task (list schedule of a batch)
   int32_t npart = 0;
   int32_t tree_used = 0;
   int64_t corner_acc = 0;
@@ -94,4 +95,10 @@ void set_error_arg(int32_t idx);
 const SelinvPlan& selinv_plan(const stiles_symbolic& s);
 // the merged factorization + solve plan (built once, thread-safe)
 const MergedPlan& merged_plan(const stiles_symbolic& s);
+// start order of a list schedule of a DAG (successors in CSR form) on
+// `workers` workers, longest remaining path (bl) first
+std::vector<int32_t> list_schedule(int32_t nt, const float* cost, const int32_t* succ_ptr, const int32_t* succ,
+                                   const int32_t* npred, const float* bl, int workers, float hop);
+// workgroups of the list schedule for these options (0 = earliest-start order)
+int schedule_workers(const stiles_opts& o);
 }
