@@ -91,9 +91,12 @@ typedef struct stiles_opts {
   int32_t nd_parts;       /* ADAPTABLE_ND: number of partitions, 2..64 (0 = choose)   */
   int32_t sched_workers;  /* ticket order of the task DAGs: the start order of a list
                              schedule (longest remaining path first) on this many
-                             workgroups (0 = 512, a full MI355X launch); -1 = order by
-                             earliest start with unlimited workgroups.  Only the speed
-                             depends on it: every order gives bitwise the same results */
+                             workgroups (0 = 512, a full MI355X launch), used for a DAG
+                             whose critical path is at least half its work per
+                             workgroup and for batches; otherwise, and with -1, the
+                             order by earliest start with unlimited workgroups.  Only
+                             the speed depends on it: every order gives bitwise the
+                             same results                                            */
   int32_t reserved[1];
 } stiles_opts;
 
