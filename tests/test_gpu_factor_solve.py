@@ -74,3 +74,46 @@ def test_factorize_solve_failure_and_mixed():
     with pytest.raises(S.StilesError) as e:
         mixed.factorize_solve(torch.from_numpy(vals).cuda(), b)
     assert e.value.status == S.STILES_ENOTSUP
+
+
+def test_ticket_order_does_not_change_results():
+    """The ticket order (sched_workers: list schedule on 512 or 64 workgroups,
+    or the earliest-start order) changes only the speed: factor, merged
+    solve and log-determinant are bitwise equal across orders."""
+    import torch
+    p = I.make_pattern(6000, 40, [20, 110, 50], seg=700)
+    vals = I.make_values(p, seed=77)
+    B = I.rhs(p.N, 4, seed=78)
+    dv = torch.from_numpy(vals).cuda()
+    out = []
+    for sw in (0, -1, 64):
+        sym = S.Symbolic.from_pattern(p, tile=64, ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=4, sched_workers=sw)
+        say("[gpu ticket order] sched_workers=%d" % sw)
+        fac = S.Factor(sym, nrhs_max=4)
+        X = to_device_cols(B)
+        fac.factorize_solve(dv, X)
+        ld = fac.logdet().item()
+        assert fac.info() == 0
+        out.append((fac.extract().cpu().numpy(), X.cpu().numpy(), ld))
+    for L, X, ld in out[1:]:
+        assert np.array_equal(L, out[0][0]) and np.array_equal(X, out[0][1]) and ld == out[0][2]
+
+
+def test_merged_trace_records_every_task():
+    """stiles_factor_set_merged_trace: one record per task of the merged DAG,
+    start >= claim and end >= start, task type in the record."""
+    import torch
+    p = I.make_pattern(3000, 20, [20, 90, 40], seg=500)
+    vals = I.make_values(p, seed=5)
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=3)
+    tasks = S.stiles_symbolic_export(sym.handle, "mtask").reshape(-1, 8)
+    fac = S.Factor(sym, nrhs_max=2)
+    tr = torch.zeros(len(tasks) * 4, dtype=torch.int64, device="cuda")
+    say("[gpu merged trace] %d tasks" % len(tasks))
+    S.stiles_factor_set_merged_trace(fac.handle, tr)
+    X = to_device_cols(I.rhs(p.N, 2, seed=6))
+    fac.factorize_solve(torch.from_numpy(vals).cuda(), X)
+    S.stiles_factor_set_merged_trace(fac.handle, None)
+    a = tr.cpu().numpy().reshape(-1, 4).astype(np.uint64)
+    assert (a[:, 0] > 0).all() and (a[:, 1] >= a[:, 0]).all() and (a[:, 2] >= a[:, 1]).all()
+    assert np.array_equal((a[:, 3] >> np.uint64(24)) & np.uint64(0xff), (tasks[:, 0] & 0xff).astype(np.uint64))

@@ -230,3 +230,20 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
             assert final_of[int(P[q, 0])] in fpred[t]
         if typ[t] in (E.FDIAG, E.BDIAG):
             assert potrf_of[int(tasks[t, 1])] in fpred[t]
+
+
+@pytest.mark.parametrize("sched_workers", [-1, 0, 16])
+def test_ticket_orders_emulate_to_the_oracle(sched_workers):
+    """Every ticket order (earliest start, list schedules on 512 or 16
+    workgroups) is topological and gives the oracle's factor and solution."""
+    p = I.make_pattern(2500, 18, [16, 70, 30], seg=500)
+    vals = I.make_values(p, seed=8)
+    sym = S.Symbolic.from_pattern(p, tile=32, ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=3,
+                                  sched_workers=sched_workers)
+    plan = E.Plan(sym)
+    A = I.to_dense(p, vals)
+    B = I.rhs(p.N, 2, seed=3)
+    _, _, X = E.factor_solve(plan, A[np.ix_(plan.perm, plan.perm)], B, mode="ticket")
+    L, info = oracle.factor(p.f, vals)
+    Xo = oracle.solve(p.f, L, B)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
