@@ -1504,17 +1504,25 @@ __device__ __forceinline__ void scatter_tile(const double* __restrict__ vals, co
     sp[threadIdx.x] = in_rp[rb + threadIdx.x];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TT; e += NT) {
-    const int r = e / T, c = e % T;   // row-wise: consecutive threads read consecutive values
-    double v = 0.0;
+  // row-wise: consecutive threads read consecutive values; all of a
+  // thread's loads are issued before any LDS store
+  constexpr int NQ = TT / NT;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const int e = (int)threadIdx.x + q * NT;
+    const int r = e / T, c = e % T;
+    v[q] = (r >= rc && m == j && r == c) ? 1.0 : 0.0;   // padding row: unit diagonal
     if (r < rc) {
       const int64_t i = rb + r, g = cb + c;
       const int64_t fi = sf[r];
-      if (c < cc && g <= i && g >= fi) v = gp(vals)[sp[r] + (g - fi)];
-    } else if (m == j && r == c) {
-      v = 1.0;   // padding row: unit diagonal
+      if (c < cc && g <= i && g >= fi) v[q] = gp(vals)[sp[r] + (g - fi)];
     }
-    buf[r * (T + 1) + c] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const int e = (int)threadIdx.x + q * NT;
+    buf[(e / T) * (T + 1) + e % T] = v[q];
   }
   __syncthreads();
   store_tile_cm<T>(buf, out, o2);
@@ -1574,22 +1582,28 @@ __device__ __forceinline__ void scatter_tile_perm(const double* __restrict__ val
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TT; e += NT) {
+  // all of a thread's loads are issued before any LDS store (TT / NT of them
+  // in flight per thread)
+  constexpr int NQ = TT / NT;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const int e = (int)threadIdx.x + q * NT;
     const int r = e / T, c = e % T;
-    double v = 0.0;
-    if (r < rc) {
-      if (c < cc && cb + c <= rb + r) {
-        const int64_t oi = pr[r], oj = pc[c];
-        const bool rowi = oi > oj;
-        const int64_t lo = rowi ? oj : oi;
-        const int64_t fh = rowi ? fr[r] : fc[c];
-        const int64_t base = rowi ? sr[r] : sc[c];
-        if (lo >= fh) v = gp(vals)[base + (lo - fh)];
-      }
-    } else if (m == j && r == c) {
-      v = 1.0;   // padding row: unit diagonal
+    v[q] = (r >= rc && m == j && r == c) ? 1.0 : 0.0;   // padding row: unit diagonal
+    if (r < rc && c < cc && cb + c <= rb + r) {
+      const int64_t oi = pr[r], oj = pc[c];
+      const bool rowi = oi > oj;
+      const int64_t lo = rowi ? oj : oi;
+      const int64_t fh = rowi ? fr[r] : fc[c];
+      const int64_t base = rowi ? sr[r] : sc[c];
+      if (lo >= fh) v[q] = gp(vals)[base + (lo - fh)];
     }
-    buf[r * (T + 1) + c] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const int e = (int)threadIdx.x + q * NT;
+    buf[(e / T) * (T + 1) + e % T] = v[q];
   }
   __syncthreads();
   store_tile_cm<T>(buf, out, o2);
