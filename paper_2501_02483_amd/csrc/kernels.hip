@@ -1304,14 +1304,13 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
                                                   int32_t total, ExecCtrl* ctrl, int nrhs) {
   constexpr bool SOLVE = KIND == EXEC_SOLVE, SELINV = KIND == EXEC_SELINV, BOTH = KIND == EXEC_FACTOR_SOLVE;
   // LDS: factorization tasks use S (tile, ld T+1 room), Xi (T x T) and rinv;
-  // solve tasks use S (factor tile), a T x 16 vector block and an inverse
-  // diagonal tile (ld T+1); selected-inversion tasks two padded tiles.  The
-  // combined factorization + solve kernel gives the solve's inverse tile the
-  // (enlarged) Xi and its vector block a buffer of its own.
-  __shared__ __attribute__((aligned(16))) double S[SELINV ? T * (T + 2) : T * (T + 1)];
-  __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : SELINV ? T * (T + 2) : BOTH ? T * (T + 1) : T * T];
+  // solve tasks only a T x 16 block (Xi in the solve kernel, LI in the
+  // combined factorization + solve kernel); selected-inversion tasks two
+  // padded tiles.
+  __shared__ __attribute__((aligned(16))) double S[SOLVE ? 2 : SELINV ? T * (T + 2) : T * (T + 1)];
+  __shared__ __attribute__((aligned(16))) double Xi[SOLVE ? T * 16 : SELINV ? T * (T + 2) : T * T];
   __shared__ double rinv[(KIND == EXEC_FACTOR || BOTH) ? T : 1];
-  __shared__ __attribute__((aligned(16))) double LI[SOLVE ? T * (T + 1) : BOTH ? T * 16 : 1];
+  __shared__ __attribute__((aligned(16))) double LI[BOTH ? T * 16 : 2];
   __shared__ int32_t s_ticket;
   // Control flow outside the task bodies is kept uniform across the
   // workgroup (values broadcast with readfirstlane, loops with uniform bounds
