@@ -190,6 +190,8 @@ void stiles_symbolic_destroy(stiles_symbolic* sym);
  *     lists (int32; built on first use)
  *   14 merged factorization + solve tasks  15 their successor lists  16 their
  *     pairs (the factorization pairs, then the solve pairs; built on first use)
+ *   17 per tile (int32): 1 if an entry of A (P A P^T) falls in it or it is a
+ *     diagonal tile, 0 if it holds fill only
  * With out == NULL, *count receives the number of elements; otherwise *count
  * is the capacity of out (elements) and receives the number copied.
  * EINVAL: unknown `which` (argument 2) or capacity too small (argument 4).

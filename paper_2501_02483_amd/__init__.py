@@ -225,7 +225,8 @@ EXPORT_KINDS = {"ftask": (0, np.int32), "fsucc": (1, np.int32), "fpairs": (2, np
                 "ssucc": (4, np.int32), "spairs": (5, np.int32), "trow_ptr": (6, np.int32), "tcol": (7, np.int32),
                 "row_base": (8, np.int64), "row_cnt": (9, np.int32), "npart": (10, np.int32),
                 "itask": (11, np.int32), "isucc": (12, np.int32), "ilist": (13, np.int32),
-                "mtask": (14, np.int32), "msucc": (15, np.int32), "mpairs": (16, np.int32)}
+                "mtask": (14, np.int32), "msucc": (15, np.int32), "mpairs": (16, np.int32),
+                "tile_has_a": (17, np.int32)}
 
 
 def stiles_symbolic_export(sym, kind):

@@ -553,6 +553,53 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
 
 namespace stiles {
 void set_error_arg(int32_t idx) { g_err_arg = idx; }
+
+std::vector<int32_t> tiles_with_entries(const stiles_symbolic& s) {
+  const int64_t TT = (int64_t)s.T * s.T;
+  std::vector<int32_t> has(s.ntiles, 0);
+  for (int32_t m = 0; m < s.ntr; m++) has[s.trow_ptr[m + 1] - 1] = 1;   // diagonal tile (last of its row)
+  if (!s.profile_input) {
+    for (int64_t o : s.map) has[o / TT] = 1;
+    return has;
+  }
+  if (s.perm_identity) {
+    // the stored tiles are those of the envelope itself
+    std::fill(has.begin(), has.end(), 1);
+    return has;
+  }
+  // row-profile input under a permutation: input row o holds columns
+  // [fin[o], o]; the new positions of a range of input indices are followed
+  // in runs on which the inverse permutation steps by +1 or -1
+  const int64_t N = s.N;
+  std::vector<int64_t> pinv(N), run_end(N);
+  for (int64_t r = 0; r < N; r++) pinv[s.perm[r]] = r;
+  for (int64_t c = N - 1; c >= 0; c--) {
+    const int64_t d = c + 1 < N ? pinv[c + 1] - pinv[c] : 0;
+    run_end[c] = (d == 1 || d == -1) ? run_end[c + 1] : c;   // consecutive unit steps share their sign
+  }
+  auto tile_row = [&](int64_t g) {
+    return (int32_t)(std::upper_bound(s.row_base.begin(), s.row_base.end(), g) - s.row_base.begin() - 1);
+  };
+  int32_t last_tr = -1, last_lo = -1, last_hi = -1;
+  for (int64_t o = 0; o < N; o++) {
+    const int32_t tr = tile_row(pinv[o]);
+    for (int64_t c0 = s.fin[o]; c0 <= o;) {
+      const int64_t e = std::min(run_end[c0], o);
+      const int32_t ta = tile_row(pinv[c0]), tb2 = tile_row(pinv[e]);
+      const int32_t lo = std::min(ta, tb2), hi = std::max(ta, tb2);
+      c0 = e + 1;
+      if (tr == last_tr && lo == last_lo && hi == last_hi) continue;
+      last_tr = tr;
+      last_lo = lo;
+      last_hi = hi;
+      for (int32_t tc = lo; tc <= hi; tc++) {
+        const int32_t t = tile_lookup(s, std::max(tr, tc), std::min(tr, tc));
+        if (t >= 0) has[t] = 1;
+      }
+    }
+  }
+  return has;
+}
 std::vector<int32_t> list_schedule(int32_t nt, const float* cost, const int32_t* succ_ptr, const int32_t* succ,
                                    const int32_t* npred, const float* bl, int workers, float hop) {
   return list_order(nt, cost, succ_ptr, succ, npred, bl, workers, hop);
@@ -1506,7 +1553,13 @@ extern "C" stiles_status stiles_symbolic_export(const stiles_symbolic* s, int32_
     case 14: src = merged_plan(*s).task.data(); n = (int64_t)merged_plan(*s).task.size(); break;
     case 15: src = merged_plan(*s).succ.data(); n = (int64_t)merged_plan(*s).succ.size(); break;
     case 16: src = merged_plan(*s).pairs.data(); n = (int64_t)merged_plan(*s).pairs.size(); break;
+    case 17: n = s->ntiles; break;
     default: g_err_arg = 2; return STILES_EINVAL;
+  }
+  std::vector<int32_t> tmp;
+  if (which == 17 && out) {
+    tmp = tiles_with_entries(*s);
+    src = tmp.data();
   }
   if (!out) { *count = n; return STILES_OK; }
   if (*count < n) { g_err_arg = 4; return STILES_EINVAL; }

@@ -31,21 +31,32 @@ struct Layout {
   size_t tiles, linv, part, shadow, orig;
   size_t vy, vz, vpart, vx, vr, vb, vd;
   size_t ldpart, stats;
-  size_t ccol_tile, ccol_row, items, item_ptr, rpart;
+  size_t rtile, ccol_tile, ccol_row, items, item_ptr, rpart;
   size_t total;
 };
 
 struct Plan {   // host-side refinement tables (mixed mode)
-  std::vector<int32_t> ccol_tile, ccol_row, items, item_ptr;
+  std::vector<int32_t> rtile, ccol_tile, ccol_row, items, item_ptr;
 };
 
 
 
+// Residual items over the tiles that hold entries of A (tiles of fill only
+// are zero in the original tiles and are skipped): kind 0 sums over a row's
+// tiles (rtile), kind 1 over a column's tiles below the diagonal (ccol_*).
 void make_plan(const stiles_symbolic& s, Plan& p) {
+  const std::vector<int32_t> has = tiles_with_entries(s);
   std::vector<std::vector<std::pair<int32_t, int32_t>>> below(s.ntr);
-  for (int32_t m = 0; m < s.ntr; m++)
-    for (int32_t t = s.trow_ptr[m]; t < s.trow_ptr[m + 1]; t++)
+  std::vector<int32_t> rptr(s.ntr + 1, 0);
+  p.rtile.clear();
+  for (int32_t m = 0; m < s.ntr; m++) {
+    for (int32_t t = s.trow_ptr[m]; t < s.trow_ptr[m + 1]; t++) {
+      if (!has[t]) continue;
+      p.rtile.push_back(t);
       if (s.tcol[t] != m) below[s.tcol[t]].push_back({t, m});
+    }
+    rptr[m + 1] = (int32_t)p.rtile.size();
+  }
   std::vector<int32_t> cptr(s.ntr + 1, 0);
   for (int32_t m = 0; m < s.ntr; m++) cptr[m + 1] = cptr[m] + (int32_t)below[m].size();
   p.ccol_tile.clear();
@@ -56,8 +67,8 @@ void make_plan(const stiles_symbolic& s, Plan& p) {
   p.items.clear();
   p.item_ptr.assign(s.ntr + 1, 0);
   for (int32_t m = 0; m < s.ntr; m++) {
-    for (int32_t lo = s.trow_ptr[m]; lo < s.trow_ptr[m + 1]; lo += CH) {
-      int32_t hi = std::min(s.trow_ptr[m + 1], lo + CH);
+    for (int32_t lo = rptr[m]; lo < rptr[m + 1]; lo += CH) {
+      int32_t hi = std::min(rptr[m + 1], lo + CH);
       int32_t it[4] = {m, 0, lo, hi};
       p.items.insert(p.items.end(), it, it + 4);
     }
@@ -128,6 +139,7 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   L.ldpart = take((size_t)s.ntr * 8);
   L.stats = take(2 * 16 * 8 + 16);
   if (mixed && plan) {
+    L.rtile = take(plan->rtile.size() * 4);
     L.ccol_tile = take(plan->ccol_tile.size() * 4);
     L.ccol_row = take(plan->ccol_row.size() * 4);
     L.items = take(plan->items.size() * 4);
@@ -311,6 +323,7 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
     U(L.mpairs, md.pairs.data(), md.pairs.size() * 4);
   }
   if (mixed) {
+    U(L.rtile, f->plan.rtile.data(), f->plan.rtile.size() * 4);
     U(L.ccol_tile, f->plan.ccol_tile.data(), f->plan.ccol_tile.size() * 4);
     U(L.ccol_row, f->plan.ccol_row.data(), f->plan.ccol_row.size() * 4);
     U(L.items, f->plan.items.data(), f->plan.items.size() * 4);
@@ -445,7 +458,7 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
     double* vz = at<double>(f, L.vz);
     unsigned long long* stats = at<unsigned long long>(f, L.stats);
     auto resid = [&](const double* X, double* R, int absmode) {
-      return launch_residual(s.T, at<double>(f, L.orig), at<int32_t>(f, L.trow), at<int32_t>(f, L.tcol),
+      return launch_residual(s.T, at<double>(f, L.orig), at<int32_t>(f, L.rtile), at<int32_t>(f, L.tcol),
                              at<int32_t>(f, L.ccol_tile), at<int32_t>(f, L.ccol_row), at<int32_t>(f, L.items),
                              (int32_t)(f->plan.items.size() / 4), at<int32_t>(f, L.item_ptr), s.ntr, X, vbb,
                              at<double>(f, L.rpart), R, absmode ? 1 : nb, absmode, st);

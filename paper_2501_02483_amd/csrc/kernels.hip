@@ -647,75 +647,11 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
   }
 }
 
-
-// ---------------------------------------------------------------- solves
+// ---------------------------------------------------------- solve tasks
 // Vector blocks are T x nrhs column-major (nrhs <= 16).  Each task computes
 // out = sum_p A_p V_p with A_p a factor tile (or its transpose) and V_p a
 // vector block, as 16 x 16 x 4 FP64 MFMA products with the right-hand sides
-// padded to 16 columns: wave w owns rows 16 w .. 16 w + 15 of the output.
-// Tiles are staged in LDS with leading dimension T + 1, so both the direct
-// and the transposed operand reads are free of bank conflicts.
-
-template <int T>
-struct SolveStage {
-  static constexpr int NVL = T * T / NT / 2;   // double2 per thread, tile
-  static constexpr int NVV = T * 16 / NT / 2;  // double2 per thread, padded vector block
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  d2 lt[NVL];
-  d2 vb[NVV];
-  __device__ __forceinline__ void load_tile(const double* __restrict__ L) {
-    const GLOBAL d2* lv = (const GLOBAL d2*)L;
-#pragma unroll
-    for (int q = 0; q < NVL; q++) lt[q] = lv[threadIdx.x + q * NT];
-  }
-  static __device__ __forceinline__ void load_vec_to(d2* dst, const double* __restrict__ v, int nrhs) {
-    const GLOBAL d2* vv = (const GLOBAL d2*)v;
-    const int nv = T * nrhs / 2;
-#pragma unroll
-    for (int q = 0; q < NVV; q++) {
-      const int e = threadIdx.x + q * NT;
-      dst[q] = e < nv ? vv[e] : d2{0.0, 0.0};
-    }
-  }
-  __device__ __forceinline__ void load_vec(const double* __restrict__ v, int nrhs) { load_vec_to(vb, v, nrhs); }
-  __device__ __forceinline__ void store_tile(double* LL) const {
-#pragma unroll
-    for (int q = 0; q < NVL; q++) {
-      const int e = 2 * (threadIdx.x + q * NT);
-      const int row = e % T, col = e / T;
-      LL[row + col * (T + 1)] = lt[q].x;
-      LL[row + 1 + col * (T + 1)] = lt[q].y;
-    }
-  }
-  __device__ __forceinline__ void store_vec(double* LV) const {
-    d2* vv = reinterpret_cast<d2*>(LV);
-#pragma unroll
-    for (int q = 0; q < NVV; q++) vv[threadIdx.x + q * NT] = vb[q];
-  }
-};
-
-// acc += A V on MFMA; A = LL (ld T+1), transposed when `trans`; V = LV (ld T)
-template <int T>
-__device__ __forceinline__ v4d solve_mma(v4d acc, const double* LL, const double* LV, bool trans, int wave, int lane) {
-  constexpr int LD = T + 1;
-  const int i = 16 * wave + (lane & 15);
-  // two accumulation chains (k = 0, 8, ... and k = 4, 12, ...) halve the
-  // dependent MFMA latency; their sum is added at the end
-  v4d acc1 = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kq = 0; kq < T; kq += 8) {
-    const int l0 = kq + (lane >> 4), l1 = l0 + 4;
-    const double a0 = trans ? LL[l0 + i * LD] : LL[i + l0 * LD];
-    const double b0 = LV[l0 + (lane & 15) * T];
-    const double a1 = trans ? LL[l1 + i * LD] : LL[i + l1 * LD];
-    const double b1 = LV[l1 + (lane & 15) * T];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
-  }
-  return acc + acc1;
-}
-
-// ---------------------------------------------------------- solve tasks
+// padded to 16 columns.
 // MFMA operands are read from global memory straight into registers.  At
 // MFMA step s the four k-groups of the 16 x 16 x 4 instruction (lane >> 4 =
 // g) take k = (T/4) g + s, so that one lane's operands are contiguous: the
@@ -1904,55 +1840,73 @@ namespace stiles {
 // transposed), and the item's partial written once.
 template <int T>
 __global__ __launch_bounds__(NT) void residual_mma_kernel(const double* __restrict__ orig,
+                                                          const int32_t* __restrict__ rtile,
                                                           const int32_t* __restrict__ tcol,
                                                           const int32_t* __restrict__ ccol_tile,
                                                           const int32_t* __restrict__ ccol_row,
                                                           const int32_t* __restrict__ items,
                                                           const double* __restrict__ X, double* part, int nrhs,
                                                           int absmode) {
-  constexpr int TT = T * T, LD = T + 1;
-  __shared__ __attribute__((aligned(16))) double LL[T * LD];
-  __shared__ __attribute__((aligned(16))) double LV[T * 16];
+  // operands straight from global memory into registers (SolveOps layout),
+  // two tiles in flight; wave w owns rows 16 w .. 16 w + 15 of the T x 16 result
+  typedef SolveOps<T> O;
+  constexpr int TT = T * T, NS = O::NS;
   const int q = blockIdx.x;
   const int m = items[4 * q], kind = items[4 * q + 1], lo = items[4 * q + 2], hi = items[4 * q + 3];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = 16 * wave < T;
-  const int col = lane & 15;
+  const int col = lane & 15, g = lane >> 4, r = 16 * wave + (lane & 15);
   const int64_t vb = (int64_t)T * nrhs;
   const int ncol = absmode ? 1 : nrhs;
-  if (absmode) {
-    for (int e = threadIdx.x; e < T * 16; e += NT) LV[e] = e < T ? 1.0 : 0.0;
-  }
+  const bool trans = kind == 1;
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-  SolveStage<T> st;
-  for (int e = lo; e < hi; e++) {
-    int tile, src;
-    if (kind == 0) { tile = e; src = tcol[e]; } else { tile = ccol_tile[e]; src = ccol_row[e]; }
-    st.load_tile(orig + (int64_t)tile * TT);
+  if (!act) return;
+  double a[2][NS], b[2][NS];
+  // operands of item entry e into slot u
+  auto load = [&](int u, int e) {
+    const int tile = kind == 0 ? rtile[e] : ccol_tile[e];
+    const int src = kind == 0 ? tcol[tile] : ccol_row[e];
+    O::load_a(a[u], orig + (int64_t)tile * TT, trans, wave, lane);
     if (absmode) {
 #pragma unroll
-      for (int k = 0; k < SolveStage<T>::NVL; k++) { st.lt[k].x = fabs(st.lt[k].x); st.lt[k].y = fabs(st.lt[k].y); }
+      for (int s = 0; s < NS; s++) b[u][s] = col == 0 ? 1.0 : 0.0;
     } else {
-      st.load_vec(X + src * vb, nrhs);
+      O::load_b(b[u], X + src * vb, nrhs, lane);
     }
-    __syncthreads();   // the previous tile's products are done with LL / LV
-    st.store_tile(LL);
-    if (!absmode) st.store_vec(LV);
-    __syncthreads();
-    if (act) acc = solve_mma<T>(acc, LL, LV, kind == 1, wave, lane);
-    if (kind == 0 && src == m) {
+  };
+  auto use = [&](int u, int e) {
+    if (absmode) {
+#pragma unroll
+      for (int s = 0; s < NS; s++) a[u][s] = fabs(a[u][s]);
+    }
+    acc = O::mma(acc, a[u], b[u]);
+    const int tile = kind == 0 ? rtile[e] : -1;
+    if (kind == 0 && tcol[tile] == m) {
       // diagonal tile: only its lower triangle is stored; add the strict
-      // lower part transposed
-      __syncthreads();
-      if ((int)threadIdx.x < T) LL[threadIdx.x * (LD + 1)] = 0.0;
-      __syncthreads();
-      if (act) acc = solve_mma<T>(acc, LL, LV, true, wave, lane);
+      // lower part transposed (A(r, k) = L(k, r), zero on the diagonal)
+      double at[NS];
+      O::load_a(at, orig + (int64_t)tile * TT, true, wave, lane);
+#pragma unroll
+      for (int s = 0; s < NS; s++) {
+        const double v = NS * g + s == r ? 0.0 : at[s];
+        at[s] = absmode ? fabs(v) : v;
+      }
+      acc = O::mma(acc, at, b[u]);
+    }
+  };
+  if (lo < hi) load(0, lo);
+  for (int e = lo; e < hi; e += 2) {
+    if (e + 1 < hi) load(1, e + 1);
+    use(0, e);
+    if (e + 1 < hi) {
+      if (e + 2 < hi) load(0, e + 2);
+      use(1, e + 1);
     }
   }
   double* out = part + (int64_t)q * vb;
-  if (act && col < ncol) {
+  if (col < ncol) {
 #pragma unroll
-    for (int r = 0; r < 4; r++) out[(16 * wave + (lane >> 4) + 4 * r) + col * T] = acc[r];
+    for (int rr = 0; rr < 4; rr++) out[(16 * wave + (lane >> 4) + 4 * rr) + col * T] = acc[rr];
   }
 }
 
@@ -1968,18 +1922,17 @@ __global__ void residual_combine_kernel(int T, const int32_t* __restrict__ item_
   }
 }
 
-hipError_t launch_residual(int T, const double* orig, const int32_t* trow, const int32_t* tcol,
+hipError_t launch_residual(int T, const double* orig, const int32_t* rtile, const int32_t* tcol,
                            const int32_t* ccol_tile, const int32_t* ccol_row, const int32_t* items, int32_t nitems,
                            const int32_t* item_ptr, int32_t ntr, const double* X, const double* B, double* part,
                            double* R, int nrhs, int absmode, hipStream_t st) {
-  (void)trow;
   if (nitems > 0) {
     if (T == 64)
-      hipLaunchKernelGGL(residual_mma_kernel<64>, dim3(nitems), dim3(NT), 0, st, orig, tcol, ccol_tile, ccol_row, items,
-                         X, part, nrhs, absmode);
+      hipLaunchKernelGGL(residual_mma_kernel<64>, dim3(nitems), dim3(NT), 0, st, orig, rtile, tcol, ccol_tile, ccol_row,
+                         items, X, part, nrhs, absmode);
     else
-      hipLaunchKernelGGL(residual_mma_kernel<32>, dim3(nitems), dim3(NT), 0, st, orig, tcol, ccol_tile, ccol_row, items,
-                         X, part, nrhs, absmode);
+      hipLaunchKernelGGL(residual_mma_kernel<32>, dim3(nitems), dim3(NT), 0, st, orig, rtile, tcol, ccol_tile, ccol_row,
+                         items, X, part, nrhs, absmode);
   }
   hipLaunchKernelGGL(residual_combine_kernel, dim3(ntr), dim3(NT), 0, st, T, item_ptr, part, B, R, nrhs, absmode);
   return hipGetLastError();

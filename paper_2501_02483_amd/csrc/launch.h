@@ -66,11 +66,12 @@ hipError_t launch_unpack(int T, const double* Z, int nrhs, const int64_t* perm, 
 
 // Mixed-mode refinement helpers (FP64, pristine tiles of A).
 // Residual items: 4 int32 each (tile row m, kind, lo, hi); kind 0 sums
-// A_(m,j) X_j over row tiles [lo,hi) (the diagonal tile used symmetrically),
-// kind 1 sums A_(i,m)^T X_i over column entries [lo,hi) of ccol_*.  Item q
-// writes partial block q; row m owns items [item_ptr[m], item_ptr[m+1]).
-// absmode != 0 replaces A by |A| and X by ones (row sums of |A|).
-hipError_t launch_residual(int T, const double* orig, const int32_t* trow, const int32_t* tcol,
+// A_(m,j) X_j over the tiles rtile[lo..hi) of row m (the diagonal tile used
+// symmetrically), kind 1 sums A_(i,m)^T X_i over column entries [lo,hi) of
+// ccol_*.  Item q writes partial block q; row m owns items
+// [item_ptr[m], item_ptr[m+1]).  absmode != 0 replaces A by |A| and X by
+// ones (row sums of |A|).
+hipError_t launch_residual(int T, const double* orig, const int32_t* rtile, const int32_t* tcol,
                            const int32_t* ccol_tile, const int32_t* ccol_row, const int32_t* items, int32_t nitems,
                            const int32_t* item_ptr, int32_t ntr, const double* X, const double* B, double* part,
                            double* R, int nrhs, int absmode, hipStream_t st);

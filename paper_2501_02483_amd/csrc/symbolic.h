@@ -101,4 +101,7 @@ std::vector<int32_t> list_schedule(int32_t nt, const float* cost, const int32_t*
                                    const int32_t* npred, const float* bl, int workers, float hop);
 // workgroups of the list schedule for these options (0 = earliest-start order)
 int schedule_workers(const stiles_opts& o);
+// per stored tile: 1 if an entry of A falls in it (or it is diagonal), 0 if
+// it holds fill only (zero in A)
+std::vector<int32_t> tiles_with_entries(const stiles_symbolic& s);
 }

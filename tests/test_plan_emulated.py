@@ -247,3 +247,47 @@ def test_ticket_orders_emulate_to_the_oracle(sched_workers):
     L, info = oracle.factor(p.f, vals)
     Xo = oracle.solve(p.f, L, B)
     assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
+
+
+@pytest.mark.parametrize("ordering,parts", [(S.STILES_ORDER_ADAPTABLE_ND, 3), (S.STILES_ORDER_ADAPTABLE_ND, 0),
+                                            (S.STILES_ORDER_NONE, 0)])
+def test_tiles_with_entries_match_the_permuted_matrix(ordering, parts):
+    """Export 17 (tiles that receive entries of A; the residual of the mixed
+    mode skips the others) against the tiles of the permuted dense matrix:
+    exactly the tiles with a nonzero entry, plus the diagonal tiles."""
+    p = I.make_pattern(3000, 24, [20, 90, 45], seg=600)
+    vals = I.make_values(p, seed=31)
+    sym = S.Symbolic.from_pattern(p, tile=32, ordering=ordering, nd_parts=parts)
+    plan = E.Plan(sym)
+    A = I.to_dense(p, vals)
+    tiles = E.scatter(plan, A[np.ix_(plan.perm, plan.perm)])
+    ref = np.array([np.any(tiles[t] != 0) or plan.trow[t] == plan.tcol[t] for t in range(len(plan.tcol))])
+    has = S.stiles_symbolic_export(sym.handle, "tile_has_a").astype(bool)
+    assert np.array_equal(has, ref)
+    if ordering == S.STILES_ORDER_ADAPTABLE_ND:
+        assert (~has).sum() > 0   # nested dissection leaves tiles of fill only
+
+
+def test_tiles_with_entries_csc_input():
+    from permute_util import profile_entries
+    p = I.make_pattern(2500, 16, [12, 60], seg=500)
+    vals = I.make_values(p, seed=12)
+    rng = np.random.default_rng(5)
+    q = np.arange(p.N)
+    q[:p.n] = rng.permutation(p.n)
+    r, c, v = profile_entries(p.f, vals)
+    rr, cc = q[r], q[c]
+    hi, lo = np.maximum(rr, cc), np.minimum(rr, cc)
+    order = np.lexsort((hi, lo))
+    colptr = np.zeros(p.N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(lo, minlength=p.N), out=colptr[1:])
+    sym = S.Symbolic.from_csc(p.N, p.a, colptr, hi[order].astype(np.int64), tile=32,
+                              ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=3)
+    plan = E.Plan(sym)
+    A = np.zeros((p.N, p.N))
+    A[hi, lo] = v
+    A[lo, hi] = v
+    tiles = E.scatter(plan, A[np.ix_(plan.perm, plan.perm)])
+    ref = np.array([np.any(tiles[t] != 0) or plan.trow[t] == plan.tcol[t] for t in range(len(plan.tcol))])
+    has = S.stiles_symbolic_export(sym.handle, "tile_has_a").astype(bool)
+    assert np.array_equal(has, ref)
