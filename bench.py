@@ -87,10 +87,28 @@ def cpu_threads():
         return os.cpu_count()
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu), or the platform string."""
+    import platform
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline_single(p, vals, B):
     """The oracle on the same matrix: factorization + solve + logdet, timed on
-    the host cores (the full matrix: about 10-20 s of CPU work)."""
+    all host threads (the full matrix: about 5-20 s of CPU work); and, for the
+    per-core rate, the oracle's factorization with one thread on a sample of
+    the same law (the first 20,000 band rows with their half-widths, and the
+    arrow), timed also with all threads."""
     import oracle
+    from paper_2501_02483_amd import inputs as I
     nt = cpu_threads()
     t0 = time.perf_counter()
     L, info = oracle.factor(p.f, vals, nthreads=nt)
@@ -99,10 +117,27 @@ def cpu_baseline_single(p, vals, B):
     ld = oracle.logdet(p.f, L)
     t2 = time.perf_counter()
     F = flops_alg(p.f)
-    return {"value": F / (t2 - t0) / 1e12, "unit": "TFLOP/s", "cores": nt, "kind": "oracle",
-            "sample": "the full workload, one step (factorize %.2f s with %d threads + sequential "
-                      "%d-RHS solve and logdet %.2f s)" % (t1 - t0, nt, B.shape[1], t2 - t1),
-            "factorize_s": t1 - t0, "step_s": t2 - t0, "info": info}, (L, X, ld)
+    res = {"value": F / (t2 - t0) / 1e12, "unit": "TFLOP/s", "cores": nt, "kind": "oracle",
+           "sample": "the full workload, one step (factorize %.2f s with %d threads + sequential "
+                     "%d-RHS solve and logdet %.2f s)" % (t1 - t0, nt, B.shape[1], t2 - t1),
+           "factorize_s": t1 - t0, "step_s": t2 - t0, "info": info, "cpu_model": cpu_model()}
+    ns = min(p.n, 20000)
+    if ns < p.n:
+        fs = np.concatenate([p.f[:ns], np.zeros(p.a, dtype=np.int64)])
+        ps = I.Pattern(ns, p.a, fs, name=p.name + "_sample")
+        vs = I.make_values(ps, seed=2)
+        Fs = flops_alg(ps.f)
+        times = {}
+        for thr in (1, nt):
+            t3 = time.perf_counter()
+            oracle.factor(ps.f, vs, nthreads=thr)
+            times[thr] = time.perf_counter() - t3
+        res["one_thread"] = {"value": Fs / times[1] / 1e12, "unit": "TFLOP/s", "cores": 1,
+                             "sample": "factorization of the first %d band rows and the %d arrow rows "
+                                       "(%.3g flops): %.2f s on 1 thread, %.2f s on %d threads"
+                                       % (ns, p.a, Fs, times[1], times[nt], nt),
+                             "all_threads_value": Fs / times[nt] / 1e12}
+    return res, (L, X, ld)
 
 
 def bench_single(args):
@@ -183,7 +218,11 @@ def bench_single(args):
     S.stiles_factor_set_timing(fac.handle, False)
     kernel_ms = float(np.mean(kms))
     solve_kernel_ms = float(np.mean(sep_s))
-    F_solve = 4.0 * sym.info.nnz_L * nrhs      # algorithmic solve flops (two sweeps)
+    # algorithmic solve flops: two sweeps, a multiply and an add per entry of
+    # the method's L (the envelope before ND) and right-hand side; executed:
+    # the same over every stored tile entry
+    F_solve = 4.0 * sym.info.nnz_L_alg * nrhs
+    F_solve_exec = 4.0 * sym.info.tiles * args.tile * args.tile * nrhs
     achieved = (F + F_solve) / (kernel_ms * 1e-3) / 1e12
     res = {
         "metric": "arrowhead Cholesky TFLOP/s (factorize+solve+logdet step)",
@@ -209,6 +248,9 @@ def bench_single(args):
         "logdet_ms": logdet_ms,
         "flops_alg": F,
         "flops_exec": sym.info.flops_exec,
+        "solve_flops_alg": F_solve,
+        "solve_flops_exec": F_solve_exec,
+        "nnz_L_alg": sym.info.nnz_L_alg,
         "info": info,
         "roofline": {"bound": "mfma", "kernel": "exec_kernel<%d,3> (merged factorization + solve DAG)" % args.tile,
                      "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK,
@@ -224,6 +266,14 @@ def bench_single(args):
     if not args.no_cpu_baseline:
         cb, _ = cpu_baseline_single(p, vals, B)
         res["cpu_baseline"] = cb
+    del fac, dv, dB0, work
+    if args.workload == "varband" and not args.no_large:
+        # the largest single-GPU workload (n = 500,000, half-width 1,000,
+        # arrow 200, Laplacian law): FP64 and mixed factorization kernels and
+        # the refined 16-RHS solve, so that their times are observed in the
+        # same run
+        torch.cuda.empty_cache()
+        res["large_n500k"] = mixed_runs(500_000, args.tile, S.STILES_ORDER_ADAPTABLE_ND, 0, steps=3)
     return res
 
 
@@ -450,30 +500,32 @@ def bench_batch(args):
                          "traffic": None, "kernel_ms": kernel_ms}}
 
 
-def bench_mixed(args):
-    """n=500,000, w=1,000, a=200, Laplacian law (kappa ~ 1e6): mixed-precision
-    factorization and 16-RHS refined solve vs the FP64 path on the same GPU."""
+def mixed_runs(n, tile, ordering, parts, steps, law="laplacian"):
+    """n band rows, half-width 1,000, arrow 200; values by `law` (Laplacian:
+    kappa ~ 1e6) drawn on the device: FP64 and mixed factorization kernel
+    times (library event pair around the launch), the 16-RHS solve (refined
+    in mixed mode), factorize + solve end to end, and the mixed results'
+    differences from the FP64 ones."""
     import torch
 
     import paper_2501_02483_amd as S
     from paper_2501_02483_amd import inputs as I
     from paper_2501_02483_amd.devgen import DevicePattern
 
-    p = I.mixed_large(n=args.n or 500_000)
+    p = I.mixed_large(n=n)
     nrhs = 16
     dp = DevicePattern(p)
-    dv = dp.values(4, law="laplacian", kappa=1e6)
+    dv = dp.values(4, law=law, kappa=1e6)
     B = torch.randn(nrhs, p.N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(104)).t()
     out = {}
-    ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
     for prec, name in ((S.STILES_FP64, "fp64"), (S.STILES_MIXED32, "mixed")):
-        sym = S.Symbolic.from_pattern(p, tile=args.tile or 64, ordering=ordering, nd_parts=args.parts)
+        sym = S.Symbolic.from_pattern(p, tile=tile or 64, ordering=ordering, nd_parts=parts)
         fac = S.Factor(sym, prec, nrhs_max=nrhs)
         fac.factorize(dv)
         torch.cuda.synchronize()
         S.stiles_factor_set_timing(fac.handle, True)
         fms = []
-        for _ in range(max(1, args.steps)):
+        for _ in range(max(1, steps)):
             fac.factorize(dv)
             fms.append(S.stiles_factor_kernel_ms(fac.handle, 0))
         S.stiles_factor_set_timing(fac.handle, False)
@@ -484,10 +536,20 @@ def bench_mixed(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ld = fac.logdet().item()
-        out[name] = {"factor_kernel_ms": float(np.median(fms)), "tflops": sym.info.flops_alg / np.median(fms) / 1e9,
-                     "solve_ms": (t1 - t0) * 1e3, "iterations": rep.iterations, "converged": rep.converged,
+        # end to end: factorization (scatter included) + solve, host clock
+        X2 = B.clone()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fac.factorize(dv)
+        fac.solve(X2)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        fk = float(np.median(fms))
+        out[name] = {"factor_kernel_ms": fk, "tflops": sym.info.flops_alg / fk / 1e9,
+                     "solve_ms": (t1 - t0) * 1e3, "factorize_solve_ms": (t3 - t2) * 1e3,
+                     "iterations": rep.iterations, "converged": rep.converged,
                      "backward_error": rep.backward_error, "logdet": ld, "info": fac.info(), "X": X,
-                     "L": fac.extract() if args.n and args.n <= 200_000 else None}
+                     "L": fac.extract() if n <= 200_000 else None, "nd_parts": sym.info.nd_parts}
         del fac
     xf, xm = out["fp64"].pop("X"), out["mixed"].pop("X")
     out["mixed"]["x_rel_diff_vs_fp64"] = float(torch.linalg.norm(xm - xf) / torch.linalg.norm(xf))
@@ -495,14 +557,32 @@ def bench_mixed(args):
     Lf, Lm = out["fp64"].pop("L"), out["mixed"].pop("L")
     if Lf is not None:
         out["mixed"]["L_rel_diff_vs_fp64"] = float(torch.linalg.norm(Lm - Lf) / torch.linalg.norm(Lf))
-    F = sym.info.flops_alg
+    out["flops_alg"] = sym.info.flops_alg
+    out["workload"] = p.name
+    out["law"] = law
+    return out
+
+
+def bench_mixed(args):
+    """n=500,000, w=1,000, a=200, Laplacian law (kappa ~ 1e6): mixed-precision
+    factorization and 16-RHS refined solve vs the FP64 path on the same GPU."""
+    import paper_2501_02483_amd as S
+    from paper_2501_02483_amd import inputs as I
+
+    p = I.mixed_large(n=args.n or 500_000)
+    nrhs = 16
+    ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
+    out = mixed_runs(args.n or 500_000, args.tile, ordering, args.parts, args.steps, law=args.law)
+    F = out["flops_alg"]
     v = out["mixed"]["tflops"]
     return {"metric": "mixed-precision arrowhead Cholesky TFLOP/s (factorization kernel)", "value": v,
             "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
             "ms_per_step": out["mixed"]["factor_kernel_ms"], "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f32-updates/f64", "data": "synthetic (device-generated, Laplacian law)",
+            "vs_baseline": None, "dtype": "f32-updates/f64",
+            "data": "synthetic (device-generated, %s law)" % args.law,
             "config": {"workload": p.name, "n": p.n, "arrow": p.a, "half_width": 1000, "nrhs": nrhs,
-                       "tile": args.tile or 64, "ordering": args.ordering, "nd_parts": sym.info.nd_parts},
+                       "tile": args.tile or 64, "ordering": args.ordering, "nd_parts": out["mixed"]["nd_parts"],
+                       "law": args.law},
             "flops_alg": F, "runs": out,
             "roofline": {"bound": "mfma", "achieved": v, "peak": FP32_PEAK, "unit": "TFLOP/s",
                          "frac": v / FP32_PEAK, "traffic": None}}
@@ -613,6 +693,10 @@ def main():
     ap.add_argument("--nd-min-rows", type=int, default=0,
                     help="batch: adaptable ND for matrices with at least this many band tile rows (0 = none)")
     ap.add_argument("--n", type=int, default=0, help="mixed: band rows (default 500,000)")
+    ap.add_argument("--law", default="laplacian", choices=["laplacian", "scaled"],
+                    help="mixed: value law (Laplacian, kappa ~ 1e6; or S A0 S with s_i = 10^(-3 u_i))")
+    ap.add_argument("--no-large", action="store_true",
+                    help="varband: skip the n = 500,000 FP64/mixed runs reported beside the main line")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for in-flight requests")
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per load point")

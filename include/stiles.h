@@ -51,6 +51,9 @@ typedef int32_t stiles_status;
 #define STILES_ENOMEM (-3)   /* caller-provided workspace too small                 */
 #define STILES_EDEVICE (-4)  /* a HIP call failed                                   */
 #define STILES_ESTATE (-5)   /* object in the wrong state (e.g. factor failed)      */
+#define STILES_ETIMEOUT (-6) /* a wait of the persistent executor passed its deadline
+                                (stiles_factor_set_wait_limit): the launch was
+                                abandoned and the factor is marked failed          */
 
 /* Orderings (Section III-A).  AUTO tries partial RCM on the band part (the
  * arrow rows are left in place) and keeps it only if it reduces the number
@@ -85,9 +88,13 @@ typedef struct stiles_opts {
                              disables the tree (sequential accumulation chain)       */
   int32_t chunk;          /* tile products per accumulation task, at most 32
                              (0: 12 at T=64, 16 at T=32)                              */
-  double refine_tol;      /* mixed mode: stop when the backward error of every
-                             right-hand side is <= refine_tol (0 = 2^-52 * N^0.5)    */
-  int32_t refine_max_iter;/* mixed mode: at most this many refinement steps (0 = 30) */
+  double refine_tol;      /* mixed mode: a right-hand side stops refining once its
+                             backward error is <= refine_tol (0 = 2^-52 (w + a), w the
+                             largest band half-width before reordering, a the arrow
+                             width), or when a step no longer halves it (the better
+                             of the last two iterates is kept), or at the step limit */
+  int32_t refine_max_iter;/* mixed mode: at most this many refinement steps per
+                             right-hand side (0 = 30)                                */
   int32_t nd_parts;       /* ADAPTABLE_ND: number of partitions, 2..64 (0 = choose)   */
   int32_t sched_workers;  /* ticket order of the task DAGs: the start order of a list
                              schedule (longest remaining path first) on this many
@@ -122,13 +129,24 @@ typedef struct stiles_symbolic_info {
                                    from band columns (about one per band tile row)   */
   int32_t tree_used;      /* 1 if the arrow corner is reduced by a tree              */
   int32_t nd_parts;       /* partitions of the adaptable ND ordering (1 if none)     */
+  int64_t nnz_L_alg;      /* entries inside the envelope before adaptable ND: nnz(L)
+                             of the method, the basis of flops_alg; the algorithmic
+                             work of a solve is 4 nnz_L_alg flops per right-hand side
+                             (two sweeps, a multiply and an add per entry).  Equals
+                             nnz_L when adaptable ND is not used                     */
 } stiles_symbolic_info;
 
 typedef struct stiles_solve_report {
-  int32_t iterations;     /* refinement steps taken (0 in FP64 mode)                 */
-  int32_t converged;      /* 1 if the stopping test was met                          */
+  int32_t iterations;     /* largest number of refinement steps any right-hand side
+                             took (0 in FP64 mode)                                   */
+  int32_t converged;      /* 1 if every right-hand side met the stopping test        */
   double backward_error;  /* max over right-hand sides of ||b-Ax||/(||A|| ||x||+||b||),
-                             inf-norms; computed in mixed mode only (else -1)        */
+                             inf-norms, of the returned x; mixed mode only (else -1) */
+  double* backward_errors;/* optional (set by the caller, may be NULL): host array of
+                             nrhs doubles that receives the backward error of each
+                             right-hand side's returned x (-1 in FP64 mode)          */
+  int32_t* rhs_iterations;/* optional host array of nrhs: refinement steps applied to
+                             each right-hand side (0 in FP64 mode)                   */
 } stiles_solve_report;
 
 /* Fill *opts with the defaults (tile 64, AUTO ordering, tree ratio 2). */
@@ -163,8 +181,11 @@ stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t* colptr, co
  * (0 <= first_col[i] <= i), the arrow rows are dense.  Values passed to
  * stiles_factorize are in row-profile order: row 0, row 1, ..., row N-1,
  * each from its first column to its diagonal (arrow row n_band + r holds
- * n_band + r + 1 entries).  No reordering is applied (ordering must be AUTO
- * or NONE): the band is already in envelope order.
+ * n_band + r + 1 entries).  Orderings: NONE and AUTO keep the input order
+ * (the band is already in envelope order, so partial RCM is not tried);
+ * ADAPTABLE_ND cuts the band into partitions as described above (the values
+ * stay in the input's row-profile order; the permutation is applied on the
+ * device).  PARTIAL_RCM is rejected (ENOTSUP, argument 4).
  */
 stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, const int64_t* first_col,
                                      const stiles_opts* opts, stiles_symbolic** out);
@@ -260,16 +281,32 @@ stiles_status stiles_factorize_batch(int32_t count, stiles_factor* const* factor
                                      size_t batch_ws_bytes, hipStream_t stream);
 
 /* Waits for the stream, then sets *info to 0 (success) or the 1-based
- * permuted column of the first non-positive pivot. */
+ * permuted column of the first non-positive pivot.  Returns STILES_ETIMEOUT
+ * (and *info = -1) when a launch of this factor since its last scatter was
+ * abandoned at the executor's wait deadline (see below); the factor then
+ * counts as failed until it is factorized again. */
 stiles_status stiles_factor_info(stiles_factor* f, hipStream_t stream, int64_t* info);
+
+/* Deadline of every wait of the persistent executor for a task's
+ * predecessors (Algorithm 2's progress check), in seconds; 0 restores the
+ * default of 10 s; at most 3600 (EINVAL otherwise, argument 2).  A correct
+ * plan never waits that long; a wait that does sets an abort flag of the
+ * launch, after which every workgroup skips its remaining tasks and exits
+ * normally: the launch returns instead of hanging the device, the factor's
+ * results are NaN, and stiles_factor_info returns STILES_ETIMEOUT.  It
+ * applies to the factorization, solve, merged, batch (the first factor's
+ * limit) and selected-inversion launches of this factor. */
+stiles_status stiles_factor_set_wait_limit(stiles_factor* f, double seconds);
 
 /*
  * Solve A X = B in place.  d_B: N x nrhs column-major, leading dimension
  * ldb >= N, original (unpermuted) ordering.  1 <= nrhs <= nrhs_max of the
  * workspace.  FP64 mode: one forward and one backward sweep over the tiles.
  * Mixed mode: the same, followed by FP64 iterative refinement against the
- * resident original A (synchronizes the stream once per step to test
- * convergence).  report may be NULL.  If the factorization failed, the
+ * resident original A, each right-hand side until its own stopping test
+ * holds (stiles_opts.refine_tol); the stream is synchronized once per step to
+ * test convergence.  report may be NULL; its optional per-right-hand-side
+ * arrays are filled when set.  If the factorization failed, the
  * result is NaN (and ESTATE is returned when the failure is already known).
  */
 stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_B, int64_t ldb, hipStream_t stream,

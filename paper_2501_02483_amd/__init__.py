@@ -24,7 +24,7 @@ __all__ = [
     "stiles_batch_destroy", "Batch", "SelInv", "stiles_selinv_query", "stiles_selinv_workspace_size",
     "stiles_selinv_create", "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract",
     "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
-    "stiles_factorize_solve", "stiles_factor_set_merged_trace",
+    "stiles_factorize_solve", "stiles_factor_set_merged_trace", "stiles_factor_set_wait_limit",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -35,6 +35,7 @@ STILES_ENOTSUP = -2
 STILES_ENOMEM = -3
 STILES_EDEVICE = -4
 STILES_ESTATE = -5
+STILES_ETIMEOUT = -6
 STILES_ORDER_AUTO = 0
 STILES_ORDER_NONE = 1
 STILES_ORDER_PARTIAL_RCM = 2
@@ -54,7 +55,7 @@ EXPORTED = [
     "stiles_batch_destroy", "stiles_selinv_query", "stiles_selinv_workspace_size", "stiles_selinv_create",
     "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract", "stiles_selinv_set_timing",
     "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy", "stiles_factorize_solve",
-    "stiles_factor_set_merged_trace",
+    "stiles_factor_set_merged_trace", "stiles_factor_set_wait_limit",
 ]
 
 
@@ -71,14 +72,16 @@ class stiles_symbolic_info(ctypes.Structure):
                 ("nnz_L", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("flops_exec", ctypes.c_double),
                 ("factor_tasks", ctypes.c_int64), ("solve_tasks", ctypes.c_int64),
                 ("corner_accumulations", ctypes.c_int64), ("tree_used", ctypes.c_int32),
-                ("nd_parts", ctypes.c_int32)]
+                ("nd_parts", ctypes.c_int32), ("nnz_L_alg", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class stiles_solve_report(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("backward_error", ctypes.c_double)]
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("backward_error", ctypes.c_double),
+                ("backward_errors", ctypes.POINTER(ctypes.c_double)),
+                ("rhs_iterations", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -114,6 +117,7 @@ def load_library(path=LIB_PATH):
         "stiles_solve": (_i32, [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(stiles_solve_report)]),
         "stiles_logdet": (_i32, [_vp, _vp, _vp]),
         "stiles_factor_set_max_workgroups": (_i32, [_vp, _i32]),
+        "stiles_factor_set_wait_limit": (_i32, [_vp, ctypes.c_double]),
         "stiles_factor_release": (None, [_vp]),
         "stiles_factor_extract": (_i32, [_vp, _vp, _vp]),
         "stiles_factor_set_timing": (_i32, [_vp, _i32]),
@@ -281,8 +285,15 @@ def stiles_factor_info(fac, stream=None):
 
 
 def stiles_solve(fac, nrhs, d_B, ldb, stream=None):
+    """Returns the report; rep.per_rhs = (backward errors, iteration counts),
+    one entry per right-hand side."""
     rep = stiles_solve_report()
+    berr = (ctypes.c_double * nrhs)()
+    its = (ctypes.c_int32 * nrhs)()
+    rep.backward_errors = ctypes.cast(berr, ctypes.POINTER(ctypes.c_double))
+    rep.rhs_iterations = ctypes.cast(its, ctypes.POINTER(ctypes.c_int32))
     _check(load_library().stiles_solve(fac, nrhs, _ptr(d_B), ldb, _stream(stream), ctypes.byref(rep)), "stiles_solve")
+    rep.per_rhs = (list(berr), list(its))
     return rep
 
 
@@ -297,6 +308,10 @@ def stiles_logdet(fac, d_out, stream=None):
 
 def stiles_factor_set_max_workgroups(fac, max_wg):
     _check(load_library().stiles_factor_set_max_workgroups(fac, max_wg), "stiles_factor_set_max_workgroups")
+
+
+def stiles_factor_set_wait_limit(fac, seconds):
+    _check(load_library().stiles_factor_set_wait_limit(fac, float(seconds)), "stiles_factor_set_wait_limit")
 
 
 def stiles_factor_release(fac):
@@ -448,6 +463,9 @@ class Factor:
 
     def set_max_workgroups(self, n):
         stiles_factor_set_max_workgroups(self.handle, n)
+
+    def set_wait_limit(self, seconds):
+        stiles_factor_set_wait_limit(self.handle, seconds)
 
     def factorize(self, d_values, stream=None):
         stiles_factorize(self.handle, d_values, stream)

@@ -659,6 +659,7 @@ extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, c
   if ((N + 63) / 16 > INT32_MAX / 4) { g_err_arg = 1; return STILES_ENOTSUP; }
   stiles_symbolic* s = new stiles_symbolic();
   init_common(*s, N, arrow, opts);
+  s->a_in = arrow;
   s->profile_input = true;
   s->ordering_used = STILES_ORDER_NONE;
   if (s->opts.ordering == STILES_ORDER_ADAPTABLE_ND && n_band > 0) {
@@ -739,6 +740,7 @@ extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t*
   if (!out) { g_err_arg = 6; return STILES_EINVAL; }
   stiles_symbolic* s = new stiles_symbolic();
   init_common(*s, N, arrow, opts);
+  s->a_in = arrow;
   s->profile_input = false;
   const int64_t n = s->n;
   // profile of the identity ordering
@@ -891,6 +893,16 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   // ---- statistics over the element envelope
   s.nnzL = 0;
   for (int64_t i = 0; i < s.N; i++) s.nnzL += i - s.f[i] + 1;
+  s.nnzL_alg = s.nnzL;
+  if (!s.f_pre.empty()) {
+    s.nnzL_alg = 0;
+    for (int64_t i = 0; i < s.N; i++) s.nnzL_alg += i - s.f_pre[i] + 1;
+  }
+  {
+    const std::vector<int64_t>& fb = s.f_pre.empty() ? s.f : s.f_pre;
+    s.w_in = 0;
+    for (int64_t i = 0; i < s.N - s.a_in; i++) s.w_in = std::max<int64_t>(s.w_in, i - fb[i]);
+  }
   s.flops_alg = envelope_flops(s.f_pre.empty() ? s.f : s.f_pre);
 
   // ---- factorization DAG
@@ -1516,6 +1528,7 @@ extern "C" stiles_status stiles_symbolic_query(const stiles_symbolic* s, stiles_
   info->solve_tasks = (int64_t)(s->stask.size() / TASK_WORDS);
   info->corner_accumulations = s->corner_acc;
   info->tree_used = s->tree_used;
+  info->nnz_L_alg = s->nnzL_alg;
   return STILES_OK;
 }
 
@@ -1578,6 +1591,7 @@ extern "C" const char* stiles_status_string(stiles_status st) {
     case STILES_ENOMEM: return "workspace too small";
     case STILES_EDEVICE: return "device error";
     case STILES_ESTATE: return "invalid state";
+    case STILES_ETIMEOUT: return "executor wait deadline passed (launch abandoned)";
     default: return "unknown status";
   }
 }

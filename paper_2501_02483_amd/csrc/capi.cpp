@@ -29,7 +29,7 @@ struct Layout {
   size_t row_base, row_cnt, trow_ptr, trow, tcol, perm;
   size_t in_rp, fprof, map, fin, in_rp_in;
   size_t tiles, linv, part, shadow, orig;
-  size_t vy, vz, vpart, vx, vr, vb, vd;
+  size_t vy, vz, vpart, vx, vr, vb, vd, vxp;
   size_t ldpart, stats;
   size_t rtile, ccol_tile, ccol_row, items, item_ptr, rpart;
   size_t total;
@@ -136,6 +136,7 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   L.vr = mixed ? take(vbytes) : 0;
   L.vb = mixed ? take(vbytes) : 0;
   L.vd = mixed ? take((size_t)s.ntr * s.T * 8) : 0;   // row sums of |A|
+  L.vxp = mixed ? take(vbytes) : 0;                      // previous refinement iterate
   L.ldpart = take((size_t)s.ntr * 8);
   L.stats = take(2 * 16 * 8 + 16);
   if (mixed && plan) {
@@ -149,6 +150,10 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   L.total = o;
   return L;
 }
+
+// default bound of an executor wait for its predecessors: 10 s of the
+// 100 MHz device wall clock (far beyond any legitimate wait here)
+constexpr uint64_t kDefaultWaitTicks = 1000000000ull;
 
 int device_wg_capacity(int T) {
   static std::mutex mu;
@@ -183,7 +188,8 @@ struct stiles_factor {
   ExecMat mf{}, ms{}, mm{};   // executor descriptors: factorization, solve, merged
   int32_t nmerged = 0;   // tasks of the merged factorization + solve DAG (FP64)
   int32_t max_wg = 0;
-  int32_t state = 0;   // 0 unknown, 1 factored ok, 2 failed, -1 not factored
+  uint64_t wait_ticks = kDefaultWaitTicks;   // bound of every executor wait (100 MHz ticks)
+  int32_t state = 0;   // 0 unknown, 1 factored ok, 2 failed (or timed out), -1 not factored
   double anorm = -1.0; // inf-norm of A (mixed mode), computed lazily
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // timing: factor pair, solve pair
   bool timing = false;
@@ -337,6 +343,15 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   return STILES_OK;
 }
 
+extern "C" stiles_status stiles_factor_set_wait_limit(stiles_factor* f, double seconds) {
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (!(seconds >= 0.0) || seconds > 3600.0) { set_error_arg(2); return STILES_EINVAL; }
+  // 100 MHz device wall clock; at least one tick
+  f->wait_ticks = seconds == 0.0 ? kDefaultWaitTicks : std::max<uint64_t>(1, (uint64_t)(seconds * 1e8));
+  return STILES_OK;
+}
+
 extern "C" stiles_status stiles_factor_set_max_workgroups(stiles_factor* f, int32_t max_wg) {
   set_error_arg(0);
   if (!f) { set_error_arg(1); return STILES_EINVAL; }
@@ -380,7 +395,7 @@ extern "C" stiles_status stiles_factorize(stiles_factor* f, const double* d_valu
   const int32_t nt = f->mf.ntasks;
   if (f->timing) (void)hipEventRecord(f->ev[0], st);
   hipError_t e = launch_exec(f->sym->T, EXEC_FACTOR, at<ExecMat>(f, f->L.mat_f), nullptr, nt, at<ExecCtrl>(f, f->L.ctrl_f), 0,
-                             nwg_for(f, nt), st);
+                             nwg_for(f, nt), f->wait_ticks, st);
   if (f->timing) (void)hipEventRecord(f->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   f->state = 0;
@@ -397,8 +412,12 @@ extern "C" stiles_status stiles_factor_info(stiles_factor* f, hipStream_t st, in
   if (hipMemcpyAsync(&v, at<unsigned long long>(f, f->L.info), 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STILES_EDEVICE;
-  *info = v == ~0ull ? 0 : (int64_t)v;
   f->state = v == ~0ull ? 1 : 2;
+  if (v == 0) {   // a launch of this factor was abandoned at its wait deadline
+    *info = -1;
+    return STILES_ETIMEOUT;
+  }
+  *info = v == ~0ull ? 0 : (int64_t)v;
   return STILES_OK;
 }
 
@@ -411,7 +430,7 @@ static stiles_status solve_sweep(stiles_factor* f, const double* d_src, int64_t 
   if (e == hipSuccess && f->timing) (void)hipEventRecord(f->ev[2], st);
   if (e == hipSuccess)
     e = launch_exec(s.T, EXEC_SOLVE, at<ExecMat>(f, L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, L.ctrl_s), nrhs,
-                    nwg_for(f, f->ms.ntasks), st);
+                    nwg_for(f, f->ms.ntasks), f->wait_ticks, st);
   if (e == hipSuccess && f->timing) (void)hipEventRecord(f->ev[3], st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
@@ -423,7 +442,7 @@ static stiles_status solve_tiles_from_tiles(stiles_factor* f, const double* d_ti
   if (hipMemcpyAsync(at<double>(f, f->L.vy), d_tile_src, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return STILES_EDEVICE;
   hipError_t e = launch_exec(s.T, EXEC_SOLVE, at<ExecMat>(f, f->L.mat_s), nullptr, f->ms.ntasks, at<ExecCtrl>(f, f->L.ctrl_s),
-                             nrhs, nwg_for(f, f->ms.ntasks), st);
+                             nrhs, nwg_for(f, f->ms.ntasks), f->wait_ticks, st);
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
 
@@ -438,7 +457,15 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
   if (f->state == 2) return STILES_ESTATE;
   const stiles_symbolic& s = *f->sym;
   const Layout& L = f->L;
-  if (report) { report->iterations = 0; report->converged = 1; report->backward_error = -1.0; }
+  if (report) {
+    report->iterations = 0;
+    report->converged = 1;
+    report->backward_error = -1.0;
+    for (int64_t c = 0; c < nrhs; c++) {
+      if (report->backward_errors) report->backward_errors[c] = -1.0;
+      if (report->rhs_iterations) report->rhs_iterations[c] = 0;
+    }
+  }
   for (int64_t c0 = 0; c0 < nrhs; c0 += 16) {
     const int nb = (int)std::min<int64_t>(16, nrhs - c0);
     double* B = d_B + c0 * ldb;
@@ -450,9 +477,11 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
         return STILES_EDEVICE;
       continue;
     }
-    // ---- mixed mode: x0 = solve(b); repeat r = b - A x, d = solve(r), x += d
+    // ---- mixed mode: x0 = solve(b); repeat r = b - A x, d = solve(r), x += d,
+    //      each right-hand side until its own stopping test holds
     const size_t vbytes = (size_t)s.ntr * s.T * nb * 8;
     double* vx = at<double>(f, L.vx);
+    double* vxp = at<double>(f, L.vxp);
     double* vr = at<double>(f, L.vr);
     double* vbb = at<double>(f, L.vb);
     double* vz = at<double>(f, L.vz);
@@ -494,12 +523,19 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
         return STILES_EDEVICE;
       for (int c = 0; c < nb; c++) { double v; std::memcpy(&v, &h[2 * c], 8); bnorm[c] = v; }
     }
-    const double tol = f->sym->opts.refine_tol > 0 ? f->sym->opts.refine_tol
-                                                   : std::ldexp(1.0, -52) * std::sqrt((double)s.N);
+    // default stopping test: a backward error of the size the FP64 factor's
+    // own solve reaches, u (w + a), w the largest band half-width
+    const double tol = f->sym->opts.refine_tol > 0
+                           ? f->sym->opts.refine_tol
+                           : std::ldexp(1.0, -52) * (double)std::max<int64_t>(1, s.w_in + s.a_in);
     const int maxit = f->sym->opts.refine_max_iter > 0 ? f->sym->opts.refine_max_iter : 30;
-    int it = 0;
-    bool conv = false;
-    double berr = INFINITY, prev = INFINITY;
+    // per right-hand side: backward error of the current x, steps taken,
+    // converged, still refining
+    std::vector<double> berr(nb, INFINITY);
+    std::vector<int> its(nb, 0);
+    std::vector<char> conv(nb, 0);
+    uint32_t active = (1u << nb) - 1u;   // nb <= 16
+    int step = 0;
     for (;;) {
       if (resid(vx, vr, 0) != hipSuccess) return STILES_EDEVICE;
       std::vector<unsigned long long> z(2 * 16, 0ull), h(2 * 16);
@@ -508,30 +544,61 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
       if (hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         return STILES_EDEVICE;
-      berr = 0.0;
+      uint32_t revert = 0;
       for (int c = 0; c < nb; c++) {
+        if (!((active >> c) & 1u)) continue;
         double rn, xn;
         std::memcpy(&rn, &h[2 * c], 8);
         std::memcpy(&xn, &h[2 * c + 1], 8);
         const double den = f->anorm * xn + bnorm[c];
-        berr = std::max(berr, den > 0 ? rn / den : rn);
+        const double be = den > 0 ? rn / den : rn;
+        const uint32_t bit = 1u << c;
+        if (!(be == be)) {                       // NaN: failed factorization
+          berr[c] = be;
+          active &= ~bit;
+        } else if (be <= tol) {                  // converged
+          berr[c] = be;
+          conv[c] = 1;
+          active &= ~bit;
+        } else if (step > 0 && be > 0.5 * berr[c]) {
+          // no longer halving (stagnation): keep the better of the last two
+          // iterates, with its backward error
+          if (be > berr[c]) {
+            revert |= bit;   // the last correction is undone
+            its[c]--;
+          } else {
+            berr[c] = be;
+          }
+          active &= ~bit;
+        } else {
+          berr[c] = be;
+          if (its[c] >= maxit) active &= ~bit;   // step limit
+        }
       }
-      if (!(berr == berr)) break;   // NaN: failed factorization
-      if (berr <= tol) { conv = true; break; }
-      if (it >= maxit || berr > 0.5 * prev) break;   // no longer halving: stagnation
-      prev = berr;
+      if (revert && launch_copy_cols(s.T, s.ntr, nb, vx, vxp, revert, st) != hipSuccess) return STILES_EDEVICE;
+      if (!active) break;
+      // x_prev = x; d = solve(r) (every column: the sweep's cost does not
+      // depend on the count); x += d on the columns still refining
+      if (hipMemcpyAsync(vxp, vx, vbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return STILES_EDEVICE;
       stiles_status r2 = solve_tiles_from_tiles(f, vr, nb, st);
       if (r2 != STILES_OK) return r2;
-      if (launch_axpy(s.T, s.ntr, nb, vx, vz, st) != hipSuccess) return STILES_EDEVICE;
-      it++;
+      if (launch_axpy(s.T, s.ntr, nb, vx, vz, active, st) != hipSuccess) return STILES_EDEVICE;
+      for (int c = 0; c < nb; c++)
+        if ((active >> c) & 1u) its[c]++;
+      step++;
     }
     if (launch_unpack(s.T, vx, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
                       s.ntr, at<unsigned long long>(f, L.info), B, ldb, st) != hipSuccess)
       return STILES_EDEVICE;
     if (report) {
-      report->iterations = std::max(report->iterations, it);
-      report->converged = report->converged && conv;
-      report->backward_error = std::max(report->backward_error, berr);
+      for (int c = 0; c < nb; c++) {
+        report->iterations = std::max(report->iterations, its[c]);
+        report->converged = report->converged && conv[c];
+        report->backward_error = std::max(report->backward_error, berr[c]);
+        if (!(berr[c] == berr[c])) report->backward_error = berr[c];
+        if (report->backward_errors) report->backward_errors[c0 + c] = berr[c];
+        if (report->rhs_iterations) report->rhs_iterations[c0 + c] = its[c];
+      }
     }
   }
   return STILES_OK;
@@ -557,7 +624,7 @@ extern "C" stiles_status stiles_factorize_solve(stiles_factor* f, const double* 
   if (e != hipSuccess) return STILES_EDEVICE;
   if (f->timing) (void)hipEventRecord(f->ev[0], st);
   e = launch_exec(sy.T, EXEC_FACTOR_SOLVE, at<ExecMat>(f, L.mat_m), nullptr, f->nmerged, at<ExecCtrl>(f, L.ctrl_m), nb,
-                  nwg_for(f, f->nmerged), st);
+                  nwg_for(f, f->nmerged), f->wait_ticks, st);
   if (f->timing) (void)hipEventRecord(f->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   f->state = 0;
@@ -813,7 +880,8 @@ extern "C" stiles_status stiles_batch_factorize(stiles_batch* b, const double* c
   if (f0->timing) (void)hipEventRecord(f0->ev[0], st);
   hipError_t e = launch_exec(b->T, EXEC_FACTOR, reinterpret_cast<const ExecMat*>(b->ws + b->B.mats),
                              reinterpret_cast<const int32_t*>(b->ws + b->B.order), b->total,
-                             reinterpret_cast<ExecCtrl*>(b->ws + b->B.ctrl), 0, std::min<int>(cap, b->total), st);
+                             reinterpret_cast<ExecCtrl*>(b->ws + b->B.ctrl), 0, std::min<int>(cap, b->total),
+                             f0->wait_ticks, st);
   if (f0->timing) (void)hipEventRecord(f0->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   for (auto* f : b->factors) { f->state = 0; f->anorm = -1.0; }
@@ -1029,7 +1097,7 @@ extern "C" stiles_status stiles_selinv_compute(stiles_selinv* si, hipStream_t st
   if (si->timing) (void)hipEventRecord(si->ev[0], st);
   hipError_t e = launch_exec(f->sym->T, EXEC_SELINV, reinterpret_cast<const ExecMat*>(si->ws + si->L.mat), nullptr,
                              si->ntasks, reinterpret_cast<ExecCtrl*>(si->ws + si->L.ctrl), 0,
-                             nwg_for(f, si->ntasks), st);
+                             nwg_for(f, si->ntasks), f->wait_ticks, st);
   if (si->timing) (void)hipEventRecord(si->ev[1], st);
   if (e != hipSuccess) return STILES_EDEVICE;
   si->done = true;

@@ -66,8 +66,6 @@ __device__ __forceinline__ void st_relaxed(int32_t* p, int32_t v) {
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
-// 1/sqrt(d): hardware estimate (about 24 bits) refined by two Newton steps
-// y <- y + y (1 - d y^2) / 2, which reach full double precision (to ~1 ulp).
 // 1/sqrt(d): hardware estimate, then one third-order correction
 // y = y0 (1 + e/2 + 3 e^2 / 8), e = 1 - d y0^2 (four dependent FP64 steps
 // instead of six for two Newton steps; the estimate's error is cubed)
@@ -76,15 +74,6 @@ __device__ __forceinline__ double rsqrt_c(double d) {
   const double e = fma(-d * y0, y0, 1.0);
   const double p = fma(0.375, e, 0.5);
   return fma(y0 * e, p, y0);
-}
-
-__device__ __forceinline__ double rsqrt_nr(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  double e = fma(-d * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-d * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  return y;
 }
 
 // ------------------------------------------------------- tile products (MFMA)
@@ -716,13 +705,41 @@ struct SolveOps {
   }
 };
 
-// the calling workgroup waits until *cnt is zero, then acquires
-__device__ __forceinline__ void wait_zero(int32_t* cnt) {
+// The calling workgroup waits until *cnt < bound (all predecessors, or all
+// predecessors of one kind, have finished), then acquires.  Wave 0 polls.
+// The wait is bounded: it gives up when another workgroup of the launch has
+// given up (ctrl->abort) or when `limit` ticks of the 100 MHz wall clock pass
+// without the counter falling; the first to give up sets ctrl->abort.  The
+// result is the same for every thread (false: gave up).  The verdict goes
+// through LDS; the second barrier keeps a later wait from overwriting it
+// before every wave has read it.
+__device__ __forceinline__ bool wait_below(int32_t* cnt, int32_t bound, ExecCtrl* ctrl, uint64_t limit) {
+  __shared__ int32_t s_ok;
   if (threadIdx.x < 64) {
-    while (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) > 0) __builtin_amdgcn_s_sleep(1);
+    int32_t ok = 1;
+    if (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) >= bound) {
+      const uint64_t t0 = wall_clock64();
+      for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) < bound) break;
+        if (__builtin_amdgcn_readfirstlane(ld_relaxed(&ctrl->abort)) != 0) {
+          ok = 0;
+          break;
+        }
+        if (wall_clock64() - t0 > limit) {
+          st_relaxed(&ctrl->abort, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
     fence_acquire();
+    if (threadIdx.x == 0) s_ok = ok;
   }
   __syncthreads();
+  const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
+  __syncthreads();
+  return ok;
 }
 
 // A solve task (FUPD, FDIAG, BUPD, BDIAG, FPART).  It waits for its
@@ -730,9 +747,11 @@ __device__ __forceinline__ void wait_zero(int32_t* cnt) {
 // two fused products and the inverse diagonal tile) are read into registers
 // first, so that only the small vector blocks are loaded once the
 // predecessors are done.  The factor tiles must be final when it is called.
+// `ok` enters false when the launch was already abandoned and leaves false
+// when this task's own wait gave up; the task then writes nothing.
 template <int T, int K>
 __device__ __forceinline__ uint64_t task_solve_r(const ExecMat& M, const int32_t* w, int nrhs, int32_t* cnt,
-                                                           double* LV) {
+                                                 double* LV, ExecCtrl* ctrl, uint64_t limit, bool& ok) {
   typedef SolveOps<T> O;
   constexpr int TT = T * T, NS = O::NS;
   const int type = __builtin_amdgcn_readfirstlane(w[0]) & 0xff;
@@ -758,7 +777,8 @@ __device__ __forceinline__ uint64_t task_solve_r(const ExecMat& M, const int32_t
       if (np > 1) O::load_a(a1, M.tiles + (int64_t)word(pv, 2) * TT, !fwd, wave, lane);
       O::load_a(ai, M.linv + (int64_t)m * TT, !fwd, wave, lane);
     }
-    wait_zero(cnt);
+    if (ok) ok = wait_below(cnt, 1, ctrl, limit);
+    if (!ok) return 0;
     const uint64_t t_start = M.trace ? wall_clock64() : 0;
     double bs[4];
     if (act) {
@@ -795,7 +815,8 @@ __device__ __forceinline__ uint64_t task_solve_r(const ExecMat& M, const int32_t
     O::load_a(a[0], M.tiles + (int64_t)word(pv, 0) * TT, !fwd, wave, lane);
     if (np > 1) O::load_a(a[1], M.tiles + (int64_t)word(pv, 2) * TT, !fwd, wave, lane);
   }
-  wait_zero(cnt);
+  if (ok) ok = wait_below(cnt, 1, ctrl, limit);
+  if (!ok) return 0;
   const uint64_t t_start = M.trace ? wall_clock64() : 0;
   if (act) {
     if (np > 0) O::load_b(b[0], vsrc + word(pv, 1) * vb, nrhs, lane);
@@ -1237,7 +1258,7 @@ __device__ __attribute__((noinline)) void task_tsum(const ExecMat& M, const int3
 // separate kernels so that each carries only its own code.
 template <int T, int KIND>
 __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__ mats, const int32_t* __restrict__ order,
-                                                  int32_t total, ExecCtrl* ctrl, int nrhs) {
+                                                  int32_t total, ExecCtrl* ctrl, int nrhs, uint64_t limit) {
   constexpr bool SOLVE = KIND == EXEC_SOLVE, SELINV = KIND == EXEC_SELINV, BOTH = KIND == EXEC_FACTOR_SOLVE;
   // LDS: factorization tasks use S (tile, ld T+1 room), Xi (T x T) and rinv;
   // solve tasks only a T x 16 block (Xi in the solve kernel, LI in the
@@ -1273,14 +1294,9 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     // merged factorization + solve DAG: a solve task first waits for its
     // factorization predecessors only (the counter falls below MERGED_FDEP);
     // its factor tiles are final then
+    bool ok = true;
     if constexpr (BOTH) {
-      if (type >= TK_FUPD) {
-        if (threadIdx.x < 64) {
-          while (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) >= MERGED_FDEP) __builtin_amdgcn_s_sleep(1);
-          fence_acquire();
-        }
-        __syncthreads();
-      }
+      if (type >= TK_FUPD) ok = wait_below(cnt, MERGED_FDEP, ctrl, limit);
     }
     // solve tasks other than FSUM wait for their predecessors themselves,
     // after reading their factor tiles
@@ -1288,7 +1304,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     // wait until every predecessor has finished (Alg. 2 progress check);
     // wave 0 polls, then acquires for the workgroup (all its waves share
     // the CU's caches that the acquire invalidates)
-    if (!self_wait) wait_zero(cnt);
+    if (!self_wait && ok) ok = wait_below(cnt, 1, ctrl, limit);
     if (M.trace) t_start = wall_clock64();
     // tasks on the pivot chain (diagonal factorization, panel solve, diagonal
     // solve steps) raise their waves' issue priority over the co-resident
@@ -1298,17 +1314,24 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
                                 : (type == TK_POTRF || type == TK_TRSM || type == TK_FDIAG || type == TK_BDIAG);
     if (chain) __builtin_amdgcn_s_setprio(3);
     if constexpr (SELINV) {
-      if (type == TK_SWE) task_swe<T>(M, w, S, Xi);
+      if (!ok) {
+      } else if (type == TK_SWE) task_swe<T>(M, w, S, Xi);
       else if (type == TK_SW) task_sw<T>(M, w, S, Xi);
       else if (type == TK_SDIAG) task_sdiag<T>(M, w, S, Xi);
       else task_tsum<T>(M, w);
     } else if constexpr (SOLVE) {
-      if (type == TK_FSUM) task_fsum<T, KIND>(M, w, nrhs);
-      else t_start = task_solve_r<T, KIND>(M, w, nrhs, cnt, Xi);
+      if (type == TK_FSUM) {
+        if (ok) task_fsum<T, KIND>(M, w, nrhs);
+      } else {
+        t_start = task_solve_r<T, KIND>(M, w, nrhs, cnt, Xi, ctrl, limit, ok);
+      }
     } else if (BOTH && type >= TK_FUPD) {
-      if (type == TK_FSUM) task_fsum<T, KIND>(M, w, nrhs);
-      else t_start = task_solve_r<T, KIND>(M, w, nrhs, cnt, LI);
-    } else {
+      if (type == TK_FSUM) {
+        if (ok) task_fsum<T, KIND>(M, w, nrhs);
+      } else {
+        t_start = task_solve_r<T, KIND>(M, w, nrhs, cnt, LI, ctrl, limit, ok);
+      }
+    } else if (ok) {
       switch (type) {
         case TK_UPD: task_update<T, KIND>(M, w, 0, S, Xi); break;
         case TK_PART: task_update<T, KIND>(M, w, 1, S, Xi); break;
@@ -1318,6 +1341,14 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       }
     }
     if (chain) __builtin_amdgcn_s_setprio(0);
+    if (!ok) {
+      // abandoned launch: the task is skipped and its matrix marked as timed
+      // out (info 0, below every failing column); no successor is notified
+      // and the counters are re-armed by the last workgroup to leave
+      if (threadIdx.x == 0) atomicMin(M.info, 0ull);
+      __syncthreads();
+      continue;
+    }
     // every wave waits for its own stores (device-scope stores, coherent
     // once complete), then wave 0 notifies the successors (Alg. 2 progress
     // update); the workgroup-scope release only orders the notification
@@ -1346,9 +1377,35 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       tr[3] = ((unsigned long long)blockIdx.x << 32) | ((unsigned)type << 24) | ((unsigned)t & 0xffffffu);
     }
   }
+  // the last workgroup to leave re-arms the control block; after an abort it
+  // also re-arms every progress counter of the launch (skipped tasks did not
+  // re-arm theirs, and some were notified after being skipped).  Every
+  // workgroup's notifications are complete before it counts itself out.
+  __shared__ int32_t s_last;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
   if (threadIdx.x == 0) {
+    fence_release();
     const int e = atomicAdd(&ctrl->exited, 1);
-    if (e == (int)gridDim.x - 1) {   // every other workgroup has left: re-arm
+    s_last = e == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (__builtin_amdgcn_readfirstlane(s_last)) {
+    fence_acquire();
+    if (__builtin_amdgcn_readfirstlane(ld_relaxed(&ctrl->abort)) != 0) {
+      for (int32_t t = threadIdx.x; t < total; t += NT) {
+        int32_t mi = 0, lid = t;
+        if (order) {
+          mi = order[2 * t];
+          lid = order[2 * t + 1];
+        }
+        st_relaxed(mats[mi].remaining + lid, mats[mi].tasks[(int64_t)lid * TASK_WORDS + 7]);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      st_relaxed(&ctrl->abort, 0);
       ctrl->ticket = 0;
       ctrl->exited = 0;
     }
@@ -1356,11 +1413,11 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
 }
 
 hipError_t launch_exec(int T, int kind, const ExecMat* d_mats, const int32_t* d_order, int32_t total,
-                       ExecCtrl* d_ctrl, int nrhs, int nwg, hipStream_t st) {
+                       ExecCtrl* d_ctrl, int nrhs, int nwg, uint64_t wait_ticks, hipStream_t st) {
   if (total <= 0) return hipSuccess;
   if (nwg > total) nwg = total;
 #define STILES_EXEC(TT, KK) \
-  hipLaunchKernelGGL((exec_kernel<TT, KK>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs)
+  hipLaunchKernelGGL((exec_kernel<TT, KK>), dim3(nwg), dim3(NT), 0, st, d_mats, d_order, total, d_ctrl, nrhs, wait_ticks)
   if (T == 64) {
     if (kind == EXEC_SOLVE) STILES_EXEC(64, EXEC_SOLVE);
     else if (kind == EXEC_SELINV) STILES_EXEC(64, EXEC_SELINV);
@@ -1484,9 +1541,6 @@ __global__ __launch_bounds__(NT) void scatter_profile_kernel(const double* __res
 // (r, c) of tile (m, j) is the input entry (perm[row], perm[col]), taken from
 // the lower triangle (larger index as the row).  The gathers follow the tile
 // rows; entries of reversed blocks are read transposed.
-// Tile of P A P^T from row-profile values of the input ordering: element
-// (r, c) of tile (m, j) is the input entry (perm[row], perm[col]), taken from
-// the lower triangle (larger index as the row).
 template <int T>
 __device__ __forceinline__ void scatter_tile_perm(const double* __restrict__ vals, const int64_t* __restrict__ in_rp,
                                                   const int64_t* __restrict__ fin, const int64_t* __restrict__ perm,
@@ -1983,14 +2037,27 @@ hipError_t launch_norms(int T, int32_t ntr, int nrhs, const double* R, const dou
   return hipGetLastError();
 }
 
-__global__ void axpy_kernel(int64_t n, double* X, const double* __restrict__ D) {
+// X(:, c) += D(:, c) (assign = 0) or X(:, c) = D(:, c) (assign = 1) for the
+// right-hand sides c whose bit is set in `mask`; blocks of T x nrhs, so
+// element e belongs to column (e / T) mod nrhs
+__global__ void colmask_kernel(int64_t n, int T, int nrhs, double* X, const double* __restrict__ D, uint32_t mask,
+                               int assign) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) X[e] += D[e];
+  if (e >= n) return;
+  const int c = (int)((e / T) % nrhs);
+  if (!((mask >> c) & 1u)) return;
+  X[e] = assign ? D[e] : X[e] + D[e];
 }
 
-hipError_t launch_axpy(int T, int32_t ntr, int nrhs, double* X, const double* D, hipStream_t st) {
+hipError_t launch_axpy(int T, int32_t ntr, int nrhs, double* X, const double* D, uint32_t mask, hipStream_t st) {
   const int64_t n = (int64_t)T * nrhs * ntr;
-  hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n, X, D);
+  hipLaunchKernelGGL(colmask_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n, T, nrhs, X, D, mask, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(int T, int32_t ntr, int nrhs, double* X, const double* P, uint32_t mask, hipStream_t st) {
+  const int64_t n = (int64_t)T * nrhs * ntr;
+  hipLaunchKernelGGL(colmask_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n, T, nrhs, X, P, mask, 1);
   return hipGetLastError();
 }
 

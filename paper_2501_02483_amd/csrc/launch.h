@@ -12,9 +12,12 @@ namespace stiles {
 // means one matrix (mats[0]) with tasks in their own order, else order[2t],
 // order[2t+1] = (matrix index, task id).
 // EXEC_FACTOR_SOLVE runs a merged DAG of factorization and solve tasks.
+// wait_ticks bounds every wait for predecessors (ticks of the 100 MHz device
+// wall clock); past it the launch is abandoned: the skipped tasks' matrices
+// get info = 0 (timeout) and every workgroup exits normally.
 enum ExecKind { EXEC_FACTOR = 0, EXEC_SOLVE = 1, EXEC_SELINV = 2, EXEC_FACTOR_SOLVE = 3 };
 hipError_t launch_exec(int T, int kind, const ExecMat* d_mats, const int32_t* d_order, int32_t total,
-                       ExecCtrl* d_ctrl, int nrhs, int nwg, hipStream_t st);
+                       ExecCtrl* d_ctrl, int nrhs, int nwg, uint64_t wait_ticks, hipStream_t st);
 
 // diagonal of the selected inverse in the original ordering (NaN on failure)
 hipError_t launch_selinv_diag(int T, const double* sigma, const int32_t* trow_ptr, const int64_t* row_base,
@@ -78,7 +81,9 @@ hipError_t launch_residual(int T, const double* orig, const int32_t* rtile, cons
 // stats[2c] = max_i |R_ic|, stats[2c+1] = max_i |X_ic| (bit patterns, atomically maxed)
 hipError_t launch_norms(int T, int32_t ntr, int nrhs, const double* R, const double* X, unsigned long long* stats,
                         hipStream_t st);
-// X += D
-hipError_t launch_axpy(int T, int32_t ntr, int nrhs, double* X, const double* D, hipStream_t st);
+// X(:, c) += D(:, c) for the right-hand sides c set in mask
+hipError_t launch_axpy(int T, int32_t ntr, int nrhs, double* X, const double* D, uint32_t mask, hipStream_t st);
+// X(:, c) = P(:, c) for the right-hand sides c set in mask
+hipError_t launch_copy_cols(int T, int32_t ntr, int nrhs, double* X, const double* P, uint32_t mask, hipStream_t st);
 
 }  // namespace stiles

@@ -121,11 +121,19 @@ struct BatchDesc {
   int32_t ntr;
 };
 
-// Launch control block (one per concurrent launch).
+// Launch control block (one per concurrent launch).  `abort` is set by the
+// first workgroup whose wait for its predecessors passes the launch's
+// deadline; every later wait of the launch then gives up at once, so all
+// workgroups skip their remaining tasks and exit.  The last workgroup to
+// leave re-arms the block (and, after an abort, every progress counter).
+// `abort` sits on a cache line of its own, away from the ticket counter.
 struct ExecCtrl {
   int32_t ticket;
   int32_t exited;
-  int32_t pad[62];          // keep the next block on its own cache lines
+  int32_t pad0[30];
+  int32_t abort;
+  int32_t pad1[31];
 };
+static_assert(sizeof(ExecCtrl) == 256, "ExecCtrl spans two 128-byte cache lines");
 
 }  // namespace stiles

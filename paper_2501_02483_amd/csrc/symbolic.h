@@ -27,6 +27,8 @@ struct MergedPlan {
 struct stiles_symbolic {
   stiles_opts opts;
   int64_t N = 0, n = 0, a = 0;
+  int64_t a_in = 0;            // arrow width of the input (before ND adds separators)
+  int64_t w_in = 0;            // largest lower half-width of the band rows before ND
   int32_t T = 64;
   int32_t ordering_used = STILES_ORDER_NONE;
   bool profile_input = false;
@@ -84,6 +86,7 @@ struct stiles_symbolic {
 
   // statistics
   int64_t nnzL = 0;
+  int64_t nnzL_alg = 0;   // envelope entries before adaptable ND (the method's nnz(L))
   double flops_alg = 0.0;
   double flops_exec = 0.0;
 };

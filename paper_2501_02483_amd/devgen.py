@@ -53,13 +53,35 @@ class DevicePattern:
             self.wmax = max(self.wmax, int(i[early].max()))
         self.tmp = torch.empty(2 * N, dtype=torch.float64, device=device)
 
-    def values(self, seed, out=None, stream=None, law="dominant", kappa=1e6, tmp=None):
+    def values(self, seed, out=None, stream=None, law="dominant", kappa=1e6, tmp=None, decades=3.0):
         """Seeded values on the device; law "dominant" (diagonal = |row| + 1)
         or "laplacian" (-|z| off-diagonals, diagonal = |row| + eps with
-        eps = 2 max|row| / kappa, so that the smallest eigenvalue is eps).
+        eps = 2 max|row| / kappa, so that the smallest eigenvalue is eps), or
+        "scaled": the dominant matrix A0 scaled symmetrically, S A0 S with
+        s_i = 10^(-decades u_i), u_i ~ U[0, 1) from torch's generator seeded
+        with `seed` (condition number up to ~10^(2 decades) while the
+        diagonally scaled matrix stays well conditioned).
         tmp: scratch of at least 2N doubles; calls that may overlap on
         different streams must each pass their own (the default is shared)."""
         import torch
+        if law == "scaled":
+            v = self.values(seed, out=out, stream=stream, law="dominant", tmp=tmp)
+            st = stream if stream is not None else torch.cuda.current_stream()
+            with torch.cuda.stream(st):
+                g = torch.Generator(device=v.device).manual_seed(int(seed))
+                s = torch.pow(10.0, -decades * torch.rand(self.N, dtype=torch.float64, device=v.device,
+                                                          generator=g))
+                # entry e of row i sits at column f_i + (e - rp_i); rows in blocks
+                rp = self.rp
+                step = 1 << 14
+                for r0 in range(0, self.N, step):
+                    r1 = min(self.N, r0 + step)
+                    lens = rp[r0 + 1:r1 + 1] - rp[r0:r1]
+                    rows = torch.repeat_interleave(torch.arange(r0, r1, device=v.device), lens)
+                    lo, hi = int(rp[r0]), int(rp[r1])
+                    cols = torch.arange(lo, hi, device=v.device) - rp[rows] + self.f[rows]
+                    v[lo:hi] *= s[rows] * s[cols]
+            return v
         if out is None:
             out = torch.empty(self.nnz, dtype=torch.float64, device=self.rp.device)
         if tmp is None:

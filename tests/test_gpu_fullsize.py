@@ -1,9 +1,13 @@
 """Parity at the benchmarked sizes, in the launch configurations the bench
 times: the variable-bandwidth matrix (n = 200,000, arrow 100, 8 right-hand
-sides) under the natural ordering and under adaptable ND, and the 512-matrix
-batch.  The oracle runs on the full inputs on the host cores (a few seconds
-each); solutions and log-determinants are compared in full, the natural-order
-factor element by element."""
+sides) under the natural ordering and under adaptable ND -- including the
+merged factorization + solve launch exactly as the bench times it -- the
+512-matrix batch and the n = 500,000 mixed-precision workload.  The oracle
+runs on the full inputs on the host cores (a few seconds each).  Every
+solution and log-determinant is compared in full; errors are normwise
+relative (per right-hand side for X), and the natural-order factor is
+checked both as a whole and per tile column (the largest
+||dL(:,k)||_F / ||L_o(:,k)||_F over the tile columns k)."""
 import os
 
 import numpy as np
@@ -13,7 +17,7 @@ import oracle
 import paper_2501_02483_amd as S
 from paper_2501_02483_amd import inputs as I
 
-from gpu_util import rel, say, to_device_cols
+from gpu_util import col_tile_err, oracle_solve_cols, rel, rel_cols, say, to_device_cols
 
 pytestmark = pytest.mark.gpu
 
@@ -48,14 +52,44 @@ def test_varband_full_size(varband, ordering, parts):
     ld = fac.logdet().item()
     dB = to_device_cols(B)
     fac.solve(dB)
-    eX = rel(dB.cpu().numpy(), Xref)
+    eX = rel_cols(dB.cpu().numpy(), Xref)
     eld = abs(ld - ldref) / abs(ldref)
-    say("   errors: X %.2e  logdet %.2e" % (eX, eld))
+    say("   errors: X %.2e (worst right-hand side)  logdet %.2e" % (eX, eld))
     assert eX <= TOL and eld <= TOL
     if ordering == S.STILES_ORDER_NONE:
-        eL = rel(fac.extract().cpu().numpy(), Lref)
-        say("   error L %.2e" % eL)
-        assert eL <= TOL
+        Lg = fac.extract().cpu().numpy()
+        eL = rel(Lg, Lref)
+        eLc = col_tile_err(Lg, Lref, p.f, 64)
+        say("   error L %.2e, worst tile column %.2e" % (eL, eLc))
+        assert eL <= TOL and eLc <= TOL
+
+
+def test_merged_launch_full_size(varband):
+    """The bench's step exactly: automatic adaptable ND, T = 64, the merged
+    factorization + solve launch with 8 right-hand sides.  X (every column)
+    and logdet against the oracle within 1e-12, and X bitwise equal to
+    separate factorize + solve launches on the same symbolic object."""
+    import torch
+    p, vals, B, Lref, ldref, Xref = varband
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=S.STILES_ORDER_ADAPTABLE_ND)
+    say("[gpu fullsize] merged launch, varband T=64, %d partitions, 8 RHS" % sym.info.nd_parts)
+    dv = torch.from_numpy(vals).cuda()
+    fac = S.Factor(sym, nrhs_max=8)
+    Xm = to_device_cols(B)
+    fac.factorize_solve(dv, Xm)
+    assert fac.info() == 0
+    ld = fac.logdet().item()
+    eX = rel_cols(Xm.cpu().numpy(), Xref)
+    eld = abs(ld - ldref) / abs(ldref)
+    say("   errors: X %.2e (worst right-hand side)  logdet %.2e" % (eX, eld))
+    assert eX <= TOL and eld <= TOL
+    sep = S.Factor(sym, nrhs_max=8)
+    sep.factorize(dv)
+    Xs = to_device_cols(B)
+    sep.solve(Xs)
+    assert sep.info() == 0
+    assert torch.equal(Xm, Xs), "merged launch differs from separate launches"
+    assert torch.equal(fac.logdet(), sep.logdet())
 
 
 @pytest.fixture(scope="module")
@@ -141,8 +175,8 @@ def test_small_bench_configuration():
 def test_mixed_full_size():
     """The n = 500,000 / half-width 1,000 / arrow 200 Laplacian workload
     (κ ≈ 1e6) in mixed precision, as the bench runs it (adaptable ND, 16
-    right-hand sides, FP64 refinement): four sampled right-hand sides and
-    the log-determinant against the oracle on the device-drawn values."""
+    right-hand sides, FP64 refinement): all sixteen solutions (each column)
+    and the log-determinant against the oracle on the device-drawn values."""
     import torch
 
     from paper_2501_02483_amd.devgen import DevicePattern
@@ -159,17 +193,18 @@ def test_mixed_full_size():
     rep = fac.solve(X)
     ld = fac.logdet().item()
     vals = dv.cpu().numpy()
-    Bh = np.ascontiguousarray(B.cpu().numpy()[:, :4])
-    Xh = np.ascontiguousarray(X.cpu().numpy()[:, :4])
+    Bh = np.ascontiguousarray(B.cpu().numpy())
+    Xh = np.ascontiguousarray(X.cpu().numpy())
     del fac, dv
     say("   oracle factorization (host)")
     L, info = oracle.factor(p.f, vals, nthreads=_threads())
     assert info == 0
     ld_o = oracle.logdet(p.f, L)
-    X_o = oracle.solve(p.f, L, Bh)
-    eX = rel(Xh, X_o)
+    X_o = oracle_solve_cols(p.f, L, Bh)
+    eX = rel_cols(Xh, X_o)
     eld = abs(ld - ld_o) / abs(ld_o)
-    say("   errors: X %.2e  logdet %.2e  refinement steps %d  backward error %.2e" % (
-        eX, eld, rep.iterations, rep.backward_error))
+    say("   errors: X %.2e (worst of 16 right-hand sides)  logdet %.2e  refinement steps %d  "
+        "backward error %.2e" % (eX, eld, rep.iterations, rep.backward_error))
     assert rep.converged == 1
+    assert max(rep.per_rhs[0]) == rep.backward_error
     assert eX <= 1e-9 and eld <= 1e-6
