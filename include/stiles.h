@@ -333,6 +333,22 @@ stiles_status stiles_factorize_solve(stiles_factor* f, const double* d_values, i
  * Deterministic fixed-shape reduction.  NaN if the factorization failed. */
 stiles_status stiles_logdet(stiles_factor* f, double* d_out, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * log-determinant as stiles_logdet, bitwise, with the per-tile-row partial
+ * sums kept in a fixed device array of the library instead of the factor's
+ * workspace.  The array holds STILES_STATIC_LOGDET_MAX_ROWS tile rows
+ * (512 KiB per GPU the library runs on, held until the process ends); a
+ * factor with more tile rows (stiles_symbolic_info.tile_rows) is rejected
+ * with STILES_ENOTSUP before anything is launched.  The call allocates
+ * nothing; its address is looked up once per device (with that device
+ * current).  Every call on one GPU shares the array: calls that overlap on
+ * one GPU (different streams, or host threads) race and must be serialized
+ * by the caller.  d_out, the factor's state and the failure value (NaN) as
+ * for stiles_logdet. */
+#define STILES_STATIC_LOGDET_MAX_ROWS 65536
+stiles_status stiles_logdet_static(stiles_factor* f, double* d_out, hipStream_t stream);
+
 /* Copy the factor L out of the tile store into d_L, in row-profile order of
  * the permuted envelope: row i of P A P^T holds columns f_i..i, f_i being the
  * first column of row i in P A P^T (for stiles_analyze_profile input with the

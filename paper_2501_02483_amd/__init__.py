@@ -25,6 +25,7 @@ __all__ = [
     "stiles_selinv_create", "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract",
     "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
     "stiles_factorize_solve", "stiles_factor_set_merged_trace", "stiles_factor_set_wait_limit",
+    "stiles_logdet_static", "STILES_STATIC_LOGDET_MAX_ROWS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
@@ -42,6 +43,7 @@ STILES_ORDER_PARTIAL_RCM = 2
 STILES_ORDER_ADAPTABLE_ND = 3
 STILES_FP64 = 0
 STILES_MIXED32 = 1
+STILES_STATIC_LOGDET_MAX_ROWS = 65536
 
 # every symbol include/stiles.h declares
 EXPORTED = [
@@ -55,7 +57,7 @@ EXPORTED = [
     "stiles_batch_destroy", "stiles_selinv_query", "stiles_selinv_workspace_size", "stiles_selinv_create",
     "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract", "stiles_selinv_set_timing",
     "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy", "stiles_factorize_solve",
-    "stiles_factor_set_merged_trace", "stiles_factor_set_wait_limit",
+    "stiles_factor_set_merged_trace", "stiles_factor_set_wait_limit", "stiles_logdet_static",
 ]
 
 
@@ -116,6 +118,7 @@ def load_library(path=LIB_PATH):
         "stiles_factor_info": (_i32, [_vp, _vp, ctypes.POINTER(_i64)]),
         "stiles_solve": (_i32, [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(stiles_solve_report)]),
         "stiles_logdet": (_i32, [_vp, _vp, _vp]),
+        "stiles_logdet_static": (_i32, [_vp, _vp, _vp]),
         "stiles_factor_set_max_workgroups": (_i32, [_vp, _i32]),
         "stiles_factor_set_wait_limit": (_i32, [_vp, ctypes.c_double]),
         "stiles_factor_release": (None, [_vp]),
@@ -304,6 +307,10 @@ def stiles_factorize_solve(fac, d_values, nrhs, d_B, ldb, stream=None):
 
 def stiles_logdet(fac, d_out, stream=None):
     _check(load_library().stiles_logdet(fac, _ptr(d_out), _stream(stream)), "stiles_logdet")
+
+
+def stiles_logdet_static(fac, d_out, stream=None):
+    _check(load_library().stiles_logdet_static(fac, _ptr(d_out), _stream(stream)), "stiles_logdet_static")
 
 
 def stiles_factor_set_max_workgroups(fac, max_wg):

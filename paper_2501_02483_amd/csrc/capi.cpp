@@ -656,6 +656,19 @@ extern "C" stiles_status stiles_logdet(stiles_factor* f, double* d_out, hipStrea
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
 
+extern "C" stiles_status stiles_logdet_static(stiles_factor* f, double* d_out, hipStream_t st) {
+  static_assert(STILES_STATIC_LOGDET_MAX_ROWS == STATIC_LOGDET_ROWS, "public and internal limits differ");
+  set_error_arg(0);
+  if (!f) { set_error_arg(1); return STILES_EINVAL; }
+  if (!d_out) { set_error_arg(2); return STILES_EINVAL; }
+  if (f->sym->ntr > STATIC_LOGDET_ROWS) { set_error_arg(1); return STILES_ENOTSUP; }
+  if (f->state == -1 || f->state == 2) return STILES_ESTATE;
+  const Layout& L = f->L;
+  hipError_t e = launch_logdet_static(f->sym->T, at<double>(f, L.tiles), at<int32_t>(f, L.trow_ptr), f->sym->ntr,
+                                      at<unsigned long long>(f, L.info), d_out, st);
+  return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
+}
+
 // ------------------------------------------------------------------ batches
 
 namespace {

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "launch.h"
 #include "stiles_internal.h"
 
@@ -1828,6 +1830,48 @@ hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, in
     hipLaunchKernelGGL(logdet_partial_kernel<32>, dim3(ntr), dim3(NT), 0, st, tiles, trow_ptr, part);
   hipLaunchKernelGGL(logdet_final_kernel, dim3(1), dim3(NT), 0, st, part, ntr, info, out);
   return hipGetLastError();
+}
+
+// Per-tile-row partial sums of the log-determinant for callers that cannot
+// allocate device memory (launch_logdet_static): a fixed array of the
+// library, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// for the symbol): it uses the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.  Every call
+// on one GPU shares the array; each launch overwrites the partials of its
+// own rows before the final sum reads them, so nothing needs clearing, and
+// calls that overlap on one GPU race.
+static __device__ __align__(256) double scratch[STATIC_LOGDET_ROWS];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t static_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_logdet_static(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr,
+                                const unsigned long long* info, double* out, hipStream_t st) {
+  if (ntr < 1 || ntr > STATIC_LOGDET_ROWS) return hipErrorInvalidValue;
+  double* part = nullptr;
+  hipError_t e = static_scratch(&part);
+  if (e != hipSuccess) return e;
+  return launch_logdet(T, tiles, trow_ptr, ntr, part, info, out, st);
 }
 
 hipError_t launch_logdet_batch(int T, const BatchDesc* desc, int32_t count, const int2* rmap, int64_t total_rows,

@@ -44,6 +44,12 @@ hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const i
 hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr, double* part,
                          const unsigned long long* info, double* out, hipStream_t st);
 
+// the same with the per-tile-row partials in the library's fixed device
+// array (STATIC_LOGDET_ROWS rows): allocates nothing; hipErrorInvalidValue
+// when ntr is out of range
+hipError_t launch_logdet_static(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr,
+                                const unsigned long long* info, double* out, hipStream_t st);
+
 // row-profile values of the input ordering -> tile store of P A P^T
 // (perm: new row -> input row); same conventions as launch_scatter_profile
 hipError_t launch_scatter_perm(int T, const double* vals, const int64_t* in_rp, const int64_t* fin, const int64_t* perm,

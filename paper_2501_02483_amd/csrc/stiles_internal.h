@@ -76,6 +76,9 @@ constexpr int32_t SIG_TRANS = 1 << 30;
 // solve predecessors are still running.
 constexpr int32_t MERGED_FDEP = 1 << 16;
 constexpr int32_t SUCC_FDEP = 1 << 30;
+// Tile rows the library's fixed log-determinant array holds (one FP64
+// partial per tile row, 512 KiB); the public limit of stiles_logdet_static.
+constexpr int32_t STATIC_LOGDET_ROWS = 65536;
 
 // Device-side description of one matrix (or one solve) for the executor.
 struct ExecMat {
