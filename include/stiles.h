@@ -104,7 +104,11 @@ typedef struct stiles_opts {
                              order by earliest start with unlimited workgroups.  Only
                              the speed depends on it: every order gives bitwise the
                              same results                                            */
-  int32_t reserved[1];
+  int32_t ublock;         /* 2 x 2 blocked tile updates (two tile rows of two adjacent
+                             band tile columns share their operand tiles): columns per
+                             block task, 1..15; 0 or -1 (default): no blocks, every
+                             update is a single-tile chain (measured faster on the
+                             default workloads)                                      */
 } stiles_opts;
 
 typedef struct stiles_symbolic_info {
@@ -134,6 +138,7 @@ typedef struct stiles_symbolic_info {
                              work of a solve is 4 nnz_L_alg flops per right-hand side
                              (two sweeps, a multiply and an add per entry).  Equals
                              nnz_L when adaptable ND is not used                     */
+  int64_t update_blocks;  /* 2 x 2 update blocks of the factorization DAG (ublock)   */
 } stiles_symbolic_info;
 
 typedef struct stiles_solve_report {

@@ -10,6 +10,7 @@
 #include <limits>
 #include <numeric>
 #include <queue>
+#include <set>
 #include <utility>
 
 #include "symbolic.h"
@@ -24,6 +25,7 @@ struct TaskBuilder {
   std::vector<int32_t> words;             // TASK_WORDS per task (succ/ndeps filled later)
   std::vector<std::vector<int32_t>> preds;
   std::vector<float> cost;
+  std::vector<int32_t> late;   // the one predecessor waited for last (two-stage wait), or -1
 
   int add(int32_t type_flags, int32_t tile, int32_t a, int32_t b, int32_t c, float cst) {
     int id = (int)cost.size();
@@ -31,7 +33,15 @@ struct TaskBuilder {
     words.insert(words.end(), w, w + TASK_WORDS);
     preds.emplace_back();
     cost.push_back(cst);
+    late.push_back(-1);
     return id;
+  }
+  // two-stage wait: every other predecessor is waited for first
+  void set_late(int task, int pred) {
+    if (pred < 0) return;
+    dep(task, pred);
+    late[task] = pred;
+    words[(size_t)task * TASK_WORDS] |= TF_SPLIT;
   }
   void dep(int task, int pred) {
     if (pred >= 0 && pred != task) preds[task].push_back(pred);
@@ -156,12 +166,20 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
     int32_t* w = &tasks_out[(size_t)i * TASK_WORDS];
     std::memcpy(w, &tb.words[(size_t)t * TASK_WORDS], sizeof(int32_t) * TASK_WORDS);
     w[5] = (int32_t)succ_out.size();
-    std::vector<int32_t> s;
-    for (int x : succ[t]) s.push_back(newid[x]);
+    // an edge into a two-stage task from one of its early predecessors
+    // carries SUCC_FDEP (it subtracts MERGED_FDEP from the counter)
+    std::vector<std::pair<int32_t, int32_t>> s;
+    for (int x : succ[t]) s.push_back({newid[x], tb.late[x] >= 0 && tb.late[x] != t ? SUCC_FDEP : 0});
     std::sort(s.begin(), s.end());
-    succ_out.insert(succ_out.end(), s.begin(), s.end());
+    for (auto& e : s) succ_out.push_back(e.first | e.second);
     w[6] = (int32_t)succ_out.size();
-    w[7] = (int32_t)tb.preds[t].size();
+    if (tb.late[t] >= 0) {
+      const int32_t early = (int32_t)tb.preds[t].size() - 1;
+      if (early >= (1 << 14)) { fprintf(stderr, "stiles: too many predecessors\n"); abort(); }
+      w[7] = early * MERGED_FDEP + 1;
+    } else {
+      w[7] = (int32_t)tb.preds[t].size();
+    }
     if (est_out) (*est_out)[i] = est[t];
     if (cost_out) (*cost_out)[i] = tb.cost[t];
   }
@@ -169,7 +187,7 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
   for (int i = 0; i < nt; i++) {
     const int32_t* w = &tasks_out[(size_t)i * TASK_WORDS];
     for (int q = w[5]; q < w[6]; q++)
-      if (succ_out[q] <= i) { fprintf(stderr, "stiles: schedule is not topological\n"); abort(); }
+      if ((succ_out[q] & ~SUCC_FDEP) <= i) { fprintf(stderr, "stiles: schedule is not topological\n"); abort(); }
   }
 }
 
@@ -544,6 +562,7 @@ stiles_status check_opts(const stiles_opts* o, int arg) {
   if (o->nd_parts < 0 || o->nd_parts > 64) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->chunk < 0 || o->chunk > 32 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->sched_workers < -1 || o->sched_workers > 65536) { g_err_arg = arg; return STILES_EINVAL; }
+  if (o->ublock < -1 || o->ublock > 15) { g_err_arg = arg; return STILES_EINVAL; }
   return STILES_OK;
 }
 
@@ -916,25 +935,227 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   s.corner_acc = 0;
   double fexec = 0.0;
   const double T3 = (double)T * T * T;
+  // 2 x 2 blocks of update targets: band columns k, k+1 (the same partition,
+  // tile (k+1, k) stored) and two tile rows ra < rb.  A block task computes
+  // the four updates C_(r,c) -= sum_j L_(r,j) L_(c,j)^T, r in {ra, rb},
+  // c in {k, k+1}, over a chunk of the columns j <= k-2, reading each
+  // operand tile once for (up to) two products: a band tile column update is
+  // a tall-skinny product, and pairing two rows and two columns halves the
+  // operand reads per product.  The block covers every product of its
+  // targets with a column j <= k-2 (a target whose operand tile at some j is
+  // absent skips that column).  The diagonal block (ra, rb) = (k, k+1) has
+  // three targets, (k,k), (k+1,k), (k+1,k+1), and two operand tiles per
+  // column.  What is left of a target's products: column k-1 (fused into
+  // its POTRF/TRSM for column k; for column k+1, together with column k,
+  // fused into its TRSM, or an update task of its own when the target is on
+  // the pivot chain -- the diagonal tile (k+1,k+1) and the panel (k+2,k+1)).
+  const int32_t bchunk = s.opts.ublock > 0 ? s.opts.ublock : 0;
+  struct UBlock {
+    int32_t k, ra, rb;
+    int32_t tgt[4];   // (ra,k), (rb,k), (ra,k+1), (rb,k+1); -1 if absent
+    std::vector<int32_t> J;
+  };
+  std::vector<UBlock> blocks;
+  std::vector<int32_t> tblock(s.ntiles, -1);
+  std::vector<std::vector<int32_t>> col_blocks(ntr);
+  if (bchunk > 0) {
+    for (int32_t k = 0; k + 1 < s.ntb;) {
+      const bool same = s.nd_parts <= 1 || s.band_part.empty() || s.band_part[k] == s.band_part[k + 1];
+      if (!same || tile_lookup(s, k + 1, k) < 0) { k++; continue; }
+      std::vector<int32_t> rows;
+      for (auto& mt : ctiles[k]) if (mt.first > k + 1) rows.push_back(mt.first);
+      for (auto& mt : ctiles[k + 1]) if (mt.first > k + 1) rows.push_back(mt.first);
+      std::sort(rows.begin(), rows.end());
+      rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+      std::vector<std::pair<int32_t, int32_t>> cand{{k, k + 1}};
+      for (size_t q = 0; q + 1 < rows.size(); q += 2) cand.push_back({rows[q], rows[q + 1]});
+      for (auto [ra, rb] : cand) {
+        UBlock b;
+        b.k = k; b.ra = ra; b.rb = rb;
+        const bool dg = ra == k;
+        b.tgt[0] = tile_lookup(s, ra, k);
+        b.tgt[1] = tile_lookup(s, rb, k);
+        b.tgt[2] = dg ? -1 : tile_lookup(s, ra, k + 1);
+        b.tgt[3] = tile_lookup(s, rb, k + 1);
+        // the columns j <= k-2 of the targets' products
+        std::vector<int32_t> J;
+        int ntg = 0;
+        for (int q = 0; q < 4; q++) {
+          if (b.tgt[q] < 0) continue;
+          const int32_t m = q & 1 ? rb : ra, c = q < 2 ? k : k + 1;
+          const size_t before = J.size();
+          int32_t p = s.trow_ptr[m], pe = s.trow_ptr[m + 1], r = s.trow_ptr[c], re = s.trow_ptr[c + 1];
+          while (p < pe && r < re) {
+            const int32_t cm = s.tcol[p], cc = s.tcol[r];
+            if (cm > k - 2 || cc > k - 2) break;
+            if (cm == cc) { J.push_back(cm); p++; r++; }
+            else if (cm < cc) p++;
+            else r++;
+          }
+          if (J.size() == before) b.tgt[q] = -1;   // no product in the block's columns
+          else ntg++;
+        }
+        std::sort(J.begin(), J.end());
+        J.erase(std::unique(J.begin(), J.end()), J.end());
+        if (ntg < 2 || J.size() < 2) continue;
+        b.J = std::move(J);
+        const int32_t id = (int32_t)blocks.size();
+        for (int32_t t : b.tgt) if (t >= 0) tblock[t] = id;
+        col_blocks[k].push_back(id);
+        blocks.push_back(std::move(b));
+      }
+      k += 2;
+    }
+  }
+  s.ublocks = (int64_t)blocks.size();
+  // the update chain of every tile (the last task that wrote it)
+  std::vector<int32_t> tlast(s.ntiles, -1);
+  // products (tile (m,j), tile (c,j)), j < c, of target tile (m, c), ascending j
+  auto products = [&](int32_t m, int32_t c, std::vector<std::pair<int32_t, int32_t>>& pr, std::vector<int32_t>& pj) {
+    pr.clear();
+    pj.clear();
+    int32_t p = s.trow_ptr[m], pe = s.trow_ptr[m + 1];
+    int32_t q = s.trow_ptr[c], qe = s.trow_ptr[c + 1] - 1;   // exclude the diagonal tile (c,c)
+    while (p < pe && q < qe) {
+      int32_t cm = s.tcol[p], ck = s.tcol[q];
+      if (cm >= c) break;
+      if (cm == ck) { pr.push_back({p, q}); pj.push_back(cm); p++; q++; }
+      else if (cm < ck) p++;
+      else q++;
+    }
+  };
+  // ordinary update chunks of a target over products [lo, hi) of pr
+  auto upd_chain = [&](int32_t tgt, bool diag, const std::vector<std::pair<int32_t, int32_t>>& pr, size_t lo0,
+                       size_t hi0, std::vector<int32_t>& pairs_out) {
+    for (size_t lo = lo0; lo < hi0; lo += chunk) {
+      size_t hi = std::min(hi0, lo + chunk);
+      int32_t p0 = (int32_t)(pairs_out.size() / 2);
+      for (size_t q = lo; q < hi; q++) { pairs_out.push_back(pr[q].first); pairs_out.push_back(pr[q].second); }
+      int32_t p1 = (int32_t)(pairs_out.size() / 2);
+      float c = 0.5f + (diag ? 1.35f : 1.8f) * (float)(t3 * (hi - lo));
+      int t = tb.add(TK_UPD | (diag ? TF_DIAG : 0), tgt, p0, p1, 0, c);
+      fexec += (diag ? 1.5 : 2.0) * T3 * (hi - lo);
+      for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+      tb.dep(t, tlast[tgt]);
+      tlast[tgt] = t;
+    }
+  };
+  std::vector<std::pair<int32_t, int32_t>> pr;  // (tile m j, tile k j) ascending j
+  std::vector<int32_t> pj;
   for (int32_t k = 0; k < ntr; k++) {
-    const int32_t kb = s.trow_ptr[k], ke = s.trow_ptr[k + 1];   // row k tiles (cols ascending, last = k)
     int32_t potrf_task = -1;
-    for (auto& mt : ctiles[k]) {
-      const int32_t m = mt.first, tgt = mt.second;
-      // pairs (m,j),(k,j), j < k, both present
-      std::vector<std::pair<int32_t, int32_t>> pr;  // (tile m j, tile k j) ascending j
-      std::vector<int32_t> pj;
-      {
-        int32_t p = s.trow_ptr[m], pe = s.trow_ptr[m + 1];
-        int32_t q = kb, qe = ke - 1;   // exclude the diagonal tile (k,k)
-        while (p < pe && q < qe) {
-          int32_t cm = s.tcol[p], ck = s.tcol[q];
-          if (cm >= k) break;
-          if (cm == ck) { pr.push_back({p, q}); pj.push_back(cm); p++; q++; }
-          else if (cm < ck) p++;
-          else q++;
+    if (!col_blocks[k].empty()) {
+      // the block tasks: chunks of the block's columns, oldest first; the two
+      // most recent chunks (their columns are final last, close to the pivot
+      // chain) hold one and two columns
+      for (int32_t bi : col_blocks[k]) {
+        const UBlock& b = blocks[bi];
+        const bool dg = b.ra == k;
+        const int32_t nJ = (int32_t)b.J.size();
+        std::vector<std::pair<int32_t, int32_t>> ch;
+        {
+          int32_t hi = nJ;
+          const int32_t tail[2] = {1, 2};
+          for (int q = 0; hi > 0; q++) {
+            int32_t len = q < 2 ? tail[q] : bchunk;
+            if (q >= 2) {
+              // the rest in nearly equal chunks of at most bchunk
+              const int32_t nc = (hi + bchunk - 1) / bchunk;
+              for (int32_t ci = nc - 1; ci >= 0; ci--) ch.push_back({(int32_t)((int64_t)hi * ci / nc), (int32_t)((int64_t)hi * (ci + 1) / nc)});
+              break;
+            }
+            const int32_t lo = std::max(0, hi - len);
+            ch.push_back({lo, hi});
+            hi = lo;
+          }
+          std::reverse(ch.begin(), ch.end());
+        }
+        for (auto [lo, hi] : ch) {
+          const int32_t p0 = (int32_t)(pairs.size() / 2);
+          for (int q = 0; q < 4; q++) pairs.push_back(b.tgt[q]);
+          std::vector<int32_t> ops;
+          double prods = 0.0, fl = 0.0;
+          for (int32_t x = lo; x < hi; x++) {
+            const int32_t j = b.J[x];
+            const int32_t yk = tile_lookup(s, k, j), yk1 = tile_lookup(s, k + 1, j);
+            const int32_t xa = dg ? yk : tile_lookup(s, b.ra, j), xb = dg ? yk1 : tile_lookup(s, b.rb, j);
+            const int32_t o[4] = {xa, xb, yk, yk1};
+            for (int q = 0; q < 4; q++) {
+              pairs.push_back(o[q]);
+              if (o[q] >= 0) ops.push_back(o[q]);
+            }
+            for (int q = 0; q < 4; q++) {
+              if (b.tgt[q] < 0 || o[q & 1] < 0 || o[2 + (q >> 1)] < 0) continue;
+              const bool td = dg && q != 1;
+              prods += 1.0;
+              fl += (td ? 1.5 : 2.0) * T3;
+            }
+          }
+          int t = tb.add(TK_UPDB | (dg ? TF_DIAG : 0), -1, p0, hi - lo, 0, 0.5f + 1.4f * (float)(t3 * prods));
+          fexec += fl;
+          for (int32_t o : ops) tb.dep(t, final_task[o]);
+          for (int q = 0; q < 4; q++)
+            if (b.tgt[q] >= 0) tb.dep(t, tlast[b.tgt[q]]);
+          for (int q = 0; q < 4; q++)
+            if (b.tgt[q] >= 0) tlast[b.tgt[q]] = t;
         }
       }
+    }
+    for (auto& mt : ctiles[k]) {
+      const int32_t m = mt.first, tgt = mt.second;
+      if (tblock[tgt] >= 0) {
+        // a block target: its products with columns after k-2 of its block
+        // (block column kb = blocks[..].k): column k-1 when the target is in
+        // column kb, columns kb-1 and kb when it is in column kb+1
+        const UBlock& b = blocks[tblock[tgt]];
+        products(m, k, pr, pj);
+        std::vector<std::pair<int32_t, int32_t>> rest;
+        for (size_t q = 0; q < pr.size(); q++)
+          if (pj[q] > b.k - 2) rest.push_back(pr[q]);
+        const bool diag = (m == k);
+        // on the pivot chain: the diagonal tile and the panel below it
+        const bool chain = diag || m == k + 1;
+        // fused into the finalizer: the last product, and for an off-chain
+        // TRSM the one before it as well
+        size_t nfuse = rest.empty() ? 0 : 1;
+        if (!diag && !chain && rest.size() >= 2) nfuse = 2;
+        if (rest.size() > nfuse) {
+          // (at most one product here; a chain target's column k-2)
+          upd_chain(tgt, diag, rest, 0, rest.size() - nfuse, pairs);
+        }
+        int32_t f0 = (int32_t)(pairs.size() / 2), f1 = f0;
+        for (size_t q = rest.size() - nfuse; q < rest.size(); q++) {
+          pairs.push_back(rest[q].first);
+          pairs.push_back(rest[q].second);
+          f1++;
+          fexec += 2.0 * T3;
+        }
+        if (diag) {
+          int t = tb.add(TK_POTRF, tgt, k, f0, f1, (T == 64 ? 10.f : 4.f) + (f1 > f0 ? 1.5f * (float)t3 : 0.f));
+          fexec += 2.0 * T3 / 3.0;
+          tb.dep(t, tlast[tgt]);
+          for (size_t q = rest.size() - nfuse; q < rest.size(); q++) {
+            tb.dep(t, final_task[rest[q].first]);
+            tb.dep(t, final_task[rest[q].second]);
+          }
+          if (nfuse > 0) tb.set_late(t, final_task[rest.back().first]);
+          potrf_task = t;
+          final_task[tgt] = t;
+        } else {
+          int t = tb.add(TK_TRSM, tgt, k, f0, f1, 0.5f + 1.8f * (float)t3 * (float)(1 + (f1 - f0)));
+          fexec += 2.0 * T3;
+          tb.set_late(t, potrf_task);
+          tb.dep(t, tlast[tgt]);
+          for (size_t q = rest.size() - nfuse; q < rest.size(); q++) {
+            tb.dep(t, final_task[rest[q].first]);
+            tb.dep(t, final_task[rest[q].second]);
+          }
+          final_task[tgt] = t;
+        }
+        continue;
+      }
+      // pairs (m,j),(k,j), j < k, both present
+      products(m, k, pr, pj);
       const bool diag = (m == k);
       int32_t last = -1;
       size_t start = 0;
@@ -1104,14 +1325,18 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
         int t = tb.add(TK_POTRF, tgt, k, f0, f1, (T == 64 ? 10.f : 4.f) + (f1 > f0 ? 1.5f * (float)t3 : 0.f));
         fexec += 2.0 * T3 / 3.0;
         tb.dep(t, last);
-        if (fuse_last) { tb.dep(t, final_task[pr.back().first]); tb.dep(t, final_task[pr.back().second]); }
+        if (fuse_last) {
+          tb.dep(t, final_task[pr.back().first]);
+          tb.dep(t, final_task[pr.back().second]);
+          tb.set_late(t, final_task[pr.back().first]);   // the panel of column k-1
+        }
         potrf_task = t;
         final_task[tgt] = t;
       } else {
         // the diagonal tile (k,k) comes first in the column list
         int t = tb.add(TK_TRSM, tgt, k, f0, f1, 0.5f + 1.8f * (float)t3 * (f1 > f0 ? 2.f : 1.f));
         fexec += 2.0 * T3;
-        tb.dep(t, potrf_task);
+        tb.set_late(t, potrf_task);
         tb.dep(t, last);
         if (fuse_last) { tb.dep(t, final_task[pr.back().first]); tb.dep(t, final_task[pr.back().second]); }
         final_task[tgt] = t;
@@ -1396,9 +1621,14 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
   const int32_t nfp = (int32_t)(s.fpairs.size() / 2);
   const int32_t n = nf + ns;
   std::vector<std::vector<int32_t>> pred(n);
+  // factorization edges that subtract MERGED_FDEP (two-stage waits)
+  std::set<std::pair<int32_t, int32_t>> fheavy;
   for (int32_t t = 0; t < nf; t++)
-    for (int32_t q = s.ftask[(size_t)t * TASK_WORDS + 5]; q < s.ftask[(size_t)t * TASK_WORDS + 6]; q++)
-      pred[s.fsucc[q]].push_back(t);
+    for (int32_t q = s.ftask[(size_t)t * TASK_WORDS + 5]; q < s.ftask[(size_t)t * TASK_WORDS + 6]; q++) {
+      const int32_t x = s.fsucc[q] & ~SUCC_FDEP;
+      pred[x].push_back(t);
+      if (s.fsucc[q] & SUCC_FDEP) fheavy.insert({t, x});
+    }
   for (int32_t t = 0; t < ns; t++)
     for (int32_t q = s.stask[(size_t)t * TASK_WORDS + 5]; q < s.stask[(size_t)t * TASK_WORDS + 6]; q++)
       pred[nf + s.ssucc[q]].push_back(nf + t);
@@ -1466,11 +1696,13 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
     for (int32_t x : sl)
       if (x <= i) { fprintf(stderr, "stiles: merged DAG order is not topological\n"); abort(); }
     w[5] = (int32_t)D.succ.size();
-    // edges from a factorization task to a solve task carry SUCC_FDEP
-    for (int32_t x : sl) D.succ.push_back(t < nf && order[x] >= nf ? (x | SUCC_FDEP) : x);
+    // edges from a factorization task to a solve task carry SUCC_FDEP, and so
+    // do the factorization DAG's own early edges into two-stage tasks
+    for (int32_t x : sl)
+      D.succ.push_back(t < nf && (order[x] >= nf || fheavy.count({t, order[x]})) ? (x | SUCC_FDEP) : x);
     w[6] = (int32_t)D.succ.size();
     if (t < nf) {
-      w[7] = (int32_t)pred[t].size();
+      w[7] = s.ftask[(size_t)t * TASK_WORDS + 7];   // the factorization DAG's counter, with its weights
     } else {
       int32_t nfd = 0;
       for (int32_t x : pred[t]) nfd += x < nf;
@@ -1529,6 +1761,7 @@ extern "C" stiles_status stiles_symbolic_query(const stiles_symbolic* s, stiles_
   info->corner_accumulations = s->corner_acc;
   info->tree_used = s->tree_used;
   info->nnz_L_alg = s->nnzL_alg;
+  info->update_blocks = s->ublocks;
   return STILES_OK;
 }
 

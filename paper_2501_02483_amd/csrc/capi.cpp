@@ -209,6 +209,7 @@ hipError_t upload(stiles_factor* f, size_t off, const void* src, size_t bytes, h
   return hipMemcpyAsync(f->ws + off, src, bytes, hipMemcpyHostToDevice, st);
 }
 
+
 int nwg_for(const stiles_factor* f, int32_t ntasks) {
   int cap = device_wg_capacity(f->sym->T);
   if (f->max_wg > 0) cap = std::min(cap, (int)f->max_wg);
@@ -767,12 +768,13 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
         const int32_t g = off[i] + t;
         const int32_t* w = &sy.ftask[(size_t)t * TASK_WORDS];
         cost[g] = sy.fcost[t];
-        npred[g] = w[7];
         owner[g] = i;
-        for (int32_t q = w[5]; q < w[6]; q++) sflat.push_back(off[i] + sy.fsucc[q]);
+        for (int32_t q = w[5]; q < w[6]; q++) sflat.push_back(off[i] + (sy.fsucc[q] & ~SUCC_FDEP));
         sptr[g + 1] = (int32_t)sflat.size();
       }
     }
+    // predecessor counts (the task counters weight early predecessors)
+    for (int32_t q = 0; q < (int32_t)sflat.size(); q++) npred[sflat[q]]++;
     // remaining path lengths: each matrix's tasks are in topological order
     for (int32_t g = n - 1; g >= 0; g--) {
       float b2 = 0.f;

@@ -171,6 +171,44 @@ struct TileStage {
 
 // ------------------------------------------------------------ task bodies
 
+// The calling workgroup waits until *cnt < bound (all predecessors, or all
+// predecessors of one kind, have finished), then acquires.  Wave 0 polls.
+// The wait is bounded: it gives up when another workgroup of the launch has
+// given up (ctrl->abort) or when `limit` ticks of the 100 MHz wall clock pass
+// without the counter falling; the first to give up sets ctrl->abort.  The
+// result is the same for every thread (false: gave up).  The verdict goes
+// through LDS; the second barrier keeps a later wait from overwriting it
+// before every wave has read it.
+__device__ __forceinline__ bool wait_below(int32_t* cnt, int32_t bound, ExecCtrl* ctrl, uint64_t limit) {
+  __shared__ int32_t s_ok;
+  if (threadIdx.x < 64) {
+    int32_t ok = 1;
+    if (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) >= bound) {
+      const uint64_t t0 = wall_clock64();
+      for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) < bound) break;
+        if (__builtin_amdgcn_readfirstlane(ld_relaxed(&ctrl->abort)) != 0) {
+          ok = 0;
+          break;
+        }
+        if (wall_clock64() - t0 > limit) {
+          st_relaxed(&ctrl->abort, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    fence_acquire();
+    if (threadIdx.x == 0) s_ok = ok;
+  }
+  __syncthreads();
+  const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
+  __syncthreads();
+  return ok;
+}
+
+
 // UPD / PART: acc = sum_p X_p Y_p^T over a list of tile pairs (at most 32).
 // mode 0: C_t -= acc (UPD), mode 1: P = acc (PART).  LX, LY: LDS tiles.
 template <int T, int K>
@@ -283,6 +321,153 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
   }
 }
 
+// UPDB: a 2 x 2 block of update targets C_(r,c) -= sum_j L_(r,j) L_(c,j)^T,
+// r in {ra, rb}, c in {k, k+1}, over a list of columns j.  Wave q owns
+// target q: rows from operand X_(q & 1) = L_(ra|rb, j), columns from
+// Y_(q >> 1) = L_(k|k+1, j), a whole T x T tile in its registers, so each
+// operand tile is read once from memory for two products.  Per column j
+// the four operand tiles go through LDS in two halves of T/2 k-columns
+// (X halves in LX, Y halves in LY; a half of a column-major tile is
+// contiguous); the next half is in flight in registers while the current
+// one is multiplied.  The diagonal block (TF_DIAG: ra = k, rb = k+1) reads
+// X_a = Y_k and X_b = Y_(k+1), stages only the Y halves, and its two
+// diagonal targets compute their lower 16 x 16 blocks only.  E = double on
+// the FP64 factor tiles, float on the FP32 copies in mixed mode (the
+// product is then subtracted from the FP64 tile).
+template <int T, typename E>
+struct BlockOps;
+template <int T>
+struct BlockOps<T, double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ __forceinline__ const double* src(const ExecMat& M) { return M.tiles; }
+};
+template <int T>
+struct BlockOps<T, float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ const float* src(const ExecMat& M) { return M.shadow; }
+};
+
+template <int T, typename E>
+__device__ __forceinline__ void update_block(const ExecMat& M, const int32_t* w, double* LXd, double* LYd) {
+  typedef BlockOps<T, E> O;
+  typedef typename O::acc_t acc_t;
+  typedef E vec __attribute__((ext_vector_type(16 / sizeof(E))));
+  constexpr int TT = T * T, H = T / 2, HE = T * H, NB = T / 16;
+  constexpr int EPV = 16 / sizeof(E), NV = HE / NT / EPV;   // vectors per thread per half tile
+  E* LX = reinterpret_cast<E*>(LXd);
+  E* LY = reinterpret_cast<E*>(LYd);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool dg = (__builtin_amdgcn_readfirstlane(w[0]) & TF_DIAG) != 0;
+  const int p0 = __builtin_amdgcn_readfirstlane(w[2]), nj = __builtin_amdgcn_readfirstlane(w[3]);
+  const int pv = load_words(M.pairs + 2 * p0, 4 + 4 * nj);
+  const int tgt = word(pv, wave);
+  const bool active = tgt >= 0;
+  const bool tdiag = dg && wave != 1;
+  const int xs = wave & 1, ys = wave >> 1;
+  const E* tiles = O::src(M);
+  // staged halves: the Y tiles (k, j), (k+1, j), then (non-diagonal block)
+  // the X tiles (ra, j), (rb, j)
+  const int nst = dg ? 2 : 4;
+  vec st[4][NV];
+  // an operand tile id of -1 (absent) is neither loaded nor used: the waves
+  // whose X or Y it is skip that column
+  auto stage_load = [&](int step) {
+    const int j = step >> 1, h = step & 1;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      // slot order in the list: xa, xb, yk, yk1
+      const int id = q < nst ? word(pv, 4 + 4 * j + (q < 2 ? 2 + q : q - 2)) : -1;
+      if (id >= 0) {
+        const GLOBAL vec* g = (const GLOBAL vec*)(tiles + (int64_t)id * TT + h * HE);
+#pragma unroll
+        for (int v = 0; v < NV; v++) st[q][v] = g[threadIdx.x + v * NT];
+      }
+    }
+  };
+  auto stage_store = [&](int step) {
+    const int j = step >> 1;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int id = q < nst ? word(pv, 4 + 4 * j + (q < 2 ? 2 + q : q - 2)) : -1;
+      if (id >= 0) {
+        vec* l = reinterpret_cast<vec*>((q < 2 ? LY : LX) + (q & 1) * HE);
+#pragma unroll
+        for (int v = 0; v < NV; v++) l[threadIdx.x + v * NT] = st[q][v];
+      }
+    }
+  };
+  acc_t acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; i++)
+#pragma unroll
+    for (int jj = 0; jj < NB; jj++) acc[i][jj] = acc_t{0, 0, 0, 0};
+  const E* xl = (dg ? LY : LX) + xs * HE + (lane & 15) + (lane >> 4) * T;
+  const E* yl = LY + ys * HE + (lane & 15) + (lane >> 4) * T;
+  const int nsteps = 2 * nj;
+  bool any = false;   // this wave's target received a product
+  stage_load(0);
+  for (int step = 0; step < nsteps; step++) {
+    __syncthreads();
+    stage_store(step);
+    __syncthreads();
+    if (step + 1 < nsteps) stage_load(step + 1);
+    const int j = step >> 1;
+    const bool use = active && word(pv, 4 + 4 * j + xs) >= 0 && word(pv, 4 + 4 * j + 2 + ys) >= 0;
+    any |= use;
+    if (use) {
+#pragma unroll 2
+      for (int k = 0; k < H; k += 4) {
+        E a[NB], b[NB];
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+          a[q] = yl[q * 16 + k * T];
+          b[q] = xl[q * 16 + k * T];
+        }
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+#pragma unroll
+          for (int jj = 0; jj < NB; jj++)
+            if (!tdiag || jj >= i) acc[i][jj] = O::mfma(a[i], b[jj], acc[i][jj]);
+      }
+    }
+  }
+  if (!any) return;
+  GLOBAL double* out = gp(M.tiles + (int64_t)tgt * TT);
+#pragma unroll
+  for (int i = 0; i < NB; i++) {
+    double cin[NB][4];
+#pragma unroll
+    for (int jj = 0; jj < NB; jj++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = 16 * jj + (lane & 15), col = 16 * i + O::col(lane, r);
+        cin[jj][r] = (!tdiag || jj >= i) ? out[row + col * T] : 0.0;
+      }
+#pragma unroll
+    for (int jj = 0; jj < NB; jj++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = 16 * jj + (lane & 15), col = 16 * i + O::col(lane, r);
+        if (!tdiag || row >= col) st_dev(out + row + col * T, cin[jj][r] - (double)acc[i][jj][r]);
+      }
+  }
+}
+
+template <int T, int K>
+__device__ __attribute__((noinline)) void task_update_block(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
+  if (M.mixed) update_block<T, float>(M, w, LX, LY);
+  else update_block<T, double>(M, w, LX, LY);
+}
+
 // TREE: P_c = P_a + P_b, or C_t -= P_a (+ P_b) at the root (Alg. 3 GEADD).
 template <int T, int K>
 __device__ __attribute__((noinline)) void task_tree(const ExecMat& M, const int32_t* w) {
@@ -302,34 +487,53 @@ __device__ __attribute__((noinline)) void task_tree(const ExecMat& M, const int3
   }
 }
 
-// TRSM: L_t = (C_t - [X Y^T]) Linv_k^T as staged tile products; FP32 copy
-// in mixed mode.  The optional fused product is the update with column k-1.
+// TRSM: L_t = (C_t - [sum X Y^T]) Linv_k^T as staged tile products; FP32
+// copy in mixed mode.  The optional fused products (at most two) are the
+// updates with the most recent columns.  The task waits for its
+// predecessors itself: with TF_SPLIT, first for the early ones (its tile's
+// update chain and the fused operands), then it stages its tile and does
+// the fused products, and only then waits for the POTRF of its column, so
+// that the pivot chain sees one tile product.  Returns the time its last
+// wait ended (per-task trace); `ok` as for the solve tasks.
 template <int T, int K>
-__device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int32_t* w, double* LX, double* LY) {
+__device__ __attribute__((noinline)) uint64_t task_trsm(const ExecMat& M, const int32_t* w, double* LX, double* LY,
+                                                        int32_t* cnt, ExecCtrl* ctrl, uint64_t limit, bool& ok) {
   constexpr int TT = T * T, W = T / 2, NB = T / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
+  const bool split = (__builtin_amdgcn_readfirstlane(w[0]) & TF_SPLIT) != 0;
+  if (ok) ok = wait_below(cnt, split ? MERGED_FDEP : 1, ctrl, limit);
+  if (!ok) return 0;
+  uint64_t t_start = M.trace ? wall_clock64() : 0;
   double* C = M.tiles + (int64_t)w[1] * TT;
+  const double* Li = M.linv + (int64_t)w[2] * TT;
   GLOBAL double* Cg = gp(C);
-  const bool fused = w[4] > w[3];
+  const int f0 = __builtin_amdgcn_readfirstlane(w[3]), nf = __builtin_amdgcn_readfirstlane(w[4]) - f0;
   TileStage<T, double> sx, sy;
   v4d acc[NB][NB];
 #pragma unroll
   for (int i = 0; i < NB; i++)
 #pragma unroll
     for (int j = 0; j < NB; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  if (fused) {
-    sx.load(M.tiles + (int64_t)M.pairs[2 * w[3]] * TT);
-    sy.load(M.tiles + (int64_t)M.pairs[2 * w[3] + 1] * TT);
-    sx.store(LX);
-    sy.store(LY);
-    sx.load(C);
-    sy.load(M.linv + (int64_t)w[2] * TT);
+  if (nf > 0) {
+    sx.load(M.tiles + (int64_t)M.pairs[2 * f0] * TT);
+    sy.load(M.tiles + (int64_t)M.pairs[2 * f0 + 1] * TT);
+    for (int q = 0; q < nf; q++) {
+      __syncthreads();
+      sx.store(LX);
+      sy.store(LY);
+      if (q + 1 < nf) {
+        sx.load(M.tiles + (int64_t)M.pairs[2 * (f0 + q + 1)] * TT);
+        sy.load(M.tiles + (int64_t)M.pairs[2 * (f0 + q + 1) + 1] * TT);
+      } else {
+        sx.load(C);
+        if (!split) sy.load(Li);
+      }
+      __syncthreads();
+      mma_f64<T>(acc, LX, LY, r0, c0, lane);   // X Y^T
+    }
     __syncthreads();
-    mma_f64<T>(acc, LX, LY, r0, c0, lane);   // X Y^T
-    __syncthreads();
     sx.store(LX);
-    sy.store(LY);
     __syncthreads();
     // C -= X Y^T in LDS, each wave on its own quarter
 #pragma unroll
@@ -344,10 +548,17 @@ __device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int3
         }
   } else {
     sx.load(C);
-    sy.load(M.linv + (int64_t)w[2] * TT);
+    if (!split) sy.load(Li);
     sx.store(LX);
-    sy.store(LY);
   }
+  if (split) {
+    // the POTRF of the column: its inverse is the last operand
+    ok = wait_below(cnt, 1, ctrl, limit);
+    if (!ok) return 0;
+    if (M.trace) t_start = wall_clock64();
+    sy.load(Li);
+  }
+  sy.store(LY);
   __syncthreads();
   mma_f64<T>(acc, LX, LY, r0, c0, lane);
   GLOBAL float* S = M.mixed ? gp(M.shadow + (int64_t)w[1] * TT) : nullptr;
@@ -361,6 +572,7 @@ __device__ __attribute__((noinline)) void task_trsm(const ExecMat& M, const int3
         st_dev(Cg + row + col * T, acc[i][j][r]);
         if (S) st_dev(S + row + col * T, (float)acc[i][j][r]);
       }
+  return t_start;
 }
 
 // ------------------------------------------------- diagonal tile: POTRF + TRTRI
@@ -526,18 +738,33 @@ __device__ __forceinline__ void inv_row_block(double* S, double* Xi, int b, int 
   for (int rr = 0; rr < 4; rr++) Xi[(16 * b + (lane >> 4) + 4 * rr) + (16 * q + (lane & 15)) * T] = -xv[rr];
 }
 
+// POTRF waits for its predecessors itself: with TF_SPLIT it prefetches its
+// tile once the early ones (its update chain) have finished and waits last
+// for the TRSM of its fused operand X = L_(k,k-1) (the panel of the previous
+// column, on the pivot chain).  Returns the time its last wait ended.
 template <int T, int K>
-__device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi, double* rinv) {
+__device__ __attribute__((noinline)) uint64_t task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi,
+                                                         double* rinv, int32_t* cnt, ExecCtrl* ctrl, uint64_t limit,
+                                                         bool& ok) {
   constexpr int TT = T * T, NBK = T / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool split = (__builtin_amdgcn_readfirstlane(w[0]) & TF_SPLIT) != 0;
+  if (ok) ok = wait_below(cnt, split ? MERGED_FDEP : 1, ctrl, limit);
+  if (!ok) return 0;
+  uint64_t t_start = M.trace ? wall_clock64() : 0;
   double* C = M.tiles + (int64_t)w[1] * TT;
   const int k = w[2];
   {
-    // C and the fused operand X = L_(k,k-1) are loaded together
+    // C is prefetched; the fused operand X = L_(k,k-1) follows the last wait
     const bool fused = w[4] > w[3];
     const int64_t xt = fused ? __builtin_amdgcn_readfirstlane(M.pairs[2 * w[3]]) : 0;
     TileStage<T, double> st, sx;
     st.load(C);
+    if (split) {
+      ok = wait_below(cnt, 1, ctrl, limit);
+      if (!ok) return 0;
+      if (M.trace) t_start = wall_clock64();
+    }
     if (fused) sx.load(M.tiles + xt * TT);
     st.store(S);
     if (fused) {
@@ -636,6 +863,7 @@ __device__ __attribute__((noinline)) void task_potrf(const ExecMat& M, const int
     st_dev(C + e, row >= col ? S[e] : 0.0);
     st_dev(Li + e, Xi[e]);
   }
+  return t_start;
 }
 
 // ---------------------------------------------------------- solve tasks
@@ -706,43 +934,6 @@ struct SolveOps {
     return acc + acc1;
   }
 };
-
-// The calling workgroup waits until *cnt < bound (all predecessors, or all
-// predecessors of one kind, have finished), then acquires.  Wave 0 polls.
-// The wait is bounded: it gives up when another workgroup of the launch has
-// given up (ctrl->abort) or when `limit` ticks of the 100 MHz wall clock pass
-// without the counter falling; the first to give up sets ctrl->abort.  The
-// result is the same for every thread (false: gave up).  The verdict goes
-// through LDS; the second barrier keeps a later wait from overwriting it
-// before every wave has read it.
-__device__ __forceinline__ bool wait_below(int32_t* cnt, int32_t bound, ExecCtrl* ctrl, uint64_t limit) {
-  __shared__ int32_t s_ok;
-  if (threadIdx.x < 64) {
-    int32_t ok = 1;
-    if (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) >= bound) {
-      const uint64_t t0 = wall_clock64();
-      for (;;) {
-        __builtin_amdgcn_s_sleep(1);
-        if (__builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) < bound) break;
-        if (__builtin_amdgcn_readfirstlane(ld_relaxed(&ctrl->abort)) != 0) {
-          ok = 0;
-          break;
-        }
-        if (wall_clock64() - t0 > limit) {
-          st_relaxed(&ctrl->abort, 1);
-          ok = 0;
-          break;
-        }
-      }
-    }
-    fence_acquire();
-    if (threadIdx.x == 0) s_ok = ok;
-  }
-  __syncthreads();
-  const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
-  __syncthreads();
-  return ok;
-}
 
 // A solve task (FUPD, FDIAG, BUPD, BDIAG, FPART).  It waits for its
 // predecessors itself (*cnt): the factor tiles of a diagonal step (at most
@@ -1301,8 +1492,9 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       if (type >= TK_FUPD) ok = wait_below(cnt, MERGED_FDEP, ctrl, limit);
     }
     // solve tasks other than FSUM wait for their predecessors themselves,
-    // after reading their factor tiles
-    const bool self_wait = (SOLVE || BOTH) && type >= TK_FUPD && type != TK_FSUM;
+    // after reading their factor tiles; so do POTRF and TRSM (two-stage)
+    const bool self_wait = ((SOLVE || BOTH) && type >= TK_FUPD && type != TK_FSUM) ||
+                           (!SOLVE && !SELINV && (type == TK_POTRF || type == TK_TRSM));
     // wait until every predecessor has finished (Alg. 2 progress check);
     // wave 0 polls, then acquires for the workgroup (all its waves share
     // the CU's caches that the acquire invalidates)
@@ -1336,10 +1528,11 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     } else if (ok) {
       switch (type) {
         case TK_UPD: task_update<T, KIND>(M, w, 0, S, Xi); break;
+        case TK_UPDB: task_update_block<T, KIND>(M, w, S, Xi); break;
         case TK_PART: task_update<T, KIND>(M, w, 1, S, Xi); break;
         case TK_TREE: task_tree<T, KIND>(M, w); break;
-        case TK_POTRF: task_potrf<T, KIND>(M, w, S, Xi, rinv); break;
-        default: task_trsm<T, KIND>(M, w, S, Xi); break;
+        case TK_POTRF: t_start = task_potrf<T, KIND>(M, w, S, Xi, rinv, cnt, ctrl, limit, ok); break;
+        default: t_start = task_trsm<T, KIND>(M, w, S, Xi, cnt, ctrl, limit, ok); break;
       }
     }
     if (chain) __builtin_amdgcn_s_setprio(0);
@@ -1364,8 +1557,8 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       const int32_t q = q0 + (int32_t)threadIdx.x;
       if (threadIdx.x < 64 && q < s1) {
         int32_t sq = M.succ[q], dec = 1;
-        if constexpr (BOTH) {
-          dec = (sq & SUCC_FDEP) ? MERGED_FDEP : 1;
+        if (sq & SUCC_FDEP) {   // an early predecessor of a two-stage wait
+          dec = MERGED_FDEP;
           sq &= ~SUCC_FDEP;
         }
         __hip_atomic_fetch_add(M.remaining + sq, -dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -23,6 +23,7 @@ enum TaskType : int32_t {
   TK_TREE = 3,   // P_o = P_a + P_b, or C_t -= P_a (+ P_b)       [Alg. 3 GEADD tree]
   TK_POTRF = 4,  // [C_kk -= X X^T]; L_kk = chol(C_kk); Linv_k   [Alg. 1 SYRK, POTRF]
   TK_TRSM = 5,   // [C_t -= X Y^T]; L_t = C_t Linv_k^T           [Alg. 1 GEMM, TRSM]
+  TK_UPDB = 6,   // 2 x 2 block: C_(r,c) -= sum_j L_(r,j) L_(c,j)^T  [Alg. 1 SYRK/GEMM]
   TK_FUPD = 8,   // solve, forward:  Y_m -= sum L_(m,j) Y_j
   TK_FDIAG = 9,  // solve, forward:  Y_m  = Linv_m (Y_m - [L_(m,j) Y_j])
   TK_BUPD = 10,  // solve, backward: Z_m  = (first ? Y_m : Z_m) - sum L_(i,m)^T Z_i
@@ -42,6 +43,7 @@ enum TaskFlag : int32_t {
   TF_DIAG = 1 << 8,   // UPD target is a diagonal tile (lower half only)
   TF_FIRST = 1 << 9,  // BUPD: first chunk reads Y_m; BDIAG: no BUPD, reads Y_m
   TF_ACC = 1 << 10,   // PART: P_s += sum (continues a chain) instead of P_s = sum
+  TF_SPLIT = 1 << 11, // POTRF/TRSM: two-stage wait (early predecessors, then the chain one)
 };
 
 // One task = 8 int32.
@@ -49,6 +51,10 @@ enum TaskFlag : int32_t {
 //  w2 a                w3 b              w4 c
 //  w5 succ_lo          w6 succ_hi        w7 ndeps
 // UPD:  a,b = pair range          PART: a,b = pair range, c = out slot
+// UPDB: a = first pair of its list, b = column count nj; list (int32 words):
+//       the targets (ra,k), (rb,k), (ra,k+1), (rb,k+1) (-1: absent), then per
+//       column j the operand tiles (ra,j), (rb,j), (k,j), (k+1,j); TF_DIAG:
+//       the diagonal block (ra, rb) = (k, k+1), whose (ra,j) = (k,j)
 // TREE: a = slot, b = slot or -1, c = out slot or -1 (then subtract into tile)
 // POTRF: a = tile row k, b,c = fused pair range (C_kk -= X X^T first, 0 or 1 pair)
 // TRSM:  a = tile row k of the diagonal tile, b,c = fused pair range
@@ -68,12 +74,19 @@ enum TaskFlag : int32_t {
 //        1: pushed-partial slots (qpart); summed in list order
 constexpr int TASK_WORDS = 8;
 constexpr int32_t SIG_TRANS = 1 << 30;
-// Merged factorization + solve DAG: a solve task's counter holds its solve
-// predecessors plus MERGED_FDEP per factorization predecessor, and a
-// successor entry with SUCC_FDEP set (an edge from a factorization task to a
-// solve task) subtracts MERGED_FDEP.  A solve task can therefore stage its
-// factor tiles as soon as the counter falls below MERGED_FDEP, while its
-// solve predecessors are still running.
+// Two-stage waits.  A task's counter can hold some predecessors with weight
+// MERGED_FDEP ("early" ones) and the others with weight 1; a successor entry
+// with SUCC_FDEP set subtracts MERGED_FDEP.  Once the counter falls below
+// MERGED_FDEP every early predecessor has finished, and the task can stage
+// what those produced while the others are still running.
+// Merged factorization + solve DAG: the early predecessors of a solve task
+// are its factorization predecessors (its factor tiles are then final).
+// Factorization DAG (TF_SPLIT): a TRSM's early predecessors are the update
+// chain of its tile and the tasks that finalize its fused operands, its
+// late one the POTRF of its column, so it prefetches its tile and does its
+// fused product before the POTRF ends; a POTRF with a fused product waits
+// late for the TRSM of that operand (the panel of the previous column) and
+// prefetches its tile before.
 constexpr int32_t MERGED_FDEP = 1 << 16;
 constexpr int32_t SUCC_FDEP = 1 << 30;
 // Tile rows the library's fixed log-determinant array holds (one FP64

@@ -70,6 +70,7 @@ struct stiles_symbolic {
   int32_t npart = 0;
   int32_t tree_used = 0;
   int64_t corner_acc = 0;
+  int64_t ublocks = 0;      // 2 x 2 update blocks in the factorization DAG
 
   // solve DAG
   int32_t nspart = 0;             // partial slots of long forward rows

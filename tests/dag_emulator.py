@@ -11,10 +11,10 @@ import numpy as np
 
 import paper_2501_02483_amd as S
 
-UPD, PART, TREE, POTRF, TRSM = 1, 2, 3, 4, 5
+UPD, PART, TREE, POTRF, TRSM, UPDB = 1, 2, 3, 4, 5, 6
 FUPD, FDIAG, BUPD, BDIAG, FPART, FSUM = 8, 9, 10, 11, 12, 13
 SWE, SW, SDIAG, TSUM = 16, 17, 18, 19
-TF_DIAG, TF_FIRST, TF_ACC = 1 << 8, 1 << 9, 1 << 10
+TF_DIAG, TF_FIRST, TF_ACC, TF_SPLIT = 1 << 8, 1 << 9, 1 << 10, 1 << 11
 SIG_TRANS = 1 << 30
 MERGED_FDEP, SUCC_FDEP = 1 << 16, 1 << 30
 
@@ -96,6 +96,27 @@ def scatter(plan, Aperm):
     return tiles
 
 
+def update_block(w, P, tiles, done=None):
+    """UPDB: a 2 x 2 block of targets (ra,k), (rb,k), (ra,k+1), (rb,k+1)
+    (-1: absent); per column j the operands (ra,j), (rb,j), (k,j), (k+1,j).
+    `done` (merged emulation): the operand tiles must be final."""
+    words = P.reshape(-1)[2 * w[2]:2 * w[2] + 4 + 4 * w[3]]
+    tg = words[:4]
+    ops = words[4:].reshape(-1, 4)
+    if done is not None:
+        o = ops.reshape(-1)
+        assert done[o[o >= 0]].all(), "block update read a tile before it was final"
+    for q in range(4):
+        if tg[q] < 0:
+            continue
+        use = [o for o in ops if o[q & 1] >= 0 and o[2 + (q >> 1)] >= 0]   # -1: absent operand
+        if not use:
+            continue
+        acc = sum(tiles[o[q & 1]] @ tiles[o[2 + (q >> 1)]].T for o in use)
+        diag = (w[0] & TF_DIAG) and q != 1
+        tiles[tg[q]] -= np.tril(acc) if diag else acc
+
+
 def factor(plan, Aperm, mode="ticket", seed=0):
     rng = np.random.default_rng(seed)
     T = plan.T
@@ -117,6 +138,8 @@ def factor(plan, Aperm, mode="ticket", seed=0):
                 part[w[4]] += acc
             else:
                 part[w[4]] = acc
+        elif typ == UPDB:
+            update_block(w, P, tiles)
         elif typ == TREE:
             s = part[w[2]] + (part[w[3]] if w[3] >= 0 else 0.0)
             if w[4] >= 0:
@@ -296,6 +319,8 @@ def factor_solve(plan, Aperm, B, mode="ticket", seed=0):
                 part[w[4]] += acc
             else:
                 part[w[4]] = acc
+        elif typ == UPDB:
+            update_block(w, P, tiles, done_tile)
         elif typ == TREE:
             s_ = part[w[2]] + (part[w[3]] if w[3] >= 0 else 0.0)
             if w[4] >= 0:

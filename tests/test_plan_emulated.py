@@ -204,6 +204,7 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
     is_fac = typ < E.FUPD
     n = len(tasks)
     fpred = [set() for _ in range(n)]
+    fweight = [0] * n      # factorization tasks: counter weight of their predecessors
     spred = [0] * n
     final_of, potrf_of = {}, {}
     for t in range(n):
@@ -214,14 +215,24 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
         for q in range(tasks[t, 5], tasks[t, 6]):
             x, dec = E.succ_edge(succ[q])
             assert x > t
-            assert (dec == E.MERGED_FDEP) == (is_fac[t] and not is_fac[x])
+            if not is_fac[t] or not is_fac[x]:
+                # factorization -> solve edges weigh MERGED_FDEP, solve -> solve 1
+                assert (dec == E.MERGED_FDEP) == (is_fac[t] and not is_fac[x])
+            else:
+                # factorization -> factorization: MERGED_FDEP only into a
+                # two-stage POTRF/TRSM, from one of its early predecessors
+                assert dec == 1 or tasks[x, 0] & E.TF_SPLIT
+                fweight[x] += dec
             if is_fac[t]:
                 fpred[x].add(t)
             else:
                 spred[x] += 1
     for t in range(n):
         if is_fac[t]:
-            assert tasks[t, 7] == len(fpred[t]) and spred[t] == 0
+            assert tasks[t, 7] == fweight[t] and spred[t] == 0
+            if tasks[t, 0] & E.TF_SPLIT:
+                # exactly one late predecessor (weight 1)
+                assert fweight[t] % E.MERGED_FDEP == 1
             continue
         assert tasks[t, 7] == spred[t] + E.MERGED_FDEP * len(fpred[t])
         if typ[t] == E.FSUM:
@@ -291,3 +302,30 @@ def test_tiles_with_entries_csc_input():
     ref = np.array([np.any(tiles[t] != 0) or plan.trow[t] == plan.tcol[t] for t in range(len(plan.tcol))])
     has = S.stiles_symbolic_export(sym.handle, "tile_has_a").astype(bool)
     assert np.array_equal(has, ref)
+
+
+@pytest.mark.parametrize("ublock", [1, 3, 6])
+@pytest.mark.parametrize("mode", ["ticket", "random"])
+@pytest.mark.parametrize("ordering,parts", [(S.STILES_ORDER_NONE, 0), (S.STILES_ORDER_ADAPTABLE_ND, 3)],
+                         ids=["natural", "nd3"])
+def test_emulated_block_updates(ublock, mode, ordering, parts):
+    """2 x 2 block update tasks (two tile rows of two adjacent band columns
+    sharing their operand tiles, absent operands skipped per target) in the
+    factorization and the merged DAG: the emulated factor and solution match
+    the oracle."""
+    p = I.make_pattern(2500, 40, [20, 150, 70, 110], seg=600)
+    vals = I.make_values(p, seed=31)
+    sym = S.Symbolic.from_pattern(p, tile=32, ordering=ordering, nd_parts=parts, ublock=ublock)
+    assert sym.info.update_blocks > 0
+    plan = E.Plan(sym)
+    A = I.to_dense(p, vals)[np.ix_(plan.perm, plan.perm)]
+    L, info = oracle.factor(p.f, vals)
+    assert info == 0
+    if ordering == S.STILES_ORDER_NONE:
+        tiles, linv = E.factor(plan, A, mode=mode, seed=ublock)
+        Lo, _ = _oracle_dense_L(p, vals)
+        assert np.linalg.norm(E.dense_factor(plan, tiles) - Lo) / np.linalg.norm(Lo) <= 1e-12
+    B = I.rhs(p.N, 2, seed=5)
+    _, _, X = E.factor_solve(plan, A, B, mode=mode, seed=ublock + 1)
+    Xo = oracle.solve(p.f, L, B)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
