@@ -28,7 +28,9 @@ __all__ = [
     "stiles_logdet_static", "STILES_STATIC_LOGDET_MAX_ROWS",
 ]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
+# STILES_LIBRARY names another build of the same library (the host-sanitized
+# one, see sanitize.py); the default is the in-tree libstiles.so
+LIB_PATH = os.environ.get("STILES_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstiles.so")
 
 STILES_OK = 0
 STILES_EINVAL = -1
