@@ -1,0 +1,230 @@
+// Threaded host emulation of the persistent executor's protocol, for
+// ThreadSanitizer.  Worker threads take tickets in the plan's static order,
+// wait on per-task counters (two-stage for TF_SPLIT tasks: the early
+// predecessors, which weigh 2^16, then the late one), run the task on host
+// tiles and notify the successors (an entry with bit 30 set subtracts 2^16)
+// -- the counter protocol of the device executor with C++ acquire/release
+// atomics in place of the device's coherent stores and fences.  A missing
+// dependency in the plan, or a task that reads before its wait, is a data
+// race between the tile accesses of two tasks, which ThreadSanitizer
+// reports; random delays vary the interleavings.  Task semantics are those
+// of the device task bodies (factorization DAG: UPD, PART, TREE, POTRF,
+// TRSM, UPDB), written here as plain loops.
+//
+// Input (binary, little-endian int32 header then arrays):
+//   T, ntiles, ntr, ntasks, nsucc, npairw (int32 words of the pair array),
+//   npart; tasks (8 int32 per task), succ, pair words, tiles (ntiles T x T
+//   column-major doubles).
+// Usage: exec_race <in> <out> <threads> <seed> [drop_edge]
+//   out receives the factored tiles; drop_edge removes one successor entry
+//   (and its weight from the successor's counter) to plant a missing
+//   dependency.
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr int TK_UPD = 1, TK_PART = 2, TK_TREE = 3, TK_POTRF = 4, TK_TRSM = 5, TK_UPDB = 6;
+constexpr int TF_DIAG = 1 << 8, TF_ACC = 1 << 10, TF_SPLIT = 1 << 11;
+constexpr int32_t W = 1 << 16, FDEP = 1 << 30;
+
+struct Plan {
+  int32_t T = 0, ntiles = 0, ntr = 0, ntasks = 0, nsucc = 0, npairw = 0, npart = 0;
+  std::vector<int32_t> tasks, succ, pairs;
+  std::vector<double> tiles;
+};
+
+bool read_plan(const char* path, Plan& p) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return false;
+  int32_t h[7];
+  bool ok = std::fread(h, 4, 7, f) == 7;
+  if (ok) {
+    p.T = h[0]; p.ntiles = h[1]; p.ntr = h[2]; p.ntasks = h[3]; p.nsucc = h[4]; p.npairw = h[5]; p.npart = h[6];
+    p.tasks.resize((size_t)p.ntasks * 8);
+    p.succ.resize(p.nsucc);
+    p.pairs.resize(p.npairw);
+    p.tiles.resize((size_t)p.ntiles * p.T * p.T);
+    ok = std::fread(p.tasks.data(), 4, p.tasks.size(), f) == p.tasks.size() &&
+         std::fread(p.succ.data(), 4, p.succ.size(), f) == p.succ.size() &&
+         std::fread(p.pairs.data(), 4, p.pairs.size(), f) == p.pairs.size() &&
+         std::fread(p.tiles.data(), 8, p.tiles.size(), f) == p.tiles.size();
+  }
+  std::fclose(f);
+  return ok;
+}
+
+struct Exec {
+  Plan& p;
+  std::vector<double> linv, part;
+  std::vector<std::atomic<int32_t>> cnt;
+  std::atomic<int32_t> ticket{0};
+  std::atomic<bool> failed{false};
+  explicit Exec(Plan& pl)
+      : p(pl), linv((size_t)pl.ntr * pl.T * pl.T), part((size_t)std::max(pl.npart, 1) * pl.T * pl.T), cnt(pl.ntasks) {
+    for (int32_t t = 0; t < pl.ntasks; t++) cnt[t].store(pl.tasks[(size_t)t * 8 + 7], std::memory_order_relaxed);
+  }
+  double* tile(int32_t id) { return p.tiles.data() + (size_t)id * p.T * p.T; }
+  double* slot(int32_t id) { return part.data() + (size_t)id * p.T * p.T; }
+  // C -= X Y^T (lower only when `lower`)
+  void sub_prod(double* C, const double* X, const double* Y, bool lower) {
+    const int T = p.T;
+    for (int c = 0; c < T; c++)
+      for (int r = lower ? c : 0; r < T; r++) {
+        double s = 0.0;
+        for (int k = 0; k < T; k++) s += X[r + k * T] * Y[c + k * T];
+        C[r + c * T] -= s;
+      }
+  }
+  void wait_below(int32_t t, int32_t bound, std::mt19937& rng) {
+    int spins = 0;
+    while (cnt[t].load(std::memory_order_acquire) >= bound) {
+      if (++spins > 64) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 20));
+      else std::this_thread::yield();
+      if (failed.load(std::memory_order_relaxed)) return;
+    }
+  }
+  void run_task(int32_t t, std::mt19937& rng) {
+    const int32_t* w = &p.tasks[(size_t)t * 8];
+    const int type = w[0] & 0xff, T = p.T;
+    const bool split = (w[0] & TF_SPLIT) != 0;
+    std::vector<double> C((size_t)T * T);
+    if (type == TK_POTRF || type == TK_TRSM) {
+      wait_below(t, split ? W : 1, rng);
+      std::memcpy(C.data(), tile(w[1]), C.size() * 8);   // its own tile: an early input
+      if (type == TK_TRSM)                                  // fused products: early inputs
+        for (int32_t q = w[3]; q < w[4]; q++) sub_prod(C.data(), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), false);
+      if (split) wait_below(t, 1, rng);
+      if (type == TK_POTRF) {
+        for (int32_t q = w[3]; q < w[4]; q++) sub_prod(C.data(), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), true);
+        // Cholesky of the lower triangle, then the inverse of the factor
+        for (int j = 0; j < T; j++) {
+          double d = C[j + j * T];
+          for (int k = 0; k < j; k++) d -= C[j + k * T] * C[j + k * T];
+          if (!(d > 0.0)) { failed.store(true); return; }
+          const double l = std::sqrt(d);
+          C[j + j * T] = l;
+          for (int i = j + 1; i < T; i++) {
+            double s = C[i + j * T];
+            for (int k = 0; k < j; k++) s -= C[i + k * T] * C[j + k * T];
+            C[i + j * T] = s / l;
+          }
+        }
+        for (int c = 0; c < T; c++)
+          for (int r = 0; r < c; r++) C[r + c * T] = 0.0;
+        double* Li = linv.data() + (size_t)w[2] * T * T;
+        for (int c = 0; c < T; c++)
+          for (int r = 0; r < T; r++) {
+            if (r < c) { Li[r + c * T] = 0.0; continue; }
+            double s = r == c ? 1.0 : 0.0;
+            for (int k = c; k < r; k++) s -= C[r + k * T] * Li[k + c * T];
+            Li[r + c * T] = s / C[r + r * T];
+          }
+      } else {
+        const double* Li = linv.data() + (size_t)w[2] * T * T;
+        std::vector<double> out((size_t)T * T, 0.0);
+        for (int c = 0; c < T; c++)
+          for (int r = 0; r < T; r++) {
+            double s = 0.0;
+            for (int k = 0; k < T; k++) s += C[r + k * T] * Li[c + k * T];
+            out[r + c * T] = s;
+          }
+        C.swap(out);
+      }
+      std::memcpy(tile(w[1]), C.data(), C.size() * 8);
+      return;
+    }
+    wait_below(t, 1, rng);
+    if (type == TK_UPD) {
+      for (int32_t q = w[2]; q < w[3]; q++)
+        sub_prod(tile(w[1]), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), (w[0] & TF_DIAG) != 0);
+    } else if (type == TK_PART) {
+      std::fill(C.begin(), C.end(), 0.0);
+      for (int32_t q = w[2]; q < w[3]; q++) sub_prod(C.data(), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), false);
+      double* P = slot(w[4]);
+      for (size_t e = 0; e < C.size(); e++) P[e] = (w[0] & TF_ACC) ? P[e] - C[e] : -C[e];
+    } else if (type == TK_TREE) {
+      const double* a = slot(w[2]);
+      const double* b = w[3] >= 0 ? slot(w[3]) : nullptr;
+      double* dst = w[4] >= 0 ? slot(w[4]) : tile(w[1]);
+      for (size_t e = 0; e < C.size(); e++) {
+        const double s = a[e] + (b ? b[e] : 0.0);
+        dst[e] = w[4] >= 0 ? s : dst[e] - s;
+      }
+    } else if (type == TK_UPDB) {
+      const int32_t* words = &p.pairs[2 * (size_t)w[2]];
+      const int32_t nj = w[3];
+      for (int q = 0; q < 4; q++) {
+        if (words[q] < 0) continue;
+        const bool lower = (w[0] & TF_DIAG) && q != 1;
+        for (int32_t j = 0; j < nj; j++) {
+          const int32_t* o = words + 4 + 4 * j;
+          if (o[q & 1] < 0 || o[2 + (q >> 1)] < 0) continue;
+          sub_prod(tile(words[q]), tile(o[q & 1]), tile(o[2 + (q >> 1)]), lower);
+        }
+      }
+    } else {
+      std::fprintf(stderr, "exec_race: unknown task type %d\n", type);
+      failed.store(true);
+    }
+  }
+  void worker(unsigned seed) {
+    std::mt19937 rng(seed);
+    for (;;) {
+      const int32_t t = ticket.fetch_add(1, std::memory_order_relaxed);
+      if (t >= p.ntasks || failed.load(std::memory_order_relaxed)) break;
+      run_task(t, rng);
+      if (rng() % 8 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 50));
+      const int32_t* w = &p.tasks[(size_t)t * 8];
+      for (int32_t q = w[5]; q < w[6]; q++) {
+        const int32_t v = p.succ[q];
+        if (v == -1) continue;   // a planted missing edge
+        cnt[v & ~FDEP].fetch_sub((v & FDEP) ? W : 1, std::memory_order_release);
+      }
+    }
+  }
+};
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc < 5) {
+    std::fprintf(stderr, "usage: exec_race in out threads seed [drop_edge]\n");
+    return 2;
+  }
+  Plan p;
+  if (!read_plan(argv[1], p)) {
+    std::fprintf(stderr, "exec_race: cannot read %s\n", argv[1]);
+    return 2;
+  }
+  if (argc > 5) {
+    // plant a missing dependency: the successor no longer waits for it
+    const int32_t e = std::atoi(argv[5]);
+    const int32_t v = p.succ[e];
+    p.tasks[(size_t)(v & ~FDEP) * 8 + 7] -= (v & FDEP) ? W : 1;
+    p.succ[e] = -1;
+  }
+  Exec ex(p);
+  const int nth = std::atoi(argv[3]);
+  const unsigned seed = (unsigned)std::atoi(argv[4]);
+  std::vector<std::thread> th;
+  for (int i = 0; i < nth; i++) th.emplace_back([&ex, seed, i] { ex.worker(seed * 7919u + (unsigned)i); });
+  for (auto& x : th) x.join();
+  if (ex.failed.load()) {
+    std::fprintf(stderr, "exec_race: a task failed\n");
+    return 3;
+  }
+  FILE* f = std::fopen(argv[2], "wb");
+  if (!f) return 2;
+  const bool ok = std::fwrite(p.tiles.data(), 8, p.tiles.size(), f) == p.tiles.size();
+  std::fclose(f);
+  return ok ? 0 : 2;
+}
