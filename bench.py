@@ -522,7 +522,7 @@ def mixed_runs(n, tile, ordering, parts, steps, law="laplacian"):
     dv = dp.values(4, law=law, kappa=1e6)
     B = torch.randn(nrhs, p.N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(104)).t()
     out = {}
-    for prec, name in ((S.STILES_FP64, "fp64"), (S.STILES_MIXED32, "mixed")):
+    for prec, name in ((S.STILES_FP64, "fp64"), (S.STILES_MIXED32, "mixed"), (S.STILES_MIXED32_FULL, "mixed_corner_fp32")):
         sym = S.Symbolic.from_pattern(p, tile=tile or 64, ordering=ordering, nd_parts=parts, ublock=UBLOCK)
         fac = S.Factor(sym, prec, nrhs_max=nrhs)
         fac.factorize(dv)
@@ -548,19 +548,31 @@ def mixed_runs(n, tile, ordering, parts, steps, law="laplacian"):
         fac.solve(X2)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        # the same in one launch of the merged graph (mixed: its solve is the
+        # first iterate of the refinement)
+        X3 = B.clone()
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        fac.factorize_solve(dv, X3)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
         fk = float(np.median(fms))
         out[name] = {"factor_kernel_ms": fk, "tflops": sym.info.flops_alg / fk / 1e9,
                      "solve_ms": (t1 - t0) * 1e3, "factorize_solve_ms": (t3 - t2) * 1e3,
+                     "factorize_solve_merged_ms": (t5 - t4) * 1e3,
                      "iterations": rep.iterations, "converged": rep.converged,
                      "backward_error": rep.backward_error, "logdet": ld, "info": fac.info(), "X": X,
                      "L": fac.extract() if n <= 200_000 else None, "nd_parts": sym.info.nd_parts}
         del fac
-    xf, xm = out["fp64"].pop("X"), out["mixed"].pop("X")
-    out["mixed"]["x_rel_diff_vs_fp64"] = float(torch.linalg.norm(xm - xf) / torch.linalg.norm(xf))
-    out["mixed"]["logdet_rel_diff_vs_fp64"] = abs(out["mixed"]["logdet"] - out["fp64"]["logdet"]) / abs(out["fp64"]["logdet"])
-    Lf, Lm = out["fp64"].pop("L"), out["mixed"].pop("L")
-    if Lf is not None:
-        out["mixed"]["L_rel_diff_vs_fp64"] = float(torch.linalg.norm(Lm - Lf) / torch.linalg.norm(Lf))
+    # both placements of the arrow-corner accumulation (FP64 in "mixed",
+    # FP32 in "mixed_corner_fp32"): differences from the FP64 results
+    xf, Lf = out["fp64"].pop("X"), out["fp64"].pop("L")
+    for name in ("mixed", "mixed_corner_fp32"):
+        xm, Lm = out[name].pop("X"), out[name].pop("L")
+        out[name]["x_rel_diff_vs_fp64"] = float(torch.linalg.norm(xm - xf) / torch.linalg.norm(xf))
+        out[name]["logdet_rel_diff_vs_fp64"] = abs(out[name]["logdet"] - out["fp64"]["logdet"]) / abs(out["fp64"]["logdet"])
+        if Lf is not None:
+            out[name]["L_rel_diff_vs_fp64"] = float(torch.linalg.norm(Lm - Lf) / torch.linalg.norm(Lf))
     out["flops_alg"] = sym.info.flops_alg
     out["workload"] = p.name
     out["law"] = law

@@ -72,8 +72,14 @@ typedef int32_t stiles_status;
 
 /* Precisions of the numerical factorization. */
 #define STILES_FP64 0     /* every step in FP64                                     */
-#define STILES_MIXED32 1  /* band/arrow tile updates in FP32 on MFMA; POTRF, TRSM,
-                             arrow-corner accumulation, logdet and refinement FP64  */
+#define STILES_MIXED32 1  /* band/arrow tile updates in FP32 on MFMA (under adaptable
+                             ND also the separator rows' partial sums); POTRF, TRSM,
+                             the arrow-corner accumulation, logdet and refinement
+                             FP64                                                   */
+#define STILES_MIXED32_FULL 2 /* as STILES_MIXED32, and the arrow-corner accumulation
+                             (the partial products summed into the corner tiles) also
+                             in FP32: the placement the FP64 corner avoids, kept to
+                             measure what that choice buys                          */
 
 typedef struct stiles_symbolic stiles_symbolic; /* opaque, host memory, immutable  */
 typedef struct stiles_factor stiles_factor;     /* opaque host handle bound to a
@@ -318,18 +324,20 @@ stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_B, int64_t 
                            stiles_solve_report* report);
 
 /*
- * Factorization and solve in one persistent launch (FP64 only; ENOTSUP in
- * mixed precision): stiles_factorize(f, d_values) followed by
- * stiles_solve(f, nrhs, d_B, ldb), with the two task graphs merged, so that
- * tile rows whose factor is final are solved while the rest of the matrix is
- * still being factored (the forward sweep of the adaptable-ND partitions
- * overlaps the factorization of the separators).  Results are bitwise those
- * of the two separate calls (the same tasks in the same accumulation order).
+ * Factorization and solve in one persistent launch: stiles_factorize(f,
+ * d_values) followed by stiles_solve(f, nrhs, d_B, ldb), with the two task
+ * graphs merged, so that tile rows whose factor is final are solved while
+ * the rest of the matrix is still being factored (the forward sweep of the
+ * adaptable-ND partitions overlaps the factorization of the separators).
+ * Results are bitwise those of the two separate calls (the same tasks in the
+ * same accumulation order).  In mixed precision the launch's solve is the
+ * first iterate of the FP64 refinement, which then runs as in stiles_solve
+ * (the call waits for it; use stiles_solve for the per-RHS report).
  * d_B: N x nrhs column-major (ldb >= N), original ordering, overwritten by X;
  * right-hand sides beyond the first 16 are solved by ordinary solve sweeps
- * after the launch.  If the factorization fails, X is NaN and
- * stiles_factor_info reports the column.  The timing hook's factorization
- * event pair brackets the merged launch.
+ * (refined in mixed mode) after the launch.  If the factorization fails, X
+ * is NaN and stiles_factor_info reports the column.  The timing hook's
+ * factorization event pair brackets the merged launch.
  */
 stiles_status stiles_factorize_solve(stiles_factor* f, const double* d_values, int64_t nrhs, double* d_B, int64_t ldb,
                                      hipStream_t stream);
@@ -384,8 +392,7 @@ stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_factor_trace, vo
 
 /* The same per-task trace for the merged launch of stiles_factorize_solve
  * (32 bytes per task of that DAG: stiles_symbolic_export kind 14 holds 8
- * words per task).  FP64 factors only (STILES_ENOTSUP otherwise); NULL
- * switches it off. */
+ * words per task); NULL switches it off. */
 stiles_status stiles_factor_set_merged_trace(stiles_factor* f, void* d_trace, hipStream_t stream);
 
 /* Upper bound on the workgroups a factorization launch uses (0 = fill the

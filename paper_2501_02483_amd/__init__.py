@@ -45,6 +45,7 @@ STILES_ORDER_PARTIAL_RCM = 2
 STILES_ORDER_ADAPTABLE_ND = 3
 STILES_FP64 = 0
 STILES_MIXED32 = 1
+STILES_MIXED32_FULL = 2
 STILES_STATIC_LOGDET_MAX_ROWS = 65536
 
 # every symbol include/stiles.h declares

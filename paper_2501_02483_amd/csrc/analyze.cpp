@@ -1160,6 +1160,11 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
       int32_t last = -1;
       size_t start = 0;
       const bool corner = (m >= s.ntb && k >= s.ntb);
+      // a tile of the arrow corner proper (the arrow's own tile rows, after
+      // the separators that adaptable ND adds to the corner): its partial
+      // products stay FP64 in mixed mode
+      const int32_t arrow0 = ntr - (int32_t)((s.a_in + T - 1) / T);
+      const int32_t arrow_flag = (m >= arrow0 && k >= arrow0) ? TF_ARROW : 0;
       if (corner) {
         size_t nb = 0;
         while (nb < pr.size() && pj[nb] < s.ntb) nb++;
@@ -1189,7 +1194,8 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
               int32_t p0 = (int32_t)(pairs.size() / 2);
               for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
               int32_t p1 = (int32_t)(pairs.size() / 2);
-              int t = tb.add(TK_PART | (prev >= 0 ? TF_ACC : 0), -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+              int t = tb.add(TK_PART | (prev >= 0 ? TF_ACC : 0) | arrow_flag, -1, p0, p1, slot,
+                             0.5f + 1.8f * (float)(t3 * (hi - lo)));
               fexec += 2.0 * T3 * (hi - lo);
               for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
               tb.dep(t, prev);
@@ -1226,7 +1232,7 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
             for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
             int32_t p1 = (int32_t)(pairs.size() / 2);
             int32_t slot = s.npart++;
-            int t = tb.add(TK_PART, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+            int t = tb.add(TK_PART | arrow_flag, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
             fexec += 2.0 * T3 * (hi - lo);
             for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
             level.push_back({slot, t});
@@ -1270,7 +1276,7 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
             for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
             int32_t p1 = (int32_t)(pairs.size() / 2);
             const int32_t slot = s.npart++;
-            int t = tb.add(TK_PART, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+            int t = tb.add(TK_PART | arrow_flag, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
             fexec += 2.0 * T3 * (hi - lo);
             for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
             level.push_back({slot, t});

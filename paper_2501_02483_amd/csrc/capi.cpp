@@ -31,7 +31,7 @@ struct Layout {
   size_t tiles, linv, part, shadow, orig;
   size_t vy, vz, vpart, vx, vr, vb, vd, vxp;
   size_t ldpart, stats;
-  size_t rtile, ccol_tile, ccol_row, items, item_ptr, rpart;
+  size_t rtile, ccol_tile, ccol_row, items, item_ptr, rpart, rapart;
   size_t total;
 };
 
@@ -89,7 +89,9 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   const size_t nft = s.ftask.size() / TASK_WORDS, nst = s.stask.size() / TASK_WORDS;
   L.ctrl_f = take(sizeof(ExecCtrl));
   L.ctrl_s = take(sizeof(ExecCtrl));
-  if (precision == STILES_FP64) {
+  {
+    // merged factorization + solve DAG (every precision: in mixed mode its
+    // solve gives the first iterate of the refinement)
     const size_t nm = nft + nst;
     L.ctrl_m = take(sizeof(ExecCtrl));
     L.mat_m = take(sizeof(ExecMat));
@@ -125,7 +127,7 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
   L.tiles = take(s.ntiles * TT * 8);
   L.linv = take((size_t)s.ntr * TT * 8);
   L.part = take((size_t)s.npart * TT * 8);
-  const bool mixed = precision == STILES_MIXED32;
+  const bool mixed = precision != STILES_FP64;
   L.shadow = mixed ? take(s.ntiles * TT * 4) : 0;
   L.orig = mixed ? take(s.ntiles * TT * 8) : 0;
   const size_t vbytes = (size_t)s.ntr * s.T * nrhs_max * 8;
@@ -146,6 +148,7 @@ Layout make_layout(const stiles_symbolic& s, int32_t precision, int64_t nrhs_max
     L.items = take(plan->items.size() * 4);
     L.item_ptr = take(plan->item_ptr.size() * 4);
     L.rpart = take((plan->items.size() / 4) * (size_t)s.T * nrhs_max * 8);
+    L.rapart = take((plan->items.size() / 4) * (size_t)s.T * 8);   // row sums of |A| per item
   }
   L.total = o;
   return L;
@@ -222,12 +225,15 @@ extern "C" stiles_status stiles_workspace_size(const stiles_symbolic* s, int32_t
                                                size_t* bytes) {
   set_error_arg(0);
   if (!s) { set_error_arg(1); return STILES_EINVAL; }
-  if (precision != STILES_FP64 && precision != STILES_MIXED32) { set_error_arg(2); return STILES_EINVAL; }
+  if (precision != STILES_FP64 && precision != STILES_MIXED32 && precision != STILES_MIXED32_FULL) {
+    set_error_arg(2);
+    return STILES_EINVAL;
+  }
   if (nrhs_max < 1) { set_error_arg(3); return STILES_EINVAL; }
   if (!bytes) { set_error_arg(4); return STILES_EINVAL; }
   Plan p;
-  if (precision == STILES_MIXED32) make_plan(*s, p);
-  *bytes = make_layout(*s, precision, nrhs_max, precision == STILES_MIXED32 ? &p : nullptr).total;
+  if (precision != STILES_FP64) make_plan(*s, p);
+  *bytes = make_layout(*s, precision, nrhs_max, precision != STILES_FP64 ? &p : nullptr).total;
   return STILES_OK;
 }
 
@@ -235,7 +241,10 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
                                                void* d_ws, size_t ws_bytes, hipStream_t st, stiles_factor** out) {
   set_error_arg(0);
   if (!s) { set_error_arg(1); return STILES_EINVAL; }
-  if (precision != STILES_FP64 && precision != STILES_MIXED32) { set_error_arg(2); return STILES_EINVAL; }
+  if (precision != STILES_FP64 && precision != STILES_MIXED32 && precision != STILES_MIXED32_FULL) {
+    set_error_arg(2);
+    return STILES_EINVAL;
+  }
   if (nrhs_max < 1) { set_error_arg(3); return STILES_EINVAL; }
   if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % ALIGN) != 0) { set_error_arg(4); return STILES_EINVAL; }
   if (!out) { set_error_arg(7); return STILES_EINVAL; }
@@ -245,7 +254,7 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   f->nrhs_max = nrhs_max;
   f->ws = static_cast<char*>(d_ws);
   f->bytes = ws_bytes;
-  const bool mixed = precision == STILES_MIXED32;
+  const bool mixed = precision != STILES_FP64;
   if (mixed) make_plan(*s, f->plan);
   f->L = make_layout(*s, precision, nrhs_max, mixed ? &f->plan : nullptr);
   if (ws_bytes < f->L.total) { delete f; set_error_arg(5); return STILES_ENOMEM; }
@@ -273,7 +282,7 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   mf.row_base = at<int64_t>(f, L.row_base);
   mf.ntasks = (int32_t)nft;
   mf.ntr = s->ntr;
-  mf.mixed = mixed ? 1 : 0;
+  mf.mixed = !mixed ? 0 : precision == STILES_MIXED32_FULL ? 2 : 1;
   ExecMat& ms = f->ms;
   ms = mf;
   ms.tasks = at<int32_t>(f, L.stask);
@@ -311,7 +320,7 @@ extern "C" stiles_status stiles_workspace_init(const stiles_symbolic* s, int32_t
   if (!s->in_rp_in.empty()) U(L.in_rp_in, s->in_rp_in.data(), s->in_rp_in.size() * 8);
   std::vector<int32_t> mrem;
   ExecMat& mm = f->mm;
-  if (!mixed) {
+  {
     const MergedPlan& md = merged_plan(*s);
     f->nmerged = (int32_t)(md.task.size() / TASK_WORDS);
     mrem.resize(f->nmerged);
@@ -364,7 +373,7 @@ extern "C" stiles_status stiles_factor_set_max_workgroups(stiles_factor* f, int3
 static stiles_status scatter_values(stiles_factor* f, const double* d_values, hipStream_t st) {
   const stiles_symbolic& s = *f->sym;
   const Layout& L = f->L;
-  double* orig = f->precision == STILES_MIXED32 ? at<double>(f, L.orig) : nullptr;
+  double* orig = f->precision != STILES_FP64 ? at<double>(f, L.orig) : nullptr;
   hipError_t e;
   if (s.profile_input && !s.perm_identity)
     e = launch_scatter_perm(s.T, d_values, at<int64_t>(f, L.in_rp_in), at<int64_t>(f, L.fin), at<int64_t>(f, L.perm),
@@ -447,6 +456,146 @@ static stiles_status solve_tiles_from_tiles(stiles_factor* f, const double* d_ti
   return e == hipSuccess ? STILES_OK : STILES_EDEVICE;
 }
 
+// Mixed mode: iterative refinement in FP64 of the nb right-hand sides at B
+// (column offset c0 of the caller's report).  x0 = solve(b) (already in vz
+// when x0_ready: the merged factorization + solve launch computed it); then
+// per right-hand side r = b - A x with the resident FP64 tiles of A,
+// d = solve(r), x += d until its own stopping test holds.
+stiles_status refine_mixed(stiles_factor* f, double* B, int64_t ldb, int nb, int64_t c0, hipStream_t st,
+                           stiles_solve_report* report, bool x0_ready) {
+  const stiles_symbolic& s = *f->sym;
+  const Layout& L = f->L;
+  // ---- mixed mode: x0 = solve(b); repeat r = b - A x, d = solve(r), x += d,
+  //      each right-hand side until its own stopping test holds
+  const size_t vbytes = (size_t)s.ntr * s.T * nb * 8;
+  double* vx = at<double>(f, L.vx);
+  double* vxp = at<double>(f, L.vxp);
+  double* vr = at<double>(f, L.vr);
+  double* vbb = at<double>(f, L.vb);
+  double* vz = at<double>(f, L.vz);
+  unsigned long long* stats = at<unsigned long long>(f, L.stats);
+  // r = b - A x; the first residual after a factorization also gives the
+  // row sums of |A| (||A||_inf, kept until the next factorization) from
+  // the same pass over A
+  auto resid = [&](const double* X, double* R, bool rowsums) {
+    return launch_residual(s.T, at<double>(f, L.orig), at<int32_t>(f, L.rtile), at<int32_t>(f, L.tcol),
+                           at<int32_t>(f, L.ccol_tile), at<int32_t>(f, L.ccol_row), at<int32_t>(f, L.items),
+                           (int32_t)(f->plan.items.size() / 4), at<int32_t>(f, L.item_ptr), s.ntr, X, vbb,
+                           at<double>(f, L.rpart), R, nb, 0, st, rowsums ? at<double>(f, L.rapart) : nullptr,
+                           rowsums ? at<double>(f, L.vd) : nullptr);
+  };
+  if (!x0_ready) {
+    stiles_status r = solve_sweep(f, B, ldb, nb, st);      // packs b into Y
+    if (r != STILES_OK) return r;
+  }
+  // keep b (tile layout) and x
+  if (launch_pack(s.T, B, ldb, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
+                  s.ntr, vbb, st) != hipSuccess)
+    return STILES_EDEVICE;
+  if (hipMemcpyAsync(vx, vz, vbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return STILES_EDEVICE;
+  std::vector<double> bnorm(nb, 0.0);
+  {
+    // ||b||_inf per column, from the packed copy (host reduction of a small
+    // device-side max: reuse the norms kernel with R = b)
+    std::vector<unsigned long long> z(2 * 16, 0ull);
+    if (hipMemcpyAsync(stats, z.data(), z.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) return STILES_EDEVICE;
+    if (launch_norms(s.T, s.ntr, nb, vbb, vbb, stats, st) != hipSuccess) return STILES_EDEVICE;
+    std::vector<unsigned long long> h(2 * 16);
+    if (hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return STILES_EDEVICE;
+    for (int c = 0; c < nb; c++) { double v; std::memcpy(&v, &h[2 * c], 8); bnorm[c] = v; }
+  }
+  // default stopping test: a backward error of the size the FP64 factor's
+  // own solve reaches, u (w + a), w the largest band half-width
+  const double tol = f->sym->opts.refine_tol > 0
+                         ? f->sym->opts.refine_tol
+                         : std::ldexp(1.0, -52) * (double)std::max<int64_t>(1, s.w_in + s.a_in);
+  const int maxit = f->sym->opts.refine_max_iter > 0 ? f->sym->opts.refine_max_iter : 30;
+  // per right-hand side: backward error of the current x, steps taken,
+  // converged, still refining
+  std::vector<double> berr(nb, INFINITY);
+  std::vector<int> its(nb, 0);
+  std::vector<char> conv(nb, 0);
+  uint32_t active = (1u << nb) - 1u;   // nb <= 16
+  int step = 0;
+  for (;;) {
+    const bool rowsums = f->anorm < 0;
+    if (resid(vx, vr, rowsums) != hipSuccess) return STILES_EDEVICE;
+    if (rowsums) {
+      std::vector<double> rsum((size_t)s.ntr * s.T);
+      if (hipMemcpyAsync(rsum.data(), at<double>(f, L.vd), rsum.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return STILES_EDEVICE;
+      double a = 0.0;
+      for (double v : rsum) a = std::max(a, v);
+      f->anorm = a;
+    }
+    std::vector<unsigned long long> z(2 * 16, 0ull), h(2 * 16);
+    if (hipMemcpyAsync(stats, z.data(), z.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) return STILES_EDEVICE;
+    if (launch_norms(s.T, s.ntr, nb, vr, vx, stats, st) != hipSuccess) return STILES_EDEVICE;
+    if (hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return STILES_EDEVICE;
+    uint32_t revert = 0;
+    for (int c = 0; c < nb; c++) {
+      if (!((active >> c) & 1u)) continue;
+      double rn, xn;
+      std::memcpy(&rn, &h[2 * c], 8);
+      std::memcpy(&xn, &h[2 * c + 1], 8);
+      const double den = f->anorm * xn + bnorm[c];
+      const double be = den > 0 ? rn / den : rn;
+      const uint32_t bit = 1u << c;
+      if (!(be == be)) {                       // NaN: failed factorization
+        berr[c] = be;
+        active &= ~bit;
+      } else if (be <= tol) {                  // converged
+        berr[c] = be;
+        conv[c] = 1;
+        active &= ~bit;
+      } else if (step > 0 && be > 0.5 * berr[c]) {
+        // no longer halving (stagnation): keep the better of the last two
+        // iterates, with its backward error
+        if (be > berr[c]) {
+          revert |= bit;   // the last correction is undone
+          its[c]--;
+        } else {
+          berr[c] = be;
+        }
+        active &= ~bit;
+      } else {
+        berr[c] = be;
+        if (its[c] >= maxit) active &= ~bit;   // step limit
+      }
+    }
+    if (revert && launch_copy_cols(s.T, s.ntr, nb, vx, vxp, revert, st) != hipSuccess) return STILES_EDEVICE;
+    if (!active) break;
+    // x_prev = x; d = solve(r) (every column: the sweep's cost does not
+    // depend on the count); x += d on the columns still refining
+    if (hipMemcpyAsync(vxp, vx, vbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return STILES_EDEVICE;
+    stiles_status r2 = solve_tiles_from_tiles(f, vr, nb, st);
+    if (r2 != STILES_OK) return r2;
+    if (launch_axpy(s.T, s.ntr, nb, vx, vz, active, st) != hipSuccess) return STILES_EDEVICE;
+    for (int c = 0; c < nb; c++)
+      if ((active >> c) & 1u) its[c]++;
+    step++;
+  }
+  if (launch_unpack(s.T, vx, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
+                    s.ntr, at<unsigned long long>(f, L.info), B, ldb, st) != hipSuccess)
+    return STILES_EDEVICE;
+  if (report) {
+    for (int c = 0; c < nb; c++) {
+      report->iterations = std::max(report->iterations, its[c]);
+      report->converged = report->converged && conv[c];
+      report->backward_error = std::max(report->backward_error, berr[c]);
+      if (!(berr[c] == berr[c])) report->backward_error = berr[c];
+      if (report->backward_errors) report->backward_errors[c0 + c] = berr[c];
+      if (report->rhs_iterations) report->rhs_iterations[c0 + c] = its[c];
+    }
+  }
+  return STILES_OK;
+}
+
 extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_B, int64_t ldb, hipStream_t st,
                                       stiles_solve_report* report) {
   set_error_arg(0);
@@ -470,7 +619,7 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
   for (int64_t c0 = 0; c0 < nrhs; c0 += 16) {
     const int nb = (int)std::min<int64_t>(16, nrhs - c0);
     double* B = d_B + c0 * ldb;
-    if (f->precision != STILES_MIXED32) {
+    if (f->precision == STILES_FP64) {
       stiles_status r = solve_sweep(f, B, ldb, nb, st);
       if (r != STILES_OK) return r;
       if (launch_unpack(s.T, at<double>(f, L.vz), nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
@@ -478,129 +627,8 @@ extern "C" stiles_status stiles_solve(stiles_factor* f, int64_t nrhs, double* d_
         return STILES_EDEVICE;
       continue;
     }
-    // ---- mixed mode: x0 = solve(b); repeat r = b - A x, d = solve(r), x += d,
-    //      each right-hand side until its own stopping test holds
-    const size_t vbytes = (size_t)s.ntr * s.T * nb * 8;
-    double* vx = at<double>(f, L.vx);
-    double* vxp = at<double>(f, L.vxp);
-    double* vr = at<double>(f, L.vr);
-    double* vbb = at<double>(f, L.vb);
-    double* vz = at<double>(f, L.vz);
-    unsigned long long* stats = at<unsigned long long>(f, L.stats);
-    auto resid = [&](const double* X, double* R, int absmode) {
-      return launch_residual(s.T, at<double>(f, L.orig), at<int32_t>(f, L.rtile), at<int32_t>(f, L.tcol),
-                             at<int32_t>(f, L.ccol_tile), at<int32_t>(f, L.ccol_row), at<int32_t>(f, L.items),
-                             (int32_t)(f->plan.items.size() / 4), at<int32_t>(f, L.item_ptr), s.ntr, X, vbb,
-                             at<double>(f, L.rpart), R, absmode ? 1 : nb, absmode, st);
-    };
-    if (f->anorm < 0) {
-      // ||A||_inf from the row sums of |A| (one column of sums)
-      if (resid(vx, at<double>(f, L.vd), 1) != hipSuccess) return STILES_EDEVICE;
-      std::vector<double> rs((size_t)s.ntr * s.T);
-      if (hipMemcpyAsync(rs.data(), at<double>(f, L.vd), rs.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        return STILES_EDEVICE;
-      double a = 0.0;
-      for (double v : rs) a = std::max(a, v);
-      f->anorm = a;
-    }
-    stiles_status r = solve_sweep(f, B, ldb, nb, st);      // packs b into Y
+    stiles_status r = refine_mixed(f, B, ldb, nb, c0, st, report, false);
     if (r != STILES_OK) return r;
-    // keep b (tile layout) and x
-    if (launch_pack(s.T, B, ldb, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
-                    s.ntr, vbb, st) != hipSuccess)
-      return STILES_EDEVICE;
-    if (hipMemcpyAsync(vx, vz, vbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return STILES_EDEVICE;
-    std::vector<double> bnorm(nb, 0.0);
-    {
-      // ||b||_inf per column, from the packed copy (host reduction of a small
-      // device-side max: reuse the norms kernel with R = b)
-      std::vector<unsigned long long> z(2 * 16, 0ull);
-      if (hipMemcpyAsync(stats, z.data(), z.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) return STILES_EDEVICE;
-      if (launch_norms(s.T, s.ntr, nb, vbb, vbb, stats, st) != hipSuccess) return STILES_EDEVICE;
-      std::vector<unsigned long long> h(2 * 16);
-      if (hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        return STILES_EDEVICE;
-      for (int c = 0; c < nb; c++) { double v; std::memcpy(&v, &h[2 * c], 8); bnorm[c] = v; }
-    }
-    // default stopping test: a backward error of the size the FP64 factor's
-    // own solve reaches, u (w + a), w the largest band half-width
-    const double tol = f->sym->opts.refine_tol > 0
-                           ? f->sym->opts.refine_tol
-                           : std::ldexp(1.0, -52) * (double)std::max<int64_t>(1, s.w_in + s.a_in);
-    const int maxit = f->sym->opts.refine_max_iter > 0 ? f->sym->opts.refine_max_iter : 30;
-    // per right-hand side: backward error of the current x, steps taken,
-    // converged, still refining
-    std::vector<double> berr(nb, INFINITY);
-    std::vector<int> its(nb, 0);
-    std::vector<char> conv(nb, 0);
-    uint32_t active = (1u << nb) - 1u;   // nb <= 16
-    int step = 0;
-    for (;;) {
-      if (resid(vx, vr, 0) != hipSuccess) return STILES_EDEVICE;
-      std::vector<unsigned long long> z(2 * 16, 0ull), h(2 * 16);
-      if (hipMemcpyAsync(stats, z.data(), z.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) return STILES_EDEVICE;
-      if (launch_norms(s.T, s.ntr, nb, vr, vx, stats, st) != hipSuccess) return STILES_EDEVICE;
-      if (hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        return STILES_EDEVICE;
-      uint32_t revert = 0;
-      for (int c = 0; c < nb; c++) {
-        if (!((active >> c) & 1u)) continue;
-        double rn, xn;
-        std::memcpy(&rn, &h[2 * c], 8);
-        std::memcpy(&xn, &h[2 * c + 1], 8);
-        const double den = f->anorm * xn + bnorm[c];
-        const double be = den > 0 ? rn / den : rn;
-        const uint32_t bit = 1u << c;
-        if (!(be == be)) {                       // NaN: failed factorization
-          berr[c] = be;
-          active &= ~bit;
-        } else if (be <= tol) {                  // converged
-          berr[c] = be;
-          conv[c] = 1;
-          active &= ~bit;
-        } else if (step > 0 && be > 0.5 * berr[c]) {
-          // no longer halving (stagnation): keep the better of the last two
-          // iterates, with its backward error
-          if (be > berr[c]) {
-            revert |= bit;   // the last correction is undone
-            its[c]--;
-          } else {
-            berr[c] = be;
-          }
-          active &= ~bit;
-        } else {
-          berr[c] = be;
-          if (its[c] >= maxit) active &= ~bit;   // step limit
-        }
-      }
-      if (revert && launch_copy_cols(s.T, s.ntr, nb, vx, vxp, revert, st) != hipSuccess) return STILES_EDEVICE;
-      if (!active) break;
-      // x_prev = x; d = solve(r) (every column: the sweep's cost does not
-      // depend on the count); x += d on the columns still refining
-      if (hipMemcpyAsync(vxp, vx, vbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return STILES_EDEVICE;
-      stiles_status r2 = solve_tiles_from_tiles(f, vr, nb, st);
-      if (r2 != STILES_OK) return r2;
-      if (launch_axpy(s.T, s.ntr, nb, vx, vz, active, st) != hipSuccess) return STILES_EDEVICE;
-      for (int c = 0; c < nb; c++)
-        if ((active >> c) & 1u) its[c]++;
-      step++;
-    }
-    if (launch_unpack(s.T, vx, nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base), at<int32_t>(f, L.row_cnt),
-                      s.ntr, at<unsigned long long>(f, L.info), B, ldb, st) != hipSuccess)
-      return STILES_EDEVICE;
-    if (report) {
-      for (int c = 0; c < nb; c++) {
-        report->iterations = std::max(report->iterations, its[c]);
-        report->converged = report->converged && conv[c];
-        report->backward_error = std::max(report->backward_error, berr[c]);
-        if (!(berr[c] == berr[c])) report->backward_error = berr[c];
-        if (report->backward_errors) report->backward_errors[c0 + c] = berr[c];
-        if (report->rhs_iterations) report->rhs_iterations[c0 + c] = its[c];
-      }
-    }
   }
   return STILES_OK;
 }
@@ -615,7 +643,6 @@ extern "C" stiles_status stiles_factorize_solve(stiles_factor* f, const double* 
   if (nrhs < 1 || nrhs > f->nrhs_max) { set_error_arg(3); return STILES_EINVAL; }
   if (!d_B) { set_error_arg(4); return STILES_EINVAL; }
   if (ldb < sy.N) { set_error_arg(5); return STILES_EINVAL; }
-  if (f->precision != STILES_FP64) return STILES_ENOTSUP;
   stiles_status r = scatter_values(f, d_values, st);
   if (r != STILES_OK) return r;
   const Layout& L = f->L;
@@ -630,13 +657,24 @@ extern "C" stiles_status stiles_factorize_solve(stiles_factor* f, const double* 
   if (e != hipSuccess) return STILES_EDEVICE;
   f->state = 0;
   f->anorm = -1.0;
-  if (launch_unpack(sy.T, at<double>(f, L.vz), nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
-                    at<int32_t>(f, L.row_cnt), sy.ntr, at<unsigned long long>(f, L.info), d_B, ldb, st) != hipSuccess)
+  if (f->precision != STILES_FP64) {
+    // mixed mode: the launch's solve is the first iterate of the refinement
+    r = refine_mixed(f, d_B, ldb, nb, 0, st, nullptr, true);
+    if (r != STILES_OK) return r;
+  } else if (launch_unpack(sy.T, at<double>(f, L.vz), nb, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
+                           at<int32_t>(f, L.row_cnt), sy.ntr, at<unsigned long long>(f, L.info), d_B, ldb, st) !=
+             hipSuccess) {
     return STILES_EDEVICE;
+  }
   // right-hand sides beyond the first 16: ordinary solve sweeps
   for (int64_t c0 = nb; c0 < nrhs; c0 += 16) {
     const int nb2 = (int)std::min<int64_t>(16, nrhs - c0);
     double* B = d_B + c0 * ldb;
+    if (f->precision != STILES_FP64) {
+      r = refine_mixed(f, B, ldb, nb2, c0, st, nullptr, false);
+      if (r != STILES_OK) return r;
+      continue;
+    }
     r = solve_sweep(f, B, ldb, nb2, st);
     if (r != STILES_OK) return r;
     if (launch_unpack(sy.T, at<double>(f, L.vz), nb2, at<int64_t>(f, L.perm), at<int64_t>(f, L.row_base),
@@ -829,7 +867,7 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
     d.row_base = at<int64_t>(f, L.row_base);
     d.row_cnt = at<int32_t>(f, L.row_cnt);
     d.tiles = at<double>(f, L.tiles);
-    d.orig = f->precision == STILES_MIXED32 ? at<double>(f, L.orig) : nullptr;
+    d.orig = f->precision != STILES_FP64 ? at<double>(f, L.orig) : nullptr;
     d.ldpart = at<double>(f, L.ldpart);
     d.info = at<unsigned long long>(f, L.info);
     d.ntiles = (int32_t)s.ntiles;
@@ -951,7 +989,6 @@ extern "C" stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_facto
 extern "C" stiles_status stiles_factor_set_merged_trace(stiles_factor* f, void* d_trace, hipStream_t st) {
   set_error_arg(0);
   if (!f) { set_error_arg(1); return STILES_EINVAL; }
-  if (f->precision != STILES_FP64) return STILES_ENOTSUP;
   f->mm.trace = static_cast<unsigned long long*>(d_trace);
   hipError_t e = hipMemcpyAsync(f->ws + f->L.mat_m, &f->mm, sizeof(ExecMat), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

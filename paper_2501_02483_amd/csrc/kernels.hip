@@ -220,7 +220,10 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
   const bool diag = (w[0] & TF_DIAG) != 0;
   const bool active = !(diag && wc > wr);   // strictly upper quarter of a diagonal tile
   const int p0 = __builtin_amdgcn_readfirstlane(w[2]), np = __builtin_amdgcn_readfirstlane(w[3]) - p0;
-  const bool mixed = M.mixed && mode == 0;
+  // FP32 products in mixed mode: the updates, and the partials of corner
+  // tiles other than the arrow corner (separator rows under adaptable ND);
+  // the arrow corner's partials too in the all-FP32 variant (mixed == 2)
+  const bool mixed = M.mixed && (mode == 0 || M.mixed == 2 || (w[0] & TF_ARROW) == 0);
   const bool accum = mode == 1 && (w[0] & TF_ACC) != 0;   // partial chain: P += sum
   GLOBAL double* out = gp(mode == 0 ? M.tiles + (int64_t)w[1] * TT : M.part + (int64_t)w[4] * TT);
   const int pv = load_words(M.pairs + 2 * p0, 2 * np);
@@ -315,7 +318,11 @@ __device__ __attribute__((noinline)) void task_update(const ExecMat& M, const in
 #pragma unroll
           for (int r = 0; r < 4; r++) {
             const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + 4 * (lane >> 4) + r;
-            if (!diag || row >= col) st_dev(out + row + col * T, cin[i][j][r] - (double)acc[i][j][r]);
+            if (mode == 0) {
+              if (!diag || row >= col) st_dev(out + row + col * T, cin[i][j][r] - (double)acc[i][j][r]);
+            } else {
+              st_dev(out + row + col * T, accum ? cin[i][j][r] + (double)acc[i][j][r] : (double)acc[i][j][r]);
+            }
           }
     }
   }
@@ -2136,10 +2143,12 @@ __global__ __launch_bounds__(NT) void residual_mma_kernel(const double* __restri
                                                           const int32_t* __restrict__ ccol_tile,
                                                           const int32_t* __restrict__ ccol_row,
                                                           const int32_t* __restrict__ items,
-                                                          const double* __restrict__ X, double* part, int nrhs,
-                                                          int absmode) {
+                                                          const double* __restrict__ X, double* part, double* apart,
+                                                          int nrhs, int absmode) {
   // operands straight from global memory into registers (SolveOps layout),
-  // two tiles in flight; wave w owns rows 16 w .. 16 w + 15 of the T x 16 result
+  // two tiles in flight; wave w owns rows 16 w .. 16 w + 15 of the T x 16 result.
+  // With apart (residual pass), the row sums of |A| over the same operands
+  // are accumulated too (one pass over A gives both).
   typedef SolveOps<T> O;
   constexpr int TT = T * T, NS = O::NS;
   const int q = blockIdx.x;
@@ -2151,6 +2160,7 @@ __global__ __launch_bounds__(NT) void residual_mma_kernel(const double* __restri
   const int ncol = absmode ? 1 : nrhs;
   const bool trans = kind == 1;
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  double rs = 0.0;   // this lane's share of the row sum of |A| (apart)
   if (!act) return;
   double a[2][NS], b[2][NS];
   // operands of item entry e into slot u
@@ -2169,6 +2179,9 @@ __global__ __launch_bounds__(NT) void residual_mma_kernel(const double* __restri
     if (absmode) {
 #pragma unroll
       for (int s = 0; s < NS; s++) a[u][s] = fabs(a[u][s]);
+    } else if (apart) {
+#pragma unroll
+      for (int s = 0; s < NS; s++) rs += fabs(a[u][s]);
     }
     acc = O::mma(acc, a[u], b[u]);
     const int tile = kind == 0 ? rtile[e] : -1;
@@ -2181,6 +2194,7 @@ __global__ __launch_bounds__(NT) void residual_mma_kernel(const double* __restri
       for (int s = 0; s < NS; s++) {
         const double v = NS * g + s == r ? 0.0 : at[s];
         at[s] = absmode ? fabs(v) : v;
+        if (apart && !absmode) rs += fabs(v);
       }
       acc = O::mma(acc, at, b[u]);
     }
@@ -2199,10 +2213,17 @@ __global__ __launch_bounds__(NT) void residual_mma_kernel(const double* __restri
 #pragma unroll
     for (int rr = 0; rr < 4; rr++) out[(16 * wave + (lane >> 4) + 4 * rr) + col * T] = acc[rr];
   }
+  if (apart) {
+    // the four lanes of a row (k groups g = 0..3) hold its whole sum
+    rs += __shfl_xor(rs, 16, 64);
+    rs += __shfl_xor(rs, 32, 64);
+    if (g == 0) apart[(int64_t)q * T + r] = rs;
+  }
 }
 
 __global__ void residual_combine_kernel(int T, const int32_t* __restrict__ item_ptr, const double* __restrict__ part,
-                                        const double* __restrict__ B, double* R, int nrhs, int absmode) {
+                                        const double* __restrict__ B, double* R, int nrhs, int absmode,
+                                        const double* __restrict__ apart, double* D) {
   const int m = blockIdx.x;
   const int64_t vb = (int64_t)T * nrhs;
   const int ncol = absmode ? 1 : nrhs;
@@ -2211,21 +2232,30 @@ __global__ void residual_combine_kernel(int T, const int32_t* __restrict__ item_
     for (int q = item_ptr[m]; q < item_ptr[m + 1]; q++) s += part[(int64_t)q * vb + e];
     R[m * vb + e] = absmode ? s : B[m * vb + e] - s;
   }
+  if (apart) {
+    for (int e = threadIdx.x; e < T; e += blockDim.x) {
+      double s = 0.0;
+      for (int q = item_ptr[m]; q < item_ptr[m + 1]; q++) s += apart[(int64_t)q * T + e];
+      D[(int64_t)m * T + e] = s;
+    }
+  }
 }
 
 hipError_t launch_residual(int T, const double* orig, const int32_t* rtile, const int32_t* tcol,
                            const int32_t* ccol_tile, const int32_t* ccol_row, const int32_t* items, int32_t nitems,
                            const int32_t* item_ptr, int32_t ntr, const double* X, const double* B, double* part,
-                           double* R, int nrhs, int absmode, hipStream_t st) {
+                           double* R, int nrhs, int absmode, hipStream_t st, double* apart, double* D) {
+  if (absmode) apart = nullptr;
   if (nitems > 0) {
     if (T == 64)
       hipLaunchKernelGGL(residual_mma_kernel<64>, dim3(nitems), dim3(NT), 0, st, orig, rtile, tcol, ccol_tile, ccol_row,
-                         items, X, part, nrhs, absmode);
+                         items, X, part, apart, nrhs, absmode);
     else
       hipLaunchKernelGGL(residual_mma_kernel<32>, dim3(nitems), dim3(NT), 0, st, orig, rtile, tcol, ccol_tile, ccol_row,
-                         items, X, part, nrhs, absmode);
+                         items, X, part, apart, nrhs, absmode);
   }
-  hipLaunchKernelGGL(residual_combine_kernel, dim3(ntr), dim3(NT), 0, st, T, item_ptr, part, B, R, nrhs, absmode);
+  hipLaunchKernelGGL(residual_combine_kernel, dim3(ntr), dim3(NT), 0, st, T, item_ptr, part, B, R, nrhs, absmode,
+                     apart, D);
   return hipGetLastError();
 }
 

@@ -79,11 +79,14 @@ hipError_t launch_unpack(int T, const double* Z, int nrhs, const int64_t* perm, 
 // symmetrically), kind 1 sums A_(i,m)^T X_i over column entries [lo,hi) of
 // ccol_*.  Item q writes partial block q; row m owns items
 // [item_ptr[m], item_ptr[m+1]).  absmode != 0 replaces A by |A| and X by
-// ones (row sums of |A|).
+// ones (row sums of |A|).  With apart (items x T doubles) and D (ntr x T),
+// a residual pass (absmode 0) also writes the row sums of |A| to D, from
+// the same reads of A.
 hipError_t launch_residual(int T, const double* orig, const int32_t* rtile, const int32_t* tcol,
                            const int32_t* ccol_tile, const int32_t* ccol_row, const int32_t* items, int32_t nitems,
                            const int32_t* item_ptr, int32_t ntr, const double* X, const double* B, double* part,
-                           double* R, int nrhs, int absmode, hipStream_t st);
+                           double* R, int nrhs, int absmode, hipStream_t st, double* apart = nullptr,
+                           double* D = nullptr);
 // stats[2c] = max_i |R_ic|, stats[2c+1] = max_i |X_ic| (bit patterns, atomically maxed)
 hipError_t launch_norms(int T, int32_t ntr, int nrhs, const double* R, const double* X, unsigned long long* stats,
                         hipStream_t st);

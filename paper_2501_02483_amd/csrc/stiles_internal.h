@@ -44,6 +44,7 @@ enum TaskFlag : int32_t {
   TF_FIRST = 1 << 9,  // BUPD: first chunk reads Y_m; BDIAG: no BUPD, reads Y_m
   TF_ACC = 1 << 10,   // PART: P_s += sum (continues a chain) instead of P_s = sum
   TF_SPLIT = 1 << 11, // POTRF/TRSM: two-stage wait (early predecessors, then the chain one)
+  TF_ARROW = 1 << 12, // PART: partial of an arrow-corner tile (FP64 in mixed mode)
 };
 
 // One task = 8 int32.

@@ -71,9 +71,40 @@ def test_factorize_solve_failure_and_mixed():
     assert fac.info() > 0
     assert torch.isnan(b).all()
     mixed = S.Factor(sym, S.STILES_MIXED32)
-    with pytest.raises(S.StilesError) as e:
-        mixed.factorize_solve(torch.from_numpy(vals).cuda(), b)
-    assert e.value.status == S.STILES_ENOTSUP
+    b = torch.ones(p.N, dtype=torch.float64, device="cuda")
+    mixed.factorize_solve(torch.from_numpy(vals).cuda(), b)
+    assert mixed.info() == fac.info()
+    assert torch.isnan(b).all()
+
+
+@pytest.mark.parametrize("ordering,nrhs", [(S.STILES_ORDER_NONE, 3), (S.STILES_ORDER_ADAPTABLE_ND, 20)],
+                         ids=["natural_r3", "nd_r20"])
+def test_mixed_factorize_solve_matches_separate_calls(ordering, nrhs):
+    """Mixed precision in one launch: the merged launch's solve is the first
+    iterate of the FP64 refinement; the refined X is bitwise that of
+    stiles_factorize + stiles_solve (right-hand sides beyond 16 included)
+    and matches the oracle."""
+    import torch
+    p = I.make_pattern(8000, 40, [30, 160, 90], seg=900)
+    vals = I.make_values(p, seed=21)
+    B = I.rhs(p.N, nrhs, seed=22)
+    ref = oracle_reference(p, vals, B)
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=ordering)
+    say("[gpu factorize_solve] mixed precision, ordering %d, %d RHS" % (ordering, nrhs))
+    dv = torch.from_numpy(vals).cuda()
+    one = S.Factor(sym, S.STILES_MIXED32, nrhs_max=nrhs)
+    one.factorize(dv)
+    X1 = to_device_cols(B)
+    rep = one.solve(X1)
+    assert rep.converged == 1
+    both = S.Factor(sym, S.STILES_MIXED32, nrhs_max=nrhs)
+    X2 = to_device_cols(B)
+    both.factorize_solve(dv, X2)
+    assert both.info() == 0
+    assert torch.equal(X1, X2)
+    eX = rel(X2.cpu().numpy(), ref["X"])
+    say("   X error %.2e" % eX)
+    assert eX <= 1e-12
 
 
 def test_ticket_order_does_not_change_results():
