@@ -604,8 +604,12 @@ def bench_mixed(args):
                          "frac": v / FP32_PEAK, "traffic": None}}
 
 
+HOST_THREADS = {"auto": None, "on": True, "off": False}
+
+
 def bench_serve(args):
-    """Poisson arrivals over 8 resident patterns (continuous batching)."""
+    """Poisson arrivals over 8 resident patterns (continuous batching), FP64
+    and mixed-precision serving, each at 0.5 and 0.8 x its own saturation."""
     import torch
 
     import paper_2501_02483_amd as S
@@ -615,41 +619,61 @@ def bench_serve(args):
     pats = I.serving_patterns()
     if args.max_n:
         pats = [p for p in pats if p.n <= args.max_n]
-    ex = GpuExecutor(pats, tile=args.tile or 64, slots=args.slots,
-                     ordering=S.STILES_ORDER_ADAPTABLE_ND if args.ordering == "nd" else S.STILES_ORDER_NONE)
     budget = int(args.budget_gb * 2 ** 30)
-    # warm-up: one request per pattern and slot, so every workspace the runs
-    # below need is allocated and initialized before any clock starts
-    warm = [Request(rid=i, arrival=0.0, pattern=i // args.slots, op=i % 3, seed=4000 + i)
-            for i in range(len(pats) * args.slots)]
-    Server(ex, budget, args.slots).run(warm)
-    torch.cuda.synchronize()
-    # closed loop: saturation rate with every slot busy
-    nsat = args.requests // 2
-    rng = np.random.default_rng(5)
-    sat = [Request(rid=i, arrival=0.0, pattern=int(rng.integers(len(pats))), op=int(rng.integers(3)),
-                   seed=5000 + i) for i in range(nsat)]
-    srv = Server(ex, budget, args.slots)
-    done = srv.run(sat)
-    span = max(r.t_done for r in done)
-    mu = len(done) / span
-    res = {"saturation_rps": mu}
-    flops = lambda r: ex.flops(r.pattern)
-    for frac in (0.5, 0.8):
-        reqs = [Request(rid=i, arrival=t, pattern=pi, op=op, seed=sd)
-                for i, (t, pi, op, sd) in enumerate(I.serving_requests(len(pats), args.requests, frac * mu))]
-        srv = Server(ex, budget, args.slots)
-        d = srv.run(reqs)
-        bad = sum(1 for r in d if r.result.get("info", 0) != 0)
-        res["load_%.1f" % frac] = dict(summarize(d, flops), failed=bad, max_used_gb=srv.max_used / 2 ** 30)
-    main = res["load_0.8"]
+    ordering = S.STILES_ORDER_ADAPTABLE_ND if args.ordering == "nd" else S.STILES_ORDER_NONE
+    precisions = {"fp64": [S.STILES_FP64], "mixed": [S.STILES_MIXED32],
+                  "both": [S.STILES_FP64, S.STILES_MIXED32]}[args.serve_precision]
+
+    def serve_one(prec):
+        name = "fp64" if prec == S.STILES_FP64 else "mixed"
+        # slots per precision (measured over 2000-request runs: FP64 peaks at
+        # 2 concurrent requests, mixed precision at 4)
+        slots = args.slots or (2 if prec == S.STILES_FP64 else 4)
+        ex = GpuExecutor(pats, tile=args.tile or 64, precision=prec, slots=slots, ordering=ordering,
+                         keep_results=False, host_threads=HOST_THREADS[args.host_threads])
+        # warm-up: one request per pattern and slot, so every workspace the
+        # runs below need is allocated and initialized before any clock starts
+        warm = [Request(rid=i, arrival=0.0, pattern=i // slots, op=i % 3, seed=4000 + i, precision=prec)
+                for i in range(len(pats) * slots)]
+        Server(ex, budget, slots).run(warm)
+        torch.cuda.synchronize()
+        # closed loop: saturation rate with every slot busy
+        nsat = max(args.requests // 2, 1)
+        rng = np.random.default_rng(5)
+        sat = [Request(rid=i, arrival=0.0, pattern=int(rng.integers(len(pats))), op=int(rng.integers(3)),
+                       seed=5000 + i, precision=prec) for i in range(nsat)]
+        done = Server(ex, budget, slots).run(sat)
+        mu = len(done) / max(r.t_done for r in done)
+        print("[serve %s] saturation %.1f req/s over %d requests" % (name, mu, nsat), file=sys.stderr, flush=True)
+        res = {"saturation_rps": mu, "slots": slots, "syms_nd_parts": [s.info.nd_parts for s in ex.syms]}
+        flops = lambda r: ex.flops(r.pattern)
+        for frac in (0.5, 0.8):
+            reqs = [Request(rid=i, arrival=t, pattern=pi, op=op, seed=sd, precision=prec)
+                    for i, (t, pi, op, sd) in enumerate(I.serving_requests(len(pats), args.requests, frac * mu))]
+            srv = Server(ex, budget, slots)
+            d = srv.run(reqs)
+            bad = sum(1 for r in d if r.result.get("info", 0) != 0)
+            res["load_%.1f" % frac] = dict(summarize(d, flops), failed=bad, max_used_gb=srv.max_used / 2 ** 30)
+            print("[serve %s] load %.1f: %d requests, p50 %.1f ms, p99 %.1f ms" % (
+                name, frac, len(d), res["load_%.1f" % frac]["p50_ms"], res["load_%.1f" % frac]["p99_ms"]),
+                file=sys.stderr, flush=True)
+        ex.close()
+        del ex
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return name, res
+
+    res = dict(serve_one(p) for p in precisions)
+    head = res["fp64"] if "fp64" in res else res["mixed"]
+    main = head["load_0.8"]
     return {"metric": "serving p50/p99 request latency (ms) at 0.8 x saturation", "value": main["p99_ms"],
             "unit": "ms (p99)", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": main["mean_ms"],
-            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if "fp64" in res else "f32+f64",
             "data": "synthetic (device-generated values per request)",
             "config": {"workload": "serve8", "patterns": [(p.n, int(p.n - p.f[p.n - 1]), p.a) for p in pats],
                        "slots": args.slots, "budget_gb": args.budget_gb, "requests": args.requests,
-                       "nd_parts": [s.info.nd_parts for s in ex.syms]},
+                       "precisions": list(res), "host_threads": args.host_threads},
             "results": res}
 
 
@@ -715,9 +739,14 @@ def main():
                     help="mixed: value law (Laplacian, kappa ~ 1e6; or S A0 S with s_i = 10^(-3 u_i))")
     ap.add_argument("--no-large", action="store_true",
                     help="varband: skip the n = 500,000 FP64/mixed runs reported beside the main line")
-    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
+    ap.add_argument("--slots", type=int, default=0,
+                    help="serve: concurrent request slots (0: 2 for FP64, 4 for mixed precision)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget for in-flight requests")
-    ap.add_argument("--requests", type=int, default=60, help="serve: requests per load point")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests per load point")
+    ap.add_argument("--host-threads", default="auto", choices=list(HOST_THREADS),
+                    help="serve: issue requests from one host thread per slot (auto: mixed precision only)")
+    ap.add_argument("--serve-precision", default="both", choices=["fp64", "mixed", "both"],
+                    help="serve: FP64 factors, mixed precision (FP32 updates, FP64 refinement), or both in turn")
     ap.add_argument("--max-n", type=int, default=0, help="serve: keep patterns with n <= max-n")
     args = ap.parse_args()
     global UBLOCK

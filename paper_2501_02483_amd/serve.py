@@ -129,10 +129,15 @@ def summarize(done, flops_of=None):
            "achieved_rps": len(done) / span if span > 0 else float("nan")}
     if flops_of is not None:
         out["tflops"] = sum(flops_of(r) for r in done) / span / 1e12
-    per = {}
+    per, by_op = {}, {}
     for r in done:
         per.setdefault(r.pattern, []).append(r.latency)
+        by_op.setdefault(r.op, []).append(r.latency)
+    out["per_pattern_count"] = {int(k): len(v) for k, v in sorted(per.items())}
     out["per_pattern_p50_ms"] = {int(k): float(np.percentile(v, 50) * 1e3) for k, v in sorted(per.items())}
+    out["per_pattern_p99_ms"] = {int(k): float(np.percentile(v, 99) * 1e3) for k, v in sorted(per.items())}
+    out["per_op_p50_ms"] = {OP_NAMES[k]: float(np.percentile(v, 50) * 1e3) for k, v in sorted(by_op.items())}
+    out["per_op_p99_ms"] = {OP_NAMES[k]: float(np.percentile(v, 99) * 1e3) for k, v in sorted(by_op.items())}
     return out
 
 
@@ -197,12 +202,24 @@ class GpuExecutor:
     Per pattern: a Symbolic object, device row pointers for the value
     generator, and a pool of workspaces (Factor objects) reused across
     requests.  A request draws its values on the device (seeded), then
-    factorizes, and solves one right-hand side or takes the log-determinant."""
+    factorizes, and solves one right-hand side or takes the log-determinant.
 
-    def __init__(self, patterns, tile=64, precision=0, slots=4, nrhs=1, ordering=None, nd_min_rows=512):
+    In mixed precision a solve refines in FP64, and each refinement step
+    reads its residual norms back to the host (a stream synchronization).
+    So that one refining request does not hold up admissions and the other
+    slots, requests are then issued from one host thread per slot (the C
+    calls release the interpreter lock); completion is still observed by the
+    serving loop.  host_threads=None picks threads for mixed precision only."""
+
+    def __init__(self, patterns, tile=64, precision=0, slots=4, nrhs=1, ordering=None, nd_min_rows=512,
+                 host_threads=None, keep_results=True):
         """ordering: None/STILES_ORDER_NONE keeps the natural order; with
         STILES_ORDER_ADAPTABLE_ND, patterns with at least nd_min_rows band
-        tile rows (long pivot chains) are partitioned, the others not."""
+        tile rows (long pivot chains) are partitioned, the others not.
+        keep_results=False frees a request's values and solution on
+        completion (long runs; only info and the log-determinant stay)."""
+        import threading
+        from concurrent.futures import ThreadPoolExecutor
         import torch
         import paper_2501_02483_amd as S
         from paper_2501_02483_amd.devgen import DevicePattern
@@ -228,8 +245,14 @@ class GpuExecutor:
         nmax = max(p.N for p in patterns)
         self.gtmp = [torch.empty(2 * nmax, dtype=torch.float64, device="cuda") for _ in range(slots)]
         self.pool = {i: [] for i in range(len(patterns))}
+        self.pool_lock = threading.Lock()
         self.vals = {}            # slot -> values tensor
         self.events = {}
+        if host_threads is None:
+            host_threads = precision != S.STILES_FP64
+        self.workers = ThreadPoolExecutor(max_workers=slots) if host_threads else None
+        self.futures = {}
+        self.keep_results = keep_results
         self.cap_wg = None
         self.t0 = 0.0
 
@@ -248,12 +271,19 @@ class GpuExecutor:
         return time.perf_counter() - self.t0
 
     def _factor(self, pi, stream):
-        if self.pool[pi]:
-            return self.pool[pi].pop()
+        with self.pool_lock:
+            if self.pool[pi]:
+                return self.pool[pi].pop()
         f = self.S.Factor(self.syms[pi], self.precision, nrhs_max=self.nrhs, stream=stream)
         return f
 
     def launch(self, req, slot):
+        if self.workers is None:
+            self._issue(req, slot)
+        else:
+            self.futures[req.rid] = self.workers.submit(self._issue, req, slot)
+
+    def _issue(self, req, slot):
         torch = self.torch
         st = self.streams[slot]
         with torch.cuda.stream(st):
@@ -274,14 +304,29 @@ class GpuExecutor:
         self.events[req.rid] = ev
 
     def poll(self, req):
+        fut = self.futures.get(req.rid)
+        if fut is not None:
+            if not fut.done():
+                return False
+            del self.futures[req.rid]
+            fut.result()              # re-raises an error of the issuing thread
         ev = self.events.get(req.rid)
         if ev is None or not ev.query():
             return False
         fac = req.result.pop("factor")
         req.result["info"] = fac.info(stream=self.streams[req.slot])
-        self.pool[req.pattern].append(fac)
+        with self.pool_lock:
+            self.pool[req.pattern].append(fac)
         del self.events[req.rid]
+        if not self.keep_results:
+            req.result.pop("values", None)
+            req.result.pop("x", None)
         return True
+
+    def close(self):
+        if self.workers is not None:
+            self.workers.shutdown(wait=True)
+            self.workers = None
 
     def idle(self, next_arrival, busy):
         if busy:

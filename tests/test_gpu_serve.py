@@ -113,7 +113,9 @@ def _mix_then_alone(pats, reqs, slots, precision=0, ordering=None):
 
     budget = 64 << 30
     ex = GpuExecutor(pats, tile=64, slots=slots, precision=precision, ordering=ordering)
+    assert (ex.workers is not None) == (precision != 0)    # mixed: one issuing thread per slot
     done = Server(ex, budget, slots).run(reqs)
+    ex.close()
     torch.cuda.synchronize()
     assert len(done) == len(reqs)
     assert all(r.result["info"] == 0 for r in done)
@@ -127,6 +129,7 @@ def _mix_then_alone(pats, reqs, slots, precision=0, ordering=None):
             assert torch.equal(alone.result["x"], r.result["x"]), "request %d: x differs alone vs mix" % r.rid
         elif r.op == OP_LOGDET:
             assert torch.equal(alone.result["logdet"], r.result["logdet"]), "request %d: logdet differs" % r.rid
+    ex1.close()
     return done
 
 

@@ -71,3 +71,20 @@ def test_open_loop_latency_grows_with_load():
     p_lo = summarize(lo.run(_reqs(slow, pats)))["p99_ms"]
     p_hi = summarize(hi.run(_reqs(fast, pats)))["p99_ms"]
     assert p_hi > p_lo
+
+
+def test_summary_per_pattern_and_per_op_percentiles():
+    ex = FakeExecutor(flops=[1e9, 8e9, 3e10], ws_bytes=[10, 10, 10], rate=1e11, overhead=1e-4)
+    rng = np.random.default_rng(3)
+    arr = np.cumsum(rng.exponential(0.02, size=400))
+    reqs = [Request(rid=i, arrival=a, pattern=int(rng.integers(3)), op=i % 3, seed=i) for i, a in enumerate(arr)]
+    done = Server(ex, 1000, slots=4).run(reqs)
+    s = summarize(done)
+    assert sum(s["per_pattern_count"].values()) == 400
+    for k, p99 in s["per_pattern_p99_ms"].items():
+        lat = sorted(r.latency for r in done if r.pattern == k)
+        assert s["per_pattern_p50_ms"][k] <= p99 <= lat[-1] * 1e3 + 1e-9
+        assert p99 >= lat[int(0.98 * (len(lat) - 1))] * 1e3 - 1e-9
+    # the largest pattern has the slowest tail
+    assert s["per_pattern_p99_ms"][2] == max(s["per_pattern_p99_ms"].values())
+    assert set(s["per_op_p99_ms"]) == {"factorize", "factorize+solve", "factorize+logdet"}
