@@ -63,12 +63,17 @@ typedef int32_t stiles_status;
  * separated by blocks of rows as wide as the local bandwidth; the separators
  * move to the end of the band part and join the arrow, the partitions are
  * factored concurrently, the last one in reverse row order.  It is used only
- * if a feasible cut exists (else the ordering falls back as AUTO).  For row-
- * profile input only NONE, AUTO (= NONE) and ADAPTABLE_ND are supported. */
+ * if a feasible cut exists (else the ordering falls back as AUTO).  AMD
+ * (approximate minimum degree on the band part, the arrow rows staying last;
+ * for irregular patterns) is kept only if L then has fewer tiles than in the
+ * input order; it keeps no band shape, so it is not combined with the
+ * partitions.  For row-profile input only NONE, AUTO (= NONE) and
+ * ADAPTABLE_ND are supported. */
 #define STILES_ORDER_AUTO 0
 #define STILES_ORDER_NONE 1
 #define STILES_ORDER_PARTIAL_RCM 2
 #define STILES_ORDER_ADAPTABLE_ND 3
+#define STILES_ORDER_AMD 4
 
 /* Precisions of the numerical factorization. */
 #define STILES_FP64 0     /* every step in FP64                                     */
@@ -121,8 +126,8 @@ typedef struct stiles_symbolic_info {
   int64_t N, n, arrow;    /* order, band part, arrow width of P A P^T (with adaptable
                              ND the separators count as arrow rows)                  */
   int32_t tile;           /* tile size T                                             */
-  int32_t ordering_used;  /* STILES_ORDER_NONE, _PARTIAL_RCM or _ADAPTABLE_ND (the
-                             last possibly on top of partial RCM)                    */
+  int32_t ordering_used;  /* STILES_ORDER_NONE, _PARTIAL_RCM, _ADAPTABLE_ND (the
+                             last possibly on top of partial RCM) or _AMD            */
   int64_t tile_rows;      /* band tile rows + arrow tile rows                        */
   int64_t band_tile_rows;
   int64_t tiles;          /* stored T x T tiles of the factor                       */
@@ -196,7 +201,7 @@ stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t* colptr, co
  * (the band is already in envelope order, so partial RCM is not tried);
  * ADAPTABLE_ND cuts the band into partitions as described above (the values
  * stay in the input's row-profile order; the permutation is applied on the
- * device).  PARTIAL_RCM is rejected (ENOTSUP, argument 4).
+ * device).  PARTIAL_RCM and AMD are rejected (ENOTSUP, argument 4).
  */
 stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, const int64_t* first_col,
                                      const stiles_opts* opts, stiles_symbolic** out);

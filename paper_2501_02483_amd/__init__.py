@@ -43,6 +43,7 @@ STILES_ORDER_AUTO = 0
 STILES_ORDER_NONE = 1
 STILES_ORDER_PARTIAL_RCM = 2
 STILES_ORDER_ADAPTABLE_ND = 3
+STILES_ORDER_AMD = 4
 STILES_FP64 = 0
 STILES_MIXED32 = 1
 STILES_MIXED32_FULL = 2

@@ -303,6 +303,254 @@ std::vector<int64_t> rcm_order(int64_t n, const std::vector<int64_t>& xadj, cons
   return order;
 }
 
+// Approximate minimum degree (Section III-A names it for irregular patterns;
+// the method is Amestoy, Davis and Duff's).  Elimination runs on a quotient
+// graph: an eliminated pivot becomes an element whose member list stands for
+// the clique its elimination creates, so fill is never formed explicitly.
+// Per principal variable i: its variable neighbours A_i and its elements E_i;
+// per element e: its member variables L_e and their total weight |L_e|.
+// Variables that become indistinguishable (same A and E after a step) are
+// merged into supervariables of weight nv and are ordered together.  A
+// variable's external degree is replaced by the bound
+//   d_i = min(n_left - nv_i, d_i(old) + |L_p \ i|,
+//             |A_i \ i| + |L_p \ i| + sum over e in E_i, e != p, of |L_e \ L_p|)
+// with |L_e \ L_p| from one pass over the members of L_p; an element with
+// |L_e \ L_p| = 0 lies inside L_p and is absorbed.  Pivots are taken by
+// smallest bound, ties by lowest index.  Returns the elimination order of
+// the n band rows (the arrow rows are not part of the graph: they stay last).
+std::vector<int64_t> amd_order(int64_t n, const std::vector<int64_t>& xadj, const std::vector<int64_t>& adj) {
+  enum : char { VAR = 0, MERGED = 1, ELEM = 2, GONE = 3 };
+  std::vector<char> st(n, VAR);
+  std::vector<int64_t> nv(n, 1), deg(n), esize(n, 0), w(n, 0), wmark(n, -1), mark(n, -1);
+  std::vector<std::vector<int64_t>> A(n), E(n), Lm(n), members(n);
+  for (int64_t i = 0; i < n; i++) {
+    for (int64_t q = xadj[i]; q < xadj[i + 1]; q++)
+      if (adj[q] != i) A[i].push_back(adj[q]);
+    std::sort(A[i].begin(), A[i].end());
+    A[i].erase(std::unique(A[i].begin(), A[i].end()), A[i].end());
+    deg[i] = (int64_t)A[i].size();
+  }
+  std::set<std::pair<int64_t, int64_t>> heap;
+  for (int64_t i = 0; i < n; i++) heap.insert({deg[i], i});
+  std::vector<int64_t> order;
+  order.reserve(n);
+  int64_t left = n, stamp = 0;
+  std::vector<int64_t> Lp;
+  while (!heap.empty()) {
+    const int64_t p = heap.begin()->second;
+    heap.erase(heap.begin());
+    // order p's supervariable (p and the variables merged into it)
+    {
+      std::vector<int64_t> stack{p};
+      while (!stack.empty()) {
+        int64_t v = stack.back();
+        stack.pop_back();
+        order.push_back(v);
+        for (int64_t c : members[v]) stack.push_back(c);
+      }
+    }
+    left -= nv[p];
+    // L_p: p's variable neighbours and the members of its elements, which
+    // p absorbs
+    const int64_t sp = ++stamp;
+    mark[p] = sp;
+    Lp.clear();
+    int64_t lp_w = 0;
+    auto add = [&](int64_t j) {
+      if (st[j] == VAR && mark[j] != sp) { mark[j] = sp; Lp.push_back(j); lp_w += nv[j]; }
+    };
+    for (int64_t j : A[p]) add(j);
+    for (int64_t e : E[p]) {
+      if (st[e] != ELEM) continue;
+      for (int64_t j : Lm[e]) add(j);
+      st[e] = GONE;
+      std::vector<int64_t>().swap(Lm[e]);
+    }
+    st[p] = ELEM;
+    std::vector<int64_t>().swap(A[p]);
+    std::vector<int64_t>().swap(E[p]);
+    Lm[p] = Lp;
+    esize[p] = lp_w;
+    // |L_e \ L_p| for every other element next to a member of L_p
+    const int64_t sw = ++stamp;
+    for (int64_t i : Lp)
+      for (int64_t e : E[i]) {
+        if (st[e] != ELEM || e == p) continue;
+        if (wmark[e] != sw) { wmark[e] = sw; w[e] = esize[e]; }
+        w[e] -= nv[i];
+      }
+    // new element and variable lists, degree bounds
+    for (int64_t i : Lp) {
+      heap.erase({deg[i], i});
+      std::vector<int64_t>& Ei = E[i];
+      int64_t ew = 0;
+      size_t k = 0;
+      for (int64_t e : Ei) {
+        if (st[e] != ELEM || e == p) continue;
+        if (wmark[e] == sw && w[e] == 0) { st[e] = GONE; std::vector<int64_t>().swap(Lm[e]); continue; }
+        ew += wmark[e] == sw ? w[e] : esize[e];
+        Ei[k++] = e;
+      }
+      Ei.resize(k);
+      Ei.push_back(p);
+      std::vector<int64_t>& Ai = A[i];
+      int64_t aw = 0;
+      k = 0;
+      for (int64_t j : Ai) {
+        if (st[j] != VAR || mark[j] == sp) continue;   // eliminated, merged, p, or in L_p
+        aw += nv[j];
+        Ai[k++] = j;
+      }
+      Ai.resize(k);
+      const int64_t ext = lp_w - nv[i];
+      int64_t d = aw + ext + ew;
+      d = std::min(d, deg[i] + ext);
+      d = std::min(d, left - nv[i]);
+      deg[i] = std::max<int64_t>(d, 0);
+    }
+    // the elements absorbed above may still be listed by members of L_p
+    // processed before them: drop them
+    for (int64_t i : Lp) {
+      std::vector<int64_t>& Ei = E[i];
+      Ei.erase(std::remove_if(Ei.begin(), Ei.end(), [&](int64_t e) { return st[e] != ELEM; }), Ei.end());
+    }
+    // supervariables: members of L_p with equal A and E lists merge
+    std::vector<std::pair<uint64_t, int64_t>> h;
+    h.reserve(Lp.size());
+    for (int64_t i : Lp) {
+      std::sort(A[i].begin(), A[i].end());
+      std::sort(E[i].begin(), E[i].end());
+      uint64_t x = 1469598103934665603ull;
+      for (int64_t j : A[i]) x = (x ^ (uint64_t)j) * 1099511628211ull;
+      x = (x ^ 0x9e3779b97f4a7c15ull) * 1099511628211ull;
+      for (int64_t e : E[i]) x = (x ^ (uint64_t)e) * 1099511628211ull;
+      h.push_back({x, i});
+    }
+    std::sort(h.begin(), h.end());
+    for (size_t a = 0; a < h.size();) {
+      size_t b = a;
+      while (b < h.size() && h[b].first == h[a].first) b++;
+      for (size_t u = a; u < b; u++) {
+        const int64_t i = h[u].second;
+        if (st[i] != VAR) continue;
+        for (size_t v = u + 1; v < b; v++) {
+          const int64_t j = h[v].second;
+          if (st[j] != VAR || A[i] != A[j] || E[i] != E[j]) continue;
+          nv[i] += nv[j];
+          deg[i] -= nv[j];
+          nv[j] = 0;
+          st[j] = MERGED;
+          members[i].push_back(j);
+          std::vector<int64_t>().swap(A[j]);
+          std::vector<int64_t>().swap(E[j]);
+        }
+      }
+      a = b;
+    }
+    for (int64_t i : Lp)
+      if (st[i] == VAR) {
+        deg[i] = std::max<int64_t>(0, std::min(deg[i], left - nv[i]));
+        heap.insert({deg[i], i});
+      }
+    // L_p keeps its principal variables
+    std::vector<int64_t>& L = Lm[p];
+    L.erase(std::remove_if(L.begin(), L.end(), [&](int64_t j) { return st[j] != VAR; }), L.end());
+  }
+  return order;
+}
+
+// Postorder of the elimination tree of the band graph under `ord` (new
+// position -> node): every subtree becomes a contiguous run of rows, which
+// keeps the fill and the work of the order and groups the rows that couple
+// into the same tiles.  Tree from Liu's row-subtree walk with path
+// compression; children visited in increasing order.
+std::vector<int64_t> etree_postorder(int64_t n, const std::vector<int64_t>& xadj, const std::vector<int64_t>& adj,
+                                     const std::vector<int64_t>& ord) {
+  std::vector<int64_t> pos(n), parent(n, -1), anc(n, -1);
+  for (int64_t i = 0; i < n; i++) pos[ord[i]] = i;
+  for (int64_t i = 0; i < n; i++) {
+    const int64_t v = ord[i];
+    for (int64_t q = xadj[v]; q < xadj[v + 1]; q++) {
+      int64_t r = pos[adj[q]];
+      if (r >= i) continue;
+      while (anc[r] != -1 && anc[r] != i) {
+        const int64_t t = anc[r];
+        anc[r] = i;
+        r = t;
+      }
+      if (anc[r] == -1) { anc[r] = i; parent[r] = i; }
+    }
+  }
+  std::vector<int64_t> head(n, -1), next(n, -1);
+  for (int64_t i = n - 1; i >= 0; i--)
+    if (parent[i] >= 0) { next[i] = head[parent[i]]; head[parent[i]] = i; }
+  std::vector<int64_t> out, stack;
+  out.reserve(n);
+  for (int64_t root = 0; root < n; root++) {
+    if (parent[root] != -1) continue;
+    stack.push_back(root);
+    while (!stack.empty()) {
+      const int64_t v = stack.back();
+      if (head[v] >= 0) {           // descend into the next unvisited child
+        const int64_t c = head[v];
+        head[v] = next[c];
+        stack.push_back(c);
+      } else {
+        out.push_back(ord[v]);
+        stack.pop_back();
+      }
+    }
+  }
+  return out;
+}
+
+// Tile-level symbolic factorization: the tile columns of L from those of A
+// (a_cols[j]: tile rows >= j holding entries of tile column j).  Column j
+// of L is its own pattern merged with those of its children in the tile
+// elimination tree (the parent of j is the first off-diagonal tile row of
+// column j of L).
+std::vector<std::vector<int32_t>> tile_columns(const std::vector<std::vector<int32_t>>& a_cols) {
+  const int32_t ntr = (int32_t)a_cols.size();
+  std::vector<std::vector<int32_t>> lcol(ntr);
+  std::vector<std::vector<int32_t>> children(ntr);
+  for (int32_t j = 0; j < ntr; j++) {
+    std::vector<int32_t> c = a_cols[j];
+    for (int32_t ch : children[j]) {
+      for (int32_t r : lcol[ch]) if (r != ch) c.push_back(r);
+    }
+    std::sort(c.begin(), c.end());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
+    // rows >= j only, diagonal present
+    c.erase(std::remove_if(c.begin(), c.end(), [&](int32_t r) { return r < j; }), c.end());
+    if (c.empty() || c[0] != j) c.insert(c.begin(), j);
+    lcol[j] = c;
+    if (c.size() > 1) children[c[1]].push_back(j);
+  }
+  return lcol;
+}
+
+// Number of tiles of L when the band rows of a CSC pattern are renumbered by
+// inv (old index -> new index; the arrow rows stay last): band tile rows of T
+// rows, then the arrow's.  The fill measure of the ordering check for
+// orderings that do not keep a band shape.
+int64_t l_tiles_for(int64_t N, int64_t n, int32_t T, const int64_t* colptr, const int64_t* rowind,
+                    const std::vector<int64_t>& inv) {
+  const int64_t ntb = (n + T - 1) / T;
+  const int32_t ntr = (int32_t)(ntb + (N - n + T - 1) / T);
+  auto tile = [&](int64_t g) { return (int32_t)(g < n ? g / T : ntb + (g - n) / T); };
+  std::vector<std::vector<int32_t>> a_cols(ntr);
+  for (int32_t m = 0; m < ntr; m++) a_cols[m].push_back(m);
+  for (int64_t j = 0; j < N; j++)
+    for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
+      const int64_t p = inv[rowind[q]], c = inv[j];
+      a_cols[tile(std::min(p, c))].push_back(tile(std::max(p, c)));
+    }
+  for (auto& c : a_cols) { std::sort(c.begin(), c.end()); c.erase(std::unique(c.begin(), c.end()), c.end()); }
+  int64_t tot = 0;
+  for (const auto& c : tile_columns(a_cols)) tot += (int64_t)c.size();
+  return tot;
+}
+
 // number of tiles in the tile envelope of a lower profile f over the band part
 // (the arrow tile rows are dense and identical for every band ordering)
 int64_t envelope_tiles(const std::vector<int64_t>& f, int64_t n, int32_t T) {
@@ -558,7 +806,7 @@ double envelope_flops(const std::vector<int64_t>& f) {
 stiles_status check_opts(const stiles_opts* o, int arg) {
   if (!o) return STILES_OK;
   if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_err_arg = arg; return STILES_ENOTSUP; }
-  if (o->ordering < STILES_ORDER_AUTO || o->ordering > STILES_ORDER_ADAPTABLE_ND) { g_err_arg = arg; return STILES_EINVAL; }
+  if (o->ordering < STILES_ORDER_AUTO || o->ordering > STILES_ORDER_AMD) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->nd_parts < 0 || o->nd_parts > 64) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->chunk < 0 || o->chunk > 32 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->sched_workers < -1 || o->sched_workers > 65536) { g_err_arg = arg; return STILES_EINVAL; }
@@ -672,7 +920,10 @@ extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, c
     if (first_col[i] < 0 || first_col[i] > i) { g_err_arg = 3; return STILES_EINVAL; }
   stiles_status st = check_opts(opts, 4);
   if (st != STILES_OK) return st;
-  if (opts && opts->ordering == STILES_ORDER_PARTIAL_RCM) { g_err_arg = 4; return STILES_ENOTSUP; }
+  if (opts && (opts->ordering == STILES_ORDER_PARTIAL_RCM || opts->ordering == STILES_ORDER_AMD)) {
+    g_err_arg = 4;
+    return STILES_ENOTSUP;
+  }
   if (!out) { g_err_arg = 5; return STILES_EINVAL; }
   const int64_t N = n_band + arrow;
   if ((N + 63) / 16 > INT32_MAX / 4) { g_err_arg = 1; return STILES_ENOTSUP; }
@@ -782,24 +1033,39 @@ extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t*
     for (int64_t j = 0; j < n; j++)
       for (int64_t q = colptr[j] + 1; q < colptr[j + 1]; q++)
         if (rowind[q] < n) { adj[fillp[j]++] = rowind[q]; adj[fillp[rowind[q]]++] = j; }
-    std::vector<int64_t> ord = rcm_order(n, xadj, adj);
-    std::vector<int64_t> inv(N);
-    for (int64_t i = 0; i < n; i++) inv[ord[i]] = i;
-    for (int64_t i = n; i < N; i++) inv[i] = i;
-    std::vector<int64_t> f_r(N);
-    for (int64_t i = 0; i < N; i++) f_r[i] = i;
-    for (int64_t j = 0; j < N; j++)
-      for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
-        int64_t p = inv[rowind[q]], c = inv[j];
-        int64_t hi = std::max(p, c), lo = std::min(p, c);
-        f_r[hi] = std::min(f_r[hi], lo);
+    if (s->opts.ordering == STILES_ORDER_AMD) {
+      // approximate minimum degree, kept only if L has fewer tiles than in
+      // the input order (the fill check); no band shape is kept, so the
+      // partitions of adaptable ND are not offered on top of it
+      std::vector<int64_t> ord = etree_postorder(n, xadj, adj, amd_order(n, xadj, adj));
+      std::vector<int64_t> inv(N), id(N);
+      for (int64_t i = 0; i < n; i++) inv[ord[i]] = i;
+      for (int64_t i = n; i < N; i++) inv[i] = i;
+      std::iota(id.begin(), id.end(), 0);
+      if (l_tiles_for(N, n, s->T, colptr, rowind, inv) < l_tiles_for(N, n, s->T, colptr, rowind, id)) {
+        for (int64_t i = 0; i < n; i++) perm[i] = ord[i];
+        s->ordering_used = STILES_ORDER_AMD;
       }
-    bool use = s->opts.ordering == STILES_ORDER_PARTIAL_RCM;
-    if (s->opts.ordering == STILES_ORDER_AUTO || s->opts.ordering == STILES_ORDER_ADAPTABLE_ND)
-      use = envelope_tiles(f_r, n, s->T) < envelope_tiles(f_id, n, s->T);   // fill check
-    if (use) {
-      for (int64_t i = 0; i < n; i++) perm[i] = ord[i];
-      s->ordering_used = STILES_ORDER_PARTIAL_RCM;
+    } else {
+      std::vector<int64_t> ord = rcm_order(n, xadj, adj);
+      std::vector<int64_t> inv(N);
+      for (int64_t i = 0; i < n; i++) inv[ord[i]] = i;
+      for (int64_t i = n; i < N; i++) inv[i] = i;
+      std::vector<int64_t> f_r(N);
+      for (int64_t i = 0; i < N; i++) f_r[i] = i;
+      for (int64_t j = 0; j < N; j++)
+        for (int64_t q = colptr[j]; q < colptr[j + 1]; q++) {
+          int64_t p = inv[rowind[q]], c = inv[j];
+          int64_t hi = std::max(p, c), lo = std::min(p, c);
+          f_r[hi] = std::min(f_r[hi], lo);
+        }
+      bool use = s->opts.ordering == STILES_ORDER_PARTIAL_RCM;
+      if (s->opts.ordering == STILES_ORDER_AUTO || s->opts.ordering == STILES_ORDER_ADAPTABLE_ND)
+        use = envelope_tiles(f_r, n, s->T) < envelope_tiles(f_id, n, s->T);   // fill check
+      if (use) {
+        for (int64_t i = 0; i < n; i++) perm[i] = ord[i];
+        s->ordering_used = STILES_ORDER_PARTIAL_RCM;
+      }
     }
   }
   if (s->opts.ordering == STILES_ORDER_ADAPTABLE_ND && n > 0) {
@@ -876,21 +1142,7 @@ namespace {
 void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>& a_cols) {
   const int32_t ntr = s.ntr, T = s.T;
   // ---- tile-level symbolic factorization (elimination tree, column merge)
-  std::vector<std::vector<int32_t>> lcol(ntr);
-  std::vector<std::vector<int32_t>> children(ntr);
-  for (int32_t j = 0; j < ntr; j++) {
-    std::vector<int32_t> c = a_cols[j];
-    for (int32_t ch : children[j]) {
-      for (int32_t r : lcol[ch]) if (r != ch) c.push_back(r);
-    }
-    std::sort(c.begin(), c.end());
-    c.erase(std::unique(c.begin(), c.end()), c.end());
-    // rows >= j only, diagonal present
-    c.erase(std::remove_if(c.begin(), c.end(), [&](int32_t r) { return r < j; }), c.end());
-    if (c.empty() || c[0] != j) c.insert(c.begin(), j);
-    lcol[j] = c;
-    if (c.size() > 1) children[c[1]].push_back(j);
-  }
+  const std::vector<std::vector<int32_t>> lcol = tile_columns(a_cols);
   // ---- row lists
   std::vector<int32_t> rcount(ntr, 0);
   for (int32_t j = 0; j < ntr; j++) for (int32_t r : lcol[j]) rcount[r]++;

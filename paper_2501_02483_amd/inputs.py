@@ -237,6 +237,39 @@ def spde_space_time(nx, ny, nt, a, seed, name=""):
                 i = idx[ok]
                 rows.append(i)
                 cols.append(i + dt * nx * ny + dy * nx + dx)
+    return _assemble(n, a, rows, cols, seed, name or "spde%dx%dx%d_a%d" % (nx, ny, nt, a))
+
+
+def irregular_mesh(n, a, seed, k=6, long_edges=0, name=""):
+    """Irregular-pattern input (the case Section III-A names for minimum-degree
+    orderings): n points uniform in the unit square, each joined to its k
+    nearest neighbours (symmetrized), plus `long_edges` couplings between
+    random pairs of points (a poor-quality mesh), numbered in random order
+    (no locality in the numbering), plus `a` dense arrow rows.  Values and
+    return value as for spde_space_time (the row profile only when it is
+    small enough to hold)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    _, nb = cKDTree(pts).query(pts, k=k + 1)
+    num = rng.permutation(n).astype(np.int64)          # node -> row index
+    lu = rng.integers(0, n, size=long_edges)
+    lv = rng.integers(0, n, size=long_edges)
+    keep = lu != lv
+    u = np.concatenate([np.repeat(num, k), num[lu[keep]]])
+    v = np.concatenate([num[nb[:, 1:].reshape(-1)], num[lv[keep]]])
+    hi, lo = np.maximum(u, v), np.minimum(u, v)
+    key = np.unique(hi * n + lo)
+    return _assemble(n, a, [key // n], [key % n], seed + 1, name or "mesh%d_k%d_l%d_a%d" % (n, k, long_edges, a))
+
+
+def _assemble(n, a, rows, cols, seed, name):
+    """Lower CSC + row profile of an SPD matrix with the given strictly lower
+    band entries (rows[i] > cols[i]) and `a` dense arrow rows; off-diagonal
+    values N(0,1) in (row, column) order, diagonal = absolute sum of the full
+    symmetric row + 1."""
+    N = n + a
+    rows, cols = list(rows), list(cols)
     # arrow rows: dense
     ar = np.repeat(np.arange(n, N, dtype=np.int64), np.arange(n, N))
     ac = np.concatenate([np.arange(r, dtype=np.int64) for r in range(n, N)]) if a else np.zeros(0, np.int64)
@@ -260,10 +293,12 @@ def spde_space_time(nx, ny, nt, a, seed, name=""):
     np.cumsum(np.bincount(C, minlength=N), out=colptr[1:])
     f = np.arange(N, dtype=np.int64)
     np.minimum.at(f, R, C)
-    pat = Pattern(n=n, a=a, f=f, name=name or "spde%dx%dx%d_a%d" % (nx, ny, nt, a))
+    pat = Pattern(n=n, a=a, f=f, name=name)
     rp = pat.row_ptr()
-    prof = np.zeros(int(rp[-1]))
-    prof[rp[R] + (C - f[R])] = V
+    prof = None
+    if rp[-1] <= 1 << 28:
+        prof = np.zeros(int(rp[-1]))
+        prof[rp[R] + (C - f[R])] = V
     return {"N": N, "n": n, "a": a, "colptr": colptr, "rowind": R[co].copy(), "values": np.ascontiguousarray(V[co]),
             "pattern": pat, "profile_values": prof}
 

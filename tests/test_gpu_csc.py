@@ -111,3 +111,50 @@ def test_csc_sparse_inside_envelope():
     sym, ld, X = _run(p.N, p.a, colptr, rowind, cvals, B, tile=64, ordering=S.STILES_ORDER_NONE)
     assert rel(X, X_o) <= TOL
     assert abs(ld - ld_o) <= TOL * abs(ld_o)
+
+
+@pytest.mark.parametrize("T", [32, 64])
+def test_csc_amd_order_on_a_poor_mesh(T):
+    """An irregular mesh with long-range couplings, numbered at random: the
+    approximate minimum degree order is kept (fewer tiles than the input
+    order and than partial RCM).  L matches the oracle's factor of P A P^T
+    (per tile column), X and logdet the oracle of the same matrix."""
+    import torch
+    from gpu_util import col_tile_err
+    m = I.irregular_mesh(20000, 50, seed=1, long_edges=100)
+    N, a = m["N"], m["a"]
+    sym = S.Symbolic.from_csc(N, a, m["colptr"], m["rowind"], tile=T, ordering=S.STILES_ORDER_AMD)
+    rcm = S.Symbolic.from_csc(N, a, m["colptr"], m["rowind"], tile=T, ordering=S.STILES_ORDER_PARTIAL_RCM)
+    say("[gpu csc] AMD order, irregular mesh N=%d T=%d: %d tiles (partial RCM %d)" % (
+        N, T, sym.info.tiles, rcm.info.tiles))
+    assert sym.info.ordering_used == S.STILES_ORDER_AMD and sym.info.tiles < rcm.info.tiles
+    perm = np.array(sym.perm())
+    # oracle on the envelope of P A P^T, built from the entries of A
+    iperm = np.empty(N, dtype=np.int64)
+    iperm[perm] = np.arange(N)
+    c = iperm[np.repeat(np.arange(N), np.diff(m["colptr"]))]
+    r = iperm[m["rowind"]]
+    hi, lo = np.maximum(r, c), np.minimum(r, c)
+    f2 = np.arange(N, dtype=np.int64)
+    np.minimum.at(f2, hi, lo)
+    rp = np.concatenate([[0], np.cumsum(np.arange(N) - f2 + 1)])
+    v2 = np.zeros(int(rp[-1]))
+    v2[rp[hi] + (lo - f2[hi])] = m["values"]
+    L_o, info = oracle.factor(f2, v2, nthreads=8)
+    assert info == 0
+    B = I.rhs(N, 3, seed=21)
+    X_o = np.empty_like(B)
+    X_o[perm] = oracle.solve(f2, L_o, B[perm])
+    ld_o = oracle.logdet(f2, L_o)
+    fac = S.Factor(sym, nrhs_max=3)
+    fac.factorize(torch.from_numpy(m["values"]).cuda())
+    assert fac.info() == 0
+    eL = col_tile_err(fac.extract().cpu().numpy(), L_o, f2, T)
+    dB = to_device_cols(B)
+    fac.solve(dB)
+    ld = fac.logdet().item()
+    say("   errors: L per tile column %.2e  X %.2e  logdet %.2e" % (
+        eL, rel(dB.cpu().numpy(), X_o), abs(ld - ld_o) / abs(ld_o)))
+    assert eL <= TOL
+    assert rel(dB.cpu().numpy(), X_o) <= TOL
+    assert abs(ld - ld_o) <= TOL * abs(ld_o)
