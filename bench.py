@@ -33,7 +33,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 UBLOCK = 0           # columns per 2 x 2 block update task (0: library default)
-FUSE_PANEL = 0       # 1: POTRF tasks also form the panel tile below the diagonal; 0: separate TRSM
 FP64_PEAK = 78.6     # TFLOP/s, MI355X dense FP64 (vector = matrix)
 FP32_PEAK = 157.3    # TFLOP/s, MI355X dense FP32 matrix
 HBM_PEAK = 8000.0    # GB/s
@@ -163,7 +162,7 @@ def bench_single(args):
         tuned = tried
     ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
     sym = S.Symbolic.from_pattern(p, tile=args.tile, tree_min_ratio=args.tree_ratio, ordering=ordering,
-                                  ublock=args.ublock, fuse_panel=args.fuse_panel,
+                                  ublock=args.ublock,
                                   nd_parts=args.parts)
     fac = S.Factor(sym, S.STILES_FP64, nrhs_max=nrhs)
     dv = torch.from_numpy(vals).cuda()
@@ -294,7 +293,7 @@ def bench_selinv(args):
     vals = I.make_values(p, seed=seed)
     ordering = {"none": S.STILES_ORDER_NONE, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
     sym = S.Symbolic.from_pattern(p, tile=args.tile, tree_min_ratio=args.tree_ratio, ordering=ordering,
-                                  ublock=args.ublock, fuse_panel=args.fuse_panel,
+                                  ublock=args.ublock,
                                   nd_parts=args.parts)
     fac = S.Factor(sym, S.STILES_FP64)
     fac.factorize(torch.from_numpy(vals).cuda())
@@ -380,7 +379,7 @@ def bench_spde(args):
     g = I.spde_space_time(nx, ny, nt, a, seed=6)
     ordering = {"none": S.STILES_ORDER_AUTO, "nd": S.STILES_ORDER_ADAPTABLE_ND}[args.ordering]
     sym = S.Symbolic.from_csc(g["N"], g["a"], g["colptr"], g["rowind"], tile=args.tile, ordering=ordering,
-                              ublock=args.ublock, fuse_panel=args.fuse_panel,
+                              ublock=args.ublock,
                               nd_parts=args.parts)
     fac = S.Factor(sym, S.STILES_FP64, nrhs_max=8)
     dv = torch.from_numpy(g["values"]).cuda()
@@ -524,8 +523,7 @@ def mixed_runs(n, tile, ordering, parts, steps, law="laplacian"):
     B = torch.randn(nrhs, p.N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(104)).t()
     out = {}
     for prec, name in ((S.STILES_FP64, "fp64"), (S.STILES_MIXED32, "mixed"), (S.STILES_MIXED32_FULL, "mixed_corner_fp32")):
-        sym = S.Symbolic.from_pattern(p, tile=tile or 64, ordering=ordering, nd_parts=parts, ublock=UBLOCK,
-                                      fuse_panel=FUSE_PANEL)
+        sym = S.Symbolic.from_pattern(p, tile=tile or 64, ordering=ordering, nd_parts=parts, ublock=UBLOCK)
         fac = S.Factor(sym, prec, nrhs_max=nrhs)
         fac.factorize(dv)
         torch.cuda.synchronize()
@@ -733,8 +731,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ublock", type=int, default=0,
                     help="columns per 2 x 2 block update task (0: library default, -1: no blocks)")
-    ap.add_argument("--fuse-panel", type=int, default=0, choices=[0, 1],
-                    help="1: the POTRF task also forms the panel tile below the diagonal; 0: a separate TRSM task")
     ap.add_argument("--count", type=int, default=512, help="batch: number of matrices")
     ap.add_argument("--nd-min-rows", type=int, default=0,
                     help="batch: adaptable ND for matrices with at least this many band tile rows (0 = none)")
@@ -753,9 +749,8 @@ def main():
                     help="serve: FP64 factors, mixed precision (FP32 updates, FP64 refinement), or both in turn")
     ap.add_argument("--max-n", type=int, default=0, help="serve: keep patterns with n <= max-n")
     args = ap.parse_args()
-    global UBLOCK, FUSE_PANEL
+    global UBLOCK
     UBLOCK = args.ublock
-    FUSE_PANEL = args.fuse_panel
     if args.tile < 0:
         args.tile = 0 if args.workload == "batch" else 64
     if args.rocpd_summary:

@@ -120,12 +120,6 @@ typedef struct stiles_opts {
                              block task, 1..15; 0 or -1 (default): no blocks, every
                              update is a single-tile chain (measured faster on the
                              default workloads)                                      */
-  int32_t fuse_panel;     /* 1: the POTRF task of tile column k also forms the panel
-                             tile L_(k+1,k) with the inverse it holds (one task less
-                             per step of the pivot chain; the panel's product with
-                             column k-1 becomes an update task of its own); 0
-                             (default): a separate TRSM task, as for the other tiles
-                             of the column (measured faster)                         */
 } stiles_opts;
 
 typedef struct stiles_symbolic_info {
@@ -156,8 +150,6 @@ typedef struct stiles_symbolic_info {
                              (two sweeps, a multiply and an add per entry).  Equals
                              nnz_L when adaptable ND is not used                     */
   int64_t update_blocks;  /* 2 x 2 update blocks of the factorization DAG (ublock)   */
-  int64_t panels_fused;   /* POTRF tasks that also compute the panel tile below the
-                             diagonal (fuse_panel)                                   */
 } stiles_symbolic_info;
 
 typedef struct stiles_solve_report {

@@ -68,8 +68,7 @@ EXPORTED = [
 class stiles_opts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("ordering", ctypes.c_int32), ("tree_min_ratio", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
-                ("nd_parts", ctypes.c_int32), ("sched_workers", ctypes.c_int32), ("ublock", ctypes.c_int32),
-                ("fuse_panel", ctypes.c_int32)]
+                ("nd_parts", ctypes.c_int32), ("sched_workers", ctypes.c_int32), ("ublock", ctypes.c_int32)]
 
 
 class stiles_symbolic_info(ctypes.Structure):
@@ -79,8 +78,7 @@ class stiles_symbolic_info(ctypes.Structure):
                 ("nnz_L", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("flops_exec", ctypes.c_double),
                 ("factor_tasks", ctypes.c_int64), ("solve_tasks", ctypes.c_int64),
                 ("corner_accumulations", ctypes.c_int64), ("tree_used", ctypes.c_int32),
-                ("nd_parts", ctypes.c_int32), ("nnz_L_alg", ctypes.c_int64), ("update_blocks", ctypes.c_int64),
-                ("panels_fused", ctypes.c_int64)]
+                ("nd_parts", ctypes.c_int32), ("nnz_L_alg", ctypes.c_int64), ("update_blocks", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -194,14 +192,13 @@ def _stream(stream=None):
 # ------------------------------------------------------- raw C-ABI wrappers
 
 def stiles_default_opts(tile=64, ordering=STILES_ORDER_AUTO, tree_min_ratio=2, chunk=0, refine_tol=0.0,
-                        refine_max_iter=0, nd_parts=0, sched_workers=0, ublock=0, fuse_panel=0):
+                        refine_max_iter=0, nd_parts=0, sched_workers=0, ublock=0):
     o = stiles_opts()
     load_library().stiles_default_opts(ctypes.byref(o))
     o.tile, o.ordering, o.tree_min_ratio, o.chunk = tile, ordering, tree_min_ratio, chunk
     o.refine_tol, o.refine_max_iter, o.nd_parts = refine_tol, refine_max_iter, nd_parts
     o.sched_workers = sched_workers
     o.ublock = ublock
-    o.fuse_panel = fuse_panel
     return o
 
 

@@ -26,14 +26,6 @@ struct TaskBuilder {
   std::vector<std::vector<int32_t>> preds;
   std::vector<float> cost;
   std::vector<int32_t> late;   // the one predecessor waited for last (two-stage wait), or -1
-  // three-stage tasks (a POTRF that also computes the panel tile below it):
-  // the predecessors waited for after the late one, and those waited for
-  // first (a predecessor in both lists is waited for first)
-  std::vector<std::vector<int32_t>> stage3, stage1;
-  // edges (TF_PANEL task, successor that reads its panel tile): notified
-  // after the panel is formed; the task's other successors need only L_kk
-  // and its inverse and are notified as soon as those are stored
-  std::set<std::pair<int32_t, int32_t>> after_panel;
 
   int add(int32_t type_flags, int32_t tile, int32_t a, int32_t b, int32_t c, float cst) {
     int id = (int)cost.size();
@@ -42,8 +34,6 @@ struct TaskBuilder {
     preds.emplace_back();
     cost.push_back(cst);
     late.push_back(-1);
-    stage3.emplace_back();
-    stage1.emplace_back();
     return id;
   }
   // two-stage wait: every other predecessor is waited for first
@@ -54,31 +44,7 @@ struct TaskBuilder {
     words[(size_t)task * TASK_WORDS] |= TF_SPLIT;
   }
   void dep(int task, int pred) {
-    if (pred >= 0 && pred != task) {
-      preds[task].push_back(pred);
-      stage1[task].push_back(pred);
-    }
-  }
-  // a predecessor of a TF_PANEL task waited for last
-  void dep3(int task, int pred) {
-    if (pred >= 0 && pred != task) {
-      preds[task].push_back(pred);
-      stage3[task].push_back(pred);
-    }
-  }
-  bool panel(int task) const { return (words[(size_t)task * TASK_WORDS] & TF_PANEL) != 0; }
-  // counter decrement flag of the edge pred -> task: early predecessors of
-  // a split task weigh MERGED_FDEP; the late one weighs 1, or SUCC_MID's
-  // weight in a three-stage task, whose last-stage predecessors weigh 1
-  int32_t edge_flag(int pred, int task) const {
-    if (panel(task)) {
-      if (pred == late[task]) return SUCC_MID;
-      const auto& e = stage1[task];
-      if (std::find(e.begin(), e.end(), pred) != e.end()) return SUCC_FDEP;
-      const auto& s3 = stage3[task];
-      return std::find(s3.begin(), s3.end(), pred) != s3.end() ? 0 : SUCC_FDEP;
-    }
-    return late[task] >= 0 && late[task] != pred ? SUCC_FDEP : 0;
+    if (pred >= 0 && pred != task) preds[task].push_back(pred);
   }
 };
 
@@ -203,34 +169,11 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
     // an edge into a two-stage task from one of its early predecessors
     // carries SUCC_FDEP (it subtracts MERGED_FDEP from the counter)
     std::vector<std::pair<int32_t, int32_t>> s;
-    int32_t nearly = 0;
-    if (tb.panel(t)) {
-      // the successors notified early first (their count replaces the pair
-      // range end, which the pair list's header word implies)
-      std::vector<std::pair<int32_t, int32_t>> late_s;
-      for (int x : succ[t]) (tb.after_panel.count({t, x}) ? late_s : s).push_back({newid[x], tb.edge_flag(t, x)});
-      std::sort(s.begin(), s.end());
-      std::sort(late_s.begin(), late_s.end());
-      nearly = (int32_t)s.size();
-      s.insert(s.end(), late_s.begin(), late_s.end());
-      w[4] = nearly;
-    } else {
-      for (int x : succ[t]) s.push_back({newid[x], tb.edge_flag(t, x)});
-      std::sort(s.begin(), s.end());
-    }
+    for (int x : succ[t]) s.push_back({newid[x], tb.late[x] >= 0 && tb.late[x] != t ? SUCC_FDEP : 0});
+    std::sort(s.begin(), s.end());
     for (auto& e : s) succ_out.push_back(e.first | e.second);
     w[6] = (int32_t)succ_out.size();
-    if (tb.panel(t)) {
-      int32_t early = 0, last = 0, mid = 0;
-      for (int p : tb.preds[t]) {
-        const int32_t f = tb.edge_flag(p, t);
-        if (f == SUCC_FDEP) early++;
-        else if (f == SUCC_MID) mid++;
-        else last++;
-      }
-      if (early >= (1 << 14) || last >= MID_WEIGHT) { fprintf(stderr, "stiles: too many predecessors\n"); abort(); }
-      w[7] = early * MERGED_FDEP + mid * MID_WEIGHT + last;
-    } else if (tb.late[t] >= 0) {
+    if (tb.late[t] >= 0) {
       const int32_t early = (int32_t)tb.preds[t].size() - 1;
       if (early >= (1 << 14)) { fprintf(stderr, "stiles: too many predecessors\n"); abort(); }
       w[7] = early * MERGED_FDEP + 1;
@@ -244,7 +187,7 @@ void schedule(TaskBuilder& tb, std::vector<int32_t>& tasks_out, std::vector<int3
   for (int i = 0; i < nt; i++) {
     const int32_t* w = &tasks_out[(size_t)i * TASK_WORDS];
     for (int q = w[5]; q < w[6]; q++)
-      if ((succ_out[q] & ~SUCC_FLAGS) <= i) { fprintf(stderr, "stiles: schedule is not topological\n"); abort(); }
+      if ((succ_out[q] & ~SUCC_FDEP) <= i) { fprintf(stderr, "stiles: schedule is not topological\n"); abort(); }
   }
 }
 
@@ -276,38 +219,6 @@ int32_t tile_lookup(const stiles_symbolic& s, int64_t m, int64_t j) {
   const int32_t* p = std::lower_bound(b, e, (int32_t)j);
   if (p == e || *p != j) return -1;
   return (int32_t)(p - s.tcol.data());
-}
-
-// Whether a factorization task reads factor tile `tile` as an operand of its
-// tile products (its pair list; TREE tasks read partial slots only).
-bool task_reads_tile(const int32_t* w, const std::vector<int32_t>& pairs, int32_t tile) {
-  const int type = w[0] & 0xff;
-  int32_t p0 = 0, p1 = 0;
-  if (type == TK_UPD || type == TK_PART) {
-    p0 = w[2];
-    p1 = w[3];
-  } else if (type == TK_TRSM) {
-    p0 = w[3];
-    p1 = w[4];
-  } else if (type == TK_POTRF) {
-    p0 = w[3];
-    p1 = w[4];
-    if (w[0] & TF_PANEL) {
-      p1 = p0 + 1 + pairs[2 * (size_t)p0 + 1];
-      p0 += 1;
-    }
-  } else if (type == TK_UPDB) {
-    // the four target words, then four operand words per column
-    const size_t b = 2 * (size_t)w[2];
-    for (size_t q = 4; q < 4 + 4 * (size_t)w[3]; q++)
-      if (pairs[b + q] == tile) return true;
-    return false;
-  } else {
-    return false;
-  }
-  for (int32_t q = p0; q < p1; q++)
-    if (pairs[2 * (size_t)q] == tile || pairs[2 * (size_t)q + 1] == tile) return true;
-  return false;
 }
 
 // Reverse Cuthill-McKee on the band part (rows [0, n)) of a symmetric pattern
@@ -900,7 +811,6 @@ stiles_status check_opts(const stiles_opts* o, int arg) {
   if (o->chunk < 0 || o->chunk > 32 || o->refine_max_iter < 0 || o->refine_tol < 0) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->sched_workers < -1 || o->sched_workers > 65536) { g_err_arg = arg; return STILES_EINVAL; }
   if (o->ublock < -1 || o->ublock > 15) { g_err_arg = arg; return STILES_EINVAL; }
-  if (o->fuse_panel < 0 || o->fuse_panel > 1) { g_err_arg = arg; return STILES_EINVAL; }
   return STILES_OK;
 }
 
@@ -1384,11 +1294,8 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
   };
   std::vector<std::pair<int32_t, int32_t>> pr;  // (tile m j, tile k j) ascending j
   std::vector<int32_t> pj;
-  const bool fuse_panel = s.opts.fuse_panel > 0;
-  s.panels_fused = 0;
   for (int32_t k = 0; k < ntr; k++) {
     int32_t potrf_task = -1;
-    bool panel_fused = false;
     if (!col_blocks[k].empty()) {
       // the block tasks: chunks of the block's columns, oldest first; the two
       // most recent chunks (their columns are final last, close to the pivot
@@ -1499,274 +1406,203 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
         }
         continue;
       }
-      // the update chain of target (m, k) (pairs (m,j),(k,j), j < k, both
-      // present): corner trees and update chunks; the product with column
-      // k-1, when there is one, is left to the task that finalizes the tile
-      struct Chain {
-        int32_t last;
-        bool fuse_last;
-        std::pair<int32_t, int32_t> fpair;
-      };
-      // own_last = false: the product with column k-1 becomes an update
-      // task of its own, after the others (a panel finalized by its POTRF)
-      auto build_chain = [&](int32_t m, int32_t tgt, bool own_last) -> Chain {
-        products(m, k, pr, pj);
-        const bool diag = (m == k);
-        int32_t last = -1;
-        size_t start = 0;
-        const bool corner = (m >= s.ntb && k >= s.ntb);
-        // a tile of the arrow corner proper (the arrow's own tile rows, after
-        // the separators that adaptable ND adds to the corner): its partial
-        // products stay FP64 in mixed mode
-        const int32_t arrow0 = ntr - (int32_t)((s.a_in + T - 1) / T);
-        const int32_t arrow_flag = (m >= arrow0 && k >= arrow0) ? TF_ARROW : 0;
-        if (corner) {
-          size_t nb = 0;
-          while (nb < pr.size() && pj[nb] < s.ntb) nb++;
-          s.corner_acc = std::max<int64_t>(s.corner_acc, (int64_t)nb);
-          const int64_t G = ((int64_t)nb + chunk - 1) / chunk;
-          // under adaptable ND the band products of a corner tile come from
-          // several partitions, which progress concurrently: one chain of
-          // partial products per partition (each chunk as soon as its columns
-          // are final), then a binary tree over the partitions' partials.  A
-          // tile fed by a single partition is updated by a plain chain.
-          std::vector<std::pair<size_t, size_t>> groups;
-          if (s.nd_parts > 1 && !s.band_part.empty())
-            for (size_t q = 0; q < nb;) {
-              size_t e = q;
-              while (e < nb && s.band_part[pj[e]] == s.band_part[pj[q]]) e++;
-              groups.push_back({q, e});
-              q = e;
-            }
-          if (s.nd_parts > 1 && groups.size() >= 2 && s.opts.tree_min_ratio > 0) {
-            s.tree_used = 1;
-            std::vector<std::pair<int32_t, int32_t>> level;   // (slot, last task of its chain)
-            for (auto& gr : groups) {
-              const int32_t slot = s.npart++;
-              int prev = -1;
-              for (size_t lo = gr.first; lo < gr.second; lo += chunk) {
-                size_t hi = std::min(gr.second, lo + chunk);
-                int32_t p0 = (int32_t)(pairs.size() / 2);
-                for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
-                int32_t p1 = (int32_t)(pairs.size() / 2);
-                int t = tb.add(TK_PART | (prev >= 0 ? TF_ACC : 0) | arrow_flag, -1, p0, p1, slot,
-                               0.5f + 1.8f * (float)(t3 * (hi - lo)));
-                fexec += 2.0 * T3 * (hi - lo);
-                for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
-                tb.dep(t, prev);
-                prev = t;
-              }
-              level.push_back({slot, prev});
-            }
-            while (level.size() > 2) {
-              std::vector<std::pair<int32_t, int32_t>> next;
-              for (size_t q = 0; q + 1 < level.size(); q += 2) {
-                int32_t slot = s.npart++;
-                int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
-                tb.dep(t, level[q].second);
-                tb.dep(t, level[q + 1].second);
-                next.push_back({slot, t});
-              }
-              if (level.size() % 2) next.push_back(level.back());
-              level.swap(next);
-            }
-            int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
-            tb.dep(t, level[0].second);
-            tb.dep(t, level[1].second);
-            last = t;
-            start = nb;
-          } else if (s.nd_parts > 1) {
-            // one partition (or none): the plain chain below
-          } else if (s.opts.tree_min_ratio > 0 && G >= 2 && (int64_t)nb >= (int64_t)s.opts.tree_min_ratio * G) {
-            s.tree_used = 1;
-            // leaves: PART tasks over contiguous ranges of band columns (Alg. 3)
-            std::vector<std::pair<int32_t, int32_t>> level;   // (slot, producing task)
-            for (int64_t g = 0; g < G; g++) {
-              size_t lo = (size_t)(g * chunk), hi = std::min(nb, (size_t)((g + 1) * chunk));
-              int32_t p0 = (int32_t)(pairs.size() / 2);
-              for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
-              int32_t p1 = (int32_t)(pairs.size() / 2);
-              int32_t slot = s.npart++;
-              int t = tb.add(TK_PART | arrow_flag, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
-              fexec += 2.0 * T3 * (hi - lo);
-              for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
-              level.push_back({slot, t});
-            }
-            // binary GEADD tree in index order; the root subtracts into the target
-            while (level.size() > 2) {
-              std::vector<std::pair<int32_t, int32_t>> next;
-              for (size_t q = 0; q + 1 < level.size(); q += 2) {
-                int32_t slot = s.npart++;
-                int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
-                tb.dep(t, level[q].second);
-                tb.dep(t, level[q + 1].second);
-                next.push_back({slot, t});
-              }
-              if (level.size() % 2) next.push_back(level.back());
-              level.swap(next);
-            }
-            int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
-            tb.dep(t, level[0].second);
-            tb.dep(t, level[1].second);
-            last = t;
-            start = nb;
-          }
-        }
-        // corner tiles: the products over arrow and separator columns become
-        // available only as the separators are factored, and an arrow row
-        // meets every separator.  When there are many, they are independent
-        // partial products (each as soon as its columns are final) summed by a
-        // binary tree in index order, instead of a sequential chain of updates
-        if (corner && s.opts.tree_min_ratio > 0) {
-          const bool fl = pr.size() > start && pj.back() == k - 1;
-          // the last `chunk` products (the most recent columns, on the pivot
-          // chain) stay in an update task after the tree
-          const size_t be = (fl ? pr.size() - 1 : pr.size()) - std::min(pr.size() - (fl ? 1 : 0), (size_t)chunk);
-          if (be > start && be - start > (size_t)(2 * chunk)) {
-            s.tree_used = 1;
-            std::vector<std::pair<int32_t, int32_t>> level;   // (slot, producing task)
-            for (size_t lo = start; lo < be; lo += chunk) {
-              const size_t hi = std::min(be, lo + chunk);
-              int32_t p0 = (int32_t)(pairs.size() / 2);
-              for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
-              int32_t p1 = (int32_t)(pairs.size() / 2);
-              const int32_t slot = s.npart++;
-              int t = tb.add(TK_PART | arrow_flag, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
-              fexec += 2.0 * T3 * (hi - lo);
-              for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
-              level.push_back({slot, t});
-            }
-            while (level.size() > 2) {
-              std::vector<std::pair<int32_t, int32_t>> next;
-              for (size_t q = 0; q + 1 < level.size(); q += 2) {
-                int32_t slot = s.npart++;
-                int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
-                tb.dep(t, level[q].second);
-                tb.dep(t, level[q + 1].second);
-                next.push_back({slot, t});
-              }
-              if (level.size() % 2) next.push_back(level.back());
-              level.swap(next);
-            }
-            // be - start > 2 chunk gives at least three leaves, so two partials remain
-            int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
-            tb.dep(t, level[0].second);
-            tb.dep(t, level[1].second);
-            tb.dep(t, last);   // after the band tree's subtraction from the same tile
-            last = t;
-            start = be;
-          }
-        }
-        // chunks of `chunk` products in ascending column order; the product
-        // with column k-1 (available last, on the critical path) is fused into
-        // the task that finalizes the tile (POTRF or TRSM), so that everything
-        // before it runs ahead (lookahead) and the chain has one hop less
-        const bool fuse_last = pr.size() > start && pj.back() == k - 1;
-        const size_t body_end = fuse_last ? pr.size() - 1 : pr.size();
-        for (size_t lo = start; lo < body_end; lo += chunk) {
-          size_t hi = std::min(body_end, lo + chunk);
-          int32_t p0 = (int32_t)(pairs.size() / 2);
-          for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
-          int32_t p1 = (int32_t)(pairs.size() / 2);
-          float c = 0.5f + (diag ? 1.35f : 1.8f) * (float)(t3 * (hi - lo));
-          int t = tb.add(TK_UPD | (diag ? TF_DIAG : 0), tgt, p0, p1, 0, c);
-          fexec += (diag ? 1.5 : 2.0) * T3 * (hi - lo);
-          for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
-          tb.dep(t, last);
-          last = t;
-        }
-        if (fuse_last && !own_last) {
-          const int32_t p0 = (int32_t)(pairs.size() / 2);
-          pairs.push_back(pr.back().first);
-          pairs.push_back(pr.back().second);
-          int t = tb.add(TK_UPD | TF_CHAIN | (diag ? TF_DIAG : 0), tgt, p0, p0 + 1, 0,
-                         0.5f + (diag ? 1.35f : 1.8f) * (float)t3);
-          fexec += (diag ? 1.5 : 2.0) * T3;
-          tb.dep(t, final_task[pr.back().first]);
-          tb.dep(t, final_task[pr.back().second]);
-          tb.dep(t, last);
-          return Chain{t, false, {-1, -1}};
-        }
-        return Chain{last, fuse_last, fuse_last ? pr.back() : std::pair<int32_t, int32_t>{-1, -1}};
-      };
-      // the panel tile (k+1,k) of a diagonal tile is finalized by its POTRF
-      // (TF_PANEL): it already holds Linv_kk, and the pivot chain loses the
-      // hop to a separate TRSM
-      if (m == k + 1 && panel_fused) continue;
+      // pairs (m,j),(k,j), j < k, both present
+      products(m, k, pr, pj);
       const bool diag = (m == k);
-      const Chain ch = build_chain(m, tgt, true);
-      const int32_t last = ch.last;
-      const bool fuse_last = ch.fuse_last;
+      int32_t last = -1;
+      size_t start = 0;
+      const bool corner = (m >= s.ntb && k >= s.ntb);
+      // a tile of the arrow corner proper (the arrow's own tile rows, after
+      // the separators that adaptable ND adds to the corner): its partial
+      // products stay FP64 in mixed mode
+      const int32_t arrow0 = ntr - (int32_t)((s.a_in + T - 1) / T);
+      const int32_t arrow_flag = (m >= arrow0 && k >= arrow0) ? TF_ARROW : 0;
+      if (corner) {
+        size_t nb = 0;
+        while (nb < pr.size() && pj[nb] < s.ntb) nb++;
+        s.corner_acc = std::max<int64_t>(s.corner_acc, (int64_t)nb);
+        const int64_t G = ((int64_t)nb + chunk - 1) / chunk;
+        // under adaptable ND the band products of a corner tile come from
+        // several partitions, which progress concurrently: one chain of
+        // partial products per partition (each chunk as soon as its columns
+        // are final), then a binary tree over the partitions' partials.  A
+        // tile fed by a single partition is updated by a plain chain.
+        std::vector<std::pair<size_t, size_t>> groups;
+        if (s.nd_parts > 1 && !s.band_part.empty())
+          for (size_t q = 0; q < nb;) {
+            size_t e = q;
+            while (e < nb && s.band_part[pj[e]] == s.band_part[pj[q]]) e++;
+            groups.push_back({q, e});
+            q = e;
+          }
+        if (s.nd_parts > 1 && groups.size() >= 2 && s.opts.tree_min_ratio > 0) {
+          s.tree_used = 1;
+          std::vector<std::pair<int32_t, int32_t>> level;   // (slot, last task of its chain)
+          for (auto& gr : groups) {
+            const int32_t slot = s.npart++;
+            int prev = -1;
+            for (size_t lo = gr.first; lo < gr.second; lo += chunk) {
+              size_t hi = std::min(gr.second, lo + chunk);
+              int32_t p0 = (int32_t)(pairs.size() / 2);
+              for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+              int32_t p1 = (int32_t)(pairs.size() / 2);
+              int t = tb.add(TK_PART | (prev >= 0 ? TF_ACC : 0) | arrow_flag, -1, p0, p1, slot,
+                             0.5f + 1.8f * (float)(t3 * (hi - lo)));
+              fexec += 2.0 * T3 * (hi - lo);
+              for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+              tb.dep(t, prev);
+              prev = t;
+            }
+            level.push_back({slot, prev});
+          }
+          while (level.size() > 2) {
+            std::vector<std::pair<int32_t, int32_t>> next;
+            for (size_t q = 0; q + 1 < level.size(); q += 2) {
+              int32_t slot = s.npart++;
+              int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
+              tb.dep(t, level[q].second);
+              tb.dep(t, level[q + 1].second);
+              next.push_back({slot, t});
+            }
+            if (level.size() % 2) next.push_back(level.back());
+            level.swap(next);
+          }
+          int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
+          tb.dep(t, level[0].second);
+          tb.dep(t, level[1].second);
+          last = t;
+          start = nb;
+        } else if (s.nd_parts > 1) {
+          // one partition (or none): the plain chain below
+        } else if (s.opts.tree_min_ratio > 0 && G >= 2 && (int64_t)nb >= (int64_t)s.opts.tree_min_ratio * G) {
+          s.tree_used = 1;
+          // leaves: PART tasks over contiguous ranges of band columns (Alg. 3)
+          std::vector<std::pair<int32_t, int32_t>> level;   // (slot, producing task)
+          for (int64_t g = 0; g < G; g++) {
+            size_t lo = (size_t)(g * chunk), hi = std::min(nb, (size_t)((g + 1) * chunk));
+            int32_t p0 = (int32_t)(pairs.size() / 2);
+            for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+            int32_t p1 = (int32_t)(pairs.size() / 2);
+            int32_t slot = s.npart++;
+            int t = tb.add(TK_PART | arrow_flag, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+            fexec += 2.0 * T3 * (hi - lo);
+            for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+            level.push_back({slot, t});
+          }
+          // binary GEADD tree in index order; the root subtracts into the target
+          while (level.size() > 2) {
+            std::vector<std::pair<int32_t, int32_t>> next;
+            for (size_t q = 0; q + 1 < level.size(); q += 2) {
+              int32_t slot = s.npart++;
+              int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
+              tb.dep(t, level[q].second);
+              tb.dep(t, level[q + 1].second);
+              next.push_back({slot, t});
+            }
+            if (level.size() % 2) next.push_back(level.back());
+            level.swap(next);
+          }
+          int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
+          tb.dep(t, level[0].second);
+          tb.dep(t, level[1].second);
+          last = t;
+          start = nb;
+        }
+      }
+      // corner tiles: the products over arrow and separator columns become
+      // available only as the separators are factored, and an arrow row
+      // meets every separator.  When there are many, they are independent
+      // partial products (each as soon as its columns are final) summed by a
+      // binary tree in index order, instead of a sequential chain of updates
+      if (corner && s.opts.tree_min_ratio > 0) {
+        const bool fl = pr.size() > start && pj.back() == k - 1;
+        // the last `chunk` products (the most recent columns, on the pivot
+        // chain) stay in an update task after the tree
+        const size_t be = (fl ? pr.size() - 1 : pr.size()) - std::min(pr.size() - (fl ? 1 : 0), (size_t)chunk);
+        if (be > start && be - start > (size_t)(2 * chunk)) {
+          s.tree_used = 1;
+          std::vector<std::pair<int32_t, int32_t>> level;   // (slot, producing task)
+          for (size_t lo = start; lo < be; lo += chunk) {
+            const size_t hi = std::min(be, lo + chunk);
+            int32_t p0 = (int32_t)(pairs.size() / 2);
+            for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+            int32_t p1 = (int32_t)(pairs.size() / 2);
+            const int32_t slot = s.npart++;
+            int t = tb.add(TK_PART | arrow_flag, -1, p0, p1, slot, 0.5f + 1.8f * (float)(t3 * (hi - lo)));
+            fexec += 2.0 * T3 * (hi - lo);
+            for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+            level.push_back({slot, t});
+          }
+          while (level.size() > 2) {
+            std::vector<std::pair<int32_t, int32_t>> next;
+            for (size_t q = 0; q + 1 < level.size(); q += 2) {
+              int32_t slot = s.npart++;
+              int t = tb.add(TK_TREE, -1, level[q].first, level[q + 1].first, slot, 0.5f);
+              tb.dep(t, level[q].second);
+              tb.dep(t, level[q + 1].second);
+              next.push_back({slot, t});
+            }
+            if (level.size() % 2) next.push_back(level.back());
+            level.swap(next);
+          }
+          // be - start > 2 chunk gives at least three leaves, so two partials remain
+          int t = tb.add(TK_TREE | (diag ? TF_DIAG : 0), tgt, level[0].first, level[1].first, -1, 0.5f);
+          tb.dep(t, level[0].second);
+          tb.dep(t, level[1].second);
+          tb.dep(t, last);   // after the band tree's subtraction from the same tile
+          last = t;
+          start = be;
+        }
+      }
+      // chunks of `chunk` products in ascending column order; the product
+      // with column k-1 (available last, on the critical path) is fused into
+      // the task that finalizes the tile (POTRF or TRSM), so that everything
+      // before it runs ahead (lookahead) and the chain has one hop less
+      const bool fuse_last = pr.size() > start && pj.back() == k - 1;
+      const size_t body_end = fuse_last ? pr.size() - 1 : pr.size();
+      for (size_t lo = start; lo < body_end; lo += chunk) {
+        size_t hi = std::min(body_end, lo + chunk);
+        int32_t p0 = (int32_t)(pairs.size() / 2);
+        for (size_t q = lo; q < hi; q++) { pairs.push_back(pr[q].first); pairs.push_back(pr[q].second); }
+        int32_t p1 = (int32_t)(pairs.size() / 2);
+        float c = 0.5f + (diag ? 1.35f : 1.8f) * (float)(t3 * (hi - lo));
+        int t = tb.add(TK_UPD | (diag ? TF_DIAG : 0), tgt, p0, p1, 0, c);
+        fexec += (diag ? 1.5 : 2.0) * T3 * (hi - lo);
+        for (size_t q = lo; q < hi; q++) { tb.dep(t, final_task[pr[q].first]); tb.dep(t, final_task[pr[q].second]); }
+        tb.dep(t, last);
+        last = t;
+      }
+      int32_t f0 = (int32_t)(pairs.size() / 2), f1 = f0;
+      if (fuse_last) {
+        pairs.push_back(pr.back().first);
+        pairs.push_back(pr.back().second);
+        f1 = f0 + 1;
+        fexec += 2.0 * T3;
+      }
       if (diag) {
-        // the panel below, when it is fused: its own update chain first
-        const int32_t ptgt = fuse_panel && k + 1 < ntr ? tile_lookup(s, k + 1, k) : -1;
-        const bool pf = ptgt >= 0 && tblock[ptgt] < 0;
-        Chain pc{-1, false, {-1, -1}};
-        if (pf) pc = build_chain(k + 1, ptgt, false);
-        int32_t f0 = (int32_t)(pairs.size() / 2), f1 = f0;
-        if (pf) {
-          pairs.push_back(ptgt);
-          pairs.push_back(fuse_last ? 1 : 0);
-          f1++;
-        }
-        if (fuse_last) {
-          pairs.push_back(ch.fpair.first);
-          pairs.push_back(ch.fpair.second);
-          f1++;
-          fexec += 2.0 * T3;
-        }
-        float cost = (T == 64 ? 10.f : 4.f) + (fuse_last ? 1.5f * (float)t3 : 0.f);
-        if (pf) cost += 0.5f + 1.8f * (float)t3;
-        int t = tb.add(TK_POTRF | (pf ? TF_PANEL : 0), tgt, k, f0, f1, cost);
-        fexec += 2.0 * T3 / 3.0 + (pf ? 2.0 * T3 : 0.0);
+        int t = tb.add(TK_POTRF, tgt, k, f0, f1, (T == 64 ? 10.f : 4.f) + (f1 > f0 ? 1.5f * (float)t3 : 0.f));
+        fexec += 2.0 * T3 / 3.0;
         tb.dep(t, last);
         if (fuse_last) {
-          tb.dep(t, final_task[ch.fpair.first]);
-          tb.dep(t, final_task[ch.fpair.second]);
-          tb.set_late(t, final_task[ch.fpair.first]);   // the panel of column k-1
+          tb.dep(t, final_task[pr.back().first]);
+          tb.dep(t, final_task[pr.back().second]);
+          tb.set_late(t, final_task[pr.back().first]);   // the panel of column k-1
         }
-        if (pf) {
-          // the panel's update chain (every product of the panel, the one
-          // with column k-1 last): waited for after L_kk is factored
-          tb.dep3(t, pc.last);
-          final_task[ptgt] = t;
-          s.panels_fused++;
-        }
-        panel_fused = pf;
         potrf_task = t;
         final_task[tgt] = t;
       } else {
         // the diagonal tile (k,k) comes first in the column list
-        int32_t f0 = (int32_t)(pairs.size() / 2), f1 = f0;
-        if (fuse_last) {
-          pairs.push_back(ch.fpair.first);
-          pairs.push_back(ch.fpair.second);
-          f1 = f0 + 1;
-          fexec += 2.0 * T3;
-        }
         int t = tb.add(TK_TRSM, tgt, k, f0, f1, 0.5f + 1.8f * (float)t3 * (f1 > f0 ? 2.f : 1.f));
         fexec += 2.0 * T3;
         tb.set_late(t, potrf_task);
         tb.dep(t, last);
-        if (fuse_last) { tb.dep(t, final_task[ch.fpair.first]); tb.dep(t, final_task[ch.fpair.second]); }
+        if (fuse_last) { tb.dep(t, final_task[pr.back().first]); tb.dep(t, final_task[pr.back().second]); }
         final_task[tgt] = t;
       }
     }
   }
   s.flops_exec = fexec;
   s.fpairs = pairs;
-  // successors of a POTRF with TF_PANEL that read its panel tile
-  {
-    std::vector<std::vector<int32_t>> succ_of(tb.cost.size());
-    for (size_t x = 0; x < tb.preds.size(); x++)
-      for (int32_t p : tb.preds[x]) succ_of[p].push_back((int32_t)x);
-    for (size_t t = 0; t < tb.cost.size(); t++) {
-      if (!tb.panel((int)t)) continue;
-      const int32_t ptile = pairs[2 * (size_t)tb.words[t * TASK_WORDS + 3]];
-      for (int32_t x : succ_of[t])
-        if (task_reads_tile(&tb.words[(size_t)x * TASK_WORDS], pairs, ptile)) tb.after_panel.insert({(int32_t)t, x});
-    }
-  }
   schedule(tb, s.ftask, s.fsucc, &s.fest, &s.fcost, sched_workers(s.opts));
 
   // ---- solve DAG (forward then backward sweep over tile rows)
@@ -2043,20 +1879,14 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
   const int32_t nfp = (int32_t)(s.fpairs.size() / 2);
   const int32_t n = nf + ns;
   std::vector<std::vector<int32_t>> pred(n);
-  // factorization edges that subtract MERGED_FDEP or MID_WEIGHT (two- and
-  // three-stage waits)
-  std::set<std::pair<int32_t, int32_t>> fheavy, fmid, fafter;
-  for (int32_t t = 0; t < nf; t++) {
-    const int32_t* w = &s.ftask[(size_t)t * TASK_WORDS];
-    for (int32_t q = w[5]; q < w[6]; q++) {
-      const int32_t x = s.fsucc[q] & ~SUCC_FLAGS;
+  // factorization edges that subtract MERGED_FDEP (two-stage waits)
+  std::set<std::pair<int32_t, int32_t>> fheavy;
+  for (int32_t t = 0; t < nf; t++)
+    for (int32_t q = s.ftask[(size_t)t * TASK_WORDS + 5]; q < s.ftask[(size_t)t * TASK_WORDS + 6]; q++) {
+      const int32_t x = s.fsucc[q] & ~SUCC_FDEP;
       pred[x].push_back(t);
       if (s.fsucc[q] & SUCC_FDEP) fheavy.insert({t, x});
-      if (s.fsucc[q] & SUCC_MID) fmid.insert({t, x});
-      // successors of a TF_PANEL POTRF past its early ones read the panel
-      if ((w[0] & 0xff) == TK_POTRF && (w[0] & TF_PANEL) && q >= w[5] + w[4]) fafter.insert({t, x});
     }
-  }
   for (int32_t t = 0; t < ns; t++)
     for (int32_t q = s.stask[(size_t)t * TASK_WORDS + 5]; q < s.stask[(size_t)t * TASK_WORDS + 6]; q++)
       pred[nf + s.ssucc[q]].push_back(nf + t);
@@ -2066,7 +1896,6 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
     const int type = w[0] & 0xff;
     if (type == TK_POTRF || type == TK_TRSM) final_task[w[1]] = t;
     if (type == TK_POTRF) potrf_row[w[2]] = t;
-    if (type == TK_POTRF && (w[0] & TF_PANEL)) final_task[s.fpairs[2 * (size_t)w[3]]] = t;
   }
   for (int32_t t = 0; t < ns; t++) {
     const int32_t* w = &s.stask[(size_t)t * TASK_WORDS];
@@ -2124,28 +1953,11 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
     std::sort(sl.begin(), sl.end());
     for (int32_t x : sl)
       if (x <= i) { fprintf(stderr, "stiles: merged DAG order is not topological\n"); abort(); }
-    if (t < nf && (w[0] & 0xff) == TK_POTRF && (w[0] & TF_PANEL)) {
-      // successors that read the panel tile last (factorization ones as in
-      // the factorization DAG; solve tasks that take it as an operand)
-      const int32_t ptile = s.fpairs[2 * (size_t)w[3]];
-      auto reads_panel = [&](int32_t x) {
-        const int32_t o = order[x];
-        if (o < nf) return fafter.count({t, o}) > 0;
-        const int32_t* ws = &s.stask[(size_t)(o - nf) * TASK_WORDS];
-        if ((ws[0] & 0xff) == TK_FSUM) return false;
-        for (int32_t q = ws[2]; q < ws[3]; q++)
-          if (s.spairs[2 * (size_t)q] == ptile) return true;
-        return false;
-      };
-      std::stable_partition(sl.begin(), sl.end(), [&](int32_t x) { return !reads_panel(x); });
-      w[4] = (int32_t)std::count_if(sl.begin(), sl.end(), [&](int32_t x) { return !reads_panel(x); });
-    }
     w[5] = (int32_t)D.succ.size();
     // edges from a factorization task to a solve task carry SUCC_FDEP, and so
     // do the factorization DAG's own early edges into two-stage tasks
     for (int32_t x : sl)
-      D.succ.push_back(t < nf && (order[x] >= nf || fheavy.count({t, order[x]})) ? (x | SUCC_FDEP)
-                       : t < nf && fmid.count({t, order[x]}) ? (x | SUCC_MID) : x);
+      D.succ.push_back(t < nf && (order[x] >= nf || fheavy.count({t, order[x]})) ? (x | SUCC_FDEP) : x);
     w[6] = (int32_t)D.succ.size();
     if (t < nf) {
       w[7] = s.ftask[(size_t)t * TASK_WORDS + 7];   // the factorization DAG's counter, with its weights
@@ -2208,7 +2020,6 @@ extern "C" stiles_status stiles_symbolic_query(const stiles_symbolic* s, stiles_
   info->tree_used = s->tree_used;
   info->nnz_L_alg = s->nnzL_alg;
   info->update_blocks = s->ublocks;
-  info->panels_fused = s->panels_fused;
   return STILES_OK;
 }
 

@@ -807,7 +807,7 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
         const int32_t* w = &sy.ftask[(size_t)t * TASK_WORDS];
         cost[g] = sy.fcost[t];
         owner[g] = i;
-        for (int32_t q = w[5]; q < w[6]; q++) sflat.push_back(off[i] + (sy.fsucc[q] & ~SUCC_FLAGS));
+        for (int32_t q = w[5]; q < w[6]; q++) sflat.push_back(off[i] + (sy.fsucc[q] & ~SUCC_FDEP));
         sptr[g + 1] = (int32_t)sflat.size();
       }
     }

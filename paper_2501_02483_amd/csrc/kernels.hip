@@ -86,14 +86,13 @@ __device__ __forceinline__ double rsqrt_c(double d) {
 // row group touch 16 consecutive rows of a column-major tile.  Operands are
 // read from LDS, where a whole tile pair has been staged.
 
-template <int T, int K = T>
+template <int T>
 __device__ __forceinline__ void mma_f64(v4d (&acc)[T / 32][T / 32], const double* X, const double* Y, int r0, int c0,
                                         int lane) {
   constexpr int NB = T / 32;
   const double* xp = X + r0 + (lane & 15) + (lane >> 4) * T;
   const double* yp = Y + c0 + (lane & 15) + (lane >> 4) * T;
-  // the operands of step k + 4 are read from LDS while step k's MFMAs run;
-  // K < T: the first K columns of X and Y (a column panel, leading dimension T)
+  // the operands of step k + 4 are read from LDS while step k's MFMAs run
   double a[NB], b[NB];
 #pragma unroll
   for (int q = 0; q < NB; q++) {
@@ -101,9 +100,9 @@ __device__ __forceinline__ void mma_f64(v4d (&acc)[T / 32][T / 32], const double
     b[q] = xp[q * 16];
   }
 #pragma unroll
-  for (int k = 0; k < K; k += 4) {
+  for (int k = 0; k < T; k += 4) {
     double an[NB], bn[NB];
-    if (k + 4 < K) {
+    if (k + 4 < T) {
 #pragma unroll
       for (int q = 0; q < NB; q++) {
         an[q] = yp[q * 16 + (k + 4) * T];
@@ -116,7 +115,7 @@ __device__ __forceinline__ void mma_f64(v4d (&acc)[T / 32][T / 32], const double
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    if (k + 4 < K) {
+    if (k + 4 < T) {
 #pragma unroll
       for (int q = 0; q < NB; q++) {
         a[q] = an[q];
@@ -209,48 +208,6 @@ __device__ __forceinline__ bool wait_below(int32_t* cnt, int32_t bound, ExecCtrl
   return ok;
 }
 
-
-// Notification of the successors at entries [s0, s1) of a task's list
-// (Alg. 2 progress update) by wave 0, after every wave's stores have
-// completed (device-scope stores are coherent once complete; the
-// workgroup-scope release only orders the notification after them in the
-// compiler).  An entry with SUCC_FDEP subtracts MERGED_FDEP, one with
-// SUCC_MID MID_WEIGHT, any other 1.
-__device__ __forceinline__ void notify_succ(const ExecMat& M, int32_t s0, int32_t s1) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  for (int32_t q0 = s0; q0 < s1; q0 += 64) {
-    const int32_t q = q0 + (int32_t)threadIdx.x;
-    if (threadIdx.x < 64 && q < s1) {
-      int32_t sq = M.succ[q], dec = 1;
-      if (sq & SUCC_FDEP) {   // an early predecessor of a two- or three-stage wait
-        dec = MERGED_FDEP;
-        sq &= ~SUCC_FDEP;
-      } else if (sq & SUCC_MID) {   // the late predecessor of a three-stage wait
-        dec = MID_WEIGHT;
-        sq &= ~SUCC_MID;
-      }
-      __hip_atomic_fetch_add(M.remaining + sq, -dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-
-// Non-blocking form of wait_below: true (after an acquire for the
-// workgroup) when *cnt < bound already, false otherwise.  The result is the
-// same for every thread.
-__device__ __forceinline__ bool ready_below(int32_t* cnt, int32_t bound) {
-  __shared__ int32_t s_ready;
-  if (threadIdx.x < 64) {
-    const int32_t r = __builtin_amdgcn_readfirstlane(ld_relaxed(cnt)) < bound;
-    if (r) fence_acquire();
-    if (threadIdx.x == 0) s_ready = r;
-  }
-  __syncthreads();
-  const bool r = __builtin_amdgcn_readfirstlane(s_ready) != 0;
-  __syncthreads();
-  return r;
-}
 
 // UPD / PART: acc = sum_p X_p Y_p^T over a list of tile pairs (at most 32).
 // mode 0: C_t -= acc (UPD), mode 1: P = acc (PART).  LX, LY: LDS tiles.
@@ -795,31 +752,23 @@ __device__ __forceinline__ void inv_row_block(double* S, double* Xi, int b, int 
 template <int T, int K>
 __device__ __attribute__((noinline)) uint64_t task_potrf(const ExecMat& M, const int32_t* w, double* S, double* Xi,
                                                          double* rinv, int32_t* cnt, ExecCtrl* ctrl, uint64_t limit,
-                                                         bool& ok, int32_t& notified) {
+                                                         bool& ok) {
   constexpr int TT = T * T, NBK = T / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int flags = __builtin_amdgcn_readfirstlane(w[0]);
-  const bool split = (flags & TF_SPLIT) != 0, panel = (flags & TF_PANEL) != 0;
-  // pair list: [(panel tile, n own)], own fused pairs, [panel pairs]
-  int own0 = __builtin_amdgcn_readfirstlane(w[3]), own1 = __builtin_amdgcn_readfirstlane(w[4]), ptile = -1;
-  if (panel) {
-    ptile = __builtin_amdgcn_readfirstlane(M.pairs[2 * own0]);
-    own1 = own0 + 1 + __builtin_amdgcn_readfirstlane(M.pairs[2 * own0 + 1]);
-    own0 += 1;
-  }
-  if (ok) ok = wait_below(cnt, split || panel ? MERGED_FDEP : 1, ctrl, limit);
+  const bool split = (__builtin_amdgcn_readfirstlane(w[0]) & TF_SPLIT) != 0;
+  if (ok) ok = wait_below(cnt, split ? MERGED_FDEP : 1, ctrl, limit);
   if (!ok) return 0;
   uint64_t t_start = M.trace ? wall_clock64() : 0;
   double* C = M.tiles + (int64_t)w[1] * TT;
   const int k = w[2];
   {
-    // C is prefetched; the fused operand X = L_(k,k-1) follows the late wait
-    const bool fused = own1 > own0;
-    const int64_t xt = fused ? __builtin_amdgcn_readfirstlane(M.pairs[2 * own0]) : 0;
+    // C is prefetched; the fused operand X = L_(k,k-1) follows the last wait
+    const bool fused = w[4] > w[3];
+    const int64_t xt = fused ? __builtin_amdgcn_readfirstlane(M.pairs[2 * w[3]]) : 0;
     TileStage<T, double> st, sx;
     st.load(C);
     if (split) {
-      ok = wait_below(cnt, panel ? MID_WEIGHT : 1, ctrl, limit);
+      ok = wait_below(cnt, 1, ctrl, limit);
       if (!ok) return 0;
       if (M.trace) t_start = wall_clock64();
     }
@@ -916,51 +865,10 @@ __device__ __attribute__((noinline)) uint64_t task_potrf(const ExecMat& M, const
   }
   if (tid == 0 && fail >= 0) atomicMin(M.info, (unsigned long long)(M.row_base[k] + fail + 1));
   double* Li = M.linv + (int64_t)k * TT;
-  // the panel tile below: L_(k+1,k) = C_(k+1,k) Linv^T once its update chain
-  // has finished; usually it has by now, and its tile is then fetched while
-  // L_kk and the inverse are stored
-  TileStage<T, double> sp;
-  GLOBAL double* Cp = panel ? gp(M.tiles + (int64_t)ptile * TT) : nullptr;
-  const bool early = panel && ready_below(cnt, 1);
-  if (early) sp.load(M.tiles + (int64_t)ptile * TT);
   for (int e = tid; e < TT; e += NT) {
     const int row = e % T, col = e / T;
     st_dev(C + e, row >= col ? S[e] : 0.0);
     st_dev(Li + e, Xi[e]);
-  }
-  if (panel) {
-    // the successors that need only L_kk and its inverse (w[4] of them,
-    // first in the list) start now
-    notified = __builtin_amdgcn_readfirstlane(w[4]);
-    const int32_t s0 = __builtin_amdgcn_readfirstlane(w[5]);
-    notify_succ(M, s0, s0 + notified);
-    if (!early) {
-      ok = wait_below(cnt, 1, ctrl, limit);
-      if (!ok) return t_start;
-      sp.load(M.tiles + (int64_t)ptile * TT);
-    }
-    constexpr int W = T / 2, NB = T / 32;
-    const int r0 = (wave >> 1) * W, c0 = (wave & 1) * W;
-    __syncthreads();   // every read of S by the stores above is done
-    sp.store(S);
-    __syncthreads();
-    v4d acc[NB][NB];
-#pragma unroll
-    for (int i = 0; i < NB; i++)
-#pragma unroll
-      for (int j = 0; j < NB; j++) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-    mma_f64<T>(acc, S, Xi, r0, c0, lane);
-    GLOBAL float* Sh = M.mixed ? gp(M.shadow + (int64_t)ptile * TT) : nullptr;
-#pragma unroll
-    for (int i = 0; i < NB; i++)
-#pragma unroll
-      for (int j = 0; j < NB; j++)
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-          const int row = r0 + 16 * j + (lane & 15), col = c0 + 16 * i + (lane >> 4) + 4 * r;
-          st_dev(Cp + row + col * T, acc[i][j][r]);
-          if (Sh) st_dev(Sh + row + col * T, (float)acc[i][j][r]);
-        }
   }
   return t_start;
 }
@@ -1587,7 +1495,6 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     // factorization predecessors only (the counter falls below MERGED_FDEP);
     // its factor tiles are final then
     bool ok = true;
-    int32_t notified = 0;   // successors the task body notified itself
     if constexpr (BOTH) {
       if (type >= TK_FUPD) ok = wait_below(cnt, MERGED_FDEP, ctrl, limit);
     }
@@ -1605,8 +1512,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
     // update work of other workgroups on the same SIMDs
     const bool chain = SOLVE    ? (type == TK_FDIAG || type == TK_BDIAG)
                        : SELINV ? (type == TK_SW || type == TK_SDIAG)
-                                : (type == TK_POTRF || type == TK_TRSM || type == TK_FDIAG || type == TK_BDIAG ||
-                                   (__builtin_amdgcn_readfirstlane(w[0]) & TF_CHAIN) != 0);
+                                : (type == TK_POTRF || type == TK_TRSM || type == TK_FDIAG || type == TK_BDIAG);
     if (chain) __builtin_amdgcn_s_setprio(3);
     if constexpr (SELINV) {
       if (!ok) {
@@ -1632,7 +1538,7 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
         case TK_UPDB: task_update_block<T, KIND>(M, w, S, Xi); break;
         case TK_PART: task_update<T, KIND>(M, w, 1, S, Xi); break;
         case TK_TREE: task_tree<T, KIND>(M, w); break;
-        case TK_POTRF: t_start = task_potrf<T, KIND>(M, w, S, Xi, rinv, cnt, ctrl, limit, ok, notified); break;
+        case TK_POTRF: t_start = task_potrf<T, KIND>(M, w, S, Xi, rinv, cnt, ctrl, limit, ok); break;
         default: t_start = task_trsm<T, KIND>(M, w, S, Xi, cnt, ctrl, limit, ok); break;
       }
     }
@@ -1645,11 +1551,26 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
       __syncthreads();
       continue;
     }
-    // every wave waits for its own stores, then wave 0 notifies
+    // every wave waits for its own stores (device-scope stores, coherent
+    // once complete), then wave 0 notifies the successors (Alg. 2 progress
+    // update); the workgroup-scope release only orders the notification
+    // after the stores in the compiler
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (threadIdx.x == 0) st_relaxed(cnt, w[7]);   // re-arm for the next launch
-    // successors not yet notified (a POTRF with TF_PANEL notifies those that
-    // need only L_kk and its inverse itself, before it forms the panel)
-    notify_succ(M, __builtin_amdgcn_readfirstlane(w[5]) + notified, __builtin_amdgcn_readfirstlane(w[6]));
+    const int32_t s0 = __builtin_amdgcn_readfirstlane(w[5]), s1 = __builtin_amdgcn_readfirstlane(w[6]);
+    for (int32_t q0 = s0; q0 < s1; q0 += 64) {
+      const int32_t q = q0 + (int32_t)threadIdx.x;
+      if (threadIdx.x < 64 && q < s1) {
+        int32_t sq = M.succ[q], dec = 1;
+        if (sq & SUCC_FDEP) {   // an early predecessor of a two-stage wait
+          dec = MERGED_FDEP;
+          sq &= ~SUCC_FDEP;
+        }
+        __hip_atomic_fetch_add(M.remaining + sq, -dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
     if (M.trace && threadIdx.x == 0) {
       unsigned long long* tr = M.trace + 4 * (int64_t)lid;
       tr[0] = t_claim;

@@ -45,8 +45,6 @@ enum TaskFlag : int32_t {
   TF_ACC = 1 << 10,   // PART: P_s += sum (continues a chain) instead of P_s = sum
   TF_SPLIT = 1 << 11, // POTRF/TRSM: two-stage wait (early predecessors, then the chain one)
   TF_ARROW = 1 << 12, // PART: partial of an arrow-corner tile (FP64 in mixed mode)
-  TF_PANEL = 1 << 13, // POTRF: also computes the panel tile (k+1,k) (three-stage wait)
-  TF_CHAIN = 1 << 14, // UPD: the last product of a panel tile formed by its POTRF (raised priority)
 };
 
 // One task = 8 int32.
@@ -59,11 +57,7 @@ enum TaskFlag : int32_t {
 //       column j the operand tiles (ra,j), (rb,j), (k,j), (k+1,j); TF_DIAG:
 //       the diagonal block (ra, rb) = (k, k+1), whose (ra,j) = (k,j)
 // TREE: a = slot, b = slot or -1, c = out slot or -1 (then subtract into tile)
-// POTRF: a = tile row k, b,c = fused pair range (C_kk -= X X^T first, 0 or 1 pair);
-//        TF_PANEL: the range starts with the word pair (panel tile (k+1,k), n),
-//        then the n (0 or 1) own fused pairs: L_(k+1,k) = C_(k+1,k) Linv_k^T
-//        once L_kk is factored (every product of the panel is in its update
-//        chain, the one with column k-1 in a task of its own)
+// POTRF: a = tile row k, b,c = fused pair range (C_kk -= X X^T first, 0 or 1 pair)
 // TRSM:  a = tile row k of the diagonal tile, b,c = fused pair range
 // FUPD/BUPD: w1 = tile row m, a,b = solve-pair range
 // FDIAG/BDIAG: w1 = m, a,b = fused solve-pair range applied before the diagonal
@@ -96,14 +90,6 @@ constexpr int32_t SIG_TRANS = 1 << 30;
 // prefetches its tile before.
 constexpr int32_t MERGED_FDEP = 1 << 16;
 constexpr int32_t SUCC_FDEP = 1 << 30;
-// Three-stage waits (a POTRF with TF_PANEL): early predecessors weigh
-// MERGED_FDEP, the late one (the task that finalized the fused operand
-// L_(k,k-1)) MID_WEIGHT through an edge with SUCC_MID, and the last task of
-// the panel tile's update chain weighs 1: the task stages its tile after the
-// first wait, factors after the second and forms the panel after the third.
-constexpr int32_t MID_WEIGHT = 1 << 8;
-constexpr int32_t SUCC_MID = 1 << 29;
-constexpr int32_t SUCC_FLAGS = SUCC_FDEP | SUCC_MID;
 // Tile rows the library's fixed log-determinant array holds (one FP64
 // partial per tile row, 512 KiB); the public limit of stiles_logdet_static.
 constexpr int32_t STATIC_LOGDET_ROWS = 65536;

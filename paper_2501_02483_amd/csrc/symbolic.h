@@ -71,7 +71,6 @@ struct stiles_symbolic {
   int32_t tree_used = 0;
   int64_t corner_acc = 0;
   int64_t ublocks = 0;      // 2 x 2 update blocks in the factorization DAG
-  int64_t panels_fused = 0; // POTRF tasks that also finalize the panel tile below
 
   // solve DAG
   int32_t nspart = 0;             // partial slots of long forward rows

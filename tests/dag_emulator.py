@@ -15,50 +15,16 @@ UPD, PART, TREE, POTRF, TRSM, UPDB = 1, 2, 3, 4, 5, 6
 FUPD, FDIAG, BUPD, BDIAG, FPART, FSUM = 8, 9, 10, 11, 12, 13
 SWE, SW, SDIAG, TSUM = 16, 17, 18, 19
 TF_DIAG, TF_FIRST, TF_ACC, TF_SPLIT = 1 << 8, 1 << 9, 1 << 10, 1 << 11
-TF_PANEL = 1 << 13
 SIG_TRANS = 1 << 30
 MERGED_FDEP, SUCC_FDEP = 1 << 16, 1 << 30
-MID_WEIGHT, SUCC_MID = 1 << 8, 1 << 29
 
 
 def succ_edge(v):
     """(successor, counter decrement) of a successor entry: an entry with
-    SUCC_FDEP (an early predecessor of a two- or three-stage task, or a
-    factorization task before a solve task in the merged DAG) subtracts
-    MERGED_FDEP, one with SUCC_MID (the late predecessor of a three-stage
-    task) MID_WEIGHT, any other 1."""
+    SUCC_FDEP (merged DAG, factorization task -> solve task) subtracts
+    MERGED_FDEP."""
     v = int(v)
-    if v & SUCC_FDEP:
-        return v & ~SUCC_FDEP, MERGED_FDEP
-    if v & SUCC_MID:
-        return v & ~SUCC_MID, MID_WEIGHT
-    return v, 1
-
-
-def potrf(w, P, tiles, linv, done=None):
-    """POTRF task: C_kk -= own fused products, L_kk and its inverse; with
-    TF_PANEL also L_(k+1,k) = C_(k+1,k) Linv^T.  Pair list of a TF_PANEL
-    task: (panel tile, n own), then the n own pairs (its w[4] is the number
-    of successors notified before the panel is formed)."""
-    p0 = w[3]
-    panel = None
-    if w[0] & TF_PANEL:
-        panel, nown = int(P[p0, 0]), int(P[p0, 1])
-        own = range(p0 + 1, p0 + 1 + nown)
-    else:
-        own = range(p0, w[4])
-    C = tiles[w[1]].copy()
-    for p in own:
-        C -= tiles[P[p, 0]] @ tiles[P[p, 1]].T
-    L = np.linalg.cholesky(np.tril(C) + np.tril(C, -1).T)
-    tiles[w[1]] = L
-    linv[w[2]] = np.linalg.inv(L)
-    if done is not None:
-        done[w[1]] = True
-    if panel is not None:
-        tiles[panel] = tiles[panel] @ linv[w[2]].T
-        if done is not None:
-            done[panel] = True
+    return (v & ~SUCC_FDEP, MERGED_FDEP) if v & SUCC_FDEP else (v, 1)
 
 
 class Plan:
@@ -181,7 +147,13 @@ def factor(plan, Aperm, mode="ticket", seed=0):
             else:
                 tiles[w[1]] -= s
         elif typ == POTRF:
-            potrf(w, P, tiles, linv)
+            C = tiles[w[1]].copy()
+            for p in range(w[3], w[4]):
+                C -= tiles[P[p, 0]] @ tiles[P[p, 1]].T
+            Cs = np.tril(C) + np.tril(C, -1).T
+            L = np.linalg.cholesky(Cs)
+            tiles[w[1]] = L
+            linv[w[2]] = np.linalg.inv(L)
         elif typ == TRSM:
             C = tiles[w[1]].copy()
             for p in range(w[3], w[4]):
@@ -356,7 +328,13 @@ def factor_solve(plan, Aperm, B, mode="ticket", seed=0):
             else:
                 tiles[w[1]] -= s_
         elif typ == POTRF:
-            potrf(w, P, tiles, linv, done_tile)
+            C = tiles[w[1]].copy()
+            for p in range(w[3], w[4]):
+                C -= tiles[P[p, 0]] @ tiles[P[p, 1]].T
+            L = np.linalg.cholesky(np.tril(C) + np.tril(C, -1).T)
+            tiles[w[1]] = L
+            linv[w[2]] = np.linalg.inv(L)
+            done_tile[w[1]] = True
         elif typ == TRSM:
             C = tiles[w[1]].copy()
             for p in range(w[3], w[4]):

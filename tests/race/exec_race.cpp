@@ -1,11 +1,9 @@
 // Threaded host emulation of the persistent executor's protocol, for
 // ThreadSanitizer.  Worker threads take tickets in the plan's static order,
 // wait on per-task counters (two-stage for TF_SPLIT tasks: the early
-// predecessors, which weigh 2^16, then the late one; three-stage for a
-// POTRF with TF_PANEL: early, late (weight 2^8), then the predecessors of
-// the panel tile it also computes), run the task on host tiles and notify
-// the successors (an entry with bit 30 set subtracts 2^16, one with bit 29
-// 2^8) -- the counter protocol of the device executor with C++ acquire/release
+// predecessors, which weigh 2^16, then the late one), run the task on host
+// tiles and notify the successors (an entry with bit 30 set subtracts 2^16)
+// -- the counter protocol of the device executor with C++ acquire/release
 // atomics in place of the device's coherent stores and fences.  A missing
 // dependency in the plan, or a task that reads before its wait, is a data
 // race between the tile accesses of two tasks, which ThreadSanitizer
@@ -35,12 +33,8 @@
 namespace {
 
 constexpr int TK_UPD = 1, TK_PART = 2, TK_TREE = 3, TK_POTRF = 4, TK_TRSM = 5, TK_UPDB = 6;
-constexpr int TF_DIAG = 1 << 8, TF_ACC = 1 << 10, TF_SPLIT = 1 << 11, TF_PANEL = 1 << 13;
-constexpr int32_t W = 1 << 16, FDEP = 1 << 30, WMID = 1 << 8, MID = 1 << 29;
-
-// successor index and counter decrement of a successor entry
-inline int32_t succ_of(int32_t v) { return v & ~(FDEP | MID); }
-inline int32_t succ_weight(int32_t v) { return (v & FDEP) ? W : (v & MID) ? WMID : 1; }
+constexpr int TF_DIAG = 1 << 8, TF_ACC = 1 << 10, TF_SPLIT = 1 << 11;
+constexpr int32_t W = 1 << 16, FDEP = 1 << 30;
 
 struct Plan {
   int32_t T = 0, ntiles = 0, ntr = 0, ntasks = 0, nsucc = 0, npairw = 0, npart = 0;
@@ -98,40 +92,24 @@ struct Exec {
       if (failed.load(std::memory_order_relaxed)) return;
     }
   }
-  void notify(int32_t s0, int32_t s1) {
-    for (int32_t q = s0; q < s1; q++) {
-      const int32_t v = p.succ[q];
-      if (v == -1) continue;   // a planted missing edge
-      cnt[succ_of(v)].fetch_sub(succ_weight(v), std::memory_order_release);
-    }
-  }
-  // returns the number of successor entries the task notified itself
-  int32_t run_task(int32_t t, std::mt19937& rng) {
+  void run_task(int32_t t, std::mt19937& rng) {
     const int32_t* w = &p.tasks[(size_t)t * 8];
     const int type = w[0] & 0xff, T = p.T;
-    const bool split = (w[0] & TF_SPLIT) != 0, panel = type == TK_POTRF && (w[0] & TF_PANEL) != 0;
+    const bool split = (w[0] & TF_SPLIT) != 0;
     std::vector<double> C((size_t)T * T);
     if (type == TK_POTRF || type == TK_TRSM) {
-      // pair ranges: a TF_PANEL POTRF's list starts with (panel tile, n own)
-      int32_t q0 = w[3], q1 = w[4], ptile = -1;
-      if (panel) {
-        ptile = p.pairs[2 * q0];
-        q0 += 1;
-        q1 = q0 + p.pairs[2 * w[3] + 1];
-      }
-      wait_below(t, split || panel ? W : 1, rng);
+      wait_below(t, split ? W : 1, rng);
       std::memcpy(C.data(), tile(w[1]), C.size() * 8);   // its own tile: an early input
       if (type == TK_TRSM)                                  // fused products: early inputs
-        for (int32_t q = q0; q < q1; q++) sub_prod(C.data(), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), false);
-      if (panel) wait_below(t, WMID, rng);
-      else if (split) wait_below(t, 1, rng);
+        for (int32_t q = w[3]; q < w[4]; q++) sub_prod(C.data(), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), false);
+      if (split) wait_below(t, 1, rng);
       if (type == TK_POTRF) {
-        for (int32_t q = q0; q < q1; q++) sub_prod(C.data(), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), true);
+        for (int32_t q = w[3]; q < w[4]; q++) sub_prod(C.data(), tile(p.pairs[2 * q]), tile(p.pairs[2 * q + 1]), true);
         // Cholesky of the lower triangle, then the inverse of the factor
         for (int j = 0; j < T; j++) {
           double d = C[j + j * T];
           for (int k = 0; k < j; k++) d -= C[j + k * T] * C[j + k * T];
-          if (!(d > 0.0)) { failed.store(true); return 0; }
+          if (!(d > 0.0)) { failed.store(true); return; }
           const double l = std::sqrt(d);
           C[j + j * T] = l;
           for (int i = j + 1; i < T; i++) {
@@ -150,24 +128,6 @@ struct Exec {
             for (int k = c; k < r; k++) s -= C[r + k * T] * Li[k + c * T];
             Li[r + c * T] = s / C[r + r * T];
           }
-        if (panel) {
-          // L_kk and the inverse are stored: the first w[4] successors (which
-          // need only those) are notified; then, after the panel tile's own
-          // predecessors, L_(k+1,k) = C_(k+1,k) Linv^T
-          std::memcpy(tile(w[1]), C.data(), C.size() * 8);
-          notify(w[5], w[5] + w[4]);
-          wait_below(t, 1, rng);
-          std::vector<double> P((size_t)T * T), out((size_t)T * T, 0.0);
-          std::memcpy(P.data(), tile(ptile), P.size() * 8);
-          for (int c = 0; c < T; c++)
-            for (int r = 0; r < T; r++) {
-              double s = 0.0;
-              for (int k = 0; k < T; k++) s += P[r + k * T] * Li[c + k * T];
-              out[r + c * T] = s;
-            }
-          std::memcpy(tile(ptile), out.data(), out.size() * 8);
-          return w[4];
-        }
       } else {
         const double* Li = linv.data() + (size_t)w[2] * T * T;
         std::vector<double> out((size_t)T * T, 0.0);
@@ -180,7 +140,7 @@ struct Exec {
         C.swap(out);
       }
       std::memcpy(tile(w[1]), C.data(), C.size() * 8);
-      return 0;
+      return;
     }
     wait_below(t, 1, rng);
     if (type == TK_UPD) {
@@ -215,17 +175,20 @@ struct Exec {
       std::fprintf(stderr, "exec_race: unknown task type %d\n", type);
       failed.store(true);
     }
-    return 0;
   }
   void worker(unsigned seed) {
     std::mt19937 rng(seed);
     for (;;) {
       const int32_t t = ticket.fetch_add(1, std::memory_order_relaxed);
       if (t >= p.ntasks || failed.load(std::memory_order_relaxed)) break;
-      const int32_t done = run_task(t, rng);
+      run_task(t, rng);
       if (rng() % 8 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 50));
       const int32_t* w = &p.tasks[(size_t)t * 8];
-      notify(w[5] + done, w[6]);
+      for (int32_t q = w[5]; q < w[6]; q++) {
+        const int32_t v = p.succ[q];
+        if (v == -1) continue;   // a planted missing edge
+        cnt[v & ~FDEP].fetch_sub((v & FDEP) ? W : 1, std::memory_order_release);
+      }
     }
   }
 };
@@ -246,7 +209,7 @@ int main(int argc, char** argv) {
     // plant a missing dependency: the successor no longer waits for it
     const int32_t e = std::atoi(argv[5]);
     const int32_t v = p.succ[e];
-    p.tasks[(size_t)succ_of(v) * 8 + 7] -= succ_weight(v);
+    p.tasks[(size_t)(v & ~FDEP) * 8 + 7] -= (v & FDEP) ? W : 1;
     p.succ[e] = -1;
   }
   Exec ex(p);

@@ -212,8 +212,6 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
             final_of[int(tasks[t, 1])] = t
         if typ[t] == E.POTRF:
             potrf_of[int(tasks[t, 2])] = t
-            if tasks[t, 0] & E.TF_PANEL:
-                final_of[int(P[tasks[t, 3], 0])] = t     # the panel tile it finalizes
         for q in range(tasks[t, 5], tasks[t, 6]):
             x, dec = E.succ_edge(succ[q])
             assert x > t
@@ -222,10 +220,8 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
                 assert (dec == E.MERGED_FDEP) == (is_fac[t] and not is_fac[x])
             else:
                 # factorization -> factorization: MERGED_FDEP only into a
-                # two- or three-stage POTRF/TRSM, from one of its early
-                # predecessors; MID_WEIGHT only into a three-stage POTRF
-                assert dec == 1 or tasks[x, 0] & (E.TF_SPLIT | E.TF_PANEL)
-                assert dec != E.MID_WEIGHT or tasks[x, 0] & E.TF_PANEL
+                # two-stage POTRF/TRSM, from one of its early predecessors
+                assert dec == 1 or tasks[x, 0] & E.TF_SPLIT
                 fweight[x] += dec
             if is_fac[t]:
                 fpred[x].add(t)
@@ -234,11 +230,7 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
     for t in range(n):
         if is_fac[t]:
             assert tasks[t, 7] == fweight[t] and spred[t] == 0
-            if tasks[t, 0] & E.TF_PANEL:
-                # at most one late predecessor (MID_WEIGHT), with TF_SPLIT
-                late = (fweight[t] % E.MERGED_FDEP) // E.MID_WEIGHT
-                assert late == (1 if tasks[t, 0] & E.TF_SPLIT else 0)
-            elif tasks[t, 0] & E.TF_SPLIT:
+            if tasks[t, 0] & E.TF_SPLIT:
                 # exactly one late predecessor (weight 1)
                 assert fweight[t] % E.MERGED_FDEP == 1
             continue
@@ -337,82 +329,3 @@ def test_emulated_block_updates(ublock, mode, ordering, parts):
     _, _, X = E.factor_solve(plan, A, B, mode=mode, seed=ublock + 1)
     Xo = oracle.solve(p.f, L, B)
     assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
-
-
-def _reads_tile(w, P, tile, solve=False):
-    """Whether a task takes factor tile `tile` as an operand (pair lists)."""
-    typ = w[0] & 0xff
-    if solve:
-        if typ == E.FSUM:
-            return False
-        return any(int(P[q, 0]) == tile for q in range(w[2], w[3]))
-    if typ in (E.UPD, E.PART):
-        rng_ = range(w[2], w[3])
-    elif typ == E.TRSM:
-        rng_ = range(w[3], w[4])
-    elif typ == E.POTRF:
-        rng_ = range(w[3] + 1, w[3] + 1 + int(P[w[3], 1])) if w[0] & E.TF_PANEL else range(w[3], w[4])
-    elif typ == E.UPDB:
-        words = P.reshape(-1)[2 * w[2]:2 * w[2] + 4 + 4 * w[3]]
-        return tile in set(int(x) for x in words[4:])
-    else:
-        return False
-    return any(int(P[q, 0]) == tile or int(P[q, 1]) == tile for q in rng_)
-
-
-@pytest.mark.parametrize("ordering,parts", [(S.STILES_ORDER_NONE, 0), (S.STILES_ORDER_ADAPTABLE_ND, 3)],
-                         ids=["natural", "nd3"])
-def test_panel_fusion_notifies_early_only_tasks_that_skip_the_panel(ordering, parts):
-    """A POTRF that also forms the panel tile L_(k+1,k) notifies its first
-    w[4] successors before it forms the panel: none of them may read that
-    tile, every later one does (factorization and merged DAGs)."""
-    p = I.make_pattern(3000, 40, [16, 90, 40], seg=600)
-    sym = S.Symbolic.from_pattern(p, tile=32, ordering=ordering, nd_parts=parts, fuse_panel=1)
-    off = S.Symbolic.from_pattern(p, tile=32, ordering=ordering, nd_parts=parts)
-    assert sym.info.panels_fused > 0 and off.info.panels_fused == 0
-    ex = lambda k: S.stiles_symbolic_export(sym.handle, k)
-    nf = len(ex("ftask")) // 8
-    for tname, sname, pname in (("ftask", "fsucc", "fpairs"), ("mtask", "msucc", "mpairs")):
-        tasks, succ, P = ex(tname).reshape(-1, 8), ex(sname), ex(pname).reshape(-1, 2)
-        merged = tname == "mtask"
-        fac = set(range(len(tasks))) if not merged else {t for t in range(len(tasks)) if (tasks[t, 0] & 0xff) < E.FUPD}
-        npanel = 0
-        for t in range(len(tasks)):
-            w = tasks[t]
-            if (w[0] & 0xff) != E.POTRF or not (w[0] & E.TF_PANEL):
-                continue
-            npanel += 1
-            ptile = int(P[w[3], 0])
-            for i, q in enumerate(range(w[5], w[6])):
-                x = E.succ_edge(succ[q])[0]
-                reads = _reads_tile(tasks[x], P, ptile, solve=x not in fac)
-                assert reads == (i >= w[4]), (tname, t, x)
-        assert npanel == sym.info.panels_fused
-
-
-@pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[5]], ids=["n700_T64", "n2000_T32"])
-@pytest.mark.parametrize("mode", ["ticket", "random"])
-@pytest.mark.parametrize("parts", [0, 3])
-def test_emulated_panel_fusion_matches_oracle(shape, mode, parts):
-    """POTRF tasks that also form the panel tile below the diagonal
-    (fuse_panel): the factorization and the merged factorization + solve
-    DAGs give the oracle's factor and solution, in ticket and random orders."""
-    n, a, w, seg, T, ratio = shape
-    p = I.make_pattern(n, a, w, seg=seg)
-    vals = I.make_values(p, seed=n + a)
-    kw = dict(ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=parts) if parts else {}
-    sym = S.Symbolic.from_pattern(p, tile=T, tree_min_ratio=ratio, fuse_panel=1, **kw)
-    assert sym.info.panels_fused > 0
-    plan = E.Plan(sym)
-    Ap = I.to_dense(p, vals)[np.ix_(plan.perm, plan.perm)]
-    L, info = oracle.factor(p.f, vals)
-    B = I.rhs(p.N, 3, seed=9)
-    Xo = oracle.solve(p.f, L, B)
-    tiles, linv = E.factor(plan, Ap, mode=mode, seed=n)
-    X = E.solve(plan, tiles, linv, B, mode=mode, seed=n + 1)
-    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
-    if not parts:
-        Lo, _ = _oracle_dense_L(p, vals)
-        assert np.linalg.norm(E.dense_factor(plan, tiles) - Lo) / np.linalg.norm(Lo) <= 1e-12
-    _, _, X2 = E.factor_solve(plan, Ap, B, mode=mode, seed=n + 3)
-    assert np.linalg.norm(X2 - Xo) / np.linalg.norm(Xo) <= 1e-12

@@ -3,9 +3,8 @@
 tests/race/exec_race.cpp runs an exported factorization DAG on worker
 threads with the device executor's protocol: tickets in the static order,
 per-task counters, two-stage waits for TF_SPLIT tasks (the early
-predecessors first, then the late one), three-stage waits for a POTRF that
-also computes the panel tile below it (TF_PANEL), notifications that
-subtract the edge's weight; acquire/release atomics order the tile accesses.  Under
+predecessors first, then the late one), notifications that subtract the
+edge's weight; acquire/release atomics order the tile accesses.  Under
 ThreadSanitizer a task that reads a tile before the task that writes it is
 ordered before it (a missing edge in the plan, or a read placed before the
 wait that covers it) is reported as a data race.  Each plan runs with 8
@@ -78,25 +77,23 @@ def _oracle_factor_permuted(p, vals, perm):
 
 
 CASES = [
-    # n, arrow, widths, segment, tile, ordering, parts, ublock, fuse_panel
-    (900, 40, [15, 70, 30], 300, 32, S.STILES_ORDER_NONE, 0, 0, 0),
-    (1500, 24, [20, 60, 35], 300, 32, S.STILES_ORDER_ADAPTABLE_ND, 3, 0, 0),
-    (1200, 30, [30, 90], 400, 32, S.STILES_ORDER_NONE, 0, 3, 0),
-    (1500, 24, [20, 60, 35], 300, 32, S.STILES_ORDER_ADAPTABLE_ND, 3, 0, 1),
+    # n, arrow, widths, segment, tile, ordering, parts, ublock
+    (900, 40, [15, 70, 30], 300, 32, S.STILES_ORDER_NONE, 0, 0),
+    (1500, 24, [20, 60, 35], 300, 32, S.STILES_ORDER_ADAPTABLE_ND, 3, 0),
+    (1200, 30, [30, 90], 400, 32, S.STILES_ORDER_NONE, 0, 3),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=["natural_tree", "nd3", "blocks", "nd3_panels"])
+@pytest.mark.parametrize("case", CASES, ids=["natural_tree", "nd3", "blocks"])
 def test_protocol_has_no_races(exe, tmp_path, case):
-    n, a, w, seg, T, ordering, parts, ub, fp = case
+    n, a, w, seg, T, ordering, parts, ub = case
     p = I.make_pattern(n, a, w, seg=seg)
     vals = I.make_values(p, seed=n + a)
-    sym = S.Symbolic.from_pattern(p, tile=T, ordering=ordering, nd_parts=parts, ublock=ub, fuse_panel=fp)
+    sym = S.Symbolic.from_pattern(p, tile=T, ordering=ordering, nd_parts=parts, ublock=ub)
     plan = E.Plan(sym)
     Aperm = I.to_dense(p, vals)[np.ix_(plan.perm, plan.perm)]
     tasks, _ = _export(plan, Aperm, str(tmp_path / "plan.bin"))
     assert (tasks[:, 0] & E.TF_SPLIT).any()          # two-stage waits are exercised
-    assert bool((tasks[:, 0] & E.TF_PANEL).any()) == bool(fp)   # three-stage ones with panel fusion
     Lo = _oracle_factor_permuted(p, vals, plan.perm)
     for seed in (1, 2, 3):
         r = _run(exe, str(tmp_path / "plan.bin"), str(tmp_path / "out.bin"), seed)
@@ -121,7 +118,7 @@ def test_planted_missing_edge_is_reported(exe, tmp_path):
     drop = None
     for t in np.nonzero(typ == E.POTRF)[0][2:]:
         for q in range(tasks[t, 5], tasks[t, 6]):
-            x = E.succ_edge(succ[q])[0]
+            x = int(succ[q]) & ~E.SUCC_FDEP
             if typ[x] == E.TRSM:
                 drop = q
                 break
