@@ -267,10 +267,14 @@ stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStre
 /*
  * Many independent factorizations in one persistent launch (Appendix A:
  * concurrent factorizations).  factors[i] must use distinct workspaces and
- * share one tile size.  stiles_batch_create merges the per-matrix static
- * schedules (by their start estimates) into one ticket order and uploads it
- * into d_batch_ws (>= stiles_batch_workspace_size bytes, 256-byte aligned,
- * caller-owned, kept alive with the batch); it synchronizes the stream once.
+ * share one tile size.  stiles_batch_create builds one ticket order for the
+ * union of the matrices' task graphs (a list schedule on the launch's
+ * workgroups, longest remaining path first; with opts.sched_workers = -1
+ * the per-matrix schedules merged by start estimate) and uploads it, with
+ * copies of the task tables whose waits are single-stage (no pivot chain
+ * bounds a batch), into d_batch_ws (>= stiles_batch_workspace_size bytes,
+ * 256-byte aligned, caller-owned, kept alive with the batch); it
+ * synchronizes the stream once.
  * stiles_batch_factorize then scatters every matrix's values (one launch over
  * all tiles when every matrix was analyzed from a row profile) and runs all
  * factorizations in one launch (asynchronous); it may be called again with

@@ -712,8 +712,10 @@ extern "C" stiles_status stiles_logdet_static(stiles_factor* f, double* d_out, h
 
 namespace {
 
+inline char* b_ws_at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
 struct BatchSizes {
-  size_t tasks = 0, tiles = 0, rows = 0;
+  size_t tasks = 0, tiles = 0, rows = 0, succ = 0;
 };
 
 BatchSizes batch_sizes(int32_t count, stiles_factor* const* factors) {
@@ -722,15 +724,17 @@ BatchSizes batch_sizes(int32_t count, stiles_factor* const* factors) {
     z.tasks += factors[i]->mf.ntasks;
     z.tiles += factors[i]->sym->ntiles;
     z.rows += factors[i]->sym->ntr;
+    z.succ += factors[i]->sym->fsucc.size();
   }
   return z;
 }
 
 // batch workspace: control block, executor descriptors, merged ticket order,
-// scatter/logdet descriptors, (matrix, tile) and (matrix, tile row) maps, and
-// the array of value pointers
+// the matrices' task tables without two-stage waits (tasks, successor lists,
+// counters), scatter/logdet descriptors, (matrix, tile) and (matrix, tile
+// row) maps, and the array of value pointers
 struct BatchLayout {
-  size_t ctrl, mats, order, desc, tmap, rmap, vptr, total;
+  size_t ctrl, mats, order, tasks, succ, rem, desc, tmap, rmap, vptr, total;
 };
 
 BatchLayout batch_layout(int32_t count, const BatchSizes& z) {
@@ -740,6 +744,9 @@ BatchLayout batch_layout(int32_t count, const BatchSizes& z) {
   B.ctrl = take(sizeof(ExecCtrl));
   B.mats = take(sizeof(ExecMat) * count);
   B.order = take(z.tasks * 8);
+  B.tasks = take(z.tasks * TASK_WORDS * 4);
+  B.succ = take(z.succ * 4);
+  B.rem = take(z.tasks * 4);
   B.desc = take(sizeof(BatchDesc) * count);
   B.tmap = take(z.tiles * 8);
   B.rmap = take(z.rows * 8);
@@ -846,11 +853,42 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
   std::vector<BatchDesc> desc(count);
   std::vector<int32_t> tmap, rmap;
   stiles_batch* b = new stiles_batch();
+  b->z = batch_sizes(count, factors);
+  b->B = batch_layout(count, b->z);
+  // The batch runs the matrices' factorization DAGs without their two-stage
+  // waits: in a launch over many matrices no single pivot chain bounds the
+  // run, and the second counter round trip of a split task only costs
+  // throughput (512-matrix batch: executor 14.1 -> 13.7 ms).  Same tasks,
+  // same products in the same order: the results do not change.
+  std::vector<int32_t> btasks, bsucc, brem;
+  btasks.reserve(b->z.tasks * TASK_WORDS);
+  bsucc.reserve(b->z.succ);
+  std::vector<size_t> task_off(count), succ_off(count);
+  for (int32_t i = 0; i < count; i++) {
+    const stiles_symbolic& s = *factors[i]->sym;
+    const int32_t nt = factors[i]->mf.ntasks;
+    task_off[i] = btasks.size() / TASK_WORDS;
+    succ_off[i] = bsucc.size();
+    std::vector<int32_t> npred(nt, 0);
+    for (int32_t v : s.fsucc) npred[v & ~SUCC_FDEP]++;
+    for (int32_t t = 0; t < nt; t++) {
+      const int32_t* w = &s.ftask[(size_t)t * TASK_WORDS];
+      btasks.insert(btasks.end(), w, w + TASK_WORDS);
+      int32_t* bw = &btasks[btasks.size() - TASK_WORDS];
+      bw[0] &= ~TF_SPLIT;
+      bw[7] = npred[t];
+      brem.push_back(npred[t]);
+    }
+    for (int32_t v : s.fsucc) bsucc.push_back(v & ~SUCC_FDEP);
+  }
   for (int32_t i = 0; i < count; i++) {
     stiles_factor* f = factors[i];
     const stiles_symbolic& s = *f->sym;
     const Layout& L = f->L;
     mats[i] = f->mf;
+    mats[i].tasks = reinterpret_cast<const int32_t*>(b_ws_at(d_batch_ws, b->B.tasks)) + task_off[i] * TASK_WORDS;
+    mats[i].succ = reinterpret_cast<const int32_t*>(b_ws_at(d_batch_ws, b->B.succ)) + succ_off[i];
+    mats[i].remaining = reinterpret_cast<int32_t*>(b_ws_at(d_batch_ws, b->B.rem)) + task_off[i];
     BatchDesc& d = desc[i];
     if (s.profile_input && !s.perm_identity) {
       d.in_rp = at<int64_t>(f, L.in_rp_in);
@@ -880,12 +918,14 @@ extern "C" stiles_status stiles_batch_create(int32_t count, stiles_factor* const
   b->ws = static_cast<char*>(d_batch_ws);
   b->total = (int32_t)(order.size() / 2);
   b->T = T;
-  b->z = batch_sizes(count, factors);
-  b->B = batch_layout(count, b->z);
   ExecCtrl ctrl{};
   char* w = b->ws;
   hipError_t e = hipMemcpyAsync(w + b->B.ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.mats, mats.data(), sizeof(ExecMat) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.tasks, btasks.data(), btasks.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !bsucc.empty())
+    e = hipMemcpyAsync(w + b->B.succ, bsucc.data(), bsucc.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.rem, brem.data(), brem.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.order, order.data(), order.size() * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(w + b->B.desc, desc.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !tmap.empty())

@@ -18,7 +18,8 @@
 // Usage: exec_race <in> <out> <threads> <seed> [drop_edge]
 //   out receives the factored tiles; drop_edge removes one successor entry
 //   (and its weight from the successor's counter) to plant a missing
-//   dependency.
+//   dependency; the task that lost the edge then starts 20 ms late, so that
+//   its former successor runs first in every interleaving.
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -92,7 +93,9 @@ struct Exec {
       if (failed.load(std::memory_order_relaxed)) return;
     }
   }
+  int32_t slow_task = -1;   // the source of a planted missing edge
   void run_task(int32_t t, std::mt19937& rng) {
+    if (t == slow_task) std::this_thread::sleep_for(std::chrono::milliseconds(20));
     const int32_t* w = &p.tasks[(size_t)t * 8];
     const int type = w[0] & 0xff, T = p.T;
     const bool split = (w[0] & TF_SPLIT) != 0;
@@ -213,6 +216,11 @@ int main(int argc, char** argv) {
     p.succ[e] = -1;
   }
   Exec ex(p);
+  if (argc > 5) {
+    const int32_t e = std::atoi(argv[5]);
+    for (int32_t t = 0; t < p.ntasks; t++)
+      if (p.tasks[(size_t)t * 8 + 5] <= e && e < p.tasks[(size_t)t * 8 + 6]) ex.slow_task = t;
+  }
   const int nth = std::atoi(argv[3]);
   const unsigned seed = (unsigned)std::atoi(argv[4]);
   std::vector<std::thread> th;
