@@ -584,10 +584,10 @@ __device__ __attribute__((noinline)) uint64_t task_trsm(const ExecMat& M, const 
 
 // ------------------------------------------------- diagonal tile: POTRF + TRTRI
 // Blocked right-looking Cholesky of one T x T tile held in LDS, with 16-wide
-// panels.  For each panel the 16 x 16 diagonal block is factored and inverted
-// in the registers of wave 0 (diag_block16), the panel below is solved
-// against the inverse block and the trailing matrix is updated, both as
-// 16 x 16 x 16 MFMA products.  The inverse of the whole factor is built one
+// panels.  For each panel the 16 x 16 diagonal block is factored in the
+// registers of wave 0 (diag_block16) and inverted by all four waves
+// (inv_block16), the panel below is solved against the inverse block and
+// the trailing matrix is updated, both as 16 x 16 x 16 MFMA products.  The inverse of the whole factor is built one
 // block row at a time, as soon as its diagonal block is inverted, on the
 // waves the panel leaves idle:
 //   X_ii = D_i^{-1},  X_ib = -D_i^{-1} sum_{b <= q < i} L_iq X_qb.
@@ -639,19 +639,19 @@ __device__ __forceinline__ double row_bcast(double v, int r) {
   return __hiloint2double(row_bcast32(__double2hiint(v), r), row_bcast32(__double2loint(v), r));
 }
 
-// Cholesky factor and inverse of one 16 x 16 diagonal block on one wave.
-// Lane l holds row i = l & 15 of the columns g + 4 s (g = l >> 4, s = 0..3).
-// Column j: the pivot is read from its lane, the owner lanes scale the
-// column and publish it through LDS (the operations of one wave reach LDS in
-// order), and every lane applies its part of the rank-1 update.  The inverse
-// is built by forward substitution for all 16 right-hand sides at once, row
-// by row; each final row is broadcast inside its 16-lane row by DPP.  The
-// published columns go to pcol (16 columns with leading dimension T): the
-// caller passes the upper block (0, T/16 - 1) of the tile buffer, which no
-// other step uses while a diagonal block is factored.
+// Cholesky factor of one 16 x 16 diagonal block on one wave.  Lane l holds
+// row i = l & 15 of the columns g + 4 s (g = l >> 4, s = 0..3).  Column j:
+// the pivot is read from its lane, the owner lanes scale the column and
+// publish it through LDS (the operations of one wave reach LDS in order),
+// and every lane applies its part of the rank-1 update.  The published
+// columns (zero above the diagonal) go to pcol (16 columns with leading
+// dimension T), the reciprocal pivots to rinv: the caller passes the upper
+// block (0, T/16 - 1) of the tile buffer, which no other step uses while a
+// diagonal block is factored and inverted.  The wave's issue rate, not the
+// latency of the pivot chain, sets its time, so the inverse is left to all
+// four waves (inv_block16).
 template <int T>
-__device__ __forceinline__ void diag_block16(double* S, double* Xi, double* rinv, double* pcol, int c0, int lane,
-                                             int& fail) {
+__device__ __forceinline__ void diag_block16(double* S, double* rinv, double* pcol, int c0, int lane, int& fail) {
   const int i = lane & 15, g = lane >> 4;
   double a[4];
 #pragma unroll
@@ -694,32 +694,27 @@ __device__ __forceinline__ void diag_block16(double* S, double* Xi, double* rinv
 #pragma unroll
     for (int j = 0; j < 16; j++) rinv[c0 + j] = piv[j];
   }
-  double x[4];
-#pragma unroll
-  for (int s = 0; s < 4; s++) x[s] = i == g + 4 * s ? 1.0 : 0.0;
-#pragma unroll
-  for (int r = 0; r < 16; r++) {
-    const double lir = pcol[i + r * T];   // L(i, r)
-    if (i == r) {
-#pragma unroll
-      for (int s = 0; s < 4; s++) x[s] *= piv[r];
-    }
-#pragma unroll
-    for (int s = 0; s < 4; s++) {
-      const double xb = row_bcast(x[s], r);
-      if (i > r) x[s] = fma(-lir, xb, x[s]);
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < 4; s++) {
-    const int c = g + 4 * s;
-    if (i >= c) Xi[(c0 + i) + (c0 + c) * T] = x[s];
-  }
 }
 
-// X(b, q) = -D_b^{-1} sum_{q <= p < b} L(b, p) X(p, q) for one 16 x 16 block
-// of the inverse of the factor (one wave); the partial sum is staged in the
-// unused upper triangle of S at block (q, b)
+// Inverse of a factored 16 x 16 diagonal block (its columns in pcol, the
+// reciprocal pivots in rinv), by all four waves after a barrier: the
+// 16-lane row g of wave w computes column 4 w + g of D^{-1} by forward
+// substitution, each final entry broadcast inside its 16-lane row by DPP.
+template <int T>
+__device__ __forceinline__ void inv_block16(double* Xi, const double* rinv, const double* pcol, int c0, int wave,
+                                            int lane) {
+  const int i = lane & 15, c = 4 * wave + (lane >> 4);
+  double x = i == c ? 1.0 : 0.0;
+#pragma unroll
+  for (int rr = 0; rr < 16; rr++) {
+    const double lir = pcol[i + rr * T];   // L(i, rr)
+    if (i == rr) x *= rinv[c0 + rr];
+    const double xb = row_bcast(x, rr);
+    if (i > rr) x = fma(-lir, xb, x);
+  }
+  if (i >= c) Xi[(c0 + i) + (c0 + c) * T] = x;
+}
+
 template <int T>
 __device__ __forceinline__ void inv_row_block(double* S, double* Xi, int b, int q, int lane) {
   v4d u = v4d{0.0, 0.0, 0.0, 0.0};
@@ -802,11 +797,13 @@ __device__ __attribute__((noinline)) uint64_t task_potrf(const ExecMat& M, const
   __syncthreads();
   int fail = -1;
   double* pcol = S + (T - 16) * T;   // upper block (0, T/16 - 1), unused by the factorization
-  if (tid < 64) diag_block16<T>(S, Xi, rinv, pcol, 0, lane, fail);
+  if (tid < 64) diag_block16<T>(S, rinv, pcol, 0, lane, fail);
 #pragma unroll 1
   for (int b = 0; b < NBK; b++) {
     const int c0 = 16 * b;
     __syncthreads();   // diagonal block b factored, trailing updates of step b-1 done
+    inv_block16<T>(Xi, rinv, pcol, c0, wave, lane);
+    __syncthreads();   // D_b^{-1} complete
     // ---- row block b of the inverse, X(b, q) for q < b, on the waves that
     //      the panel below leaves idle (every input is final by now)
     {
@@ -859,7 +856,7 @@ __device__ __attribute__((noinline)) uint64_t task_potrf(const ExecMat& M, const
       }
       if (tid < 64) {
         __builtin_amdgcn_wave_barrier();
-        diag_block16<T>(S, Xi, rinv, pcol, c0 + 16, lane, fail);
+        diag_block16<T>(S, rinv, pcol, c0 + 16, lane, fail);
       }
     }
   }
