@@ -289,6 +289,34 @@ stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStre
  * of that factor.  STILES_ESTATE if a factor is not factorized.
  * stiles_factorize_batch = create + factorize + destroy.
  */
+/*
+ * Out-of-core (streamed) factorization of a band-plus-arrow envelope given
+ * by its profile (as stiles_analyze_profile, natural order), for a factor
+ * larger than the device memory one wants to commit (the paper leaves
+ * matrices beyond device memory to future work, Sections IV-B and VI).
+ * The band rows are processed in consecutive segments of seg_rows rows:
+ * each segment is factored in core as an arrowhead matrix whose arrow is
+ * the next segment's rows that couple back into it followed by the true
+ * arrow; the trailing factor of that matrix gives the segment's Schur
+ * complement (L_c L_c^T, on the device), which seeds the next segment.  Only
+ * one segment is resident at a time.
+ *   h_values  host, FP64, the matrix in row-profile order (as for
+ *             stiles_factorize with a row-profile analysis)
+ *   seg_rows  band rows per segment; at least the band's reach (every row
+ *             coupling back across a segment boundary must lie in the next
+ *             segment), else EINVAL (argument 5)
+ *   tile      0, 32 or 64
+ *   h_L       host, receives L in the same row-profile layout
+ *   logdet    receives log det A (NaN if not SPD); info: 0, or the 1-based
+ *             row of the first non-positive pivot
+ *   peak_device_bytes  optional: the largest device footprint of a segment
+ * This entry point allocates device memory itself (hipMalloc/hipFree, freed
+ * before it returns) and synchronizes the stream once per segment.
+ */
+stiles_status stiles_factorize_ooc(int64_t n_band, int64_t arrow, const int64_t* first_col, const double* h_values,
+                                   int64_t seg_rows, int32_t tile, double* h_L, double* logdet, int64_t* info,
+                                   size_t* peak_device_bytes, hipStream_t stream);
+
 typedef struct stiles_batch stiles_batch;
 stiles_status stiles_batch_workspace_size(int32_t count, stiles_factor* const* factors, size_t* bytes);
 stiles_status stiles_batch_create(int32_t count, stiles_factor* const* factors, void* d_batch_ws,

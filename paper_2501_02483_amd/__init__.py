@@ -25,7 +25,7 @@ __all__ = [
     "stiles_selinv_create", "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract",
     "stiles_selinv_set_timing", "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy",
     "stiles_factorize_solve", "stiles_factor_set_merged_trace", "stiles_factor_set_wait_limit",
-    "stiles_logdet_static", "STILES_STATIC_LOGDET_MAX_ROWS",
+    "stiles_logdet_static", "STILES_STATIC_LOGDET_MAX_ROWS", "stiles_factorize_ooc",
 ]
 
 # STILES_LIBRARY names another build of the same library (the host-sanitized
@@ -62,6 +62,7 @@ EXPORTED = [
     "stiles_selinv_compute", "stiles_selinv_diag", "stiles_selinv_extract", "stiles_selinv_set_timing",
     "stiles_selinv_kernel_ms", "stiles_selinv_set_trace", "stiles_selinv_destroy", "stiles_factorize_solve",
     "stiles_factor_set_merged_trace", "stiles_factor_set_wait_limit", "stiles_logdet_static",
+    "stiles_factorize_ooc",
 ]
 
 
@@ -104,6 +105,10 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libstiles.so is not built (%s): run __graft_entry__.build() or "
                            "python paper_2501_02483_amd/build.py" % path)
+    # torch first: its HIP runtime is then the one the library's HIP calls
+    # bind to (the library loaded first would bring a second runtime into
+    # the process, which does not see the device torch has opened)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     sig = {
         "stiles_default_opts": (None, [ctypes.POINTER(stiles_opts)]),
@@ -123,6 +128,8 @@ def load_library(path=LIB_PATH):
         "stiles_solve": (_i32, [_vp, _i64, _vp, _i64, _vp, ctypes.POINTER(stiles_solve_report)]),
         "stiles_logdet": (_i32, [_vp, _vp, _vp]),
         "stiles_logdet_static": (_i32, [_vp, _vp, _vp]),
+        "stiles_factorize_ooc": (_i32, [_i64, _i64, _vp, _vp, _i64, _i32, _vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_size_t), _vp]),
         "stiles_factor_set_max_workgroups": (_i32, [_vp, _i32]),
         "stiles_factor_set_wait_limit": (_i32, [_vp, ctypes.c_double]),
         "stiles_factor_release": (None, [_vp]),
@@ -312,6 +319,20 @@ def stiles_factorize_solve(fac, d_values, nrhs, d_B, ldb, stream=None):
 
 def stiles_logdet(fac, d_out, stream=None):
     _check(load_library().stiles_logdet(fac, _ptr(d_out), _stream(stream)), "stiles_logdet")
+
+
+def stiles_factorize_ooc(n_band, arrow, first_col, values, seg_rows, tile=64, stream=None):
+    """Out-of-core factorization (host arrays in row-profile order): returns
+    (L as a host array in the same layout, logdet, info, peak device bytes
+    of one segment)."""
+    first_col = np.ascontiguousarray(first_col, dtype=np.int64)
+    values = np.ascontiguousarray(values, dtype=np.float64)
+    L = np.empty_like(values)
+    ld, info, peak = ctypes.c_double(), _i64(), ctypes.c_size_t()
+    _check(load_library().stiles_factorize_ooc(n_band, arrow, _ptr(first_col), _ptr(values), seg_rows, tile,
+                                               _ptr(L), ctypes.byref(ld), ctypes.byref(info), ctypes.byref(peak),
+                                               _stream(stream)), "stiles_factorize_ooc")
+    return L, ld.value, info.value, peak.value
 
 
 def stiles_logdet_static(fac, d_out, stream=None):

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstiles.so")
 GEN_LIB = os.path.join(HERE, "libstiles_gen.so")
-SOURCES = ["analyze.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["analyze.cpp", "capi.cpp", "ooc.cpp", "kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

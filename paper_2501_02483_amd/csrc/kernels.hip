@@ -2256,6 +2256,73 @@ hipError_t launch_residual(int T, const double* orig, const int32_t* rtile, cons
   return hipGetLastError();
 }
 
+// ------------------------------------------------ out-of-core factorization
+// S = Lc Lc^T (lower part, c x c, row-major) for the dense lower-triangular
+// trailing block Lc of a factor stored in row-profile order: Lc(i, t) =
+// L[rp[r0 + i] + (c0 + t - f[r0 + i])], t <= i.  16 x 16 tiles of S per
+// workgroup, 64 columns of both row panels staged in LDS per step.
+__global__ __launch_bounds__(256) void gram_lower_kernel(int32_t c, const double* __restrict__ L,
+                                                         const int64_t* __restrict__ rp, const int64_t* __restrict__ f,
+                                                         int64_t r0, int64_t c0, double* __restrict__ S) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  __shared__ double A[16][65], B[16][65];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int ri = 16 * bi + ty, rj = 16 * bj + ty;   // rows staged by this thread
+  const int64_t oi = ri < c ? rp[r0 + ri] + c0 - f[r0 + ri] : 0;
+  const int64_t oj = rj < c ? rp[r0 + rj] + c0 - f[r0 + rj] : 0;
+  const int tmax = min(c, 16 * bj + 16);            // Lc(j, t) = 0 for t > j
+  double acc = 0.0;
+  for (int t0 = 0; t0 < tmax; t0 += 64) {
+#pragma unroll
+    for (int q = tx; q < 64; q += 16) {
+      const int t = t0 + q;
+      A[ty][q] = (ri < c && t <= ri) ? L[oi + t] : 0.0;
+      B[ty][q] = (rj < c && t <= rj) ? L[oj + t] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int q = 0; q < 64; q++) acc = fma(A[ty][q], B[tx][q], acc);
+    __syncthreads();
+  }
+  const int i = 16 * bi + ty, j = 16 * bj + tx;
+  if (i < c && j <= i) S[(int64_t)i * c + j] = acc;
+}
+
+hipError_t launch_gram_lower(int32_t c, const double* L, const int64_t* rp, const int64_t* f, int64_t r0, int64_t c0,
+                             double* S, hipStream_t st) {
+  if (c <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((c + 15) / 16);
+  hipLaunchKernelGGL(gram_lower_kernel, dim3(nb, nb), dim3(256), 0, st, c, L, rp, f, r0, c0, S);
+  return hipGetLastError();
+}
+
+// acc += 2 sum_r log L(r, r) over rows [r0, r1) of a factor in row-profile
+// order (diagonal = last entry of a row); one workgroup, fixed summation
+// order (per-thread strided sums, then a tree), so the result is
+// reproducible.  NaN when a pivot is not positive.
+__global__ __launch_bounds__(256) void logdet_rows_kernel(const double* __restrict__ L, const int64_t* __restrict__ rp,
+                                                          int64_t r0, int64_t r1, double* acc) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    const double d = L[rp[r + 1] - 1];
+    s += d > 0.0 ? 2.0 * log(d) : NAN;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *acc += red[0];
+}
+
+hipError_t launch_logdet_rows(const double* L, const int64_t* rp, int64_t r0, int64_t r1, double* acc, hipStream_t st) {
+  hipLaunchKernelGGL(logdet_rows_kernel, dim3(1), dim3(256), 0, st, L, rp, r0, r1, acc);
+  return hipGetLastError();
+}
+
 // Per-column max |R| and max |X| over the tile-row blocks (T x nrhs each).
 // Block (x, c) covers 16 tile rows of column c and reduces in LDS before one
 // atomic per value.  Maxima are taken on the bit patterns of |v|

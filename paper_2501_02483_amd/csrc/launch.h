@@ -41,6 +41,12 @@ hipError_t launch_extract(int T, const double* tiles, const int64_t* rp, const i
                           const int32_t* tcol, const int64_t* row_base, const int32_t* row_cnt, int64_t ntiles,
                           int64_t nnz, double* out, hipStream_t st);
 
+// out-of-core factorization: S = Lc Lc^T of a factor's dense trailing block
+// (row-profile storage), and 2 sum log diag over a range of its rows
+hipError_t launch_gram_lower(int32_t c, const double* L, const int64_t* rp, const int64_t* f, int64_t r0, int64_t c0,
+                             double* S, hipStream_t st);
+hipError_t launch_logdet_rows(const double* L, const int64_t* rp, int64_t r0, int64_t r1, double* acc, hipStream_t st);
+
 hipError_t launch_logdet(int T, const double* tiles, const int32_t* trow_ptr, int32_t ntr, double* part,
                          const unsigned long long* info, double* out, hipStream_t st);
 

@@ -39,7 +39,7 @@ def asan_runtime():
 def build():
     os.makedirs(OUT, exist_ok=True)
     objs = []
-    for src in ("analyze.cpp", "capi.cpp"):
+    for src in ("analyze.cpp", "capi.cpp", "ooc.cpp"):
         obj = os.path.join(OUT, src + ".o")
         subprocess.check_call([HIPCC, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + SAN)
         objs.append(obj)
