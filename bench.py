@@ -677,6 +677,43 @@ def bench_serve(args):
             "results": res}
 
 
+def bench_ooc(args):
+    """Out-of-core factorization of the variable-band matrix (host values in,
+    host factor out): time per factorization and device footprint for a few
+    segment lengths, against the in-core factorization's workspace."""
+    import torch
+
+    import paper_2501_02483_amd as S
+    from paper_2501_02483_amd import inputs as I
+
+    p, seed = I.variable_band(), 2
+    vals = I.make_values(p, seed=seed)
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=S.STILES_ORDER_NONE)
+    in_core = sym.workspace_size(S.STILES_FP64, 1)
+    F = sym.info.flops_alg
+    runs = {}
+    for seg in (args.seg_rows or [10000, 20000, 50000]):
+        S.stiles_factorize_ooc(p.n, p.a, p.f[:p.n], vals, seg)          # warm-up
+        ts = []
+        for _ in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, ld, info, peak = S.stiles_factorize_ooc(p.n, p.a, p.f[:p.n], vals, seg)
+            ts.append(time.perf_counter() - t0)
+        runs[str(seg)] = {"ms": float(np.median(ts)) * 1e3, "peak_device_mb": peak / 2 ** 20, "info": info,
+                          "logdet": ld, "segments": -(-p.n // seg)}
+        print("[ooc] segments of %d rows: %.1f ms, %.1f MB" % (seg, runs[str(seg)]["ms"], peak / 2 ** 20),
+              file=sys.stderr, flush=True)
+    best = min(runs.values(), key=lambda r: r["ms"])
+    return {"metric": "out-of-core arrowhead Cholesky TFLOP/s (host values -> host factor)",
+            "value": F / (best["ms"] * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "varband%d_a%d_ooc" % (p.n, p.a), "n": p.n, "arrow": p.a, "tile": 64,
+                       "ordering": "natural"},
+            "in_core_workspace_mb": in_core / 2 ** 20, "runs": runs}
+
+
 def bench_copycal(args):
     """Plain device copy of a known size (counter calibration for HBM traffic)."""
     import torch
@@ -726,7 +763,7 @@ def main():
     ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
                     help="single-matrix workloads: natural order or adaptable nested dissection")
     ap.add_argument("--parts", type=int, default=0, help="adaptable ND partitions (0 = chosen by the analysis)")
-    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal", "selinv", "spde"])
+    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal", "selinv", "spde", "ooc"])
     ap.add_argument("--rocpd-summary", default="", help="print a per-kernel table of a rocprofv3 database and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ublock", type=int, default=0,
@@ -748,6 +785,8 @@ def main():
     ap.add_argument("--serve-precision", default="both", choices=["fp64", "mixed", "both"],
                     help="serve: FP64 factors, mixed precision (FP32 updates, FP64 refinement), or both in turn")
     ap.add_argument("--max-n", type=int, default=0, help="serve: keep patterns with n <= max-n")
+    ap.add_argument("--seg-rows", type=int, nargs="*", default=None,
+                    help="ooc: band rows per segment (default: 10000 20000 50000)")
     args = ap.parse_args()
     global UBLOCK
     UBLOCK = args.ublock
@@ -773,6 +812,8 @@ def main():
         res = bench_selinv(args)
     elif args.workload == "spde":
         res = bench_spde(args)
+    elif args.workload == "ooc":
+        res = bench_ooc(args)
     else:
         res = bench_serve(args)
     print(json.dumps(res), flush=True)
