@@ -61,6 +61,7 @@ def _export(plan, Aperm, path, drop=None):
 def _run(exe, inp, out, seed, drop=None):
     cmd = [exe, inp, out, "8", str(seed)] + ([str(drop)] if drop is not None else [])
     env = dict(os.environ, TSAN_OPTIONS=TSAN_OPTIONS)
+    env.pop("LD_PRELOAD", None)   # a preloaded ASan runtime (host sanitizer run) cannot share with TSan
     return subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
 
 
