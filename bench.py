@@ -677,6 +677,141 @@ def bench_serve(args):
             "results": res}
 
 
+def lapack_banded(p, vals):
+    """Context row (not the oracle): LAPACK's band Cholesky (pbtrf through
+    scipy.linalg.cholesky_banded, multithreaded BLAS) on the band block B of a
+    constant-half-width arrowhead matrix [[B, C^T], [C, D]], then the arrow
+    in NumPy: X = L_B^{-1} C^T by blocked forward substitution (row blocks of
+    w: a triangular solve with the diagonal block and a product with the
+    block to its left), S = D - X^T X, L_D = chol(S).  Returns the seconds of
+    each part and log det A.  The inputs are converted to LAPACK's lower band
+    storage before the clock starts."""
+    from numpy.lib.stride_tricks import as_strided
+    from scipy.linalg import blas, cholesky, cholesky_banded
+
+    n, a = p.n, p.a
+    f = p.f
+    w = int(np.max(np.arange(n) - f[:n]))
+    rp = p.row_ptr()
+    # lower band storage, column-major: ab[d, j] = A[j + d, j]; entry (i, j)
+    # of the band sits at flat index i + j w
+    ab = np.zeros((w + 1, n), order="F")
+    flat = ab.reshape(-1, order="F")
+    step = 1 << 20
+    for r0 in range(0, n, step):
+        r1 = min(n, r0 + step)
+        lens = rp[r0 + 1:r1 + 1] - rp[r0:r1]
+        rows = np.repeat(np.arange(r0, r1, dtype=np.int64), lens)
+        cols = np.arange(rp[r0], rp[r1], dtype=np.int64) - rp[rows] + f[rows]
+        flat[rows + cols * w] = vals[rp[r0]:rp[r1]]
+    C = np.zeros((a, n))
+    D = np.zeros((a, a))
+    for r in range(a):
+        i = n + r
+        row = vals[rp[i]:rp[i + 1]]          # columns 0 .. i (dense arrow)
+        C[r] = row[:n]
+        D[r, :r + 1] = row[n:]
+    t0 = time.perf_counter()
+    Lb = cholesky_banded(ab, lower=True, overwrite_ab=True, check_finite=False)
+    t1 = time.perf_counter()
+    Lf = np.asfortranarray(Lb).reshape(-1, order="F")
+
+    def view(r0, r1, c0, c1):
+        # L[r0:r1, c0:c1] read through the band storage as a column-major
+        # matrix (leading dimension w); entries outside the band (j > i or
+        # i - j > w) alias other storage, so only the triangle that lies in
+        # the band is handed to BLAS
+        return as_strided(Lf[r0 + c0 * w:], shape=(r1 - r0, c1 - c0), strides=(8, 8 * w))
+
+    # row blocks of w rows: X_k = L_kk^{-1} (C_k^T - U_k X_(k-1)), with L_kk
+    # the lower triangular diagonal block and U_k the upper triangular block
+    # to its left (the previous w columns); S = D - sum_k X_k^T X_k
+    b = max(w, 1)
+    Sc = np.asfortranarray(D)      # lower triangle; S is formed there (syrk)
+    Xprev = None
+    for s0 in range(0, n, b):
+        s1 = min(n, s0 + b)
+        rhs = np.asfortranarray(C[:, s0:s1].T)
+        if Xprev is not None:
+            U = view(s0, s1, s0 - b, s0)
+            if s1 - s0 < b:      # short last block: its rows of U, then a plain product
+                rhs -= np.triu(U) @ Xprev
+            else:
+                rhs -= blas.dtrmm(1.0, U, Xprev, side=0, lower=0)
+        Xk = blas.dtrsm(1.0, view(s0, s1, s0, s1), rhs, side=0, lower=1, overwrite_b=1)
+        Sc = blas.dsyrk(-1.0, Xk, beta=1.0, c=Sc, trans=1, lower=1, overwrite_c=1)
+        Xprev = Xk
+    Ld = cholesky(Sc, lower=True, check_finite=False)
+    t2 = time.perf_counter()
+    logdet = 2.0 * (np.sum(np.log(Lb[0])) + np.sum(np.log(np.diag(Ld))))
+    return {"band_pbtrf_s": t1 - t0, "arrow_s": t2 - t1, "total_s": t2 - t0, "logdet": float(logdet), "w": w}
+
+
+def bench_banded(args):
+    """Context row: LAPACK band Cholesky + NumPy arrow on the host cores, on
+    the constant-half-width workloads (n = 2,000, w = 50, a = 10 and
+    n = 500,000, w = 1,000, a = 200), beside the GPU's FP64 factorization +
+    log-determinant of the same matrices (adaptable ND, T = 64)."""
+    from paper_2501_02483_amd import inputs as I
+
+    pats = [I.single_small(), I.mixed_large(n=args.n or 500_000)]
+    rows = []
+    for p in pats:
+        vals = I.make_values(p, seed=4 if p.n > 100_000 else 1)
+        F = flops_alg(p.f)
+        reps = 3 if p.n <= 100_000 else 1
+        ts = [lapack_banded(p, vals) for _ in range(reps)]
+        best = min(ts, key=lambda r: r["total_s"])
+        row = {"workload": p.name, "n": p.n, "arrow": p.a, "half_width": best["w"], "flops_alg": F,
+               "lapack": best, "lapack_tflops": F / best["total_s"] / 1e12, "threads": cpu_threads(),
+               "cpu_model": cpu_model()}
+        gpu = gpu_fp64_factor(p, vals)
+        if gpu is not None:
+            row["gpu"] = gpu
+            row["gpu_tflops"] = F / (gpu["step_ms"] * 1e-3) / 1e12
+            row["gpu_over_lapack"] = best["total_s"] / (gpu["step_ms"] * 1e-3)
+            row["logdet_rel_diff"] = abs(gpu["logdet"] - best["logdet"]) / abs(best["logdet"])
+        rows.append(row)
+        print(json.dumps({"context_row": row}), file=sys.stderr, flush=True)
+    big = rows[-1]
+    return {"metric": "LAPACK band Cholesky + arrow, TFLOP/s (host context)", "value": big["lapack_tflops"],
+            "unit": "TFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": big["lapack"]["total_s"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic (host-generated, dominant law)",
+            "config": {"workload": "banded_context", "rows": [r["workload"] for r in rows]}, "rows": rows}
+
+
+def gpu_fp64_factor(p, vals):
+    """The library's FP64 scatter + factorization + log-determinant of the
+    same matrix on the GPU (values resident; adaptable ND, T = 64), median
+    of 5 after one warm-up, or None without a GPU."""
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+    except ImportError:
+        return None
+    import paper_2501_02483_amd as S
+    sym = S.Symbolic.from_pattern(p, tile=64, ordering=S.STILES_ORDER_ADAPTABLE_ND)
+    fac = S.Factor(sym)
+    dv = torch.from_numpy(vals).cuda()
+    ts, ld = [], None
+    for it in range(6):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fac.factorize(dv)
+        ld = fac.logdet()
+        e1.record()
+        torch.cuda.synchronize()
+        if it:
+            ts.append(e0.elapsed_time(e1))
+    info = fac.info()
+    del fac, sym, dv
+    torch.cuda.empty_cache()
+    return {"step_ms": float(np.median(ts)), "min_ms": float(np.min(ts)), "logdet": float(ld.item()), "info": int(info)}
+
+
 def bench_ooc(args):
     """Out-of-core factorization of the variable-band matrix (host values in,
     host factor out): time per factorization and device footprint for a few
@@ -763,7 +898,7 @@ def main():
     ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
                     help="single-matrix workloads: natural order or adaptable nested dissection")
     ap.add_argument("--parts", type=int, default=0, help="adaptable ND partitions (0 = chosen by the analysis)")
-    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal", "selinv", "spde", "ooc"])
+    ap.add_argument("--workload", default="varband", choices=["varband", "small", "batch", "mixed", "serve", "copycal", "selinv", "spde", "ooc", "banded"])
     ap.add_argument("--rocpd-summary", default="", help="print a per-kernel table of a rocprofv3 database and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ublock", type=int, default=0,
@@ -814,6 +949,8 @@ def main():
         res = bench_spde(args)
     elif args.workload == "ooc":
         res = bench_ooc(args)
+    elif args.workload == "banded":
+        res = bench_banded(args)
     else:
         res = bench_serve(args)
     print(json.dumps(res), flush=True)
