@@ -623,6 +623,7 @@ def bench_serve(args):
     ordering = S.STILES_ORDER_ADAPTABLE_ND if args.ordering == "nd" else S.STILES_ORDER_NONE
     precisions = {"fp64": [S.STILES_FP64], "mixed": [S.STILES_MIXED32],
                   "both": [S.STILES_FP64, S.STILES_MIXED32]}[args.serve_precision]
+    policies = {"sjf": ["sjf"], "fifo": ["fifo"], "both": ["fifo", "sjf"]}[args.serve_policy]
 
     def serve_one(prec):
         name = "fp64" if prec == S.STILES_FP64 else "mixed"
@@ -645,18 +646,24 @@ def bench_serve(args):
         done = Server(ex, budget, slots).run(sat)
         mu = len(done) / max(r.t_done for r in done)
         print("[serve %s] saturation %.1f req/s over %d requests" % (name, mu, nsat), file=sys.stderr, flush=True)
-        res = {"saturation_rps": mu, "slots": slots, "syms_nd_parts": [s.info.nd_parts for s in ex.syms]}
+        res = {"saturation_rps": mu, "slots": slots, "syms_nd_parts": [s.info.nd_parts for s in ex.syms],
+               "policies": {}}
         flops = lambda r: ex.flops(r.pattern)
-        for frac in (0.5, 0.8):
-            reqs = [Request(rid=i, arrival=t, pattern=pi, op=op, seed=sd, precision=prec)
-                    for i, (t, pi, op, sd) in enumerate(I.serving_requests(len(pats), args.requests, frac * mu))]
-            srv = Server(ex, budget, slots)
-            d = srv.run(reqs)
-            bad = sum(1 for r in d if r.result.get("info", 0) != 0)
-            res["load_%.1f" % frac] = dict(summarize(d, flops), failed=bad, max_used_gb=srv.max_used / 2 ** 30)
-            print("[serve %s] load %.1f: %d requests, p50 %.1f ms, p99 %.1f ms" % (
-                name, frac, len(d), res["load_%.1f" % frac]["p50_ms"], res["load_%.1f" % frac]["p99_ms"]),
-                file=sys.stderr, flush=True)
+        for policy in policies:
+            out = res["policies"][policy] = {}
+            for frac in (0.5, 0.8):
+                reqs = [Request(rid=i, arrival=t, pattern=pi, op=op, seed=sd, precision=prec)
+                        for i, (t, pi, op, sd) in enumerate(I.serving_requests(len(pats), args.requests, frac * mu))]
+                srv = Server(ex, budget, slots, policy=policy)
+                d = srv.run(reqs)
+                bad = sum(1 for r in d if r.result.get("info", 0) != 0)
+                out["load_%.1f" % frac] = dict(summarize(d, flops), failed=bad, max_used_gb=srv.max_used / 2 ** 30)
+                print("[serve %s %s] load %.1f: %d requests, p50 %.1f ms, p99 %.1f ms, mean %.1f ms" % (
+                    name, policy, frac, len(d), out["load_%.1f" % frac]["p50_ms"],
+                    out["load_%.1f" % frac]["p99_ms"], out["load_%.1f" % frac]["mean_ms"]),
+                    file=sys.stderr, flush=True)
+        # the first policy's figures are the precision's headline
+        res.update(res["policies"][policies[0]])
         ex.close()
         del ex
         torch.cuda.synchronize()
@@ -673,7 +680,7 @@ def bench_serve(args):
             "data": "synthetic (device-generated values per request)",
             "config": {"workload": "serve8", "patterns": [(p.n, int(p.n - p.f[p.n - 1]), p.a) for p in pats],
                        "slots": args.slots, "budget_gb": args.budget_gb, "requests": args.requests,
-                       "precisions": list(res), "host_threads": args.host_threads},
+                       "precisions": list(res), "host_threads": args.host_threads, "policies": policies},
             "results": res}
 
 
@@ -919,6 +926,9 @@ def main():
                     help="serve: issue requests from one host thread per slot (auto: mixed precision only)")
     ap.add_argument("--serve-precision", default="both", choices=["fp64", "mixed", "both"],
                     help="serve: FP64 factors, mixed precision (FP32 updates, FP64 refinement), or both in turn")
+    ap.add_argument("--serve-policy", default="both", choices=["sjf", "fifo", "both"],
+                    help="serve: admission order, arrival order (fifo) or least expected work first (sjf); "
+                         "both: fifo (the headline) then sjf")
     ap.add_argument("--max-n", type=int, default=0, help="serve: keep patterns with n <= max-n")
     ap.add_argument("--seg-rows", type=int, nargs="*", default=None,
                     help="ooc: band rows per segment (default: 10000 20000 50000)")

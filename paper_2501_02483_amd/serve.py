@@ -43,18 +43,31 @@ class Request:
 
 
 class Server:
-    """Admission (FIFO with bounded bypass), slot assignment, completion.
+    """Admission, slot assignment, completion.
 
     A request is admitted when a slot is free and the in-flight footprint plus
-    its own stays within the HBM budget.  When the queue head does not fit,
-    later requests that fit may bypass it, but the head can be bypassed at most
-    `max_bypass` times (no starvation)."""
+    its own stays within the HBM budget.  Two orders of admission:
 
-    def __init__(self, executor, budget_bytes, slots, max_bypass=4):
+    policy "fifo": arrival order.  When the queue head does not fit, later
+    requests that fit may bypass it, but the head can be bypassed at most
+    `max_bypass` times (no starvation).
+
+    policy "sjf": the queued request with the least expected work first
+    (executor.cost(req); ties by arrival), which shortens the waits of the
+    many small requests behind a large one.  Every admission ahead of an
+    older queued request counts as one bypass of it; a request bypassed
+    `max_overtake` times goes next (the oldest such first) and nothing else is
+    admitted until it fits, so no request starves."""
+
+    def __init__(self, executor, budget_bytes, slots, max_bypass=4, policy="fifo", max_overtake=16):
+        if policy not in ("fifo", "sjf"):
+            raise ValueError("policy must be 'fifo' or 'sjf'")
         self.ex = executor
         self.budget = budget_bytes
         self.slots = slots
         self.max_bypass = max_bypass
+        self.policy = policy
+        self.max_overtake = max_overtake
         self.inflight = {}        # slot -> request
         self.used = 0
         self.max_used = 0
@@ -80,6 +93,8 @@ class Server:
         self.ex.launch(req, slot)
 
     def _try_admit(self, queue, now):
+        if self.policy == "sjf":
+            return self._try_admit_sjf(queue, now)
         while queue and self._free_slot() >= 0:
             head = queue[0]
             if self.ex.footprint(head) > self.budget:
@@ -97,6 +112,25 @@ class Server:
                     break
             else:
                 return
+
+    def _try_admit_sjf(self, queue, now):
+        while queue and self._free_slot() >= 0:
+            for r in queue:
+                if self.ex.footprint(r) > self.budget:
+                    raise ValueError("request %d needs more than the whole budget" % r.rid)
+            starving = [r for r in queue if r.bypassed >= self.max_overtake]
+            if starving:
+                cands = [min(starving, key=lambda r: (r.arrival, r.rid))]
+            else:
+                cands = sorted(queue, key=lambda r: (self.ex.cost(r), r.arrival, r.rid))
+            pick = next((r for r in cands if self.used + self.ex.footprint(r) <= self.budget), None)
+            if pick is None:
+                return
+            for r in queue:
+                if r is not pick and (r.arrival, r.rid) < (pick.arrival, pick.rid):
+                    r.bypassed += 1
+            queue.remove(pick)
+            self._admit(pick, now)
 
     def run(self, requests):
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -164,6 +198,9 @@ class FakeExecutor:
 
     def footprint(self, req):
         return self.ws[req.pattern] + self.vb[req.pattern]
+
+    def cost(self, req):
+        return self.flops[req.pattern] / self.rate + self.overhead
 
     def launch(self, req, slot):
         self.active[req.rid] = self.flops[req.pattern] / self.rate + self.overhead
@@ -258,6 +295,11 @@ class GpuExecutor:
 
     def flops(self, pattern):
         return self.syms[pattern].info.flops_alg
+
+    def cost(self, req):
+        """Expected work of a request (for shortest-first admission): the
+        flops its factorization executes."""
+        return self.syms[req.pattern].info.flops_exec
 
     def footprint(self, req):
         p = self.patterns[req.pattern]

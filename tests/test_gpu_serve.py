@@ -30,10 +30,13 @@ def test_serve_mix_equals_alone_and_oracle():
     budget = 8 << 30
     ex = GpuExecutor(pats, tile=64, slots=4)
     reqs = [Request(rid=i, arrival=0.0, pattern=i % 3, op=(i // 3) % 3, seed=700 + i) for i in range(18)]
-    say("[gpu serve] mix of %d requests on 4 slots" % len(reqs))
-    done = Server(ex, budget, 4).run(reqs)
+    say("[gpu serve] mix of %d requests on 4 slots, shortest first" % len(reqs))
+    srv = Server(ex, budget, 4, policy="sjf")
+    done = srv.run(reqs)
     torch.cuda.synchronize()
     assert len(done) == len(reqs)
+    # all arrived at once: the four slots start with the cheapest pattern's requests
+    assert [reqs[rid].pattern for rid in srv.admit_order[:4]] == [0, 0, 0, 0]
     assert all(r.result["info"] == 0 for r in done)
     # the mix really overlapped: some request was admitted before another finished
     overlap = sum(1 for r in done for q in done if q.rid != r.rid and q.t_admit < r.t_done and r.t_admit < q.t_done)
