@@ -598,21 +598,6 @@ __device__ __forceinline__ double bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// 16 x 16 x 16 product on one wave: acc += A B with A(i, l) = a(i, l), B(l, j)
-// = b(l, j); a and b are LDS column-major with leading dimension `lda`/`ldb`.
-// Output layout: acc[r] = D[(lane >> 4) + 4 r][lane & 15] ... but A is taken
-// from the B-side for coalesced rows, see mma_f64; here the mapping is:
-// D(i, j) = sum_l A(i, l) B(l, j), lane l, reg r holds D[(l>>4)+4r][l&15].
-__device__ __forceinline__ v4d mma16(v4d acc, const double* A, int lda, const double* B, int ldb, int lane) {
-#pragma unroll
-  for (int k = 0; k < 16; k += 4) {
-    const double av = A[(lane & 15) + (k + (lane >> 4)) * lda];   // A(i = lane&15, l = k + lane>>4)
-    const double bv = B[(k + (lane >> 4)) + (lane & 15) * ldb];   // B(l = k + lane>>4, j = lane&15)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-  }
-  return acc;
-}
-
 // broadcast of lane r of every 16-lane row to the whole row (DPP row_newbcast)
 __device__ __forceinline__ int row_bcast32(int v, int r) {
   switch (r) {
