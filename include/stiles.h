@@ -295,11 +295,13 @@ stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStre
  * larger than the device memory one wants to commit (the paper leaves
  * matrices beyond device memory to future work, Sections IV-B and VI).
  * The band rows are processed in consecutive segments of seg_rows rows:
- * each segment is factored in core as an arrowhead matrix whose arrow is
- * the next segment's rows that couple back into it followed by the true
- * arrow; the trailing factor of that matrix gives the segment's Schur
- * complement (L_c L_c^T, on the device), which seeds the next segment.  Only
- * one segment is resident at a time.
+ * each segment is factored in core as an arrowhead matrix whose band part is
+ * the segment's rows followed by the next segment's rows that couple back
+ * into it (with their own profiles) and whose arrow is the true arrow; the
+ * trailing factor of that matrix (those coupling rows and the arrow) gives
+ * the segment's Schur complement (L_c L_c^T, on the device), which seeds the
+ * next segment.  Only one segment is resident at a time; the assembly of a
+ * segment's values and the scatter of its factor use up to 16 host threads.
  *   h_values  host, FP64, the matrix in row-profile order (as for
  *             stiles_factorize with a row-profile analysis)
  *   seg_rows  band rows per segment; at least the band's reach (every row

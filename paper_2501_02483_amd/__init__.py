@@ -321,13 +321,19 @@ def stiles_logdet(fac, d_out, stream=None):
     _check(load_library().stiles_logdet(fac, _ptr(d_out), _stream(stream)), "stiles_logdet")
 
 
-def stiles_factorize_ooc(n_band, arrow, first_col, values, seg_rows, tile=64, stream=None):
+def stiles_factorize_ooc(n_band, arrow, first_col, values, seg_rows, tile=64, stream=None, out=None):
     """Out-of-core factorization (host arrays in row-profile order): returns
     (L as a host array in the same layout, logdet, info, peak device bytes
-    of one segment)."""
+    of one segment).  `out`: a float64 host array of values' size to receive
+    L (reused across calls), else one is allocated."""
     first_col = np.ascontiguousarray(first_col, dtype=np.int64)
     values = np.ascontiguousarray(values, dtype=np.float64)
-    L = np.empty_like(values)
+    if out is None:
+        L = np.empty_like(values)
+    else:
+        if out.dtype != np.float64 or out.shape != values.shape or not out.flags["C_CONTIGUOUS"]:
+            raise ValueError("out must be a contiguous float64 array of the values' shape")
+        L = out
     ld, info, peak = ctypes.c_double(), _i64(), ctypes.c_size_t()
     _check(load_library().stiles_factorize_ooc(n_band, arrow, _ptr(first_col), _ptr(values), seg_rows, tile,
                                                _ptr(L), ctypes.byref(ld), ctypes.byref(info), ctypes.byref(peak),

@@ -5,12 +5,13 @@
 //
 // The band rows are cut into consecutive segments.  Segment k is factored
 // in core as an arrowhead matrix of its own, M_k: its band part is the
-// segment's rows, its arrow part the rows of the next segment that couple
-// back into segment k (the interface) followed by the true arrow.  M_k's
-// band part and the interface and arrow rows' entries in the segment's
-// columns are final entries of L (block Cholesky: eliminating the segment's
-// columns does not depend on anything after them).  Its trailing (arrow)
-// block factors the Schur complement S_k of the segment, so S_k = Lc Lc^T
+// segment's rows followed by the rows of the next segment that couple back
+// into segment k (the interface, each row with its own profile), its arrow
+// the true arrow.  The segment's rows of M_k's factor and the interface and
+// arrow rows' entries in the segment's columns are final entries of L
+// (block Cholesky: eliminating the segment's columns does not depend on
+// anything after them).  Its trailing block (interface and arrow rows and
+// columns) factors the Schur complement S_k of the segment, so S_k = Lc Lc^T
 // with Lc that block of M_k's factor (a device kernel); S_k replaces the
 // interface block, the arrow rows' interface columns and the arrow corner
 // in M_(k+1).  The last segment has no interface; its trailing block is the
@@ -23,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "launch.h"
@@ -49,6 +51,32 @@ struct DevBuf {
   template <typename E>
   E* as() const { return static_cast<E*>(p); }
 };
+
+// f(lo, hi) over [0, n) in contiguous chunks on up to 16 host threads (the
+// caller's thread takes the first chunk, and any chunk no thread could be
+// started for); every chunk writes its own rows
+template <typename F>
+void parallel_rows(int64_t n, F&& f) {
+  const unsigned hc = std::thread::hardware_concurrency();
+  const int64_t T = std::min<int64_t>({(int64_t)std::clamp(hc, 1u, 16u), n / 16, (int64_t)16});
+  if (T <= 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t started = 1;
+  try {
+    th.reserve((size_t)T - 1);
+    for (int64_t t = 1; t < T; t++) {
+      th.emplace_back([&f, n, t, T] { f(n * t / T, n * (t + 1) / T); });
+      started = t + 1;
+    }
+  } catch (...) {
+  }
+  f((int64_t)0, n / T);
+  for (int64_t t = started; t < T; t++) f(n * t / T, n * (t + 1) / T);
+  for (auto& x : th) x.join();
+}
 
 }  // namespace
 
@@ -103,45 +131,57 @@ extern "C" stiles_status stiles_factorize_ooc(int64_t n, int64_t a, const int64_
     const int64_t s0 = sb[k], s1 = sb[k + 1];
     const int64_t nb = s1 - s0, ni = k + 1 < m ? eb[k + 1] - s1 : 0, Nk = nb + ni + a;
     const bool last = k + 1 == m;
-    // M_k's profile: band rows from the segment, dense trailing rows
+    // M_k's profile: band rows from the segment and the interface rows (each
+    // from its first column in A, which is not before s0), the arrow rows
+    // dense.  An interface row starts at the segment's last column at the
+    // latest (a row of the range that does not couple back then holds one
+    // explicit zero there), so that every row of the trailing block covers
+    // all of its columns, as the Gram kernel reads them.
     std::vector<int64_t> fM(Nk, 0), rpM(Nk + 1, 0);
     for (int64_t r = 0; r < nb; r++) fM[r] = std::max(first_col[s0 + r], s0) - s0;
+    for (int64_t ii = 0; ii < ni; ii++) fM[nb + ii] = std::min(first_col[s1 + ii] - s0, nb - 1);
     for (int64_t r = 0; r < Nk; r++) rpM[r + 1] = rpM[r] + (r - fM[r] + 1);
     vM.assign(rpM[Nk], 0.0);
     // values: the original entries, except the previous segment's Schur
     // complement on its interface block, the arrow rows' interface columns
     // and the arrow corner
     auto Sp = [&](int64_t i, int64_t j) { return S_prev[(size_t)i * c_prev + j]; };
-    for (int64_t r = 0; r < nb; r++) {
-      const int64_t i = s0 + r;
-      for (int64_t cM = fM[r]; cM <= r; cM++) {
-        const int64_t gc = s0 + cM;
-        vM[rpM[r] + cM - fM[r]] = (k > 0 && i < eb[k] && gc < eb[k]) ? Sp(i - s0, gc - s0) : A(i, gc);
-      }
-    }
-    for (int64_t ii = 0; ii < ni; ii++) {
-      const int64_t i = s1 + ii, r = nb + ii;
-      for (int64_t cM = 0; cM <= r; cM++) vM[rpM[r] + cM] = A(i, cM < nb ? s0 + cM : s1 + (cM - nb));
-    }
-    for (int64_t t = 0; t < a; t++) {
-      const int64_t r = nb + ni + t;
-      for (int64_t cM = 0; cM <= r; cM++) {
-        double v;
-        if (cM < nb) {
+    parallel_rows(nb, [&](int64_t lo, int64_t hi) {
+      for (int64_t r = lo; r < hi; r++) {
+        const int64_t i = s0 + r;
+        for (int64_t cM = fM[r]; cM <= r; cM++) {
           const int64_t gc = s0 + cM;
-          v = (k > 0 && gc < eb[k]) ? Sp(ni_prev + t, gc - s0) : A(n + t, gc);
-        } else if (cM < nb + ni) {
-          v = A(n + t, s1 + (cM - nb));
-        } else {
-          const int64_t u = cM - nb - ni;
-          v = k > 0 ? Sp(ni_prev + t, ni_prev + u) : A(n + t, n + u);
+          vM[rpM[r] + cM - fM[r]] = (k > 0 && i < eb[k] && gc < eb[k]) ? Sp(i - s0, gc - s0) : A(i, gc);
         }
-        vM[rpM[r] + cM] = v;
       }
-    }
+    });
+    parallel_rows(ni, [&](int64_t lo, int64_t hi) {
+      for (int64_t ii = lo; ii < hi; ii++) {
+        const int64_t i = s1 + ii, r = nb + ii;
+        for (int64_t cM = fM[r]; cM <= r; cM++) vM[rpM[r] + cM - fM[r]] = A(i, cM < nb ? s0 + cM : s1 + (cM - nb));
+      }
+    });
+    parallel_rows(a, [&](int64_t lo, int64_t hi) {
+      for (int64_t t = lo; t < hi; t++) {
+        const int64_t r = nb + ni + t;
+        for (int64_t cM = 0; cM <= r; cM++) {
+          double v;
+          if (cM < nb) {
+            const int64_t gc = s0 + cM;
+            v = (k > 0 && gc < eb[k]) ? Sp(ni_prev + t, gc - s0) : A(n + t, gc);
+          } else if (cM < nb + ni) {
+            v = A(n + t, s1 + (cM - nb));
+          } else {
+            const int64_t u = cM - nb - ni;
+            v = k > 0 ? Sp(ni_prev + t, ni_prev + u) : A(n + t, n + u);
+          }
+          vM[rpM[r] + cM] = v;
+        }
+      }
+    });
     // in-core factorization of M_k
     stiles_symbolic* sym = nullptr;
-    stiles_status r = stiles_analyze_profile(nb, ni + a, fM.data(), &o, &sym);
+    stiles_status r = stiles_analyze_profile(nb + ni, a, fM.data(), &o, &sym);
     if (r != STILES_OK) return r;
     size_t wsb = 0;
     r = stiles_workspace_size(sym, STILES_FP64, 1, &wsb);
@@ -196,21 +236,27 @@ extern "C" stiles_status stiles_factorize_ooc(int64_t n, int64_t a, const int64_
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return STILES_EDEVICE;
     // final entries of L in the numbering and row-profile order of A
-    for (int64_t rr = 0; rr < nb; rr++) {
-      const int64_t i = s0 + rr;
-      for (int64_t cM = fM[rr]; cM <= rr; cM++) h_L[rpA[i] + (s0 + cM) - fA(i)] = hM[rpM[rr] + cM - fM[rr]];
-    }
-    for (int64_t ii = 0; ii < ni; ii++) {
-      const int64_t i = s1 + ii, rr = nb + ii;
-      for (int64_t cM = std::max<int64_t>(0, first_col[i] - s0); cM < nb; cM++)
-        h_L[rpA[i] + (s0 + cM) - first_col[i]] = hM[rpM[rr] + cM];
-    }
-    for (int64_t t = 0; t < a; t++) {
-      const int64_t rr = nb + ni + t;
-      for (int64_t cM = 0; cM < nb; cM++) h_L[rpA[n + t] + s0 + cM] = hM[rpM[rr] + cM];
-      if (last)
-        for (int64_t u = 0; u <= t; u++) h_L[rpA[n + t] + n + u] = hM[rpM[rr] + nb + u];
-    }
+    parallel_rows(nb, [&](int64_t lo, int64_t hi) {
+      for (int64_t rr = lo; rr < hi; rr++) {
+        const int64_t i = s0 + rr;
+        for (int64_t cM = fM[rr]; cM <= rr; cM++) h_L[rpA[i] + (s0 + cM) - fA(i)] = hM[rpM[rr] + cM - fM[rr]];
+      }
+    });
+    parallel_rows(ni, [&](int64_t lo, int64_t hi) {
+      for (int64_t ii = lo; ii < hi; ii++) {
+        const int64_t i = s1 + ii, rr = nb + ii;
+        for (int64_t cM = std::max(fM[rr], first_col[i] - s0); cM < nb; cM++)
+          h_L[rpA[i] + (s0 + cM) - first_col[i]] = hM[rpM[rr] + cM - fM[rr]];
+      }
+    });
+    parallel_rows(a, [&](int64_t lo, int64_t hi) {
+      for (int64_t t = lo; t < hi; t++) {
+        const int64_t rr = nb + ni + t;
+        for (int64_t cM = 0; cM < nb; cM++) h_L[rpA[n + t] + s0 + cM] = hM[rpM[rr] + cM];
+        if (last)
+          for (int64_t u = 0; u <= t; u++) h_L[rpA[n + t] + n + u] = hM[rpM[rr] + nb + u];
+      }
+    });
     S_prev.swap(S);
     c_prev = (int64_t)c;
     ni_prev = ni;

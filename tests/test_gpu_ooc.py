@@ -1,6 +1,7 @@
 """Out-of-core (streamed) factorization: the band is factored segment by
-segment, each segment in core with the next segment's coupling rows and the
-arrow as its arrow, its Schur complement seeding the next one.  L (whole
+segment, each segment in core with the next segment's coupling rows after
+its own and the arrow as its arrow, its Schur complement seeding the next
+one.  L (whole
 factor, and per tile column) and the log-determinant match the FP64 oracle
 within 1e-12 for several segment lengths and both tile sizes, one segment
 reproduces the in-core factor, the device footprint of a segment stays
@@ -26,9 +27,13 @@ def _oracle(p, vals):
     return L, oracle.logdet(p.f, L)
 
 
-@pytest.mark.parametrize("seg,T", [(700, 64), (2500, 64), (1000, 32), (0, 64)],
-                         ids=["seg700_T64", "seg2500_T64", "seg1000_T32", "one_segment_T64"])
+@pytest.mark.parametrize("seg,T", [(700, 64), (2500, 64), (1000, 32), (600, 64), (0, 64)],
+                         ids=["seg700_T64", "seg2500_T64", "seg1000_T32", "seg600_T64", "one_segment_T64"])
 def test_ooc_matches_oracle(seg, T):
+    # the half-width grows at rows 700 (20 -> 200) and 2,100 (90 -> 130):
+    # segments of 600 and 1,000 rows end 100 and 100 rows before such a
+    # row, so the rows that couple back across the boundary are not
+    # contiguous there (80 and 10 rows in between do not)
     p = I.make_pattern(20000, 40, [20, 200, 90, 130], seg=700)
     vals = I.make_values(p, seed=77)
     L_o, ld_o = _oracle(p, vals)
@@ -57,6 +62,27 @@ def test_ooc_one_segment_is_the_in_core_factor_and_segments_save_memory():
         peak1 / 2 ** 20, peak4 / 2 ** 20, rel(L4, L1)))
     assert peak4 < peak1 / 4
     assert rel(L4, L1) <= TOL and abs(ld4 - ld1) <= TOL * abs(ld1)
+
+
+def test_ooc_writes_every_entry_of_a_reused_output_and_repeats_bitwise():
+    """The factor goes into a caller's array (filled with NaN first): every
+    entry is written, and a second call into the same array gives the same
+    bits (the host assembly and scatter run on several threads, each on its
+    own rows)."""
+    p = I.make_pattern(12000, 30, [60, 220, 140], seg=3000)
+    vals = I.make_values(p, seed=12)
+    out = np.full(p.nnz, np.nan)
+    L, ld, info, _ = S.stiles_factorize_ooc(p.n, p.a, p.f[:p.n], vals, 2500, tile=64, out=out)
+    assert info == 0 and L is out
+    assert not np.isnan(out).any()
+    first = out.copy()
+    out[:] = np.nan
+    _, ld2, _, _ = S.stiles_factorize_ooc(p.n, p.a, p.f[:p.n], vals, 2500, tile=64, out=out)
+    assert np.array_equal(out, first) and ld2 == ld
+    Lo, info_o = oracle.factor(p.f, vals)
+    assert info_o == 0 and rel(out, Lo) <= TOL
+    with pytest.raises(ValueError):
+        S.stiles_factorize_ooc(p.n, p.a, p.f[:p.n], vals, 2500, tile=64, out=np.empty(p.nnz - 1))
 
 
 def test_ooc_reports_the_failing_row():
