@@ -301,7 +301,8 @@ stiles_status stiles_factorize(stiles_factor* f, const double* d_values, hipStre
  * trailing factor of that matrix (those coupling rows and the arrow) gives
  * the segment's Schur complement (L_c L_c^T, on the device), which seeds the
  * next segment.  Only one segment is resident at a time; the assembly of a
- * segment's values and the scatter of its factor use up to 16 host threads.
+ * segment's values and the scatter of its factor use up to 16 host threads,
+ * and the next segment's symbolic analysis runs on one more meanwhile.
  *   h_values  host, FP64, the matrix in row-profile order (as for
  *             stiles_factorize with a row-profile analysis)
  *   seg_rows  band rows per segment; at least the band's reach (every row

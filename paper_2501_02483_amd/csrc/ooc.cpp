@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -127,20 +128,51 @@ extern "C" stiles_status stiles_factorize_ooc(int64_t n, int64_t a, const int64_
   stiles_default_opts(&o);
   o.tile = tile;
   o.ordering = STILES_ORDER_NONE;
+  // M_k's profile and its symbolic analysis (host only, independent of the
+  // values): band rows from the segment and the interface rows (each from
+  // its first column in A, which is not before s0), the arrow rows dense.
+  // An interface row starts at the segment's last column at the latest (a
+  // row of the range that does not couple back then holds one explicit zero
+  // there), so that every row of the trailing block covers all of its
+  // columns, as the Gram kernel reads them.  The analysis of segment k + 1
+  // runs on a helper thread while segment k is assembled and factored.
+  struct Seg {
+    std::vector<int64_t> fM, rpM;
+    stiles_symbolic* sym = nullptr;
+    stiles_status status = STILES_OK;
+    ~Seg() { if (sym) stiles_symbolic_destroy(sym); }
+  };
+  auto prepare = [&](int k, Seg& g) {
+    const int64_t s0 = sb[k], s1 = sb[k + 1];
+    const int64_t nb = s1 - s0, ni = k + 1 < m ? eb[k + 1] - s1 : 0, Nk = nb + ni + a;
+    g.fM.assign(Nk, 0);
+    g.rpM.assign(Nk + 1, 0);
+    for (int64_t r = 0; r < nb; r++) g.fM[r] = std::max(first_col[s0 + r], s0) - s0;
+    for (int64_t ii = 0; ii < ni; ii++) g.fM[nb + ii] = std::min(first_col[s1 + ii] - s0, nb - 1);
+    for (int64_t r = 0; r < Nk; r++) g.rpM[r + 1] = g.rpM[r] + (r - g.fM[r] + 1);
+    g.status = stiles_analyze_profile(nb + ni, a, g.fM.data(), &o, &g.sym);
+  };
+  std::unique_ptr<Seg> cur(new Seg), nxt;
+  prepare(0, *cur);
   for (int k = 0; k < m; k++) {
     const int64_t s0 = sb[k], s1 = sb[k + 1];
     const int64_t nb = s1 - s0, ni = k + 1 < m ? eb[k + 1] - s1 : 0, Nk = nb + ni + a;
     const bool last = k + 1 == m;
-    // M_k's profile: band rows from the segment and the interface rows (each
-    // from its first column in A, which is not before s0), the arrow rows
-    // dense.  An interface row starts at the segment's last column at the
-    // latest (a row of the range that does not couple back then holds one
-    // explicit zero there), so that every row of the trailing block covers
-    // all of its columns, as the Gram kernel reads them.
-    std::vector<int64_t> fM(Nk, 0), rpM(Nk + 1, 0);
-    for (int64_t r = 0; r < nb; r++) fM[r] = std::max(first_col[s0 + r], s0) - s0;
-    for (int64_t ii = 0; ii < ni; ii++) fM[nb + ii] = std::min(first_col[s1 + ii] - s0, nb - 1);
-    for (int64_t r = 0; r < Nk; r++) rpM[r + 1] = rpM[r] + (r - fM[r] + 1);
+    nxt.reset(last ? nullptr : new Seg);
+    std::thread helper;
+    if (nxt) {
+      try {
+        helper = std::thread(prepare, k + 1, std::ref(*nxt));
+      } catch (...) {
+        prepare(k + 1, *nxt);
+      }
+    }
+    struct Join {
+      std::thread& t;
+      ~Join() { if (t.joinable()) t.join(); }
+    } join{helper};
+    const std::vector<int64_t>& fM = cur->fM;
+    const std::vector<int64_t>& rpM = cur->rpM;
     vM.assign(rpM[Nk], 0.0);
     // values: the original entries, except the previous segment's Schur
     // complement on its interface block, the arrow rows' interface columns
@@ -180,18 +212,16 @@ extern "C" stiles_status stiles_factorize_ooc(int64_t n, int64_t a, const int64_
       }
     });
     // in-core factorization of M_k
-    stiles_symbolic* sym = nullptr;
-    stiles_status r = stiles_analyze_profile(nb + ni, a, fM.data(), &o, &sym);
+    stiles_symbolic* sym = cur->sym;
+    stiles_status r = cur->status;
     if (r != STILES_OK) return r;
     size_t wsb = 0;
     r = stiles_workspace_size(sym, STILES_FP64, 1, &wsb);
     const size_t nnz = (size_t)rpM[Nk], c = (size_t)(ni + a);
     const size_t need = wsb + nnz * 16 + (size_t)(Nk + 1) * 8 + (size_t)Nk * 8 + (last ? 0 : c * c * 8) + 8;
     if (r != STILES_OK || !ws.reserve(wsb) || !vals.reserve(nnz * 8) || !lbuf.reserve(nnz * 8) ||
-        !rpb.reserve((Nk + 1) * 8) || !fb.reserve(Nk * 8) || (!last && !sbuf.reserve(c * c * 8))) {
-      stiles_symbolic_destroy(sym);
+        !rpb.reserve((Nk + 1) * 8) || !fb.reserve(Nk * 8) || (!last && !sbuf.reserve(c * c * 8)))
       return r != STILES_OK ? r : STILES_EDEVICE;
-    }
     peak = std::max(peak, need);
     stiles_factor* fac = nullptr;
     r = stiles_workspace_init(sym, STILES_FP64, 1, ws.p, ws.n, st, &fac);
@@ -206,7 +236,6 @@ extern "C" stiles_status stiles_factorize_ooc(int64_t n, int64_t a, const int64_
     // the symbolic object's tables were uploaded asynchronously
     if (hipStreamSynchronize(st) != hipSuccess) e = hipErrorUnknown;
     if (fac) stiles_factor_release(fac);
-    stiles_symbolic_destroy(sym);
     if (e != hipSuccess) return STILES_EDEVICE;
     if (r != STILES_OK) return r;
     if (inf > 0) {
@@ -260,6 +289,8 @@ extern "C" stiles_status stiles_factorize_ooc(int64_t n, int64_t a, const int64_
     S_prev.swap(S);
     c_prev = (int64_t)c;
     ni_prev = ni;
+    if (helper.joinable()) helper.join();
+    cur = std::move(nxt);
   }
   if (hipMemcpyAsync(logdet, acc.p, 8, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return STILES_EDEVICE;
