@@ -18,7 +18,13 @@ batch (512 uneven matrices in one launch), mixed (n=500,000, w=1,000,
 a=200, FP32 updates + FP64 refinement, 16 RHS), spde (spatio-temporal CSC
 input: 40 x 40 grid x 60 time steps, arrow 50), selinv (selected inversion
 of the variable-bandwidth matrix's factor: A^{-1} on the tile pattern of L
-and its diagonal; F = sum_j 2 eta_j (eta_j + 1)).
+and its diagonal; F = sum_j 2 eta_j (eta_j + 1)), serve (Poisson request
+stream over 8 resident patterns, FP64 and mixed precision, p50/p99 latency),
+ooc (out-of-core factorization of the variable-bandwidth matrix by band
+segments, host values in and host factor out), banded (host context: LAPACK
+band Cholesky plus the arrow on the host cores, beside the GPU's FP64
+factorization of the same constant-width matrices), copycal (a device copy
+of known size, to calibrate the HBM byte counters).
 """
 import argparse
 import json
