@@ -1656,6 +1656,8 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
     int t = sb.add(TK_FDIAG, m, f0, f1, 0, 0.6f);
     sb.dep(t, last);
     for (int32_t q = body_end; q < re; q++) sb.dep(t, fdiag[s.tcol[q]]);
+    // two fused products: the one with the previous block (the chain) last
+    if (f1 - f0 == 2) sb.set_late(t, fdiag[s.tcol[re - 1]]);
     fdiag[m] = t;
   }
   for (int32_t m = ntr - 1; m >= 0; m--) {
@@ -1690,6 +1692,8 @@ void finish_symbolic(stiles_symbolic& s, const std::vector<std::vector<int32_t>>
     sb.dep(t, last);
     sb.dep(t, fdiag[m]);
     for (size_t q = body_end; q < below.size(); q++) sb.dep(t, bdiag[below[q].first]);
+    // two fused products: the one with the next block (the chain) last
+    if (f1 - f0 == 2) sb.set_late(t, bdiag[below.back().first]);
     bdiag[m] = t;
   }
   s.spairs = sp;
@@ -1887,9 +1891,14 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
       pred[x].push_back(t);
       if (s.fsucc[q] & SUCC_FDEP) fheavy.insert({t, x});
     }
+  // solve edges from an early predecessor into a two-stage diagonal step
+  std::set<std::pair<int32_t, int32_t>> sheavy;
   for (int32_t t = 0; t < ns; t++)
-    for (int32_t q = s.stask[(size_t)t * TASK_WORDS + 5]; q < s.stask[(size_t)t * TASK_WORDS + 6]; q++)
-      pred[nf + s.ssucc[q]].push_back(nf + t);
+    for (int32_t q = s.stask[(size_t)t * TASK_WORDS + 5]; q < s.stask[(size_t)t * TASK_WORDS + 6]; q++) {
+      const int32_t x = s.ssucc[q] & ~SUCC_FDEP;
+      pred[nf + x].push_back(nf + t);
+      if (s.ssucc[q] & SUCC_FDEP) sheavy.insert({nf + t, nf + x});
+    }
   std::vector<int32_t> final_task(s.ntiles, -1), potrf_row(s.ntr, -1);
   for (int32_t t = 0; t < nf; t++) {
     const int32_t* w = &s.ftask[(size_t)t * TASK_WORDS];
@@ -1955,9 +1964,14 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
       if (x <= i) { fprintf(stderr, "stiles: merged DAG order is not topological\n"); abort(); }
     w[5] = (int32_t)D.succ.size();
     // edges from a factorization task to a solve task carry SUCC_FDEP, and so
-    // do the factorization DAG's own early edges into two-stage tasks
-    for (int32_t x : sl)
-      D.succ.push_back(t < nf && (order[x] >= nf || fheavy.count({t, order[x]})) ? (x | SUCC_FDEP) : x);
+    // do the factorization DAG's own early edges into two-stage tasks; the
+    // solve DAG's early edges into two-stage diagonal steps carry SUCC_MID
+    for (int32_t x : sl) {
+      if (t < nf)
+        D.succ.push_back(order[x] >= nf || fheavy.count({t, order[x]}) ? (x | SUCC_FDEP) : x);
+      else
+        D.succ.push_back(sheavy.count({t, order[x]}) ? (x | SUCC_MID) : x);
+    }
     w[6] = (int32_t)D.succ.size();
     if (t < nf) {
       w[7] = s.ftask[(size_t)t * TASK_WORDS + 7];   // the factorization DAG's counter, with its weights
@@ -1966,7 +1980,13 @@ void build_merged(const stiles_symbolic& s, MergedPlan& D) {
       for (int32_t x : pred[t]) nfd += x < nf;
       const int32_t nsd = (int32_t)pred[t].size() - nfd;
       if (nsd >= MERGED_FDEP || nfd >= (1 << 14)) { fprintf(stderr, "stiles: merged DAG: too many predecessors\n"); abort(); }
-      w[7] = nsd + nfd * MERGED_FDEP;
+      if (w[0] & TF_SPLIT) {
+        // early solve predecessors weigh SPLIT_W, the late one 1
+        if ((nsd - 1) * SPLIT_W + 1 >= MERGED_FDEP) { fprintf(stderr, "stiles: merged DAG: too many predecessors\n"); abort(); }
+        w[7] = (nsd - 1) * SPLIT_W + 1 + nfd * MERGED_FDEP;
+      } else {
+        w[7] = nsd + nfd * MERGED_FDEP;
+      }
     }
   }
   D.pairs = s.fpairs;

@@ -928,7 +928,13 @@ struct SolveOps {
 // predecessors itself (*cnt): the factor tiles of a diagonal step (at most
 // two fused products and the inverse diagonal tile) are read into registers
 // first, so that only the small vector blocks are loaded once the
-// predecessors are done.  The factor tiles must be final when it is called.
+// predecessors are done.  A diagonal step with TF_SPLIT waits in two
+// stages: once its early predecessors are done (the counter below
+// MERGED_FDEP in a solve launch, below SPLIT_W in the merged launch, whose
+// executor has already waited for the factorization predecessors) it loads
+// its right-hand side block and does the first fused product, then waits
+// for the previous step of the chain, whose block the second product reads.
+// The factor tiles must be final when it is called.
 // `ok` enters false when the launch was already abandoned and leaves false
 // when this task's own wait gave up; the task then writes nothing.
 template <int T, int K>
@@ -953,26 +959,37 @@ __device__ __forceinline__ uint64_t task_solve_r(const ExecMat& M, const int32_t
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
   if (diag) {
     // static operands first (at most two fused products), then the wait
+    const bool split = (__builtin_amdgcn_readfirstlane(w[0]) & TF_SPLIT) != 0;
     double a0[NS], a1[NS], ai[NS], b0[NS], b1[NS];
     if (act) {
       if (np > 0) O::load_a(a0, M.tiles + (int64_t)word(pv, 0) * TT, !fwd, wave, lane);
       if (np > 1) O::load_a(a1, M.tiles + (int64_t)word(pv, 2) * TT, !fwd, wave, lane);
       O::load_a(ai, M.linv + (int64_t)m * TT, !fwd, wave, lane);
     }
-    if (ok) ok = wait_below(cnt, 1, ctrl, limit);
+    if (ok) ok = wait_below(cnt, split ? (K == EXEC_FACTOR_SOLVE ? SPLIT_W : MERGED_FDEP) : 1, ctrl, limit);
     if (!ok) return 0;
-    const uint64_t t_start = M.trace ? wall_clock64() : 0;
+    uint64_t t_start = M.trace ? wall_clock64() : 0;
     double bs[4];
     if (act) {
       if (np > 0) O::load_b(b0, vsrc + word(pv, 1) * vb, nrhs, lane);
-      if (np > 1) O::load_b(b1, vsrc + word(pv, 3) * vb, nrhs, lane);
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = 16 * wave + (lane >> 4) + 4 * r;
         bs[r] = col < nrhs ? gp(base)[row + col * T] : 0.0;
       }
       if (np > 0) acc = O::mma(acc, a0, b0);
-      if (np > 1) acc = O::mma(acc, a1, b1);
+    }
+    if (split) {
+      // the previous step of the chain: its block is the second operand
+      ok = wait_below(cnt, 1, ctrl, limit);
+      if (!ok) return 0;
+      if (M.trace) t_start = wall_clock64();
+    }
+    if (act) {
+      if (np > 1) {
+        O::load_b(b1, vsrc + word(pv, 3) * vb, nrhs, lane);
+        acc = O::mma(acc, a1, b1);
+      }
       // base - acc into LDS (T x 16, leading dimension T) for the product
       // with the inverse diagonal tile
 #pragma unroll
@@ -1549,6 +1566,9 @@ __global__ __launch_bounds__(NT, 2) void exec_kernel(const ExecMat* __restrict__
         if (sq & SUCC_FDEP) {   // an early predecessor of a two-stage wait
           dec = MERGED_FDEP;
           sq &= ~SUCC_FDEP;
+        } else if (sq & SUCC_MID) {   // merged DAG: early solve predecessor of a diagonal step
+          dec = SPLIT_W;
+          sq &= ~SUCC_MID;
         }
         __hip_atomic_fetch_add(M.remaining + sq, -dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }

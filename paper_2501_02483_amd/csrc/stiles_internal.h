@@ -43,7 +43,7 @@ enum TaskFlag : int32_t {
   TF_DIAG = 1 << 8,   // UPD target is a diagonal tile (lower half only)
   TF_FIRST = 1 << 9,  // BUPD: first chunk reads Y_m; BDIAG: no BUPD, reads Y_m
   TF_ACC = 1 << 10,   // PART: P_s += sum (continues a chain) instead of P_s = sum
-  TF_SPLIT = 1 << 11, // POTRF/TRSM: two-stage wait (early predecessors, then the chain one)
+  TF_SPLIT = 1 << 11, // POTRF/TRSM/FDIAG/BDIAG: two-stage wait (early predecessors, then the chain one)
   TF_ARROW = 1 << 12, // PART: partial of an arrow-corner tile (FP64 in mixed mode)
 };
 
@@ -88,8 +88,15 @@ constexpr int32_t SIG_TRANS = 1 << 30;
 // fused product before the POTRF ends; a POTRF with a fused product waits
 // late for the TRSM of that operand (the panel of the previous column) and
 // prefetches its tile before.
+// Solve DAG (TF_SPLIT): a diagonal step with two fused products waits late
+// for the step that solves the block of its second product (the previous
+// step of the chain) and does the product with the other one before.  In
+// the merged DAG its early solve predecessors weigh SPLIT_W (their successor
+// entries carry SUCC_MID) below the factorization predecessors' MERGED_FDEP.
 constexpr int32_t MERGED_FDEP = 1 << 16;
 constexpr int32_t SUCC_FDEP = 1 << 30;
+constexpr int32_t SPLIT_W = 1 << 8;
+constexpr int32_t SUCC_MID = 1 << 29;
 // Tile rows the library's fixed log-determinant array holds (one FP64
 // partial per tile row, 512 KiB); the public limit of stiles_logdet_static.
 constexpr int32_t STATIC_LOGDET_ROWS = 65536;

@@ -17,14 +17,21 @@ SWE, SW, SDIAG, TSUM = 16, 17, 18, 19
 TF_DIAG, TF_FIRST, TF_ACC, TF_SPLIT = 1 << 8, 1 << 9, 1 << 10, 1 << 11
 SIG_TRANS = 1 << 30
 MERGED_FDEP, SUCC_FDEP = 1 << 16, 1 << 30
+SPLIT_W, SUCC_MID = 1 << 8, 1 << 29
 
 
 def succ_edge(v):
     """(successor, counter decrement) of a successor entry: an entry with
-    SUCC_FDEP (merged DAG, factorization task -> solve task) subtracts
-    MERGED_FDEP."""
+    SUCC_FDEP (an early predecessor of a two-stage task; in the merged DAG
+    also factorization task -> solve task) subtracts MERGED_FDEP, one with
+    SUCC_MID (merged DAG: early solve predecessor of a two-stage diagonal
+    step) SPLIT_W."""
     v = int(v)
-    return (v & ~SUCC_FDEP, MERGED_FDEP) if v & SUCC_FDEP else (v, 1)
+    if v & SUCC_FDEP:
+        return v & ~SUCC_FDEP, MERGED_FDEP
+    if v & SUCC_MID:
+        return v & ~SUCC_MID, SPLIT_W
+    return v, 1
 
 
 class Plan:

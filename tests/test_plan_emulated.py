@@ -190,11 +190,13 @@ def test_emulated_merged_factor_solve_nd(parts):
 @pytest.mark.parametrize("parts", [None, 3])
 def test_merged_counters_split_factor_and_solve_predecessors(parts):
     """Merged DAG counters: a solve task counts each factorization predecessor
-    as MERGED_FDEP and each solve predecessor as 1, the flagged successor
-    entries are exactly the factorization -> solve edges, and the
-    factorization predecessors of a solve task include the final task of
-    every factor tile it reads and, for a diagonal step, the POTRF of its
-    row -- so its tiles may be staged once the counter is below MERGED_FDEP."""
+    as MERGED_FDEP and each solve predecessor as 1 -- a two-stage diagonal
+    step each early solve predecessor as SPLIT_W and its one late
+    predecessor as 1 --, the MERGED_FDEP entries are exactly the
+    factorization -> solve edges, and the factorization predecessors of a
+    solve task include the final task of every factor tile it reads and, for
+    a diagonal step, the POTRF of its row -- so its tiles may be staged once
+    the counter is below MERGED_FDEP."""
     p = I.make_pattern(2500, 18, [16, 70, 30], seg=500)
     kw = dict(ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=parts) if parts else {}
     sym = S.Symbolic.from_pattern(p, tile=32, **kw)
@@ -206,6 +208,7 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
     fpred = [set() for _ in range(n)]
     fweight = [0] * n      # factorization tasks: counter weight of their predecessors
     spred = [0] * n
+    split_steps = 0
     final_of, potrf_of = {}, {}
     for t in range(n):
         if typ[t] in (E.POTRF, E.TRSM):
@@ -216,8 +219,11 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
             x, dec = E.succ_edge(succ[q])
             assert x > t
             if not is_fac[t] or not is_fac[x]:
-                # factorization -> solve edges weigh MERGED_FDEP, solve -> solve 1
+                # factorization -> solve edges weigh MERGED_FDEP, solve -> solve 1,
+                # or SPLIT_W from an early predecessor of a two-stage diagonal step
                 assert (dec == E.MERGED_FDEP) == (is_fac[t] and not is_fac[x])
+                if dec == E.SPLIT_W:
+                    assert not is_fac[t] and tasks[x, 0] & E.TF_SPLIT and typ[x] in (E.FDIAG, E.BDIAG)
             else:
                 # factorization -> factorization: MERGED_FDEP only into a
                 # two-stage POTRF/TRSM, from one of its early predecessors
@@ -226,7 +232,7 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
             if is_fac[t]:
                 fpred[x].add(t)
             else:
-                spred[x] += 1
+                spred[x] += dec
     for t in range(n):
         if is_fac[t]:
             assert tasks[t, 7] == fweight[t] and spred[t] == 0
@@ -235,12 +241,17 @@ def test_merged_counters_split_factor_and_solve_predecessors(parts):
                 assert fweight[t] % E.MERGED_FDEP == 1
             continue
         assert tasks[t, 7] == spred[t] + E.MERGED_FDEP * len(fpred[t])
+        if tasks[t, 0] & E.TF_SPLIT:
+            # exactly one late solve predecessor (weight 1), the others SPLIT_W
+            assert typ[t] in (E.FDIAG, E.BDIAG) and spred[t] % E.SPLIT_W == 1
+            split_steps += 1
         if typ[t] == E.FSUM:
             continue
         for q in range(tasks[t, 2], tasks[t, 3]):
             assert final_of[int(P[q, 0])] in fpred[t]
         if typ[t] in (E.FDIAG, E.BDIAG):
             assert potrf_of[int(tasks[t, 1])] in fpred[t]
+    assert split_steps > 0          # the two-stage diagonal steps are exercised
 
 
 @pytest.mark.parametrize("sched_workers", [-1, 0, 16])
