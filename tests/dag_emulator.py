@@ -181,7 +181,65 @@ def dense_factor(plan, tiles):
     return np.tril(L)
 
 
-def solve(plan, tiles, linv, B, mode="ticket", seed=0):
+def _split_order(tasks, succ, rng, late_of=None, eager=False):
+    """A random topological order of the solve DAG in which every two-stage
+    diagonal step (TF_SPLIT) is two sub-tasks: stage 0 after its early
+    predecessors (the successor entries with SUCC_FDEP), stage 1 after
+    stage 0 and its late predecessor.  Items are (task, stage), stage None
+    for a single-stage task.  late_of (task -> predecessor) overrides which
+    predecessor counts as late; eager runs a ready stage 0 before anything
+    else (the first stages as early as their predecessors allow)."""
+    n = len(tasks)
+    split = [bool(tasks[t, 0] & TF_SPLIT) for t in range(n)]
+    preds = [[] for _ in range(n)]
+    late = {}
+    for t in range(n):
+        for q in range(tasks[t, 5], tasks[t, 6]):
+            x, dec = succ_edge(succ[q])
+            preds[x].append(t)
+            if split[x] and dec == 1:
+                assert x not in late, "a two-stage step has one late predecessor"
+                late[x] = t
+    if late_of is not None:
+        late.update(late_of)
+    nodes = []
+    for t in range(n):
+        nodes += [(t, 0), (t, 1)] if split[t] else [(t, None)]
+    final = lambda t: (t, 1) if split[t] else (t, None)
+    need = {}
+    for t in range(n):
+        if split[t]:
+            assert t in late
+            need[(t, 0)] = {final(x) for x in preds[t] if x != late[t]}
+            need[(t, 1)] = {(t, 0), final(late[t])}
+        else:
+            need[(t, None)] = {final(x) for x in preds[t]}
+    done, out = set(), []
+    ready = [v for v in nodes if not need[v]]
+    waiting = {v: set(need[v]) for v in nodes if need[v]}
+    users = {}
+    for v, ps in waiting.items():
+        for u in ps:
+            users.setdefault(u, []).append(v)
+    while ready:
+        first = [i for i, v in enumerate(ready) if v[1] == 0] if eager else []
+        v = ready.pop(first[0] if first else int(rng.integers(len(ready))))
+        out.append(v)
+        done.add(v)
+        for u in users.get(v, []):
+            waiting[u].discard(v)
+            if not waiting[u]:
+                ready.append(u)
+    assert len(out) == len(nodes), "split DAG has a cycle"
+    return out
+
+
+def solve(plan, tiles, linv, B, mode="ticket", seed=0, late_of=None):
+    """Forward and backward sweeps by the plan's solve tasks.  mode "ticket",
+    "random" (whole tasks), "split": two-stage diagonal steps run as two
+    sub-tasks (their first fused product before the late predecessor) in a
+    random order, or "split_eager": the same with every first stage run as
+    soon as it is ready; backward blocks not yet written read as NaN."""
     rng = np.random.default_rng(seed)
     T, ntr = plan.T, plan.ntr
     nrhs = B.shape[1]
@@ -190,13 +248,36 @@ def solve(plan, tiles, linv, B, mode="ticket", seed=0):
     for m in range(ntr):
         rb, rc = plan.row_base[m], plan.row_cnt[m]
         Y[m, :rc] = Bp[rb:rb + rc]
-    Z = np.zeros_like(Y)
+    Z = np.full_like(Y, np.nan)
     Q = {}
     P = plan.spairs
-    for t in _order(plan.stask, plan.ssucc, mode, rng):
+    if mode in ("split", "split_eager"):
+        items = _split_order(plan.stask, plan.ssucc, rng, late_of, eager=mode == "split_eager")
+    else:
+        items = [(t, None) for t in _order(plan.stask, plan.ssucc, mode, rng)]
+    held = {}
+    for t, stage in items:
         w = plan.stask[t]
         typ = w[0] & 0xff
         m = w[1]
+        if stage is not None:
+            # a two-stage diagonal step: stage 0 takes its right-hand side
+            # block and the first fused product, stage 1 the second product
+            # and the inverse diagonal tile
+            assert typ in (FDIAG, BDIAG) and w[3] - w[2] == 2
+            p = w[2] + stage
+            if typ == FDIAG:
+                if stage == 0:
+                    held[t] = Y[m].copy() - tiles[P[p, 0]] @ Y[P[p, 1]]
+                else:
+                    Y[m] = linv[m] @ (held.pop(t) - tiles[P[p, 0]] @ Y[P[p, 1]])
+            else:
+                if stage == 0:
+                    base = Y[m] if w[0] & TF_FIRST else Z[m]
+                    held[t] = base.copy() - tiles[P[p, 0]].T @ Z[P[p, 1]]
+                else:
+                    Z[m] = linv[m].T @ (held.pop(t) - tiles[P[p, 0]].T @ Z[P[p, 1]])
+            continue
         if typ == FUPD:
             for p in range(w[2], w[3]):
                 Y[m] -= tiles[P[p, 0]] @ Y[P[p, 1]]

@@ -340,3 +340,44 @@ def test_emulated_block_updates(ublock, mode, ordering, parts):
     _, _, X = E.factor_solve(plan, A, B, mode=mode, seed=ublock + 1)
     Xo = oracle.solve(p.f, L, B)
     assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
+
+
+@pytest.mark.parametrize("parts", [0, 3])
+def test_two_stage_solve_steps_read_only_final_blocks(parts):
+    """Two-stage diagonal solve steps (TF_SPLIT) run as two sub-tasks in
+    random orders: the first stage (right-hand side block and first fused
+    product) after the early predecessors only, the second after the late
+    one.  Every order reproduces the oracle's solution, with backward blocks
+    not yet written reading as NaN; and declaring another predecessor late
+    (the step's update chain, so that its first stage may read an
+    unfinished block) is caught when the first stages run as early as
+    their predecessors allow."""
+    p = I.make_pattern(2500, 18, [16, 70, 30], seg=500)
+    vals = I.make_values(p, seed=21)
+    kw = dict(ordering=S.STILES_ORDER_ADAPTABLE_ND, nd_parts=parts) if parts else {}
+    sym = S.Symbolic.from_pattern(p, tile=32, **kw)
+    plan = E.Plan(sym)
+    A = I.to_dense(p, vals)
+    tiles, linv = E.factor(plan, A[np.ix_(plan.perm, plan.perm)])
+    B = I.rhs(p.N, 2, seed=6)
+    L, info = oracle.factor(p.f, vals)
+    Xo = oracle.solve(p.f, L, B)
+    typ = plan.stask[:, 0] & 0xff
+    split = np.nonzero(plan.stask[:, 0] & E.TF_SPLIT)[0]
+    assert set(typ[split]) == {E.FDIAG, E.BDIAG}
+    for mode, seed in [("split", 0), ("split", 1), ("split", 2), ("split_eager", 3)]:
+        X = E.solve(plan, tiles, linv, B, mode=mode, seed=seed)
+        assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-12
+    # planted: the late predecessor of every split backward step that has an
+    # update chain becomes that chain's last task
+    preds = {}
+    for t in range(len(plan.stask)):
+        for q in range(plan.stask[t, 5], plan.stask[t, 6]):
+            preds.setdefault(E.succ_edge(plan.ssucc[q])[0], []).append(t)
+    late_of = {}
+    for t in split:
+        if typ[t] == E.BDIAG and not plan.stask[t, 0] & E.TF_FIRST:
+            late_of[int(t)] = max(x for x in preds[t] if typ[x] == E.BUPD)
+    assert late_of
+    X = E.solve(plan, tiles, linv, B, mode="split_eager", seed=0, late_of=late_of)
+    assert not np.all(np.isfinite(X)) or np.linalg.norm(X - Xo) / np.linalg.norm(Xo) > 1e-6
