@@ -176,7 +176,7 @@ struct TileStage {
 // The wait is bounded: it gives up when another workgroup of the launch has
 // given up (ctrl->abort) or when `limit` ticks of the 100 MHz wall clock pass
 // without the counter falling; the first to give up sets ctrl->abort.  The
-// result is the same for every thread (false: gave up).  The verdict goes
+// result is the same for every thread (false: gave up).  The outcome goes
 // through LDS; the second barrier keeps a later wait from overwriting it
 // before every wave has read it.
 __device__ __forceinline__ bool wait_below(int32_t* cnt, int32_t bound, ExecCtrl* ctrl, uint64_t limit) {
