@@ -133,18 +133,35 @@ __device__ __forceinline__ void mma_f32(v4f (&acc)[T / 32][T / 32], const float*
   constexpr int NB = T / 32;
   const float* xp = X + r0 + (lane & 15) + (lane >> 4) * T;
   const float* yp = Y + c0 + (lane & 15) + (lane >> 4) * T;
-#pragma unroll 4
-  for (int k = 0; k < T; k += 4) {
-    float a[NB], b[NB];
+  // the operands of step k + 4 are read from LDS while step k's MFMAs run
+  float a[NB], b[NB];
 #pragma unroll
-    for (int q = 0; q < NB; q++) {
-      a[q] = yp[q * 16 + k * T];
-      b[q] = xp[q * 16 + k * T];
+  for (int q = 0; q < NB; q++) {
+    a[q] = yp[q * 16];
+    b[q] = xp[q * 16];
+  }
+#pragma unroll
+  for (int k = 0; k < T; k += 4) {
+    float an[NB], bn[NB];
+    if (k + 4 < T) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) {
+        an[q] = yp[q * 16 + (k + 4) * T];
+        bn[q] = xp[q * 16 + (k + 4) * T];
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < NB; i++)
 #pragma unroll
       for (int j = 0; j < NB; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (k + 4 < T) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) {
+        a[q] = an[q];
+        b[q] = bn[q];
+      }
+    }
   }
 }
 
