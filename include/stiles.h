@@ -436,7 +436,8 @@ stiles_status stiles_factor_set_trace(stiles_factor* f, void* d_factor_trace, vo
 stiles_status stiles_factor_set_merged_trace(stiles_factor* f, void* d_trace, hipStream_t stream);
 
 /* Upper bound on the workgroups a factorization launch uses (0 = fill the
- * GPU).  Lets several factorizations on different streams share the GPU. */
+ * GPU).  Lets several factorizations on different streams share the GPU.
+ * A batch launch takes the cap of its first factor. */
 stiles_status stiles_factor_set_max_workgroups(stiles_factor* f, int32_t max_wg);
 
 /* Releases the host handle (the caller frees the workspace). */

@@ -969,8 +969,11 @@ extern "C" stiles_status stiles_batch_factorize(stiles_batch* b, const double* c
       if (r != STILES_OK) return r;
     }
   }
-  const int cap = device_wg_capacity(b->T);
   stiles_factor* f0 = b->factors[0];
+  // the first factor's workgroup cap bounds the batch launch (batches on
+  // different streams can then share the GPU)
+  int cap = device_wg_capacity(b->T);
+  if (f0->max_wg > 0) cap = std::min(cap, (int)f0->max_wg);
   if (f0->timing) (void)hipEventRecord(f0->ev[0], st);
   hipError_t e = launch_exec(b->T, EXEC_FACTOR, reinterpret_cast<const ExecMat*>(b->ws + b->B.mats),
                              reinterpret_cast<const int32_t*>(b->ws + b->B.order), b->total,

@@ -105,3 +105,29 @@ def test_batch_logdet_and_refactorize():
         assert f.info() == 0
         ref = oracle_reference(pats[i], vals2[i])
         assert abs(lds2[i].item() - ref["logdet"]) <= 1e-12 * abs(ref["logdet"])
+
+
+def test_batch_workgroup_cap_keeps_results_bitwise():
+    """A batch launch takes its first factor's workgroup cap (so batches on
+    different streams can share the GPU); fewer workgroups claim the same
+    tickets, so every factor is bitwise the uncapped one."""
+    import torch
+    from paper_2501_02483_amd import autotune
+    pats = [I.make_pattern(n, a, w, name="c%d" % i)
+            for i, (n, a, w) in enumerate([(4000, 20, 90), (2500, 8, 40), (6000, 30, 150), (1200, 5, 16)])]
+    vals = [torch.from_numpy(I.make_values(p, seed=40 + i)).cuda() for i, p in enumerate(pats)]
+    out = []
+    for cap in (0, 24):
+        syms = autotune.batch_symbolics(pats, 64, 40)
+        facs = [S.Factor(s) for s in syms]
+        facs[0].set_max_workgroups(cap)
+        batch = S.Batch(facs)
+        batch.factorize(vals)
+        lds = batch.logdet()
+        torch.cuda.synchronize()
+        assert all(f.info() == 0 for f in facs)
+        out.append(([f.extract().cpu() for f in facs], lds.cpu()))
+    say("[gpu batch] cap 24 workgroups vs the full GPU")
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
+    assert torch.equal(out[0][1], out[1][1])
