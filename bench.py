@@ -962,7 +962,7 @@ def main():
         rocpd_summary(args.rocpd_summary)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent factorizations shard across GPUs without exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
