@@ -13,7 +13,7 @@ the algorithmic factorization flops F = sum_j (eta_j + 1)^2 over the whole
 step time; the roofline object reports the merged factorization + solve
 launch (algorithmic flops: F + 4 nnz(L) nrhs for the two solve sweeps).
 
-Other workloads (--workload): small (n=2,000, w=50, a=10, tile 64, 1 RHS),
+Other workloads (--workload): small (n=2,000, w=50, a=10, 1 RHS, tile and ordering autotuned),
 batch (512 uneven matrices in one launch), mixed (n=500,000, w=1,000,
 a=200, FP32 updates + FP64 refinement, 16 RHS), spde (spatio-temporal CSC
 input: 40 x 40 grid x 60 time steps, arrow 50), selinv (selected inversion
@@ -921,7 +921,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile size; 0 = autotune (tile and ordering, or tile and ND threshold for the batch); "
-                         "default: 64, autotuned for the batch workload")
+                         "default: 64, autotuned for the batch and small workloads")
     ap.add_argument("--tree-ratio", type=int, default=2)
     ap.add_argument("--ordering", default="nd", choices=["none", "nd"],
                     help="single-matrix workloads: natural order or adaptable nested dissection")
@@ -957,7 +957,7 @@ def main():
     global UBLOCK
     UBLOCK = args.ublock
     if args.tile < 0:
-        args.tile = 0 if args.workload == "batch" else 64
+        args.tile = 0 if args.workload in ("batch", "small") else 64
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
         return
