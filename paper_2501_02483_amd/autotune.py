@@ -39,7 +39,7 @@ def _time_factor(fac, dv, reps):
 # dissection with the analysis' own partition count and a few fixed ones
 # (0 = chosen by the analysis); the schedule is the one the analysis derives
 # for each choice
-ORDERINGS = (("none", 0), ("nd", 0), ("nd", 8), ("nd", 16), ("nd", 32))
+ORDERINGS = (("none", 0), ("nd", 0), ("nd", 4), ("nd", 8), ("nd", 16), ("nd", 32))
 
 
 def tune_single(pattern, values, tiles=TILES, wg_caps=(0,), reps=3, precision=0, orderings=ORDERINGS):

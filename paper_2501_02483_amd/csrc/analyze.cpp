@@ -671,7 +671,7 @@ bool nd_plan_for(const std::vector<int64_t>& need, int64_t n, int64_t arrow, int
 }
 
 // requested P >= 2: that many parts (else the automatic choice); 0: the
-// fewest parts whose estimated chain is within 1.5x of the shortest one over
+// fewest parts whose estimated chain is within 1.3x of the shortest one over
 // P in [2, 64].  Every interior part adds a separator's width of fill across
 // its columns (executed work grows with P while the chain shrinks), so once
 // the chain is near its floor fewer parts are preferred -- except for small
