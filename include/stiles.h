@@ -106,7 +106,10 @@ typedef struct stiles_opts {
                              of the last two iterates is kept), or at the step limit */
   int32_t refine_max_iter;/* mixed mode: at most this many refinement steps per
                              right-hand side (0 = 30)                                */
-  int32_t nd_parts;       /* ADAPTABLE_ND: number of partitions, 2..64 (0 = choose)   */
+  int32_t nd_parts;       /* ADAPTABLE_ND: number of partitions, 2..64 (0 = choose:
+                             the shortest-chain count and two smaller ones are
+                             analyzed, and the least estimated factorization time
+                             -- chain steps against executed flops -- wins)       */
   int32_t sched_workers;  /* ticket order of the task DAGs: the start order of a list
                              schedule (longest remaining path first) on this many
                              workgroups (0 = 512, a full MI355X launch), used for a DAG
@@ -150,6 +153,8 @@ typedef struct stiles_symbolic_info {
                              (two sweeps, a multiply and an add per entry).  Equals
                              nnz_L when adaptable ND is not used                     */
   int64_t update_blocks;  /* 2 x 2 update blocks of the factorization DAG (ublock)   */
+  int64_t nd_chain;       /* adaptable ND: estimated chain of the plan in tile steps
+                             (longest partition, separator levels, arrow); 0 if none */
 } stiles_symbolic_info;
 
 typedef struct stiles_solve_report {

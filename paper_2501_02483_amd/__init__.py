@@ -79,7 +79,8 @@ class stiles_symbolic_info(ctypes.Structure):
                 ("nnz_L", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("flops_exec", ctypes.c_double),
                 ("factor_tasks", ctypes.c_int64), ("solve_tasks", ctypes.c_int64),
                 ("corner_accumulations", ctypes.c_int64), ("tree_used", ctypes.c_int32),
-                ("nd_parts", ctypes.c_int32), ("nnz_L_alg", ctypes.c_int64), ("update_blocks", ctypes.c_int64)]
+                ("nd_parts", ctypes.c_int32), ("nnz_L_alg", ctypes.c_int64), ("update_blocks", ctypes.c_int64),
+                ("nd_chain", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -910,8 +910,75 @@ static void init_common(stiles_symbolic& s, int64_t N, int64_t a, const stiles_o
   }
 }
 
+namespace {
+
+// Automatic partition count (adaptable ND with nd_parts = 0): the
+// chain-based choice P0 (see nd_plan) and two smaller counts are analyzed
+// in full, and the one with the least estimated time is kept.  The estimate
+// is the larger of the plan's chain (tile steps) times a step's duration
+// and its executed flops over the executor's executed rate (measured on
+// MI355X: a pivot step about 50 us at T = 64, 30 us at T = 32; about 34 and
+// 17.5 TFLOP/s executed): long narrow bands are bound by their chain, for
+// which P0 is made, wide bands by the fill that every interior partition
+// adds, which fewer partitions save.  Small matrices keep P0.
+template <typename Fn>
+stiles_status analyze_auto_parts(const stiles_opts* opts, Fn analyze_with, stiles_symbolic** out) {
+  stiles_status st = analyze_with(opts, out);
+  if (st != STILES_OK || !opts || opts->ordering != STILES_ORDER_ADAPTABLE_ND || opts->nd_parts != 0) return st;
+  stiles_symbolic* best = *out;
+  if (best->nd_parts < 4 || best->flops_alg < 2e9) return st;
+  auto estimate = [](const stiles_symbolic* s) {
+    const double step = s->T == 64 ? 50e-6 : 30e-6, rate = s->T == 64 ? 34e12 : 17.5e12;
+    return std::max((double)s->nd_chain * step, s->flops_exec / rate);
+  };
+  double best_t = estimate(best);
+  const int32_t P0 = best->nd_parts;
+  const int32_t cand[2] = {(int32_t)std::lround(0.6 * P0), (int32_t)std::lround(0.4 * P0)};
+  for (int32_t P : cand) {
+    if (P < 2 || P >= P0) continue;
+    stiles_opts o2 = *opts;
+    o2.nd_parts = P;
+    stiles_symbolic* c = nullptr;
+    if (analyze_with(&o2, &c) != STILES_OK || !c) continue;
+    const double t = estimate(c);
+    if (c->nd_parts == P && t < best_t) {
+      stiles_symbolic_destroy(best);
+      best = c;
+      best_t = t;
+    } else {
+      stiles_symbolic_destroy(c);
+    }
+  }
+  *out = best;
+  g_err_arg = 0;
+  return STILES_OK;
+}
+
+stiles_status analyze_profile_impl(int64_t n_band, int64_t arrow, const int64_t* first_col, const stiles_opts* opts,
+                                   stiles_symbolic** out);
+stiles_status analyze_csc_impl(int64_t N, int64_t arrow, const int64_t* colptr, const int64_t* rowind,
+                               const stiles_opts* opts, stiles_symbolic** out);
+
+}  // namespace
+
 extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, const int64_t* first_col,
                                                 const stiles_opts* opts, stiles_symbolic** out) {
+  return analyze_auto_parts(opts, [&](const stiles_opts* o, stiles_symbolic** r) {
+    return analyze_profile_impl(n_band, arrow, first_col, o, r);
+  }, out);
+}
+
+extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t* colptr, const int64_t* rowind,
+                                        const stiles_opts* opts, stiles_symbolic** out) {
+  return analyze_auto_parts(opts, [&](const stiles_opts* o, stiles_symbolic** r) {
+    return analyze_csc_impl(N, arrow, colptr, rowind, o, r);
+  }, out);
+}
+
+namespace {
+
+stiles_status analyze_profile_impl(int64_t n_band, int64_t arrow, const int64_t* first_col, const stiles_opts* opts,
+                                   stiles_symbolic** out) {
   g_err_arg = 0;
   if (n_band < 0) { g_err_arg = 1; return STILES_EINVAL; }
   if (arrow < 0 || n_band + arrow < 1) { g_err_arg = 2; return STILES_EINVAL; }
@@ -942,6 +1009,7 @@ extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, c
       init_common(*s, N, N - nb2, opts);   // the separators join the arrow
       s->ordering_used = STILES_ORDER_ADAPTABLE_ND;
       s->nd_parts = pl.P;
+      s->nd_chain = pl.chain;
       set_band_part(*s, segs, pl.P);
       s->perm_identity = false;
       s->perm.resize(N);
@@ -990,8 +1058,8 @@ extern "C" stiles_status stiles_analyze_profile(int64_t n_band, int64_t arrow, c
   return STILES_OK;
 }
 
-extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t* colptr, const int64_t* rowind,
-                                        const stiles_opts* opts, stiles_symbolic** out) {
+stiles_status analyze_csc_impl(int64_t N, int64_t arrow, const int64_t* colptr, const int64_t* rowind,
+                               const stiles_opts* opts, stiles_symbolic** out) {
   g_err_arg = 0;
   if (N < 1) { g_err_arg = 1; return STILES_EINVAL; }
   if (arrow < 0 || arrow > N) { g_err_arg = 2; return STILES_EINVAL; }
@@ -1091,6 +1159,7 @@ extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t*
       init_common(*s, N, N - nb2, opts);   // the separators join the arrow
       s->ordering_used = STILES_ORDER_ADAPTABLE_ND;
       s->nd_parts = pl.P;
+      s->nd_chain = pl.chain;
       set_band_part(*s, segs, pl.P);
       s->f_pre = std::move(fcur);
     }
@@ -1136,6 +1205,8 @@ extern "C" stiles_status stiles_analyze(int64_t N, int64_t arrow, const int64_t*
   *out = s;
   return STILES_OK;
 }
+
+}  // namespace
 
 namespace {
 
@@ -2040,6 +2111,7 @@ extern "C" stiles_status stiles_symbolic_query(const stiles_symbolic* s, stiles_
   info->tree_used = s->tree_used;
   info->nnz_L_alg = s->nnzL_alg;
   info->update_blocks = s->ublocks;
+  info->nd_chain = s->nd_chain;
   return STILES_OK;
 }
 

@@ -39,6 +39,7 @@ struct stiles_symbolic {
 
   bool perm_identity = true;
   int32_t nd_parts = 1;        // adaptable ND partitions (1: not used)
+  int64_t nd_chain = 0;        // ND: estimated chain of the plan, in tile steps
   std::vector<int32_t> band_part;   // ND: partition of each band tile row/column
   std::vector<int64_t> f_pre;  // profile before adaptable ND (flops_alg), empty if unused
 
